@@ -1,0 +1,202 @@
+/*
+ * libdd: two-level DD-alpha-AMG for the Wilson-clover operator on one AMD
+ * Instinct gfx950 GPU.  C ABI: plain pointers and sizes, no C++ types.
+ *
+ * The method is the one of Ishikawa & Kanamori, "Porting DDalphaAMG solver to
+ * K computer" (LATTICE2018), Sec. 2: adaptive test vectors, aggregation with
+ * chirality split (Eq. 1), Galerkin coarse operator (Eq. 2), restriction and
+ * prolongation (Eqs. 3-4), the preconditioner M (Eq. 5) with SAP post-smoothing
+ * and an even-odd coarse GMRES, inside a flexible GMRES outer solver.  The
+ * problem solved is D x = b for given links, mass m0 (kappa = 1/(8 + 2 m0)) and
+ * c_sw (Sec. 1), as a batch of right-hand sides per gauge field (Sec. 4).
+ *
+ * Conventions shared with the canonical host layouts
+ *   site     = x + Lx*(y + Ly*(z + Lz*t)); directions mu = 0..3 <-> x, y, z, t
+ *   links    : complex128 [V][4][3][3]        (site, mu, row, column)
+ *   fine vec : complex128 [nrhs][V][4][3]     (rhs, site, spin, colour)
+ *   coarse   : complex128 [nrhs][Vc][2][n]    (rhs, coarse site, chirality, vector)
+ *              coarse site = lexicographic index of the block coordinates
+ *   gamma matrices in the chiral representation, gamma5 = diag(1,1,-1,-1)
+ *   D psi(x) = A(x) psi(x) - 1/2 sum_mu [(1-g_mu) U_mu(x) psi(x+mu)
+ *                                        + (1+g_mu) U_mu(x-mu)^dag psi(x-mu)]
+ *   A(x) = (4 + m0) - (c_sw/32) sum_{mu,nu} g_mu g_nu (x) (Q_mu,nu(x) - Q_nu,mu(x))
+ *   hops that wrap around in t are multiplied by bc_t.
+ *
+ * Internal ("packed") vectors are the device layouts the kernels use; they are
+ * reached only through dd_pack_* / dd_unpack_* and sized by dd_*_vec_bytes.
+ *
+ * Ownership: the library owns every handle and its own device workspace, which
+ * counts against the context's HBM budget.  Callers own every vector buffer
+ * they pass (device pointers).  A dd_ctx is used from one host thread;
+ * concurrency comes from the streams passed in.  Apply calls are asynchronous
+ * on `stream` (a hipStream_t, NULL = default stream).  dd_setup and dd_solve
+ * synchronise `stream` at their convergence checks.
+ *
+ * Errors: every call returns a dd_status; nothing aborts or throws across the
+ * ABI.  dd_last_error() gives the text of the last error on a context.
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DD_OK = 0,
+  DD_EINVAL = 1,   /* bad argument (null pointer, unknown dtype, nrhs < 1, ...) */
+  DD_ESHAPE = 2,   /* lattice / block / n_vec combination not supported          */
+  DD_ENOMEM = 3,   /* device allocation failed                                   */
+  DD_EBUDGET = 4,  /* the request would exceed the context's HBM budget          */
+  DD_ENOCONV = 5,  /* solver stopped at max_outer_iters; x holds the best iterate */
+  DD_ENAN = 6,     /* non-finite right-hand side or breakdown                    */
+  DD_EDEVICE = 7,  /* HIP runtime error                                          */
+  DD_ESTATE = 8    /* object in use (e.g. gauge referenced by a multigrid)       */
+} dd_status;
+
+/* Arithmetic / storage type of an operation.  DD_F64: FP64 vectors and
+ * operands.  DD_F32: FP32 vectors and operands.  DD_F16 / DD_BF16: FP32
+ * vectors and arithmetic with links, clover, clover inverse and test vectors
+ * stored in half / bfloat16 (round to nearest even from FP32). */
+typedef enum { DD_F64 = 0, DD_F32 = 1, DD_F16 = 2, DD_BF16 = 3 } dd_dtype;
+
+typedef struct dd_ctx dd_ctx;
+typedef struct dd_gauge dd_gauge;
+typedef struct dd_mg dd_mg;
+
+/* The discretised problem.  `block` is the domain tiling (the paper's 4^4
+ * blocks, Sec. 4): each block is one coarse site and one SAP domain.  Every
+ * block edge must be a power of two >= 2, divide L, and leave an even number
+ * of blocks in every direction (red-black SAP and coarse even-odd need it). */
+typedef struct {
+  int32_t L[4];
+  int32_t block[4];
+  int32_t bc_t;      /* -1 antiperiodic, +1 periodic in t */
+  double m0;         /* mass; kappa = 1/(8 + 2 m0) */
+  double c_sw;
+} dd_problem;
+
+/* Multigrid parameters (defaults from dd_mg_params_default follow the paper:
+ * Sec. 2 four setup iterations, coarse stop at 5e-2; Sec. 4 N_SAP = 4). */
+typedef struct {
+  int32_t agg_block[4];       /* must equal the gauge's block                     */
+  int32_t sap_block[4];       /* must equal the gauge's block                     */
+  int32_t n_vec;              /* test vectors n (even, Sec. 3), 2n coarse dof     */
+  int32_t setup_iters;        /* adaptive iterations after the initial solves     */
+  int32_t init_sap_apps;      /* SAP approximate solves on the random vectors     */
+  int32_t sap_sweeps;         /* nu: SAP sweeps per smoother application          */
+  int32_t sap_mr_iters;       /* fixed MR iterations per domain solve             */
+  int32_t coarse_restart;     /* coarse GMRES restart length                      */
+  int32_t coarse_max_iters;   /* coarse GMRES iteration cap                       */
+  int32_t coarse_fixed_iters; /* > 0: exactly this many coarse iterations         */
+  int32_t fgmres_restart;     /* outer FGMRES(m)                                  */
+  int32_t max_outer_iters;
+  double coarse_tol;          /* relative residual of the coarse Schur system    */
+  dd_dtype inner_dtype;       /* DD_F64: all-FP64 preconditioner; else FP32      */
+  dd_dtype store_dtype;       /* operand storage inside M (F64/F32/F16/BF16)      */
+  uint64_t seed;              /* random starting vectors of dd_setup              */
+} dd_mg_params;
+
+typedef struct {
+  int32_t outer_iters, restarts, coarse_iters_total, converged;
+  double true_relres;          /* |b - D x| / |b| with the FP64 operator */
+  double t_setup_s, t_solve_s;
+  int64_t bytes_model, flops_model;
+} dd_solve_info;
+
+/* ---- context -------------------------------------------------------------- */
+dd_status dd_ctx_create(int device, size_t hbm_budget_bytes, dd_ctx** out);
+void dd_ctx_destroy(dd_ctx* ctx);
+const char* dd_status_str(dd_status s);
+const char* dd_last_error(const dd_ctx* ctx);
+size_t dd_ctx_bytes_in_use(const dd_ctx* ctx);
+void dd_mg_params_default(dd_mg_params* p);
+
+/* ---- gauge field (field preparation) ---------------------------------------
+ * Copies the links (host, canonical complex128), builds the clover term from
+ * the four plaquette leaves of every plane and inverts its two Hermitian 6x6
+ * chirality blocks in FP64 (Sec. 3 stores the full inverse, packed as 6 real
+ * plus 15 complex numbers per block).  Keeps FP64 copies for the outer
+ * operator and lazily makes the storage-dtype copies the inner solvers use.
+ * The caller may free links_host on return. */
+dd_status dd_gauge_create(dd_ctx* ctx, const dd_problem* prob, const double* links_host,
+                          dd_gauge** out);
+dd_status dd_gauge_destroy(dd_gauge* g);   /* DD_ESTATE while a dd_mg references it */
+
+/* ---- vectors ------------------------------------------------------------------ */
+size_t dd_fine_vec_bytes(const dd_gauge* g, dd_dtype dt, int nrhs);
+size_t dd_coarse_vec_bytes(const dd_mg* mg, dd_dtype dt, int nrhs);
+/* canonical complex128 device buffer <-> packed device buffer of dtype dt */
+dd_status dd_pack_fine(const dd_gauge* g, dd_dtype dt, int nrhs, const double* canon_dev,
+                       void* packed_dev, void* stream);
+dd_status dd_unpack_fine(const dd_gauge* g, dd_dtype dt, int nrhs, const void* packed_dev,
+                         double* canon_dev, void* stream);
+dd_status dd_pack_coarse(const dd_mg* mg, dd_dtype dt, int nrhs, const double* canon_dev,
+                         void* packed_dev, void* stream);
+dd_status dd_unpack_coarse(const dd_mg* mg, dd_dtype dt, int nrhs, const void* packed_dev,
+                           double* canon_dev, void* stream);
+
+/* ---- fine operator and smoother ---------------------------------------------------
+ * dd_dirac_apply: out = D in for nrhs packed vectors (Sec. 3: hopping term and
+ * clover term).  DD_F64 uses the FP64 operands; DD_F32/F16/BF16 use the stored
+ * copies of that dtype with FP32 vectors.  `in` and `out` must not overlap. */
+dd_status dd_dirac_apply(dd_gauge* g, dd_dtype dt, int nrhs, const void* in, void* out,
+                         void* stream);
+/* dd_sap_smooth: x <- SAP(b, x0 = x): p->sap_sweeps sweeps, red then black
+ * domains, each domain solved by p->sap_mr_iters even-odd MR iterations
+ * (Sec. 2 smoother).  Only sap_sweeps and sap_mr_iters of p are used. */
+dd_status dd_sap_smooth(dd_gauge* g, const dd_mg_params* p, dd_dtype dt, int nrhs,
+                        const void* b, void* x, void* stream);
+
+/* ---- setup ------------------------------------------------------------------------------
+ * dd_setup: random starting vectors from p->seed; dd_setup_from_vectors: the
+ * caller's starting vectors (host, canonical complex128 [n][V][4][3]).  Both then
+ * run init_sap_apps SAP solves, build (per-aggregate Gram-Schmidt in FP64, P,
+ * D_c = P^dag D P, coarse odd-site inverses) and setup_iters adaptive
+ * iterations lambda_i <- M lambda_i (Sec. 2). */
+dd_status dd_setup(dd_gauge* g, const dd_mg_params* p, dd_mg** out);
+dd_status dd_setup_from_vectors(dd_gauge* g, const dd_mg_params* p, const double* tv_host,
+                                dd_mg** out);
+dd_status dd_mg_destroy(dd_mg* mg);
+
+/* ---- transfer and coarse operator -------------------------------------------------------
+ * DD_F64 or DD_F32 (coarse data in that precision). */
+dd_status dd_restrict(dd_mg* mg, dd_dtype dt, int nrhs, const void* fine_in, void* coarse_out,
+                      void* stream);   /* Eq. 3 */
+dd_status dd_prolong(dd_mg* mg, dd_dtype dt, int nrhs, const void* coarse_in, void* fine_out,
+                     void* stream);    /* Eq. 4 */
+dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out,
+                          void* stream);   /* Eq. 2 stencil */
+/* approximate D_c^-1: even-odd GMRES to coarse_tol (or coarse_fixed_iters) */
+dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out,
+                          int* iters, void* stream);
+/* out = M in (Eq. 5), packed fine vectors of the inner dtype */
+dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void* stream);
+
+/* ---- solve -------------------------------------------------------------------------------
+ * FGMRES(m) right-preconditioned by M; the outer residual, orthogonalisation
+ * and Hessenberg least squares are FP64 on the device; stops when every
+ * right-hand side has |b - D x| / |b| <= tol with the FP64 operator.
+ * b and x: canonical complex128 device buffers [nrhs][V][4][3]; info: nrhs entries. */
+dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon_dev, double* x_canon_dev,
+                   double tol, dd_solve_info* info, void* stream);
+
+/* ---- exports for parity checks (host buffers) ----------------------------------------- */
+dd_status dd_export_maps(const dd_gauge* g, int32_t* agg_of_site, int32_t* local_of_site,
+                         int32_t* packed_index_of_site, int8_t* color_of_block);
+dd_status dd_export_clover(const dd_gauge* g, double* clover_host /* [V][2][36] */,
+                           double* clover_inv_host /* [V][2][36] */);
+/* raw stored operand copies of dtype dt, in the packed layout: links [4][9][V]
+ * pairs and clover [36][V] pairs of that dtype (16, 8, 4 or 4 bytes per pair);
+ * sites in packed order (dd_export_maps gives packed_index_of_site) */
+dd_status dd_export_operands(dd_gauge* g, dd_dtype dt, void* links_host, void* clover_host);
+dd_status dd_export_coarse(const dd_mg* mg, double* dc_host /* [Vc][9][2n][2n] c128 */);
+dd_status dd_export_vectors(const dd_mg* mg, double* tv_host /* [n][V][4][3] c128 */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,323 @@
+"""ctypes binding of libdd (include/dd.h).  Argument marshalling only: every
+operation runs in the HIP library.  Device buffers are torch tensors on the
+GPU (their data pointers are passed through); streams are torch streams.
+
+The library must have been built (paper_1811_00355_amd/build.py); importing
+this module fails loudly when it is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdd.so")
+
+DD_F64, DD_F32, DD_F16, DD_BF16 = 0, 1, 2, 3
+DTYPES = {"f64": DD_F64, "f32": DD_F32, "f16": DD_F16, "bf16": DD_BF16}
+STATUS = ["DD_OK", "DD_EINVAL", "DD_ESHAPE", "DD_ENOMEM", "DD_EBUDGET", "DD_ENOCONV",
+          "DD_ENAN", "DD_EDEVICE", "DD_ESTATE"]
+
+
+class DDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS[status] if 0 <= status < len(STATUS) else status}: {msg}")
+        self.status = status
+        self.name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+
+
+class dd_problem(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("block", ctypes.c_int32 * 4), ("bc_t", ctypes.c_int32),
+                ("m0", ctypes.c_double), ("c_sw", ctypes.c_double)]
+
+
+class dd_mg_params(ctypes.Structure):
+    _fields_ = [("agg_block", ctypes.c_int32 * 4), ("sap_block", ctypes.c_int32 * 4),
+                ("n_vec", ctypes.c_int32), ("setup_iters", ctypes.c_int32),
+                ("init_sap_apps", ctypes.c_int32), ("sap_sweeps", ctypes.c_int32),
+                ("sap_mr_iters", ctypes.c_int32), ("coarse_restart", ctypes.c_int32),
+                ("coarse_max_iters", ctypes.c_int32), ("coarse_fixed_iters", ctypes.c_int32),
+                ("fgmres_restart", ctypes.c_int32), ("max_outer_iters", ctypes.c_int32),
+                ("coarse_tol", ctypes.c_double), ("inner_dtype", ctypes.c_int32),
+                ("store_dtype", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class dd_solve_info(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("coarse_iters_total", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("true_relres", ctypes.c_double), ("t_setup_s", ctypes.c_double),
+                ("t_solve_s", ctypes.c_double), ("bytes_model", ctypes.c_int64),
+                ("flops_model", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_S = ctypes.c_size_t
+
+# name -> (restype, argtypes); every symbol declared in include/dd.h
+SIGNATURES = {
+    "dd_ctx_create": (_I, [_I, _S, ctypes.POINTER(_P)]),
+    "dd_ctx_destroy": (None, [_P]),
+    "dd_status_str": (ctypes.c_char_p, [_I]),
+    "dd_last_error": (ctypes.c_char_p, [_P]),
+    "dd_ctx_bytes_in_use": (_S, [_P]),
+    "dd_mg_params_default": (None, [ctypes.POINTER(dd_mg_params)]),
+    "dd_gauge_create": (_I, [_P, ctypes.POINTER(dd_problem), _P, ctypes.POINTER(_P)]),
+    "dd_gauge_destroy": (_I, [_P]),
+    "dd_fine_vec_bytes": (_S, [_P, _I, _I]),
+    "dd_coarse_vec_bytes": (_S, [_P, _I, _I]),
+    "dd_pack_fine": (_I, [_P, _I, _I, _P, _P, _P]),
+    "dd_unpack_fine": (_I, [_P, _I, _I, _P, _P, _P]),
+    "dd_pack_coarse": (_I, [_P, _I, _I, _P, _P, _P]),
+    "dd_unpack_coarse": (_I, [_P, _I, _I, _P, _P, _P]),
+    "dd_dirac_apply": (_I, [_P, _I, _I, _P, _P, _P]),
+    "dd_sap_smooth": (_I, [_P, ctypes.POINTER(dd_mg_params), _I, _I, _P, _P, _P]),
+    "dd_setup": (_I, [_P, ctypes.POINTER(dd_mg_params), ctypes.POINTER(_P)]),
+    "dd_setup_from_vectors": (_I, [_P, ctypes.POINTER(dd_mg_params), _P, ctypes.POINTER(_P)]),
+    "dd_mg_destroy": (_I, [_P]),
+    "dd_restrict": (_I, [_P, _I, _I, _P, _P, _P]),
+    "dd_prolong": (_I, [_P, _I, _I, _P, _P, _P]),
+    "dd_coarse_apply": (_I, [_P, _I, _I, _P, _P, _P]),
+    "dd_coarse_solve": (_I, [_P, _I, _I, _P, _P, ctypes.POINTER(_I), _P]),
+    "dd_precond_apply": (_I, [_P, _I, _P, _P, _P]),
+    "dd_solve": (_I, [_P, _I, _P, _P, ctypes.c_double, ctypes.POINTER(dd_solve_info), _P]),
+    "dd_export_maps": (_I, [_P, _P, _P, _P, _P]),
+    "dd_export_clover": (_I, [_P, _P, _P]),
+    "dd_export_operands": (_I, [_P, _I, _P, _P]),
+    "dd_export_coarse": (_I, [_P, _P]),
+    "dd_export_vectors": (_I, [_P, _P]),
+}
+
+
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 6 and "libamdhip64" in parts[-1]:
+                paths.add(parts[-1])
+    return paths
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"libdd is not built ({path} missing): run paper_1811_00355_amd/build.py")
+    # torch brings its own HIP runtime; load it first so that libdd binds to the
+    # same runtime (one HIP runtime per process; the soname matches).
+    import torch  # noqa: F401
+    import torch.cuda  # noqa: F401
+    lib = ctypes.CDLL(path)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError(f"two HIP runtimes mapped into the process: {sorted(rts)}")
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    def __init__(self, device=0, hbm_budget_bytes=200 << 30):
+        self.h = _P()
+        self.lib = lib()
+        st = self.lib.dd_ctx_create(device, hbm_budget_bytes, ctypes.byref(self.h))
+        if st:
+            raise DDError(st, "dd_ctx_create failed")
+
+    def check(self, st):
+        if st:
+            raise DDError(st, self.lib.dd_last_error(self.h).decode())
+
+    def bytes_in_use(self):
+        return self.lib.dd_ctx_bytes_in_use(self.h)
+
+    def close(self):
+        if self.h:
+            self.lib.dd_ctx_destroy(self.h)
+            self.h = _P()
+
+
+def default_params(**kw):
+    p = dd_mg_params()
+    lib().dd_mg_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k in ("agg_block", "sap_block", "block"):
+            for m in range(4):
+                if k in ("agg_block", "block"):
+                    p.agg_block[m] = v[m]
+                if k in ("sap_block", "block"):
+                    p.sap_block[m] = v[m]
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class Gauge:
+    """A gauge field on the device: links, clover, clover inverse."""
+
+    def __init__(self, ctx, L, block, links, m0, c_sw, bc_t=-1):
+        self.ctx = ctx
+        self.L, self.block = tuple(L), tuple(block)
+        self.V = int(np.prod(L))
+        self.Vc = int(np.prod([L[m] // block[m] for m in range(4)]))
+        pr = dd_problem()
+        for m in range(4):
+            pr.L[m] = L[m]
+            pr.block[m] = block[m]
+        pr.bc_t, pr.m0, pr.c_sw = bc_t, m0, c_sw
+        links = np.ascontiguousarray(links, dtype=np.complex128)
+        assert links.shape == (self.V, 4, 3, 3)
+        self.h = _P()
+        ctx.check(ctx.lib.dd_gauge_create(ctx.h, ctypes.byref(pr), links.ctypes.data_as(_P), ctypes.byref(self.h)))
+
+    def destroy(self):
+        if self.h:
+            self.ctx.check(self.ctx.lib.dd_gauge_destroy(self.h))
+            self.h = _P()
+
+    # vectors ---------------------------------------------------------------------------
+    def fine_vec_bytes(self, dtype, nrhs):
+        return self.ctx.lib.dd_fine_vec_bytes(self.h, dtype, nrhs)
+
+    def new_packed(self, dtype, nrhs, device="cuda"):
+        import torch
+        nb = self.fine_vec_bytes(dtype, nrhs)
+        return torch.zeros(nb, dtype=torch.uint8, device=device)
+
+    def pack(self, dtype, nrhs, canon, packed, stream=None):
+        self.ctx.check(self.ctx.lib.dd_pack_fine(self.h, dtype, nrhs, _ptr(canon), _ptr(packed), _stream(stream)))
+
+    def unpack(self, dtype, nrhs, packed, canon, stream=None):
+        self.ctx.check(self.ctx.lib.dd_unpack_fine(self.h, dtype, nrhs, _ptr(packed), _ptr(canon), _stream(stream)))
+
+    # operations ------------------------------------------------------------------------
+    def dd_dirac_apply(self, dtype, nrhs, inp, out, stream=None):
+        self.ctx.check(self.ctx.lib.dd_dirac_apply(self.h, dtype, nrhs, _ptr(inp), _ptr(out), _stream(stream)))
+
+    def dd_sap_smooth(self, params, dtype, nrhs, b, x, stream=None):
+        self.ctx.check(self.ctx.lib.dd_sap_smooth(self.h, ctypes.byref(params), dtype, nrhs, _ptr(b), _ptr(x),
+                                                  _stream(stream)))
+
+    def export_maps(self):
+        agg = np.zeros(self.V, np.int32)
+        loc = np.zeros(self.V, np.int32)
+        pidx = np.zeros(self.V, np.int32)
+        col = np.zeros(self.Vc, np.int8)
+        self.ctx.check(self.ctx.lib.dd_export_maps(self.h, agg.ctypes.data_as(_P), loc.ctypes.data_as(_P),
+                                                   pidx.ctypes.data_as(_P), col.ctypes.data_as(_P)))
+        return agg, loc, pidx, col
+
+    def export_operands(self, dtype):
+        """Raw stored links [36][V] and clover [36][V] pairs of `dtype`, packed site order."""
+        pair = {DD_F64: np.complex128, DD_F32: np.complex64, DD_F16: np.uint32, DD_BF16: np.uint32}[dtype]
+        links = np.zeros((36, self.V), dtype=pair)
+        clov = np.zeros((36, self.V), dtype=pair)
+        self.ctx.check(self.ctx.lib.dd_export_operands(self.h, dtype, links.ctypes.data_as(_P),
+                                                       clov.ctypes.data_as(_P)))
+        return links, clov
+
+    def export_clover(self):
+        a = np.zeros((self.V, 2, 36))
+        ai = np.zeros((self.V, 2, 36))
+        self.ctx.check(self.ctx.lib.dd_export_clover(self.h, a.ctypes.data_as(_P), ai.ctypes.data_as(_P)))
+        return a, ai
+
+
+class MG:
+    """A two-level multigrid setup on a gauge field."""
+
+    def __init__(self, gauge, params, tv_host=None):
+        self.g = gauge
+        self.ctx = gauge.ctx
+        self.p = params
+        self.n = params.n_vec
+        self.h = _P()
+        if tv_host is None:
+            self.ctx.check(self.ctx.lib.dd_setup(gauge.h, ctypes.byref(params), ctypes.byref(self.h)))
+        else:
+            tv = np.ascontiguousarray(tv_host, dtype=np.complex128)
+            assert tv.shape == (self.n, gauge.V, 4, 3)
+            self.ctx.check(self.ctx.lib.dd_setup_from_vectors(gauge.h, ctypes.byref(params), tv.ctypes.data_as(_P),
+                                                              ctypes.byref(self.h)))
+
+    def destroy(self):
+        if self.h:
+            self.ctx.check(self.ctx.lib.dd_mg_destroy(self.h))
+            self.h = _P()
+
+    def coarse_vec_bytes(self, dtype, nrhs):
+        return self.ctx.lib.dd_coarse_vec_bytes(self.h, dtype, nrhs)
+
+    def new_coarse(self, dtype, nrhs, device="cuda"):
+        import torch
+        return torch.zeros(self.coarse_vec_bytes(dtype, nrhs), dtype=torch.uint8, device=device)
+
+    def pack_coarse(self, dtype, nrhs, canon, packed, stream=None):
+        self.ctx.check(self.ctx.lib.dd_pack_coarse(self.h, dtype, nrhs, _ptr(canon), _ptr(packed), _stream(stream)))
+
+    def unpack_coarse(self, dtype, nrhs, packed, canon, stream=None):
+        self.ctx.check(self.ctx.lib.dd_unpack_coarse(self.h, dtype, nrhs, _ptr(packed), _ptr(canon),
+                                                     _stream(stream)))
+
+    def dd_restrict(self, dtype, nrhs, fine, coarse, stream=None):
+        self.ctx.check(self.ctx.lib.dd_restrict(self.h, dtype, nrhs, _ptr(fine), _ptr(coarse), _stream(stream)))
+
+    def dd_prolong(self, dtype, nrhs, coarse, fine, stream=None):
+        self.ctx.check(self.ctx.lib.dd_prolong(self.h, dtype, nrhs, _ptr(coarse), _ptr(fine), _stream(stream)))
+
+    def dd_coarse_apply(self, dtype, nrhs, inp, out, stream=None):
+        self.ctx.check(self.ctx.lib.dd_coarse_apply(self.h, dtype, nrhs, _ptr(inp), _ptr(out), _stream(stream)))
+
+    def dd_coarse_solve(self, dtype, nrhs, inp, out, stream=None):
+        it = _I(0)
+        self.ctx.check(self.ctx.lib.dd_coarse_solve(self.h, dtype, nrhs, _ptr(inp), _ptr(out), ctypes.byref(it),
+                                                    _stream(stream)))
+        return it.value
+
+    def dd_precond_apply(self, nrhs, inp, out, stream=None):
+        self.ctx.check(self.ctx.lib.dd_precond_apply(self.h, nrhs, _ptr(inp), _ptr(out), _stream(stream)))
+
+    def dd_solve(self, nrhs, b_canon, x_canon, tol, stream=None, raise_on_noconv=True):
+        info = (dd_solve_info * nrhs)()
+        st = self.ctx.lib.dd_solve(self.h, nrhs, _ptr(b_canon), _ptr(x_canon), tol, info, _stream(stream))
+        if st and not (st == 5 and not raise_on_noconv):
+            self.ctx.check(st)
+        return [dict(outer_iters=i.outer_iters, restarts=i.restarts, coarse_iters_total=i.coarse_iters_total,
+                     converged=bool(i.converged), true_relres=i.true_relres, t_setup_s=i.t_setup_s,
+                     t_solve_s=i.t_solve_s, bytes_model=i.bytes_model, flops_model=i.flops_model)
+                for i in info], st
+
+    def export_coarse(self):
+        nc = 2 * self.n
+        dc = np.zeros((self.g.Vc, 9, nc, nc), dtype=np.complex128)
+        self.ctx.check(self.ctx.lib.dd_export_coarse(self.h, dc.ctypes.data_as(_P)))
+        return dc
+
+    def export_vectors(self):
+        tv = np.zeros((self.n, self.g.V, 4, 3), dtype=np.complex128)
+        self.ctx.check(self.ctx.lib.dd_export_vectors(self.h, tv.ctypes.data_as(_P)))
+        return tv

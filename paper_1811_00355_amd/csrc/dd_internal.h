@@ -1,0 +1,351 @@
+// Internal declarations shared by the libdd translation units: handle
+// structs, the packed-layout geometry, device complex arithmetic, storage
+// types and the host-side kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dd.h"
+
+// ---------------------------------------------------------------------------
+// Packed geometry
+//
+// Sites are stored block-major: packed index I = slot * Bv + p * Bvh + j, where
+//   slot : block ("domain") slot; red blocks (sum of block coordinates even)
+//          take slots [0, Vc/2), black blocks [Vc/2, Vc); inside a colour the
+//          slot is (lexicographic block index) / 2,
+//   p    : site parity (block origins are even, so local parity = global parity),
+//   j    : (lexicographic position inside the block) / 2.
+// A domain is a contiguous range of Bv sites with its even sites first, and the
+// coarse lattice uses the same slots (even coarse sites = red blocks first).
+// Block edges are powers of two, so local coordinates come from shifts.
+// ---------------------------------------------------------------------------
+struct GeomDev {
+  int L[4];
+  int b[4];
+  int lb[4];      // log2 of the block edges
+  int lBv;        // log2(Bv)
+  int Bv, Bvh;    // sites per block, half of it
+  int Vc, Vch;    // blocks (coarse sites), half of it
+  long long V;
+  const int* blk_nbr;    // [8][Vc]: slot of the neighbouring block; bit 30 set when the hop wraps in t
+  const int* blk_coord;  // [Vc]: block coordinates packed as bx | by<<8 | bz<<16 | bt<<24
+  double bc_t;
+};
+
+#define DD_WRAP_BIT (1 << 30)
+#define DD_SLOT_MASK ((1 << 30) - 1)
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> cmul_conj(cx<R> a, cx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// acc += a * b
+template <typename R>
+__host__ __device__ __forceinline__ void cfma(cx<R>& acc, cx<R> a, cx<R> b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+}
+// acc += conj(a) * b
+template <typename R>
+__host__ __device__ __forceinline__ void cfma_conj(cx<R>& acc, cx<R> a, cx<R> b) {
+  acc.re += a.re * b.re + a.im * b.im;
+  acc.im += a.re * b.im - a.im * b.re;
+}
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
+
+// ---------------------------------------------------------------------------
+// storage types: a complex number stored as a pair
+// ---------------------------------------------------------------------------
+struct bf16x2 {
+  uint32_t u;  // low 16 bits: real part, high 16 bits: imaginary part
+};
+
+template <typename S>
+struct StoreTraits;
+template <>
+struct StoreTraits<double2> {
+  typedef double R;
+};
+template <>
+struct StoreTraits<float2> {
+  typedef float R;
+};
+template <>
+struct StoreTraits<__half2> {
+  typedef float R;
+};
+template <>
+struct StoreTraits<bf16x2> {
+  typedef float R;
+};
+
+template <typename R, typename S>
+__device__ __forceinline__ cx<R> ld(const S* p);
+template <>
+__device__ __forceinline__ cx<double> ld<double, double2>(const double2* p) {
+  double2 v = *p;
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ cx<float> ld<float, float2>(const float2* p) {
+  float2 v = *p;
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ cx<float> ld<float, __half2>(const __half2* p) {
+  float2 v = __half22float2(*p);
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ cx<float> ld<float, bf16x2>(const bf16x2* p) {
+  uint32_t u = p->u;
+  return {__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u)};
+}
+template <>
+__device__ __forceinline__ cx<double> ld<double, float2>(const float2* p) {
+  float2 v = *p;
+  return {(double)v.x, (double)v.y};
+}
+template <>
+__device__ __forceinline__ cx<double> ld<double, __half2>(const __half2* p) {
+  float2 v = __half22float2(*p);
+  return {(double)v.x, (double)v.y};
+}
+template <>
+__device__ __forceinline__ cx<double> ld<double, bf16x2>(const bf16x2* p) {
+  uint32_t u = p->u;
+  return {(double)__uint_as_float(u << 16), (double)__uint_as_float(u & 0xffff0000u)};
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void st(S* p, cx<R> v);
+template <>
+__device__ __forceinline__ void st<double2, double>(double2* p, cx<double> v) { *p = make_double2(v.re, v.im); }
+template <>
+__device__ __forceinline__ void st<float2, float>(float2* p, cx<float> v) { *p = make_float2(v.re, v.im); }
+template <>
+__device__ __forceinline__ void st<float2, double>(float2* p, cx<double> v) {
+  *p = make_float2((float)v.re, (float)v.im);
+}
+template <>
+__device__ __forceinline__ void st<double2, float>(double2* p, cx<float> v) {
+  *p = make_double2((double)v.re, (double)v.im);
+}
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// ---------------------------------------------------------------------------
+// packed-geometry helpers (device)
+// ---------------------------------------------------------------------------
+struct SiteLoc {
+  int slot;
+  int l[4];
+};
+
+__host__ __device__ __forceinline__ SiteLoc decode_site(const GeomDev& g, long long I) {
+  SiteLoc s;
+  s.slot = (int)(I >> g.lBv);
+  int loc = (int)(I & (g.Bv - 1));
+  int p = loc >> (g.lBv - 1);
+  int lex2 = (loc & (g.Bvh - 1)) << 1;
+  int lx0 = lex2 & (g.b[0] - 1);
+  s.l[1] = (lex2 >> g.lb[0]) & (g.b[1] - 1);
+  s.l[2] = (lex2 >> (g.lb[0] + g.lb[1])) & (g.b[2] - 1);
+  s.l[3] = lex2 >> (g.lb[0] + g.lb[1] + g.lb[2]);
+  s.l[0] = lx0 + ((p + s.l[1] + s.l[2] + s.l[3]) & 1);
+  return s;
+}
+
+__host__ __device__ __forceinline__ int encode_local(const GeomDev& g, const int l[4]) {
+  int lex = l[0] + ((l[1] + ((l[2] + (l[3] << g.lb[2])) << g.lb[1])) << g.lb[0]);
+  int p = (l[0] + l[1] + l[2] + l[3]) & 1;
+  return p * g.Bvh + (lex >> 1);
+}
+
+// Neighbour of a site in direction mu (sign +1/-1).  Returns the packed index
+// and sets `wrap` when the hop crosses the t boundary, `inside` when the
+// neighbour lies in the same block.
+__host__ __device__ __forceinline__ long long neighbor(const GeomDev& g, const SiteLoc& s, int mu, int sign,
+                                              bool& wrap, bool& inside) {
+  int l[4] = {s.l[0], s.l[1], s.l[2], s.l[3]};
+  int v = l[mu] + sign;
+  int slot = s.slot;
+  wrap = false;
+  inside = (v >= 0 && v < g.b[mu]);
+  if (!inside) {
+    int e = g.blk_nbr[(sign > 0 ? mu : 4 + mu) * g.Vc + slot];
+    wrap = (e & DD_WRAP_BIT) != 0;
+    slot = e & DD_SLOT_MASK;
+    v = (sign > 0) ? 0 : g.b[mu] - 1;
+  }
+  l[mu] = v;
+  return ((long long)slot << g.lBv) + encode_local(g, l);
+}
+
+// lexicographic site index of a packed site
+__host__ __device__ __forceinline__ long long lex_site(const GeomDev& g, const SiteLoc& s) {
+  int bc = g.blk_coord[s.slot];
+  int x = (bc & 255) * g.b[0] + s.l[0];
+  int y = ((bc >> 8) & 255) * g.b[1] + s.l[1];
+  int z = ((bc >> 16) & 255) * g.b[2] + s.l[2];
+  int t = ((bc >> 24) & 255) * g.b[3] + s.l[3];
+  return x + (long long)g.L[0] * (y + (long long)g.L[1] * (z + (long long)g.L[2] * t));
+}
+
+// ---------------------------------------------------------------------------
+// host-side objects
+// ---------------------------------------------------------------------------
+struct dd_ctx {
+  int device;
+  size_t budget;
+  size_t in_use;
+  std::string last_error;
+};
+
+// Operand copies of one storage type (links, clover, clover inverse).
+struct OpSet {
+  bool ready = false;
+  void* links = nullptr;    // [4][9][V]   complex pairs of the storage type
+  void* clover = nullptr;   // [36][V]     packed Hermitian blocks, pairs of the storage type
+  void* cinv = nullptr;     // [36][V]     same layout, inverse
+};
+
+struct dd_gauge {
+  dd_ctx* ctx;
+  dd_problem prob;
+  GeomDev geo;
+  int* d_blk_nbr = nullptr;
+  int* d_blk_coord = nullptr;
+  std::vector<int> h_blk_nbr, h_blk_coord;
+  OpSet ops[4];   // indexed by dd_dtype: F64 master, F32, F16, BF16
+  int refcount = 0;
+};
+
+struct Workspace;
+
+struct dd_mg {
+  dd_ctx* ctx;
+  dd_gauge* g;
+  dd_mg_params p;
+  int n;          // test vectors
+  int nc;         // 2n
+  dd_dtype vstore;  // storage of P inside M
+  // test vectors: FP64 master of the orthonormalised P (packed fine layout, n vectors)
+  double2* P64 = nullptr;
+  void* Pst = nullptr;     // P in the storage dtype (float2 / __half2 / bf16x2)
+  float2* tv32 = nullptr;  // working test vectors lambda_i (FP32, setup only)
+  // coarse operator: [Vc][9][col][row] complex (column-major blocks), FP64 master and FP32
+  double2* Dc64 = nullptr;
+  float2* Dc32 = nullptr;
+  // odd-site inverses of the self blocks: [Vch][col][row]
+  double2* Dinv64 = nullptr;
+  float2* Dinv32 = nullptr;
+  Workspace* ws = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+dd_status dd_fail(dd_ctx* ctx, dd_status s, const std::string& msg);
+dd_status dd_hip_check(dd_ctx* ctx, hipError_t e, const char* what);
+#define DD_HIP(ctx, call)                                            \
+  do {                                                               \
+    hipError_t _e = (call);                                          \
+    if (_e != hipSuccess) return dd_hip_check((ctx), _e, #call);    \
+  } while (0)
+
+dd_status dd_alloc(dd_ctx* ctx, void** p, size_t bytes);
+void dd_free(dd_ctx* ctx, void* p, size_t bytes);
+
+inline size_t storage_pair_bytes(dd_dtype dt) {
+  switch (dt) {
+    case DD_F64: return 16;
+    case DD_F32: return 8;
+    default: return 4;
+  }
+}
+inline size_t vector_pair_bytes(dd_dtype dt) { return dt == DD_F64 ? 16 : 8; }
+
+// ---------------------------------------------------------------------------
+// kernel launchers (each defined next to its kernels)
+// ---------------------------------------------------------------------------
+// geometry / packing
+void launch_pack_fine(const GeomDev& g, dd_dtype vt, int nrhs, const double2* canon, void* packed,
+                      hipStream_t st);
+void launch_unpack_fine(const GeomDev& g, dd_dtype vt, int nrhs, const void* packed, double2* canon,
+                        hipStream_t st);
+void launch_pack_links(const GeomDev& g, const double2* canon, double2* links64, hipStream_t st);
+// FP64 source for DD_F64 / DD_F32 targets, FP32 source for DD_F16 / DD_BF16 targets
+void launch_convert_pairs(dd_dtype to, const double2* src64, const float2* src32, void* dst, long long count,
+                          hipStream_t st);
+void launch_vec_convert(dd_dtype from, dd_dtype to, const void* src, void* dst, long long count,
+                        hipStream_t st);
+// clover
+void launch_clover_build(const GeomDev& g, const double2* links64, double m0, double csw,
+                         double2* clover64, double2* cinv64, hipStream_t st);
+// Dirac operator
+void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
+                  hipStream_t st);
+// SAP smoother
+void launch_sap(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters,
+                const void* b, void* x, hipStream_t st);
+// transfer
+void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,
+                     const void* fine, void* coarse, hipStream_t st);
+void launch_prolong(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,
+                    const void* coarse, void* fine, hipStream_t st);
+void launch_gram_schmidt(const GeomDev& g, int n, double2* P, int* bad_flag, hipStream_t st);
+void launch_coarse_build(const GeomDev& g, const OpSet& ops64, dd_dtype pst, int n, const void* P,
+                         double2* Dc64, hipStream_t st);
+void launch_coarse_invert(const GeomDev& g, int nc, const double2* Dc64, double2* Dinv64, int* bad_flag,
+                          hipStream_t st);
+// coarse operator
+void launch_coarse_apply(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, int nrhs, const void* in,
+                         void* out, int site_begin, int site_count, int dir_begin, int dir_end, double alpha,
+                         const void* zin, double beta, hipStream_t st);
+void launch_coarse_block_mul(const GeomDev& g, dd_dtype vt, int nc, const void* Dinv, int nrhs,
+                             const void* in, void* out, int site_begin, int site_count, hipStream_t st);
+// BLAS-like kernels on packed vectors (count complex entries per RHS, nrhs RHS with stride ld)
+void launch_multi_dot(dd_dtype vt, int nrhs, long long count, long long ld, const void* const* V, int nv,
+                      long long vstride, const void* w, double* partial, int nblk, hipStream_t st);
+int multi_dot_blocks(long long count);
+void launch_reduce_partials(int nrhs, int nv, int nblk, const double* partial, double2* out, hipStream_t st);

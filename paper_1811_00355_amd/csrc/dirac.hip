@@ -1,0 +1,48 @@
+// Wilson-clover operator apply: out = A psi + hopping term (Sec. 3), one
+// thread per (site, right-hand side).  The workgroup index runs over the RHS
+// fastest, so the workgroups that share a tile of sites (and its links and
+// clover) are resident together and the operator is fetched from HBM once.
+#include "dslash.h"
+
+namespace {
+
+template <typename R, typename S, typename Tv>
+__global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
+                                               int nrhs, const Tv* __restrict__ in, Tv* __restrict__ out) {
+  int r = blockIdx.x % nrhs;
+  long long I = (long long)(blockIdx.x / nrhs) * blockDim.x + threadIdx.x;
+  if (I >= g.V) return;
+  const Tv* x = in + (long long)r * 12 * g.V;
+  SiteLoc s = decode_site(g, I);
+  cx<R> psi[12], acc[12];
+  load_spinor<R, Tv>(x, g.V, I, psi);
+  clover_mul<R, S, false>(clov, g.V, I, psi, acc);
+  auto fetch = [&](long long J, bool, cx<R>* p) { load_spinor<R, Tv>(x, g.V, J, p); };
+  hop_all<R, S>(g, links, s, I, false, fetch, acc);
+  store_spinor<R, Tv>(out + (long long)r * 12 * g.V, g.V, I, acc);
+}
+
+}  // namespace
+
+void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
+                  hipStream_t st) {
+  unsigned nb = (unsigned)((g.V + 255) / 256) * nrhs;
+  switch (dt) {
+    case DD_F64:
+      k_dirac<double, double2, double2><<<nb, 256, 0, st>>>(g, (const double2*)ops.links, (const double2*)ops.clover,
+                                                            nrhs, (const double2*)in, (double2*)out);
+      break;
+    case DD_F32:
+      k_dirac<float, float2, float2><<<nb, 256, 0, st>>>(g, (const float2*)ops.links, (const float2*)ops.clover, nrhs,
+                                                         (const float2*)in, (float2*)out);
+      break;
+    case DD_F16:
+      k_dirac<float, __half2, float2><<<nb, 256, 0, st>>>(g, (const __half2*)ops.links, (const __half2*)ops.clover,
+                                                          nrhs, (const float2*)in, (float2*)out);
+      break;
+    case DD_BF16:
+      k_dirac<float, bf16x2, float2><<<nb, 256, 0, st>>>(g, (const bf16x2*)ops.links, (const bf16x2*)ops.clover, nrhs,
+                                                         (const float2*)in, (float2*)out);
+      break;
+  }
+}

@@ -1,0 +1,170 @@
+// Device building blocks of the Wilson-clover operator (Sec. 3: hopping term
+// and clover term), shared by the operator apply, the SAP smoother and the
+// coarse-operator construction.
+//
+// Chiral representation: gamma_mu = [[0, A_mu], [A_mu^dag, 0]] on (upper,
+// lower) spin pairs, A_x = -i sigma_1, A_y = -i sigma_2, A_z = -i sigma_3,
+// A_t = 1.  A hop with (1 + s gamma_mu) (s = -1 forward, +1 backward) acts on
+// the half spinor h = psi_up + s A_mu psi_dn; the lower pair of the result is
+// s A_mu^dag h.  So every hop multiplies only two colour vectors by a link.
+#pragma once
+#include "dd_internal.h"
+
+// o = A_mu d   (d, o: two colour vectors each)
+template <int MU, typename R>
+__device__ __forceinline__ void A_mul(const cx<R>* d0, const cx<R>* d1, cx<R>* o0, cx<R>* o1) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (MU == 0) { o0[a] = times_mi(d1[a]); o1[a] = times_mi(d0[a]); }
+    if (MU == 1) { o0[a] = -d1[a]; o1[a] = d0[a]; }
+    if (MU == 2) { o0[a] = times_mi(d0[a]); o1[a] = times_i(d1[a]); }
+    if (MU == 3) { o0[a] = d0[a]; o1[a] = d1[a]; }
+  }
+}
+// o = A_mu^dag h
+template <int MU, typename R>
+__device__ __forceinline__ void Adag_mul(const cx<R>* h0, const cx<R>* h1, cx<R>* o0, cx<R>* o1) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (MU == 0) { o0[a] = times_i(h1[a]); o1[a] = times_i(h0[a]); }
+    if (MU == 1) { o0[a] = h1[a]; o1[a] = -h0[a]; }
+    if (MU == 2) { o0[a] = times_i(h0[a]); o1[a] = times_mi(h1[a]); }
+    if (MU == 3) { o0[a] = h0[a]; o1[a] = h1[a]; }
+  }
+}
+
+// half spinor h = psi_up + s A_mu psi_dn  (h: 6 complex, spin-major)
+template <int MU, int SGN, typename R>
+__device__ __forceinline__ void project(const cx<R>* psi, cx<R>* h) {
+  cx<R> t0[3], t1[3];
+  A_mul<MU, R>(psi + 6, psi + 9, t0, t1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    h[a] = (SGN > 0) ? psi[a] + t0[a] : psi[a] - t0[a];
+    h[3 + a] = (SGN > 0) ? psi[3 + a] + t1[a] : psi[3 + a] - t1[a];
+  }
+}
+
+// acc += c * (h, s A_mu^dag h)
+template <int MU, int SGN, typename R>
+__device__ __forceinline__ void reconstruct_acc(const cx<R>* h, R c, cx<R>* acc) {
+  cx<R> t0[3], t1[3];
+  Adag_mul<MU, R>(h, h + 3, t0, t1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[a] = acc[a] + c * h[a];
+    acc[3 + a] = acc[3 + a] + c * h[3 + a];
+    R cs = (SGN > 0) ? c : -c;
+    acc[6 + a] = acc[6 + a] + cs * t0[a];
+    acc[9 + a] = acc[9 + a] + cs * t1[a];
+  }
+}
+
+template <typename R, typename S>
+__device__ __forceinline__ void load_link(const S* L, long long V, int mu, long long I, cx<R>* u) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u[k] = ld<R, S>(L + (long long)(mu * 9 + k) * V + I);
+}
+
+// o = U h on both spin components of a half spinor
+template <typename R>
+__device__ __forceinline__ void su3_mul_half(const cx<R>* u, const cx<R>* h, cx<R>* o) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> acc = u[3 * a] * h[3 * s];
+      cfma(acc, u[3 * a + 1], h[3 * s + 1]);
+      cfma(acc, u[3 * a + 2], h[3 * s + 2]);
+      o[3 * s + a] = acc;
+    }
+}
+// o = U^dag h
+template <typename R>
+__device__ __forceinline__ void su3_dag_mul_half(const cx<R>* u, const cx<R>* h, cx<R>* o) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> acc = cmul_conj(u[a], h[3 * s]);
+      cfma_conj(acc, u[3 + a], h[3 * s + 1]);
+      cfma_conj(acc, u[6 + a], h[3 * s + 2]);
+      o[3 * s + a] = acc;
+    }
+}
+
+// out (=|+=) C psi for a packed clover-like field (two Hermitian 6x6 blocks)
+template <typename R, typename S, bool ACC>
+__device__ __forceinline__ void clover_mul(const S* C, long long V, long long I, const cx<R>* in, cx<R>* out) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const S* B = C + (long long)(18 * c) * V + I;
+    const cx<R>* v = in + 6 * c;
+    cx<R> o[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cx<R> d = ld<R, S>(B + k * V);
+      o[2 * k] = d.re * v[2 * k];
+      o[2 * k + 1] = d.im * v[2 * k + 1];
+    }
+    int k = 3;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int q = r + 1; q < 6; ++q) {
+        cx<R> u = ld<R, S>(B + (long long)(k++) * V);
+        cfma(o[r], u, v[q]);
+        cfma_conj(o[q], u, v[r]);
+      }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) out[6 * c + r] = ACC ? out[6 * c + r] + o[r] : o[r];
+  }
+}
+
+template <typename R, typename Tv>
+__device__ __forceinline__ void load_spinor(const Tv* p, long long V, long long I, cx<R>* psi) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] = ld<R, Tv>(p + (long long)c * V + I);
+}
+template <typename R, typename Tv>
+__device__ __forceinline__ void store_spinor(Tv* p, long long V, long long I, const cx<R>* psi) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) st<Tv, R>(p + (long long)c * V + I, psi[c]);
+}
+
+// One hop term for direction MU at site s: acc += -1/2 * phase * (1 -+ gamma) U psi(neighbour).
+// The neighbour spinor is fetched by the functor `fetch(J, inside, psi)`; a
+// hop is skipped when `dirichlet` and the neighbour lies outside the block.
+template <int MU, typename R, typename S, typename Fetch>
+__device__ __forceinline__ void hop_mu(const GeomDev& g, const S* links, const SiteLoc& s, long long I, bool dirichlet,
+                                       Fetch fetch, cx<R>* acc) {
+  bool wrap, inside;
+  cx<R> psi[12], h[6], uh[6], u[9];
+  // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
+  long long J = neighbor(g, s, MU, +1, wrap, inside);
+  if (!dirichlet || inside) {
+    fetch(J, inside, psi);
+    project<MU, -1, R>(psi, h);
+    load_link<R, S>(links, g.V, MU, I, u);
+    su3_mul_half<R>(u, h, uh);
+    reconstruct_acc<MU, -1, R>(uh, (R)(wrap ? -0.5 * g.bc_t : -0.5), acc);
+  }
+  // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
+  J = neighbor(g, s, MU, -1, wrap, inside);
+  if (!dirichlet || inside) {
+    fetch(J, inside, psi);
+    project<MU, +1, R>(psi, h);
+    load_link<R, S>(links, g.V, MU, J, u);
+    su3_dag_mul_half<R>(u, h, uh);
+    reconstruct_acc<MU, +1, R>(uh, (R)(wrap ? -0.5 * g.bc_t : -0.5), acc);
+  }
+}
+
+template <typename R, typename S, typename Fetch>
+__device__ __forceinline__ void hop_all(const GeomDev& g, const S* links, const SiteLoc& s, long long I, bool dirichlet,
+                                        Fetch fetch, cx<R>* acc) {
+  hop_mu<0, R, S>(g, links, s, I, dirichlet, fetch, acc);
+  hop_mu<1, R, S>(g, links, s, I, dirichlet, fetch, acc);
+  hop_mu<2, R, S>(g, links, s, I, dirichlet, fetch, acc);
+  hop_mu<3, R, S>(g, links, s, I, dirichlet, fetch, acc);
+}

@@ -1,0 +1,206 @@
+// SAP smoother (Sec. 2): multiplicative Schwarz over the red and black
+// domains.  One launch per colour; one workgroup per (domain, right-hand side).
+//
+// For every domain B of the colour:
+//   r_B   = b - D x on the sites of B      (full operator: the halo of x comes
+//                                           from the neighbouring domains of the
+//                                           other colour, which this launch
+//                                           does not modify)
+//   rhs_e = r_e - H_eo A_oo^-1 r_o          (H = hopping term kept inside B)
+//   MR on S = A_ee - H_eo A_oo^-1 H_oe from e_e = 0, a fixed number of steps
+//   e_o   = A_oo^-1 (r_o - H_oe e_e)
+//   x_B  += e
+// Recomputing r_B from x at the start of every domain solve is the same
+// multiplicative iteration as carrying a global residual, without storing one.
+//
+// Thread j of a workgroup owns the even site j and the odd site j of the
+// domain; the half-lattice vectors exchanged between the even and odd phases
+// live in LDS.  Domains hold at most 256 sites.
+#include "dslash.h"
+
+namespace {
+
+constexpr int kMaxBvh = 128;
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// sum of (a, b, c) over the workgroup; deterministic order
+template <typename R>
+__device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[3 * w] = a;
+    red[3 * w + 1] = b;
+    red[3 * w + 2] = c;
+  }
+  __syncthreads();
+  a = b = c = (R)0;
+  for (int i = 0; i < nw; ++i) {
+    a += red[3 * i];
+    b += red[3 * i + 1];
+    c += red[3 * i + 2];
+  }
+}
+
+template <typename R, typename S, typename Tv>
+__global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
+                                                     const S* __restrict__ cinv, int nrhs, int colour, int mr_iters,
+                                                     const Tv* __restrict__ bvec, Tv* __restrict__ xvec) {
+  __shared__ cx<R> sh_e[12][kMaxBvh];
+  __shared__ cx<R> sh_o[12][kMaxBvh];
+  __shared__ R red[3 * (kMaxBvh / 64 + 1)];
+
+  const int r = blockIdx.x % nrhs;
+  const int slot = colour * g.Vch + blockIdx.x / nrhs;
+  const int j = threadIdx.x;
+  const bool act = j < g.Bvh;
+  const long long V = g.V;
+  const Tv* b = bvec + (long long)r * 12 * V;
+  Tv* x = xvec + (long long)r * 12 * V;
+  const long long Ie = ((long long)slot << g.lBv) + j;
+  const long long Io = Ie + g.Bvh;
+
+  auto fetch_x = [&](long long J, bool, cx<R>* p) { load_spinor<R, Tv>(x, V, J, p); };
+  auto fetch_e = [&](long long J, bool, cx<R>* p) {
+    int jj = (int)(J & (g.Bvh - 1));
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = sh_e[c][jj];
+  };
+  auto fetch_o = [&](long long J, bool, cx<R>* p) {
+    int jj = (int)(J & (g.Bvh - 1));
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = sh_o[c][jj];
+  };
+
+  cx<R> re[12], ro[12], rho[12], e[12], t[12], h[12];
+  SiteLoc se, so;
+  if (act) {
+    se = decode_site(g, Ie);
+    so = decode_site(g, Io);
+    // r = b - D x on both sites of this thread
+    load_spinor<R, Tv>(x, V, Ie, t);
+    clover_mul<R, S, false>(clov, V, Ie, t, h);
+    hop_all<R, S>(g, links, se, Ie, false, fetch_x, h);
+    load_spinor<R, Tv>(b, V, Ie, re);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) re[c] = re[c] - h[c];
+    load_spinor<R, Tv>(x, V, Io, t);
+    clover_mul<R, S, false>(clov, V, Io, t, h);
+    hop_all<R, S>(g, links, so, Io, false, fetch_x, h);
+    load_spinor<R, Tv>(b, V, Io, ro);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ro[c] = ro[c] - h[c];
+    // A_oo^-1 r_o
+    clover_mul<R, S, false>(cinv, V, Io, ro, t);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sh_o[c][j] = t[c];
+  }
+  __syncthreads();
+  if (act) {
+    // rhs_e = r_e - H_eo A_oo^-1 r_o
+#pragma unroll
+    for (int c = 0; c < 12; ++c) h[c] = {(R)0, (R)0};
+    hop_all<R, S>(g, links, se, Ie, true, fetch_o, h);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      rho[c] = re[c] - h[c];
+      e[c] = {(R)0, (R)0};
+    }
+  }
+  for (int k = 0; k < mr_iters; ++k) {
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sh_e[c][j] = rho[c];
+    }
+    __syncthreads();
+    if (act) {
+      // odd: u = A_oo^-1 H_oe rho
+#pragma unroll
+      for (int c = 0; c < 12; ++c) h[c] = {(R)0, (R)0};
+      hop_all<R, S>(g, links, so, Io, true, fetch_e, h);
+      clover_mul<R, S, false>(cinv, V, Io, h, t);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sh_o[c][j] = t[c];
+    }
+    __syncthreads();
+    R pr_re = 0, pr_im = 0, pp = 0;
+    if (act) {
+      // even: p = A_ee rho - H_eo u   (kept in t)
+      clover_mul<R, S, false>(clov, V, Ie, rho, t);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) h[c] = {(R)0, (R)0};
+      hop_all<R, S>(g, links, se, Ie, true, fetch_o, h);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        t[c] = t[c] - h[c];
+        cx<R> q = cmul_conj(t[c], rho[c]);   // conj(p) rho
+        pr_re += q.re;
+        pr_im += q.im;
+        pp += t[c].re * t[c].re + t[c].im * t[c].im;
+      }
+    }
+    block_sum3(pr_re, pr_im, pp, red);
+    if (act) {
+      cx<R> alpha = {(R)0, (R)0};
+      if (pp > (R)0) alpha = {pr_re / pp, pr_im / pp};
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        cfma(e[c], alpha, rho[c]);
+        rho[c] = rho[c] - alpha * t[c];
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sh_e[c][j] = e[c];
+  }
+  __syncthreads();
+  if (act) {
+    // e_o = A_oo^-1 (r_o - H_oe e_e);  x += e
+#pragma unroll
+    for (int c = 0; c < 12; ++c) h[c] = {(R)0, (R)0};
+    hop_all<R, S>(g, links, so, Io, true, fetch_e, h);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ro[c] = ro[c] - h[c];
+    clover_mul<R, S, false>(cinv, V, Io, ro, t);
+    load_spinor<R, Tv>(x, V, Io, h);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) h[c] = h[c] + t[c];
+    store_spinor<R, Tv>(x, V, Io, h);
+    load_spinor<R, Tv>(x, V, Ie, h);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) h[c] = h[c] + e[c];
+    store_spinor<R, Tv>(x, V, Ie, h);
+  }
+}
+
+template <typename R, typename S, typename Tv>
+void run(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const void* b, void* x, hipStream_t st) {
+  int threads = ((g.Bvh + 63) / 64) * 64;
+  unsigned nb = (unsigned)g.Vch * nrhs;
+  for (int s = 0; s < sweeps; ++s)
+    for (int colour = 0; colour < 2; ++colour)
+      k_sap_colour<R, S, Tv><<<nb, threads, 0, st>>>(g, (const S*)ops.links, (const S*)ops.clover, (const S*)ops.cinv,
+                                                      nrhs, colour, mr, (const Tv*)b, (Tv*)x);
+}
+
+}  // namespace
+
+void launch_sap(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters, const void* b,
+                void* x, hipStream_t st) {
+  switch (dt) {
+    case DD_F64: run<double, double2, double2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
+    case DD_F32: run<float, float2, float2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
+    case DD_F16: run<float, __half2, float2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
+    case DD_BF16: run<float, bf16x2, float2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
+  }
+}
