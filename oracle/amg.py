@@ -73,20 +73,22 @@ def gram_schmidt(lat, tv, passes=2, rank_tol=1e-12):
     orthonormalised lambda_i(X, s) restricted to X.  For every (X, s) the
     vectors are taken in order i = 0..n-1; each is orthogonalised against the
     previous ones by modified Gram-Schmidt, repeated `passes` times, and
-    normalised (real positive norm)."""
+    normalised (real positive norm).  A vector whose norm falls to rank_tol
+    times its norm before the projections marks the set as rank deficient."""
     g = to_aggregates(lat, tv)                  # [n][Vc][2][K]
     g = np.moveaxis(g, 0, 2).copy()             # [Vc][2][n][K]
     n = g.shape[2]
     for i in range(n):
         v = g[:, :, i]
+        nrm0 = np.sqrt(np.sum(np.abs(v) ** 2, axis=-1))
         for _ in range(passes):
             for j in range(i):
                 q = g[:, :, j]
                 d = np.sum(np.conj(q) * v, axis=-1)
                 v -= d[..., None] * q
         nrm = np.sqrt(np.sum(np.abs(v) ** 2, axis=-1))
-        if np.any(nrm < rank_tol):
-            bad = np.argwhere(nrm < rank_tol)[0]
+        if np.any(nrm <= rank_tol * nrm0):
+            bad = np.argwhere(nrm <= rank_tol * nrm0)[0]
             raise ValueError(f"test vectors are rank deficient on aggregate {bad[0]} chirality {bad[1]}")
         v /= nrm[..., None]
     return g

@@ -1,19 +1,757 @@
-// C ABI, part 2: multigrid setup, transfer, coarse operator and solver.
+// C ABI, part 2: multigrid setup (Sec. 2 adaptive setup), transfer, coarse
+// operator, the even-odd coarse GMRES, the preconditioner M of Eq. (5) and the
+// flexible GMRES outer solver.  Host code here only sequences kernels and
+// reads per-RHS convergence flags; all arithmetic runs on the device.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
 #include "dd_internal.h"
 
-extern "C" {
-size_t dd_coarse_vec_bytes(const dd_mg*, dd_dtype, int) { return 0; }
-dd_status dd_pack_coarse(const dd_mg*, dd_dtype, int, const double*, void*, void*) { return DD_EINVAL; }
-dd_status dd_unpack_coarse(const dd_mg*, dd_dtype, int, const void*, double*, void*) { return DD_EINVAL; }
-dd_status dd_setup(dd_gauge*, const dd_mg_params*, dd_mg**) { return DD_EINVAL; }
-dd_status dd_setup_from_vectors(dd_gauge*, const dd_mg_params*, const double*, dd_mg**) { return DD_EINVAL; }
-dd_status dd_mg_destroy(dd_mg*) { return DD_EINVAL; }
-dd_status dd_restrict(dd_mg*, dd_dtype, int, const void*, void*, void*) { return DD_EINVAL; }
-dd_status dd_prolong(dd_mg*, dd_dtype, int, const void*, void*, void*) { return DD_EINVAL; }
-dd_status dd_coarse_apply(dd_mg*, dd_dtype, int, const void*, void*, void*) { return DD_EINVAL; }
-dd_status dd_coarse_solve(dd_mg*, dd_dtype, int, const void*, void*, int*, void*) { return DD_EINVAL; }
-dd_status dd_precond_apply(dd_mg*, int, const void*, void*, void*) { return DD_EINVAL; }
-dd_status dd_solve(dd_mg*, int, const double*, double*, double, dd_solve_info*, void*) { return DD_EINVAL; }
-dd_status dd_export_coarse(const dd_mg*, double*) { return DD_EINVAL; }
-dd_status dd_export_vectors(const dd_mg*, double*) { return DD_EINVAL; }
+void launch_coarse_perm(const GeomDev& g, dd_dtype vt, int nc, int nrhs, int to_packed, const void* src, void* dst,
+                        hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// device arena: one allocation, carved into aligned pieces
+// ---------------------------------------------------------------------------
+struct Arena {
+  dd_ctx* ctx = nullptr;
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool sizing = true;
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return sizing ? nullptr : reinterpret_cast<T*>(base + off);
+  }
+};
+
+// per-RHS Hessenberg state of one GMRES(m)
+struct Arnoldi {
+  int m = 0;
+  double2 *H, *sn, *gv, *h1, *h2, *nrm2, *y;
+  double *cs, *tolabs, *beta, *est, *hnext;
+  int *active, *kcyc, *finished;
+  void carve(Arena& a, int nrhs, int mm) {
+    m = mm;
+    H = a.take<double2>((size_t)nrhs * m * (m + 1));
+    sn = a.take<double2>((size_t)nrhs * m);
+    gv = a.take<double2>((size_t)nrhs * (m + 1));
+    h1 = a.take<double2>((size_t)nrhs * (m + 1));
+    h2 = a.take<double2>((size_t)nrhs * (m + 1));
+    nrm2 = a.take<double2>(nrhs);
+    y = a.take<double2>((size_t)nrhs * m);
+    hnext = a.take<double>(nrhs);
+    cs = a.take<double>((size_t)nrhs * m);
+    tolabs = a.take<double>(nrhs);
+    beta = a.take<double>(nrhs);
+    est = a.take<double>(nrhs);
+    active = a.take<int>(nrhs);
+    kcyc = a.take<int>(nrhs);
+    finished = a.take<int>(nrhs);
+  }
+};
+
+struct Workspace {
+  int nrhs = 0;
+  bool outer = false;
+  Arena arena;
+  // V-cycle (inner dtype)
+  void *vin = nullptr, *xs = nullptr;
+  // coarse vectors (inner dtype) and the coarse Krylov basis
+  void *cb, *cy, *cr, *cw, *ct1, *ct2, *cres, *CV;
+  Arnoldi ca;
+  // outer solver
+  double2 *b64, *x64, *w64, *zt64, *V64;
+  void* Z;
+  Arnoldi fa;
+  double* partial;
+  int* hflags = nullptr;   // pinned host mirror: active[nrhs], kcyc[nrhs]
+  double* hvals = nullptr; // pinned host mirror: est[nrhs], tolabs[nrhs], nrm[nrhs]
+};
+
+static dd_dtype inner_vt(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : DD_F32; }
+static dd_dtype op_dtype(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : mg->p.store_dtype; }
+static const void* P_inner(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? (const void*)mg->P64 : mg->Pst; }
+static dd_dtype P_inner_dt(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : mg->vstore; }
+
+static void carve_ws(Workspace& w, const dd_mg* mg, int nrhs, bool outer) {
+  Arena& a = w.arena;
+  const long long V = mg->g->geo.V;
+  const long long fine = 12LL * V * nrhs;
+  const long long coarse = (long long)mg->g->geo.Vc * mg->nc * nrhs;
+  const size_t vb = vector_pair_bytes(inner_vt(mg));
+  const int mc = mg->p.coarse_restart;
+  w.vin = a.take<char>(fine * vb);
+  w.xs = a.take<char>(fine * vb);
+  w.cb = a.take<char>(coarse * vb);
+  w.cy = a.take<char>(coarse * vb);
+  w.cr = a.take<char>(coarse * vb);
+  w.cw = a.take<char>(coarse * vb);
+  w.ct1 = a.take<char>(coarse * vb);
+  w.ct2 = a.take<char>(coarse * vb);
+  w.cres = a.take<char>(coarse * vb);
+  w.CV = a.take<char>((size_t)(mc + 1) * coarse * vb);
+  w.ca.carve(a, nrhs, mc);
+  int nblk = dots_blocks(12LL * V, nrhs);
+  int nblk_c = dots_blocks((long long)mg->g->geo.Vc * mg->nc, nrhs);
+  if (nblk_c > nblk) nblk = nblk_c;
+  w.partial = a.take<double>((size_t)nrhs * 16 * nblk * 2);
+  w.b64 = w.x64 = w.w64 = w.zt64 = w.V64 = nullptr;
+  w.Z = nullptr;
+  if (outer) {
+    const int m = mg->p.fgmres_restart;
+    w.b64 = a.take<double2>(fine);
+    w.x64 = a.take<double2>(fine);
+    w.w64 = a.take<double2>(fine);
+    w.zt64 = a.take<double2>(fine);
+    w.V64 = a.take<double2>((size_t)(m + 1) * fine);
+    w.Z = a.take<char>((size_t)m * fine * vb);
+    w.fa.carve(a, nrhs, m);
+  }
 }
+
+static void free_ws(dd_mg* mg) {
+  Workspace* w = mg->ws;
+  if (!w) return;
+  dd_free(mg->ctx, w->arena.base, w->arena.cap);
+  if (w->hflags) (void)hipHostFree(w->hflags);
+  if (w->hvals) (void)hipHostFree(w->hvals);
+  delete w;
+  mg->ws = nullptr;
+}
+
+static dd_status ensure_ws(dd_mg* mg, int nrhs, bool outer) {
+  Workspace* w = mg->ws;
+  if (w && w->nrhs >= nrhs && (w->outer || !outer)) return DD_OK;
+  if (w) {
+    if (w->nrhs > nrhs) nrhs = w->nrhs;
+    outer = outer || w->outer;
+    free_ws(mg);
+  }
+  w = new Workspace();
+  w->nrhs = nrhs;
+  w->outer = outer;
+  w->arena.ctx = mg->ctx;
+  w->arena.sizing = true;
+  carve_ws(*w, mg, nrhs, outer);
+  size_t bytes = w->arena.used + 256;
+  dd_status st = dd_alloc(mg->ctx, (void**)&w->arena.base, bytes);
+  if (st) {
+    delete w;
+    return st;
+  }
+  w->arena.cap = bytes;
+  w->arena.sizing = false;
+  // start from finite values everywhere (Krylov bases are read up to the longest cycle)
+  (void)hipMemset(w->arena.base, 0, bytes);
+  w->arena.used = 0;
+  carve_ws(*w, mg, nrhs, outer);
+  if (hipHostMalloc((void**)&w->hflags, sizeof(int) * 2 * nrhs) != hipSuccess ||
+      hipHostMalloc((void**)&w->hvals, sizeof(double) * 3 * nrhs) != hipSuccess) {
+    mg->ws = w;
+    free_ws(mg);
+    return dd_fail(mg->ctx, DD_ENOMEM, "pinned host buffers");
+  }
+  mg->ws = w;
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+static int count_active(Workspace* w, const int* dev_active, int nrhs, hipStream_t st) {
+  (void)hipMemcpyAsync(w->hflags, dev_active, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st);
+  (void)hipStreamSynchronize(st);
+  int c = 0;
+  for (int r = 0; r < nrhs; ++r) c += w->hflags[r] != 0;
+  return c;
+}
+
+// longest cycle over the RHS (kcyc copied to hflags[nrhs..2 nrhs))
+static int max_kcyc(Workspace* w, Arnoldi& a, int nrhs, hipStream_t st) {
+  (void)hipMemcpyAsync(w->hflags + nrhs, a.kcyc, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st);
+  (void)hipStreamSynchronize(st);
+  int k = 0;
+  for (int r = 0; r < nrhs; ++r) k = w->hflags[nrhs + r] > k ? w->hflags[nrhs + r] : k;
+  return k;
+}
+
+// squared norms of nrhs vectors (count entries at stride ld) into out[r].x
+static void norms2(Workspace* w, dd_dtype vt, int nrhs, long long count, long long ld, const void* x, double2* out,
+                   hipStream_t st) {
+  int nblk = dots_blocks(count, nrhs);
+  launch_dots(vt, vt, nrhs, count, ld, x, 1, 0, x, w->partial, nblk, out, 1, 0, st);
+}
+
+// one CGS2 orthogonalisation of w against basis V_0..V_j, then |w|^2 -> a.nrm2
+static void cgs2(Workspace* ws, Arnoldi& a, dd_dtype vt, int nrhs, long long count, long long ld, const void* V,
+                 long long vstride, int nv, void* w, hipStream_t st) {
+  int nblk = dots_blocks(count, nrhs);
+  launch_dots(vt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h1, a.m + 1, 0, st);
+  launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, 0, -1.0, w, st);
+  launch_dots(vt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h2, a.m + 1, 0, st);
+  launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, 0, -1.0, w, st);
+  launch_dots(vt, vt, nrhs, count, ld, w, 1, 0, w, ws->partial, nblk, a.nrm2, 1, 0, st);
+}
+
+// ---------------------------------------------------------------------------
+// coarse even-odd solve
+// ---------------------------------------------------------------------------
+struct CoarseOps {
+  const GeomDev* g;
+  dd_dtype vt;
+  int nc;
+  const void *Dc, *Dinv;
+};
+
+static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
+  CoarseOps c;
+  c.g = &mg->g->geo;
+  c.vt = vt;
+  c.nc = mg->nc;
+  c.Dc = vt == DD_F64 ? (const void*)mg->Dc64 : (const void*)mg->Dc32;
+  c.Dinv = vt == DD_F64 ? (const void*)mg->Dinv64 : (const void*)mg->Dinv32;
+  return c;
+}
+
+// out_e = S v_e = D_ee v_e - D_eo D_oo^-1 D_oe v_e   (t1, t2 scratch, odd parts used)
+static void schur_apply(const CoarseOps& c, int nrhs, const void* v, void* out, void* t1, void* t2, hipStream_t st) {
+  const GeomDev& g = *c.g;
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, 1.0, v, 0.0, nullptr, t1, st);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, t1, 0.0, nullptr, 0.0, nullptr, t2, st);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 1.0, v, -1.0, t2, 0.0, nullptr, out, st);
+}
+
+// y ~= D_c^-1 b by GMRES on the even-site Schur complement, then the odd sites.
+static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, void* y, int* iters_out,
+                              hipStream_t st) {
+  Workspace* w = mg->ws;
+  CoarseOps c = coarse_ops(mg, vt);
+  const GeomDev& g = *c.g;
+  const int nc = c.nc;
+  const long long ld = (long long)g.Vc * nc, ce = (long long)g.Vch * nc;
+  const size_t vb = vector_pair_bytes(vt);
+  Arnoldi& a = w->ca;
+  const int m = a.m;
+  const bool fixed = mg->p.coarse_fixed_iters > 0;
+  const int cap = fixed ? mg->p.coarse_fixed_iters : mg->p.coarse_max_iters;
+  const double tol = fixed ? 0.0 : mg->p.coarse_tol;
+  // rhs' = b_e - D_eo D_oo^-1 b_o
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st);
+  DD_HIP(mg->ctx, hipMemsetAsync(y, 0, (size_t)nrhs * ld * vb, st));
+  // tolerance: tol * |rhs'|
+  norms2(w, vt, nrhs, ce, ld, w->cr, a.nrm2, st);
+  {
+    std::vector<double2> n2(nrhs);
+    DD_HIP(mg->ctx, hipMemcpyAsync(n2.data(), a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+    std::vector<double> tl(nrhs);
+    std::vector<int> fin(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) tl[r] = tol * std::sqrt(n2[r].x);
+    DD_HIP(mg->ctx, hipMemcpyAsync(a.tolabs, tl.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  }
+  const long long vs = (long long)nrhs * ld;   // basis stride
+  char* CV = (char*)w->CV;
+  int iters = 0;
+  while (iters < cap) {
+    // r = rhs' - S y  (first cycle: y = 0)
+    if (iters == 0) {
+      DD_HIP(mg->ctx, hipMemcpyAsync(w->cres, w->cr, (size_t)nrhs * ld * vb, hipMemcpyDeviceToDevice, st));
+    } else {
+      schur_apply(c, nrhs, y, w->cw, w->ct1, w->ct2, st);
+      launch_sub(vt, (long long)nrhs * ld, w->cr, w->cw, w->cres, st);
+    }
+    norms2(w, vt, nrhs, ce, ld, w->cres, a.nrm2, st);
+    launch_cycle_init(nrhs, m, a.nrm2, a.tolabs, a.finished, a.gv, a.beta, a.active, a.kcyc, st);
+    if (count_active(w, a.active, nrhs, st) == 0) break;
+    launch_normalize(vt, nrhs, ce, ld, w->cres, nullptr, a.beta, a.active, CV, st);
+    const int mm = (cap - iters < m) ? cap - iters : m;
+    for (int j = 0; j < mm; ++j) {
+      void* Vj = CV + (size_t)j * vs * vb;
+      schur_apply(c, nrhs, Vj, w->cw, w->ct1, w->ct2, st);
+      cgs2(w, a, vt, nrhs, ce, ld, CV, vs, j + 1, w->cw, st);
+      launch_arnoldi(nrhs, m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est,
+                     a.hnext, st);
+      ++iters;
+      if (j + 1 == mm) {
+        // the cycle ends here: close every RHS still active
+        break;
+      }
+      launch_normalize(vt, nrhs, ce, ld, w->cw, nullptr, a.hnext, a.active, CV + (size_t)(j + 1) * vs * vb, st);
+      if (count_active(w, a.active, nrhs, st) == 0) break;
+    }
+    launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
+    launch_multi_axpy(vt, vt, nrhs, ce, ld, CV, max_kcyc(w, a, nrhs, st), vs, a.y, m, 0, 1.0, y, st);
+    // RHS whose estimate met the tolerance are finished
+    DD_HIP(mg->ctx, hipMemcpyAsync(w->hvals, a.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(mg->ctx, hipMemcpyAsync(w->hvals + nrhs, a.tolabs, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(mg->ctx, hipMemcpyAsync(w->hflags, a.finished, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+    int nfin = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (w->hvals[r] <= w->hvals[nrhs + r]) w->hflags[r] = 1;
+      nfin += w->hflags[r];
+    }
+    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, w->hflags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    if (nfin == nrhs) break;
+  }
+  // odd sites: y_o = D_oo^-1 (b_o - D_oe y_e)
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st);
+  DD_HIP(mg->ctx, hipGetLastError());
+  if (iters_out) *iters_out = iters;
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner M (Eq. 5): x_c = P D_c^-1 R v, then SAP on D x = v from x_c
+// ---------------------------------------------------------------------------
+static dd_status vcycle(dd_mg* mg, int nrhs, const void* v, void* out, int* citers, hipStream_t st) {
+  Workspace* w = mg->ws;
+  dd_dtype vt = inner_vt(mg);
+  const GeomDev& g = mg->g->geo;
+  launch_restrict(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, v, w->cb, st);
+  dd_status s = coarse_solve(mg, vt, nrhs, w->cb, w->cy, citers, st);
+  if (s) return s;
+  launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, st);
+  dd_dtype od = op_dtype(mg);
+  launch_sap(g, od, mg->g->ops[od], nrhs, mg->p.sap_sweeps, mg->p.sap_mr_iters, v, out, st);
+  DD_HIP(mg->ctx, hipGetLastError());
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// build: Gram-Schmidt, stored P, D_c = P^dag D P, odd-site inverses
+// ---------------------------------------------------------------------------
+static dd_status build(dd_mg* mg, hipStream_t st) {
+  dd_gauge* g = mg->g;
+  const GeomDev& G = g->geo;
+  const long long nfine = 12LL * G.V * mg->n;
+  int* dflag = nullptr;
+  dd_status s;
+  if ((s = dd_alloc(mg->ctx, (void**)&dflag, sizeof(int)))) return s;
+  int neg = -1;
+  // P64 <- working vectors
+  launch_vec_convert(inner_vt(mg), DD_F64, mg->tv, mg->P64, nfine, st);
+  DD_HIP(mg->ctx, hipMemcpyAsync(dflag, &neg, sizeof(int), hipMemcpyHostToDevice, st));
+  launch_gram_schmidt(G, mg->n, mg->P64, dflag, st);
+  int bad = -1;
+  DD_HIP(mg->ctx, hipMemcpyAsync(&bad, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  if (bad >= 0) {
+    dd_free(mg->ctx, dflag, sizeof(int));
+    return dd_fail(mg->ctx, DD_EINVAL,
+                   "test vectors are rank deficient on aggregate slot " + std::to_string(bad / 2) + " chirality " +
+                       std::to_string(bad % 2));
+  }
+  // stored copy of P: FP32 from FP64, half precision from the FP32 copy
+  if (mg->vstore != DD_F64) {
+    if (mg->vstore == DD_F32) {
+      launch_convert_pairs(DD_F32, mg->P64, nullptr, mg->Pst, nfine, st);
+    } else {
+      launch_convert_pairs(DD_F32, mg->P64, nullptr, mg->Pst32tmp, nfine, st);
+      launch_convert_pairs(mg->vstore, nullptr, (const float2*)mg->Pst32tmp, mg->Pst, nfine, st);
+    }
+  }
+  // Galerkin operator from the stored P and the FP64 operator
+  const long long vbytes = 12LL * G.V * (long long)sizeof(double2);
+  int chunk = (int)((4LL << 30) / vbytes);
+  if (chunk < 1) chunk = 1;
+  if (chunk > mg->nc) chunk = mg->nc;
+  double2* W = nullptr;
+  if ((s = dd_alloc(mg->ctx, (void**)&W, (size_t)chunk * vbytes))) {
+    dd_free(mg->ctx, dflag, sizeof(int));
+    return s;
+  }
+  const void* Pb = mg->vstore == DD_F64 ? (const void*)mg->P64 : mg->Pst;
+  launch_coarse_build(G, g->ops[DD_F64], mg->vstore, mg->n, Pb, mg->Dc64, W, chunk, st);
+  DD_HIP(mg->ctx, hipMemcpyAsync(dflag, &neg, sizeof(int), hipMemcpyHostToDevice, st));
+  launch_coarse_invert(G, mg->nc, mg->Dc64, mg->Dinv64, dflag, st);
+  const long long ndc = (long long)G.Vc * 9 * mg->nc * mg->nc, ndi = (long long)G.Vch * mg->nc * mg->nc;
+  launch_convert_pairs(DD_F32, mg->Dc64, nullptr, mg->Dc32, ndc, st);
+  launch_convert_pairs(DD_F32, mg->Dinv64, nullptr, mg->Dinv32, ndi, st);
+  DD_HIP(mg->ctx, hipMemcpyAsync(&bad, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  dd_free(mg->ctx, W, (size_t)chunk * vbytes);
+  dd_free(mg->ctx, dflag, sizeof(int));
+  if (bad >= 0) return dd_fail(mg->ctx, DD_EINVAL, "singular coarse self block on coarse slot " + std::to_string(bad));
+  return DD_OK;
+}
+
+// lambda_i <- lambda_i / |lambda_i|
+static void normalize_vectors(dd_mg* mg, void* tv, hipStream_t st) {
+  Workspace* w = mg->ws;
+  const long long cnt = 12LL * mg->g->geo.V;
+  norms2(w, inner_vt(mg), mg->n, cnt, cnt, tv, w->ca.nrm2, st);
+  launch_normalize(inner_vt(mg), mg->n, cnt, cnt, tv, w->ca.nrm2, nullptr, nullptr, tv, st);
+}
+
+static size_t mg_bytes_P64(const dd_mg* mg) { return 16ULL * 12 * mg->g->geo.V * mg->n; }
+static size_t mg_bytes_tv(const dd_mg* mg) { return vector_pair_bytes(inner_vt(mg)) * 12ULL * mg->g->geo.V * mg->n; }
+static size_t mg_bytes_Pst(const dd_mg* mg) {
+  return mg->vstore == DD_F64 ? 0 : storage_pair_bytes(mg->vstore) * 12ULL * mg->g->geo.V * mg->n;
+}
+static size_t mg_bytes_P32tmp(const dd_mg* mg) {
+  return (mg->vstore == DD_F16 || mg->vstore == DD_BF16) ? 8ULL * 12 * mg->g->geo.V * mg->n : 0;
+}
+static size_t mg_bytes_Dc(const dd_mg* mg, size_t pb) { return pb * mg->g->geo.Vc * 9ULL * mg->nc * mg->nc; }
+static size_t mg_bytes_Dinv(const dd_mg* mg, size_t pb) { return pb * mg->g->geo.Vch * 1ULL * mg->nc * mg->nc; }
+
+static void mg_free(dd_mg* mg) {
+  free_ws(mg);
+  dd_free(mg->ctx, mg->P64, mg_bytes_P64(mg));
+  dd_free(mg->ctx, mg->tv, mg_bytes_tv(mg));
+  dd_free(mg->ctx, mg->Pst, mg_bytes_Pst(mg));
+  dd_free(mg->ctx, mg->Pst32tmp, mg_bytes_P32tmp(mg));
+  dd_free(mg->ctx, mg->Dc64, mg_bytes_Dc(mg, 16));
+  dd_free(mg->ctx, mg->Dc32, mg_bytes_Dc(mg, 8));
+  dd_free(mg->ctx, mg->Dinv64, mg_bytes_Dinv(mg, 16));
+  dd_free(mg->ctx, mg->Dinv32, mg_bytes_Dinv(mg, 8));
+  if (mg->g) mg->g->refcount--;
+  delete mg;
+}
+
+static dd_status validate_params(dd_gauge* g, const dd_mg_params* p) {
+  for (int m = 0; m < 4; ++m)
+    if (p->agg_block[m] != g->prob.block[m] || p->sap_block[m] != g->prob.block[m])
+      return dd_fail(g->ctx, DD_ESHAPE, "aggregate and SAP blocks must equal the gauge field's block tiling");
+  if (p->n_vec % 2) return dd_fail(g->ctx, DD_ESHAPE, "n_vec must be even (Sec. 3)");
+  if (!supported_nvec(p->n_vec)) return dd_fail(g->ctx, DD_ESHAPE, "n_vec must be one of 6, 8, 12, 16, 20, 24");
+  if (p->sap_sweeps < 0 || p->sap_mr_iters < 0 || p->setup_iters < 0 || p->init_sap_apps < 0)
+    return dd_fail(g->ctx, DD_EINVAL, "negative iteration counts");
+  if (p->coarse_restart < 1 || p->coarse_restart > 64 || p->fgmres_restart < 1 || p->fgmres_restart > 64)
+    return dd_fail(g->ctx, DD_EINVAL, "restart lengths must be in [1, 64]");
+  if (p->coarse_max_iters < 1 || p->max_outer_iters < 1) return dd_fail(g->ctx, DD_EINVAL, "iteration caps must be >= 1");
+  if (p->inner_dtype != DD_F64 && p->inner_dtype != DD_F32)
+    return dd_fail(g->ctx, DD_EINVAL, "inner_dtype must be DD_F64 or DD_F32");
+  if ((int)p->store_dtype < 0 || (int)p->store_dtype > 3) return dd_fail(g->ctx, DD_EINVAL, "unknown store_dtype");
+  if (p->inner_dtype == DD_F32 && p->store_dtype == DD_F64)
+    return dd_fail(g->ctx, DD_EINVAL, "FP32 inner solvers take FP32, FP16 or BF16 stored operands");
+  if (p->inner_dtype == DD_F64 && p->store_dtype != DD_F64)
+    return dd_fail(g->ctx, DD_EINVAL, "the all-FP64 preconditioner needs store_dtype DD_F64");
+  return DD_OK;
+}
+
+static dd_status setup_common(dd_gauge* g, const dd_mg_params* p, const double* tv_host, dd_mg** out) {
+  if (!g || !p || !out) return DD_EINVAL;
+  *out = nullptr;
+  dd_status s = validate_params(g, p);
+  if (s) return s;
+  hipStream_t st = 0;
+  dd_mg* mg = new dd_mg();
+  mg->ctx = g->ctx;
+  mg->g = g;
+  g->refcount++;
+  mg->p = *p;
+  mg->n = p->n_vec;
+  mg->nc = 2 * p->n_vec;
+  mg->vstore = p->inner_dtype == DD_F64 ? DD_F64 : p->store_dtype;
+  auto fail = [&](dd_status e) {
+    mg_free(mg);
+    return e;
+  };
+  dd_dtype od = op_dtype(mg);
+  if ((s = ensure_opset(g, od))) return fail(s);
+  if ((s = dd_alloc(mg->ctx, (void**)&mg->P64, mg_bytes_P64(mg))) ||
+      (s = dd_alloc(mg->ctx, (void**)&mg->tv, mg_bytes_tv(mg))) ||
+      (s = dd_alloc(mg->ctx, (void**)&mg->Pst, mg_bytes_Pst(mg))) ||
+      (s = dd_alloc(mg->ctx, (void**)&mg->Pst32tmp, mg_bytes_P32tmp(mg))) ||
+      (s = dd_alloc(mg->ctx, (void**)&mg->Dc64, mg_bytes_Dc(mg, 16))) ||
+      (s = dd_alloc(mg->ctx, (void**)&mg->Dc32, mg_bytes_Dc(mg, 8))) ||
+      (s = dd_alloc(mg->ctx, (void**)&mg->Dinv64, mg_bytes_Dinv(mg, 16))) ||
+      (s = dd_alloc(mg->ctx, (void**)&mg->Dinv32, mg_bytes_Dinv(mg, 8))))
+    return fail(s);
+  if ((s = ensure_ws(mg, mg->n, false))) return fail(s);
+  const GeomDev& G = g->geo;
+  const long long nfine = 12LL * G.V * mg->n;
+  // starting vectors, canonical FP64 -> packed working dtype (P64 is the staging buffer)
+  double2* canon = nullptr;
+  if ((s = dd_alloc(mg->ctx, (void**)&canon, sizeof(double2) * nfine))) return fail(s);
+  if (tv_host) {
+    hipError_t e = hipMemcpy(canon, tv_host, sizeof(double2) * nfine, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      dd_free(mg->ctx, canon, sizeof(double2) * nfine);
+      return fail(dd_hip_check(mg->ctx, e, "test vector upload"));
+    }
+  } else {
+    launch_gauss(p->seed, nfine, canon, st);
+  }
+  launch_pack_fine(G, inner_vt(mg), mg->n, canon, mg->tv, st);
+  hipError_t e = hipStreamSynchronize(st);
+  dd_free(mg->ctx, canon, sizeof(double2) * nfine);
+  if (e != hipSuccess) return fail(dd_hip_check(mg->ctx, e, "starting vectors"));
+  Workspace* w = mg->ws;
+  const size_t fb = vector_pair_bytes(inner_vt(mg)) * (size_t)nfine;
+  // initial approximate solves: lambda_i <- SAP(b = lambda_i, x0 = 0)
+  for (int k = 0; k < p->init_sap_apps; ++k) {
+    DD_HIP(mg->ctx, hipMemcpyAsync(w->vin, mg->tv, fb, hipMemcpyDeviceToDevice, st));
+    DD_HIP(mg->ctx, hipMemsetAsync(mg->tv, 0, fb, st));
+    launch_sap(G, od, g->ops[od], mg->n, p->sap_sweeps, p->sap_mr_iters, w->vin, mg->tv, st);
+    normalize_vectors(mg, mg->tv, st);
+  }
+  if ((s = build(mg, st))) return fail(s);
+  // adaptive iterations: lambda_i <- M lambda_i, normalise, rebuild
+  for (int k = 0; k < p->setup_iters; ++k) {
+    DD_HIP(mg->ctx, hipMemcpyAsync(w->xs, mg->tv, fb, hipMemcpyDeviceToDevice, st));
+    if ((s = vcycle(mg, mg->n, w->xs, mg->tv, nullptr, st))) return fail(s);
+    normalize_vectors(mg, mg->tv, st);
+    if ((s = build(mg, st))) return fail(s);
+  }
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(dd_hip_check(mg->ctx, e, "setup"));
+  free_ws(mg);   // the solve sizes its own workspace for its number of right-hand sides
+  *out = mg;
+  return DD_OK;
+}
+
+static dd_status check_mg_vec(dd_mg* mg, dd_dtype dt, int nrhs, const void* a, const void* b) {
+  if (!mg) return DD_EINVAL;
+  if (dt != DD_F64 && dt != DD_F32) return dd_fail(mg->ctx, DD_EINVAL, "coarse-level dtype must be DD_F64 or DD_F32");
+  if (!a || !b || nrhs < 1) return dd_fail(mg->ctx, DD_EINVAL, "bad vector arguments");
+  if (a == b) return dd_fail(mg->ctx, DD_EINVAL, "input and output must not alias");
+  return DD_OK;
+}
+
+extern "C" {
+
+dd_status dd_setup(dd_gauge* g, const dd_mg_params* p, dd_mg** out) { return setup_common(g, p, nullptr, out); }
+
+dd_status dd_setup_from_vectors(dd_gauge* g, const dd_mg_params* p, const double* tv_host, dd_mg** out) {
+  if (!tv_host) return g ? dd_fail(g->ctx, DD_EINVAL, "null test vectors") : DD_EINVAL;
+  return setup_common(g, p, tv_host, out);
+}
+
+dd_status dd_mg_destroy(dd_mg* mg) {
+  if (!mg) return DD_EINVAL;
+  (void)hipDeviceSynchronize();
+  mg_free(mg);
+  return DD_OK;
+}
+
+size_t dd_coarse_vec_bytes(const dd_mg* mg, dd_dtype dt, int nrhs) {
+  if (!mg || nrhs < 1) return 0;
+  return vector_pair_bytes(dt) * (size_t)mg->g->geo.Vc * mg->nc * nrhs;
+}
+
+dd_status dd_pack_coarse(const dd_mg* mg, dd_dtype dt, int nrhs, const double* canon, void* packed, void* stream) {
+  dd_status s = check_mg_vec((dd_mg*)mg, dt, nrhs, canon, packed);
+  if (s) return s;
+  launch_coarse_perm(mg->g->geo, dt, mg->nc, nrhs, 1, canon, packed, (hipStream_t)stream);
+  DD_HIP(mg->ctx, hipGetLastError());
+  return DD_OK;
+}
+
+dd_status dd_unpack_coarse(const dd_mg* mg, dd_dtype dt, int nrhs, const void* packed, double* canon, void* stream) {
+  dd_status s = check_mg_vec((dd_mg*)mg, dt, nrhs, packed, canon);
+  if (s) return s;
+  launch_coarse_perm(mg->g->geo, dt, mg->nc, nrhs, 0, packed, canon, (hipStream_t)stream);
+  DD_HIP(mg->ctx, hipGetLastError());
+  return DD_OK;
+}
+
+dd_status dd_restrict(dd_mg* mg, dd_dtype dt, int nrhs, const void* fine, void* coarse, void* stream) {
+  dd_status s = check_mg_vec(mg, dt, nrhs, fine, coarse);
+  if (s) return s;
+  const void* P = dt == DD_F64 ? (const void*)mg->P64 : (mg->vstore == DD_F64 ? (const void*)mg->P64 : mg->Pst);
+  dd_dtype pdt = dt == DD_F64 ? DD_F64 : mg->vstore;
+  launch_restrict(mg->g->geo, dt, pdt, mg->n, P, nrhs, fine, coarse, (hipStream_t)stream);
+  DD_HIP(mg->ctx, hipGetLastError());
+  return DD_OK;
+}
+
+dd_status dd_prolong(dd_mg* mg, dd_dtype dt, int nrhs, const void* coarse, void* fine, void* stream) {
+  dd_status s = check_mg_vec(mg, dt, nrhs, coarse, fine);
+  if (s) return s;
+  const void* P = dt == DD_F64 ? (const void*)mg->P64 : (mg->vstore == DD_F64 ? (const void*)mg->P64 : mg->Pst);
+  dd_dtype pdt = dt == DD_F64 ? DD_F64 : mg->vstore;
+  launch_prolong(mg->g->geo, dt, pdt, mg->n, P, nrhs, coarse, fine, (hipStream_t)stream);
+  DD_HIP(mg->ctx, hipGetLastError());
+  return DD_OK;
+}
+
+dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out, void* stream) {
+  dd_status s = check_mg_vec(mg, dt, nrhs, in, out);
+  if (s) return s;
+  CoarseOps c = coarse_ops(mg, dt);
+  launch_coarse_mv(mg->g->geo, dt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, mg->g->geo.Vc, 1.0, in, 1.0, in, 0.0, nullptr,
+                   out, (hipStream_t)stream);
+  DD_HIP(mg->ctx, hipGetLastError());
+  return DD_OK;
+}
+
+dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out, int* iters, void* stream) {
+  dd_status s = check_mg_vec(mg, dt, nrhs, in, out);
+  if (s) return s;
+  if ((s = ensure_ws(mg, nrhs, false))) return s;
+  return coarse_solve(mg, dt, nrhs, in, out, iters, (hipStream_t)stream);
+}
+
+dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void* stream) {
+  dd_status s = check_mg_vec(mg, inner_vt(mg), nrhs, in, out);
+  if (s) return s;
+  if ((s = ensure_ws(mg, nrhs, false))) return s;
+  return vcycle(mg, nrhs, in, out, nullptr, (hipStream_t)stream);
+}
+
+dd_status dd_export_coarse(const dd_mg* mg, double* dc_host) {
+  if (!mg || !dc_host) return DD_EINVAL;
+  const GeomDev& G = mg->g->geo;
+  const int nc = mg->nc;
+  std::vector<double2> buf((size_t)G.Vc * 9 * nc * nc);
+  DD_HIP(mg->ctx, hipMemcpy(buf.data(), mg->Dc64, buf.size() * sizeof(double2), hipMemcpyDeviceToHost));
+  int NB[4];
+  for (int m = 0; m < 4; ++m) NB[m] = G.L[m] / G.b[m];
+  for (int slot = 0; slot < G.Vc; ++slot) {
+    int bc = mg->g->h_blk_coord[slot];
+    int lex = (bc & 255) + NB[0] * (((bc >> 8) & 255) + NB[1] * (((bc >> 16) & 255) + NB[2] * ((bc >> 24) & 255)));
+    for (int d = 0; d < 9; ++d)
+      for (int col = 0; col < nc; ++col)
+        for (int row = 0; row < nc; ++row) {
+          double2 v = buf[(((size_t)slot * 9 + d) * nc + col) * nc + row];
+          double* o = dc_host + ((((size_t)lex * 9 + d) * nc + row) * nc + col) * 2;
+          o[0] = v.x;
+          o[1] = v.y;
+        }
+  }
+  return DD_OK;
+}
+
+dd_status dd_export_vectors(const dd_mg* mg, double* tv_host) {
+  if (!mg || !tv_host) return DD_EINVAL;
+  const GeomDev& G = mg->g->geo;
+  size_t bytes = sizeof(double2) * 12ULL * G.V * mg->n;
+  double2* tmp = nullptr;
+  dd_status s = dd_alloc(mg->ctx, (void**)&tmp, bytes);
+  if (s) return s;
+  launch_unpack_fine(G, DD_F64, mg->n, mg->P64, tmp, 0);
+  hipError_t e = hipMemcpy(tv_host, tmp, bytes, hipMemcpyDeviceToHost);
+  dd_free(mg->ctx, tmp, bytes);
+  if (e != hipSuccess) return dd_hip_check(mg->ctx, e, "export vectors");
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// outer flexible GMRES (FP64), right preconditioned by M
+// ---------------------------------------------------------------------------
+dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, double tol, dd_solve_info* info,
+                   void* stream) {
+  if (!mg) return DD_EINVAL;
+  if (!b_canon || !x_canon || nrhs < 1 || !(tol > 0.0)) return dd_fail(mg->ctx, DD_EINVAL, "bad solve arguments");
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = (hipStream_t)stream;
+  dd_status s = ensure_ws(mg, nrhs, true);
+  if (s) return s;
+  Workspace* w = mg->ws;
+  dd_gauge* g = mg->g;
+  const GeomDev& G = g->geo;
+  const long long cnt = 12LL * G.V, fine = cnt * nrhs;
+  const dd_dtype vt = inner_vt(mg);
+  const size_t vb = vector_pair_bytes(vt);
+  Arnoldi& a = w->fa;
+  const int m = a.m;
+  const long long vs64 = fine, vsz = fine;   // basis strides (entries)
+  launch_pack_fine(G, DD_F64, nrhs, (const double2*)b_canon, w->b64, st);
+  DD_HIP(mg->ctx, hipMemsetAsync(w->x64, 0, sizeof(double2) * fine, st));
+  // |b|, tolerance, non-finite check
+  norms2(w, DD_F64, nrhs, cnt, cnt, w->b64, a.nrm2, st);
+  std::vector<double2> n2(nrhs);
+  DD_HIP(mg->ctx, hipMemcpyAsync(n2.data(), a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
+  DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  std::vector<double> bnorm(nrhs), tl(nrhs), relres(nrhs, 1.0);
+  std::vector<int> fin(nrhs, 0), iters(nrhs, 0), restarts(nrhs, 0);
+  for (int r = 0; r < nrhs; ++r) {
+    bnorm[r] = std::sqrt(n2[r].x);
+    if (!std::isfinite(bnorm[r])) return dd_fail(mg->ctx, DD_ENAN, "non-finite right-hand side " + std::to_string(r));
+    tl[r] = tol * bnorm[r];
+    if (bnorm[r] == 0.0) {
+      fin[r] = 1;
+      relres[r] = 0.0;
+    }
+  }
+  DD_HIP(mg->ctx, hipMemcpyAsync(a.tolabs, tl.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+  int total_coarse = 0, outer = 0;
+  bool first = true;
+  while (true) {
+    // true residual r = b - D x (FP64 operator); the first cycle starts from x = 0
+    if (first) {
+      DD_HIP(mg->ctx, hipMemcpyAsync(w->w64, w->b64, sizeof(double2) * fine, hipMemcpyDeviceToDevice, st));
+    } else {
+      launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->x64, w->zt64, st);
+      launch_sub(DD_F64, fine, w->b64, w->zt64, w->w64, st);
+    }
+    first = false;
+    norms2(w, DD_F64, nrhs, cnt, cnt, w->w64, a.nrm2, st);
+    DD_HIP(mg->ctx, hipMemcpyAsync(n2.data(), a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+    int nfin = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (bnorm[r] > 0.0) relres[r] = std::sqrt(n2[r].x) / bnorm[r];
+      if (!std::isfinite(relres[r])) return dd_fail(mg->ctx, DD_ENAN, "breakdown: non-finite residual");
+      if (relres[r] <= tol) fin[r] = 1;
+      nfin += fin[r];
+    }
+    if (nfin == nrhs || outer >= mg->p.max_outer_iters) break;
+    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    launch_cycle_init(nrhs, m, a.nrm2, a.tolabs, a.finished, a.gv, a.beta, a.active, a.kcyc, st);
+    launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.beta, a.active, w->V64, st);
+    int mm = mg->p.max_outer_iters - outer < m ? mg->p.max_outer_iters - outer : m;
+    for (int j = 0; j < mm; ++j) {
+      double2* Vj = w->V64 + (size_t)j * vs64;
+      char* Zj = (char*)w->Z + (size_t)j * vsz * vb;
+      // z_j = M v_j in the inner precision
+      int ci = 0;
+      if (vt == DD_F64) {
+        if ((s = vcycle(mg, nrhs, Vj, Zj, &ci, st))) return s;
+        launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, Zj, w->w64, st);
+      } else {
+        launch_vec_convert(DD_F64, DD_F32, Vj, w->vin, fine, st);
+        if ((s = vcycle(mg, nrhs, w->vin, Zj, &ci, st))) return s;
+        launch_vec_convert(DD_F32, DD_F64, Zj, w->zt64, fine, st);
+        launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->zt64, w->w64, st);
+      }
+      total_coarse += ci;
+      cgs2(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, st);
+      launch_arnoldi(nrhs, m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est, a.hnext,
+                     st);
+      ++outer;
+      if (j + 1 == mm) break;
+      launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.hnext, a.active, w->V64 + (size_t)(j + 1) * vs64, st);
+      if (count_active(w, a.active, nrhs, st) == 0) break;
+    }
+    launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
+    int kmax = max_kcyc(w, a, nrhs, st);   // also leaves kcyc in hflags[nrhs..]
+    launch_multi_axpy(vt, DD_F64, nrhs, cnt, cnt, w->Z, kmax, vsz, a.y, m, 0, 1.0, w->x64, st);
+    for (int r = 0; r < nrhs; ++r)
+      if (!fin[r]) {
+        iters[r] += w->hflags[nrhs + r];
+        restarts[r] += 1;
+      }
+  }
+  launch_unpack_fine(G, DD_F64, nrhs, w->x64, (double2*)x_canon, st);
+  DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  double tsolve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool all = true;
+  for (int r = 0; r < nrhs; ++r) {
+    all = all && fin[r];
+    if (info) {
+      info[r].outer_iters = iters[r];
+      info[r].restarts = restarts[r];
+      info[r].coarse_iters_total = total_coarse;
+      info[r].converged = fin[r];
+      info[r].true_relres = relres[r];
+      info[r].t_setup_s = 0.0;
+      info[r].t_solve_s = tsolve;
+      info[r].bytes_model = 0;
+      info[r].flops_model = 0;
+    }
+  }
+  if (!all) return dd_fail(mg->ctx, DD_ENOCONV, "max_outer_iters reached before every right-hand side converged");
+  return DD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,338 @@
+// Vector kernels for the Krylov solvers: multi-dot products with a
+// deterministic two-stage reduction (per-workgroup partial sums, then a fixed
+// order sum), multi-axpy, masked scaling, and the small per-RHS Hessenberg
+// kernels (Givens rotations, least-squares back substitution).  All inner
+// products accumulate in FP64.
+//
+// A vector set holds nrhs vectors of `count` complex entries at stride `rs`;
+// a basis of such sets is spaced `vstride` pairs apart.
+#include "dd_internal.h"
+
+namespace {
+
+constexpr int kMaxNv = 16;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename Tv, typename Tw>
+__global__ void __launch_bounds__(256) k_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V, int nv,
+                                              long long vstride, const Tw* __restrict__ w, double* __restrict__ partial,
+                                              int nblk) {
+  __shared__ double red[4][2 * kMaxNv];
+  const int r = blockIdx.y, blk = blockIdx.x;
+  long long chunk = (count + nblk - 1) / nblk;
+  long long e0 = (long long)blk * chunk, e1 = e0 + chunk < count ? e0 + chunk : count;
+  cx<double> acc[kMaxNv];
+#pragma unroll
+  for (int i = 0; i < kMaxNv; ++i) acc[i] = {0.0, 0.0};
+  const Tw* wr = w + (long long)r * rs;
+  const Tv* vr = V + (long long)r * rs;
+  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    cx<double> x = ld<double, Tw>(wr + e);
+#pragma unroll
+    for (int i = 0; i < kMaxNv; ++i)
+      if (i < nv) cfma_conj(acc[i], ld<double, Tv>(vr + (long long)i * vstride + e), x);
+  }
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < kMaxNv; ++i) {
+    if (i < nv) {
+      double a = wave_sum(acc[i].re), b = wave_sum(acc[i].im);
+      if (lane == 0) {
+        red[wv][2 * i] = a;
+        red[wv][2 * i + 1] = b;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * nv) {
+    double s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    int i = threadIdx.x >> 1, c = threadIdx.x & 1;
+    partial[(((long long)r * nv + i) * nblk + blk) * 2 + c] = s;
+  }
+}
+
+// out[r * ldo + off + i] = sum over blocks of partial[r][i][blk]
+__global__ void __launch_bounds__(256) k_reduce(int nv, int nblk, const double* __restrict__ partial,
+                                                double2* __restrict__ out, int ldo, int off) {
+  __shared__ double red[2][256];
+  const int q = blockIdx.x;   // r * nv + i
+  const int r = q / nv, i = q % nv;
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    a += partial[((long long)q * nblk + k) * 2];
+    b += partial[((long long)q * nblk + k) * 2 + 1];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(long long)r * ldo + off + i] = make_double2(red[0][0], red[1][0]);
+}
+
+// w[r] += sign * sum_i coef[r * ldc + coff + i] * V_i[r]
+template <typename Tv, typename Tw>
+__global__ void __launch_bounds__(256) k_multi_axpy(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
+                                                    int nv, long long vstride, const double2* __restrict__ coef, int ldc,
+                                                    int coff, double sign, Tw* __restrict__ w) {
+  __shared__ cx<double> c[kMaxNv];
+  const int r = blockIdx.y;
+  if (threadIdx.x < nv) {
+    double2 v = coef[(long long)r * ldc + coff + threadIdx.x];
+    c[threadIdx.x] = {sign * v.x, sign * v.y};
+  }
+  __syncthreads();
+  const Tv* vr = V + (long long)r * rs;
+  Tw* wr = w + (long long)r * rs;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x) {
+    cx<double> acc = ld<double, Tw>(wr + e);
+    for (int i = 0; i < nv; ++i)
+      if (c[i].re != 0.0 || c[i].im != 0.0) cfma(acc, c[i], ld<double, Tv>(vr + (long long)i * vstride + e));
+    st<Tw, double>(wr + e, acc);
+  }
+}
+
+// dst[r] = src[r] / sqrt(nrm[r].x) where mask[r] != 0 (mask may be null); zero norm gives zero
+template <typename Tv>
+__global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, long long rs, const Tv* __restrict__ src,
+                                                   const double2* __restrict__ nrm2, const double* __restrict__ nrm,
+                                                   const int* __restrict__ mask, Tv* __restrict__ dst) {
+  const int r = blockIdx.y;
+  if (mask && !mask[r]) return;
+  double n = nrm ? nrm[r] : sqrt(nrm2[r].x);
+  double s = n > 0.0 ? 1.0 / n : 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x) {
+    cx<double> v = ld<double, Tv>(src + (long long)r * rs + e);
+    st<Tv, double>(dst + (long long)r * rs + e, s * v);
+  }
+}
+
+// out = a - b   (elementwise, same layout)
+template <typename Tv>
+__global__ void k_sub(long long n, const Tv* __restrict__ a, const Tv* __restrict__ b, Tv* __restrict__ out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    cx<double> x = ld<double, Tv>(a + i), y = ld<double, Tv>(b + i);
+    st<Tv, double>(out + i, x - y);
+  }
+}
+
+template <typename Tv>
+__global__ void k_add(long long n, const Tv* __restrict__ a, Tv* __restrict__ out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    cx<double> x = ld<double, Tv>(a + i), y = ld<double, Tv>(out + i);
+    st<Tv, double>(out + i, x + y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-RHS Hessenberg kernels (one thread per RHS)
+// ---------------------------------------------------------------------------
+// start of a cycle: g = (beta, 0, ...), active if beta > tolabs and not finished
+__global__ void k_cycle_init(int nrhs, int m, const double2* __restrict__ nrm2, const double* __restrict__ tolabs,
+                             const int* __restrict__ finished, double2* __restrict__ gv, double* __restrict__ beta,
+                             int* __restrict__ active, int* __restrict__ kcyc) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double b = sqrt(nrm2[r].x);
+  beta[r] = b;
+  for (int i = 0; i <= m; ++i) gv[r * (m + 1) + i] = make_double2(i == 0 ? b : 0.0, 0.0);
+  active[r] = (!finished[r] && b > tolabs[r]) ? 1 : 0;
+  kcyc[r] = 0;
+}
+
+// column j of the Hessenberg matrix from the two CGS passes and the norm, Givens update
+__global__ void k_arnoldi(int nrhs, int m, int j, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                          const double2* __restrict__ nrm2, double2* __restrict__ H, double* __restrict__ cs,
+                          double2* __restrict__ sn, double2* __restrict__ gv, const double* __restrict__ tolabs,
+                          int* __restrict__ active, int* __restrict__ kcyc, double* __restrict__ est,
+                          double* __restrict__ hnext) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  double2* Hc = H + ((long long)r * m + j) * (m + 1);   // column j
+  for (int i = 0; i <= j; ++i) {
+    double2 a = h1[r * (m + 1) + i], b = h2[r * (m + 1) + i];
+    Hc[i] = make_double2(a.x + b.x, a.y + b.y);
+  }
+  double hn = sqrt(nrm2[r].x);
+  Hc[j + 1] = make_double2(hn, 0.0);
+  hnext[r] = hn;
+  // previous rotations
+  for (int i = 0; i < j; ++i) {
+    cx<double> a = {Hc[i].x, Hc[i].y}, b = {Hc[i + 1].x, Hc[i + 1].y};
+    cx<double> s = {sn[r * m + i].x, sn[r * m + i].y};
+    double c = cs[r * m + i];
+    cx<double> na = c * a + s * b;
+    cx<double> nb = c * b - conj(s) * a;
+    Hc[i] = make_double2(na.re, na.im);
+    Hc[i + 1] = make_double2(nb.re, nb.im);
+  }
+  // new rotation zeroing H[j+1][j]: c real, [c s; -conj(s) c] [a; b] = [rho; 0]
+  cx<double> a = {Hc[j].x, Hc[j].y};
+  double bn = hn;
+  double c;
+  cx<double> s;
+  double aa = sqrt(a.re * a.re + a.im * a.im);
+  if (bn == 0.0) {
+    c = 1.0;
+    s = {0.0, 0.0};
+  } else if (aa == 0.0) {
+    c = 0.0;
+    s = {1.0, 0.0};
+  } else {
+    double t = sqrt(aa * aa + bn * bn);
+    c = aa / t;
+    s = (bn / t) * cx<double>{a.re / aa, a.im / aa};   // (a/|a|) conj(b)/t with b = hn real
+  }
+  cs[r * m + j] = c;
+  sn[r * m + j] = make_double2(s.re, s.im);
+  cx<double> rho = c * a + s * cx<double>{bn, 0.0};
+  Hc[j] = make_double2(rho.re, rho.im);
+  Hc[j + 1] = make_double2(0.0, 0.0);
+  cx<double> gj = {gv[r * (m + 1) + j].x, gv[r * (m + 1) + j].y};
+  cx<double> g1 = -(conj(s) * gj);
+  cx<double> g0 = c * gj;
+  gv[r * (m + 1) + j] = make_double2(g0.re, g0.im);
+  gv[r * (m + 1) + j + 1] = make_double2(g1.re, g1.im);
+  double e = sqrt(g1.re * g1.re + g1.im * g1.im);
+  est[r] = e;
+  kcyc[r] = j + 1;
+  if (e <= tolabs[r] || hn == 0.0 || j + 1 == m) active[r] = 0;
+}
+
+// y = R^-1 g over the kcyc[r] leading entries; y beyond kcyc is zero
+__global__ void k_lsq(int nrhs, int m, const double2* __restrict__ H, const double2* __restrict__ gv,
+                      const int* __restrict__ kcyc, double2* __restrict__ y) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  int k = kcyc[r];
+  for (int i = m - 1; i >= k; --i) y[r * m + i] = make_double2(0.0, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    cx<double> acc = {gv[r * (m + 1) + i].x, gv[r * (m + 1) + i].y};
+    for (int q = i + 1; q < k; ++q) {
+      double2 h = H[((long long)r * m + q) * (m + 1) + i];
+      double2 yq = y[r * m + q];
+      acc = acc - cx<double>{h.x, h.y} * cx<double>{yq.x, yq.y};
+    }
+    double2 d = H[((long long)r * m + i) * (m + 1) + i];
+    double den = d.x * d.x + d.y * d.y;
+    cx<double> inv = den > 0.0 ? cx<double>{d.x / den, -d.y / den} : cx<double>{0.0, 0.0};
+    cx<double> v = acc * inv;
+    y[r * m + i] = make_double2(v.re, v.im);
+  }
+}
+
+inline unsigned grid1(long long n) {
+  long long b = (n + 255) / 256;
+  return (unsigned)(b > 65535 ? 65535 : b);
+}
+
+}  // namespace
+
+int dots_blocks(long long count, int nrhs) {
+  long long per = 16384;   // entries per workgroup, at least
+  long long nb = (count + per - 1) / per;
+  int cap = 2048 / (nrhs > 0 ? nrhs : 1);
+  if (cap < 8) cap = 8;
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long rs, const void* V, int nv,
+                 long long vstride, const void* w, double* partial, int nblk, double2* out, int ldo, int off,
+                 hipStream_t st) {
+  for (int i0 = 0; i0 < nv; i0 += kMaxNv) {
+    int n = nv - i0 < kMaxNv ? nv - i0 : kMaxNv;
+    dim3 grid(nblk, nrhs);
+    size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
+    const void* Vi = (const char*)V + (size_t)i0 * vstride * es;
+    if (vt == DD_F64 && wt == DD_F64)
+      k_dots<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, (const double2*)w,
+                                                     partial, nblk);
+    else if (vt != DD_F64 && wt != DD_F64)
+      k_dots<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, (const float2*)w,
+                                                   partial, nblk);
+    else if (vt == DD_F64)
+      k_dots<double2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, (const float2*)w,
+                                                    partial, nblk);
+    else
+      k_dots<float2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, (const double2*)w,
+                                                    partial, nblk);
+    k_reduce<<<nrhs * n, 256, 0, st>>>(n, nblk, partial, out, ldo, off + i0);
+  }
+}
+
+void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long rs, const void* V, int nv,
+                       long long vstride, const double2* coef, int ldc, int coff, double sign, void* w,
+                       hipStream_t st) {
+  for (int i0 = 0; i0 < nv; i0 += kMaxNv) {
+    int n = nv - i0 < kMaxNv ? nv - i0 : kMaxNv;
+    dim3 grid(grid1(count), nrhs);
+    size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
+    const void* Vi = (const char*)V + (size_t)i0 * vstride * es;
+    if (vt == DD_F64 && wt == DD_F64)
+      k_multi_axpy<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, coef, ldc,
+                                                           coff + i0, sign, (double2*)w);
+    else if (vt != DD_F64 && wt != DD_F64)
+      k_multi_axpy<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, coef, ldc,
+                                                         coff + i0, sign, (float2*)w);
+    else if (vt != DD_F64)
+      k_multi_axpy<float2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, coef, ldc,
+                                                          coff + i0, sign, (double2*)w);
+    else
+      k_multi_axpy<double2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, coef, ldc,
+                                                          coff + i0, sign, (float2*)w);
+  }
+}
+
+void launch_normalize(dd_dtype vt, int nrhs, long long count, long long rs, const void* src, const double2* nrm2,
+                      const double* nrm, const int* mask, void* dst, hipStream_t st) {
+  dim3 grid(grid1(count), nrhs);
+  if (vt == DD_F64)
+    k_normalize<double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)src, nrm2, nrm, mask, (double2*)dst);
+  else
+    k_normalize<float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)src, nrm2, nrm, mask, (float2*)dst);
+}
+
+void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st) {
+  unsigned nb = (unsigned)((n + 255) / 256);
+  if (vt == DD_F64)
+    k_sub<double2><<<nb, 256, 0, st>>>(n, (const double2*)a, (const double2*)b, (double2*)out);
+  else
+    k_sub<float2><<<nb, 256, 0, st>>>(n, (const float2*)a, (const float2*)b, (float2*)out);
+}
+
+void launch_add(dd_dtype vt, long long n, const void* a, void* out, hipStream_t st) {
+  unsigned nb = (unsigned)((n + 255) / 256);
+  if (vt == DD_F64)
+    k_add<double2><<<nb, 256, 0, st>>>(n, (const double2*)a, (double2*)out);
+  else
+    k_add<float2><<<nb, 256, 0, st>>>(n, (const float2*)a, (float2*)out);
+}
+
+void launch_cycle_init(int nrhs, int m, const double2* nrm2, const double* tolabs, const int* finished, double2* gv,
+                       double* beta, int* active, int* kcyc, hipStream_t st) {
+  k_cycle_init<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, nrm2, tolabs, finished, gv, beta, active, kcyc);
+}
+
+void launch_arnoldi(int nrhs, int m, int j, const double2* h1, const double2* h2, const double2* nrm2, double2* H,
+                    double* cs, double2* sn, double2* gv, const double* tolabs, int* active, int* kcyc, double* est,
+                    double* hnext, hipStream_t st) {
+  k_arnoldi<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, j, h1, h2, nrm2, H, cs, sn, gv, tolabs, active, kcyc, est, hnext);
+}
+
+void launch_lsq(int nrhs, int m, const double2* H, const double2* gv, const int* kcyc, double2* y, hipStream_t st) {
+  k_lsq<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, H, gv, kcyc, y);
+}

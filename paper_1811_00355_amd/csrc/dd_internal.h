@@ -136,6 +136,11 @@ __device__ __forceinline__ cx<float> ld<float, bf16x2>(const bf16x2* p) {
   return {__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u)};
 }
 template <>
+__device__ __forceinline__ cx<float> ld<float, double2>(const double2* p) {
+  double2 v = *p;
+  return {(float)v.x, (float)v.y};
+}
+template <>
 __device__ __forceinline__ cx<double> ld<double, float2>(const float2* p) {
   float2 v = *p;
   return {(double)v.x, (double)v.y};
@@ -271,8 +276,9 @@ struct dd_mg {
   dd_dtype vstore;  // storage of P inside M
   // test vectors: FP64 master of the orthonormalised P (packed fine layout, n vectors)
   double2* P64 = nullptr;
-  void* Pst = nullptr;     // P in the storage dtype (float2 / __half2 / bf16x2)
-  float2* tv32 = nullptr;  // working test vectors lambda_i (FP32, setup only)
+  void* Pst = nullptr;       // P in the storage dtype (float2 / __half2 / bf16x2)
+  void* Pst32tmp = nullptr;  // FP32 staging of P for half-precision storage
+  void* tv = nullptr;        // working test vectors lambda_i (inner dtype)
   // coarse operator: [Vc][9][col][row] complex (column-major blocks), FP64 master and FP32
   double2* Dc64 = nullptr;
   float2* Dc32 = nullptr;
@@ -308,7 +314,7 @@ inline size_t vector_pair_bytes(dd_dtype dt) { return dt == DD_F64 ? 16 : 8; }
 // ---------------------------------------------------------------------------
 // kernel launchers (each defined next to its kernels)
 // ---------------------------------------------------------------------------
-// geometry / packing
+// geometry / packing / conversion / random vectors
 void launch_pack_fine(const GeomDev& g, dd_dtype vt, int nrhs, const double2* canon, void* packed,
                       hipStream_t st);
 void launch_unpack_fine(const GeomDev& g, dd_dtype vt, int nrhs, const void* packed, double2* canon,
@@ -319,6 +325,7 @@ void launch_convert_pairs(dd_dtype to, const double2* src64, const float2* src32
                           hipStream_t st);
 void launch_vec_convert(dd_dtype from, dd_dtype to, const void* src, void* dst, long long count,
                         hipStream_t st);
+void launch_gauss(unsigned long long seed, long long n, double2* out, hipStream_t st);
 // clover
 void launch_clover_build(const GeomDev& g, const double2* links64, double m0, double csw,
                          double2* clover64, double2* cinv64, hipStream_t st);
@@ -328,24 +335,39 @@ void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, con
 // SAP smoother
 void launch_sap(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters,
                 const void* b, void* x, hipStream_t st);
-// transfer
+// transfer and coarse construction
+bool supported_nvec(int n);
 void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,
                      const void* fine, void* coarse, hipStream_t st);
 void launch_prolong(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,
                     const void* coarse, void* fine, hipStream_t st);
 void launch_gram_schmidt(const GeomDev& g, int n, double2* P, int* bad_flag, hipStream_t st);
 void launch_coarse_build(const GeomDev& g, const OpSet& ops64, dd_dtype pst, int n, const void* P,
-                         double2* Dc64, hipStream_t st);
+                         double2* Dc64, double2* W, int chunk, hipStream_t st);
 void launch_coarse_invert(const GeomDev& g, int nc, const double2* Dc64, double2* Dinv64, int* bad_flag,
                           hipStream_t st);
-// coarse operator
-void launch_coarse_apply(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, int nrhs, const void* in,
-                         void* out, int site_begin, int site_count, int dir_begin, int dir_end, double alpha,
-                         const void* zin, double beta, hipStream_t st);
-void launch_coarse_block_mul(const GeomDev& g, dd_dtype vt, int nc, const void* Dinv, int nrhs,
-                             const void* in, void* out, int site_begin, int site_count, hipStream_t st);
-// BLAS-like kernels on packed vectors (count complex entries per RHS, nrhs RHS with stride ld)
-void launch_multi_dot(dd_dtype vt, int nrhs, long long count, long long ld, const void* const* V, int nv,
-                      long long vstride, const void* w, double* partial, int nblk, hipStream_t st);
-int multi_dot_blocks(long long count);
-void launch_reduce_partials(int nrhs, int nv, int nblk, const double* partial, double2* out, hipStream_t st);
+// coarse operator: out = a_self M xs + a_hop sum_d D_c(d) xh(X+d) + beta z on sites [begin, begin+count)
+void launch_coarse_mv(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, const void* Minv, int use_inv,
+                      int nrhs, int site_begin, int count, double a_self, const void* xs, double a_hop,
+                      const void* xh, double beta, const void* z, void* out, hipStream_t st);
+// vector kernels
+int dots_blocks(long long count, int nrhs);
+void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long ld, const void* V, int nv,
+                 long long vstride, const void* w, double* partial, int nblk, double2* out, int ldo, int off,
+                 hipStream_t st);
+void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long ld, const void* V, int nv,
+                       long long vstride, const double2* coef, int ldc, int coff, double sign, void* w,
+                       hipStream_t st);
+void launch_normalize(dd_dtype vt, int nrhs, long long count, long long ld, const void* src, const double2* nrm2,
+                      const double* nrm, const int* mask, void* dst, hipStream_t st);
+void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st);
+void launch_add(dd_dtype vt, long long n, const void* a, void* out, hipStream_t st);
+void launch_cycle_init(int nrhs, int m, const double2* nrm2, const double* tolabs, const int* finished,
+                       double2* gv, double* beta, int* active, int* kcyc, hipStream_t st);
+void launch_arnoldi(int nrhs, int m, int j, const double2* h1, const double2* h2, const double2* nrm2,
+                    double2* H, double* cs, double2* sn, double2* gv, const double* tolabs, int* active,
+                    int* kcyc, double* est, double* hnext, hipStream_t st);
+void launch_lsq(int nrhs, int m, const double2* H, const double2* gv, const int* kcyc, double2* y,
+                hipStream_t st);
+
+dd_status ensure_opset(dd_gauge* g, dd_dtype dt);

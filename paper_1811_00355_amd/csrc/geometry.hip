@@ -129,3 +129,47 @@ void launch_vec_convert(dd_dtype from, dd_dtype to, const void* src, void* dst, 
   else
     hipMemcpyAsync(dst, src, n * sizeof(float2), hipMemcpyDeviceToDevice, st);
 }
+
+// ---------------------------------------------------------------------------
+// Random starting vectors: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// keyed by the seed, counter = entry index, and the Box-Muller transform
+// (one 4x32 draw per complex entry: two uniforms -> real and imaginary part).
+// ---------------------------------------------------------------------------
+namespace {
+
+__device__ __forceinline__ void philox_round(uint32_t c[4], const uint32_t k[2]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+  uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+  uint32_t n0 = hi1 ^ c[1] ^ k[0];
+  uint32_t n2 = hi0 ^ c[3] ^ k[1];
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+__global__ void k_gauss(unsigned long long seed, long long n, double2* __restrict__ out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0u, 0u};
+  uint32_t k[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k);
+    k[0] += 0x9E3779B9u;
+    k[1] += 0xBB67AE85u;
+  }
+  double u1 = ((double)c[0] + 0.5) * (1.0 / 4294967296.0);
+  double u2 = ((double)c[1] + 0.5) * (1.0 / 4294967296.0);
+  double rr = sqrt(-2.0 * log(u1));
+  double s, co;
+  sincospi(2.0 * u2, &s, &co);
+  out[i] = make_double2(rr * co, rr * s);
+}
+
+}  // namespace
+
+void launch_gauss(unsigned long long seed, long long n, double2* out, hipStream_t st) {
+  k_gauss<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(seed, n, out);
+}

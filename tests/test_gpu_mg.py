@@ -1,0 +1,214 @@
+"""GPU parity of the multigrid pieces against the oracle: Gram-Schmidt, P, R,
+the Galerkin coarse operator, its stencil apply, the even-odd coarse solve in
+fixed-iteration mode, the V-cycle, the adaptive setup, and whole solves
+(true residual rechecked with the oracle's operator)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (L, block, eps, m0, c_sw, seed, n)
+    "c1": ((4, 4, 4, 4), (2, 2, 2, 2), 0.3, -0.4, 1.0, 1001, 8),
+    "asym": ((8, 4, 4, 8), (2, 2, 2, 4), 0.25, -0.2, 1.3, 17, 6),
+    "b4": ((8, 8, 8, 16), (4, 4, 4, 4), 0.2, -0.1, 1.0, 23, 20),
+}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1811_00355_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _build(ctx, name, **pkw):
+    from paper_1811_00355_amd import Gauge, MG, default_params
+    from oracle.lattice import Lattice
+    from oracle.dirac import WilsonClover
+    from workloads import su3_field, gauss_vectors
+    L, blk, eps, m0, csw, seed, n = CASES[name]
+    U = su3_field(L, eps, seed)
+    lat = Lattice(L, blk)
+    W = WilsonClover(U, lat, m0, csw)
+    g = Gauge(ctx, L, blk, U, m0, csw)
+    tv0 = gauss_vectors(n, lat.V, seed + 7).reshape(n, lat.V, 4, 3)
+    kw = dict(block=blk, n_vec=n, inner_dtype=0, store_dtype=0, init_sap_apps=0, setup_iters=0)
+    kw.update(pkw)
+    p = default_params(**kw)
+    print(f"case {name}: L={L} block={blk} n={n} params={kw}", flush=True)
+    mg = MG(g, p, tv_host=tv0)
+    return dict(U=U, lat=lat, W=W, g=g, mg=mg, tv0=tv0, n=n, p=p)
+
+
+def _close(d):
+    d["mg"].destroy()
+    d["g"].destroy()
+
+
+def _coarse_roundtrip(mg, dtype, nrhs, vin, fn):
+    import torch
+    import _gpu
+    cin = _gpu.to_dev(vin.reshape(nrhs, -1))
+    pin = mg.new_coarse(dtype, nrhs)
+    pout = mg.new_coarse(dtype, nrhs)
+    mg.pack_coarse(dtype, nrhs, cin, pin)
+    fn(pin, pout)
+    cout = torch.zeros_like(cin)
+    mg.unpack_coarse(dtype, nrhs, pout, cout)
+    torch.cuda.synchronize()
+    return _gpu.to_host(cout).reshape(vin.shape)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_build_P_and_coarse_operator(ctx, name):
+    import _gpu
+    from oracle import amg
+    d = _build(ctx, name)
+    lat, mg = d["lat"], d["mg"]
+    Pb = amg.gram_schmidt(lat, d["tv0"])
+    P_ref = amg.from_aggregates(lat, np.moveaxis(Pb, 2, 0))   # [n][V][4][3]
+    P_gpu = mg.export_vectors()
+    err = _gpu.max_rel(P_gpu, P_ref)
+    print(f"P error {err:.2e}", flush=True)
+    assert err < 1e-12
+    Dc_ref = amg.coarse_operator(d["W"], Pb)
+    Dc_gpu = mg.export_coarse()
+    err = _gpu.max_rel(Dc_gpu, Dc_ref)
+    print(f"D_c error {err:.2e}", flush=True)
+    assert err < 1e-12
+    _close(d)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_restrict_prolong_coarse_apply(ctx, name):
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_spinor, gauss_vectors
+    d = _build(ctx, name)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    Pb = amg.gram_schmidt(lat, d["tv0"])
+    Dc = amg.coarse_operator(d["W"], Pb)
+    nrhs = 3
+    f = gauss_spinor(lat.L, nrhs, 31)
+    c = gauss_vectors(nrhs, lat.Vc, 32, ncomp=2 * n)
+    for dtype, tol in ((0, 1e-12), (1, 1e-5)):
+        fr = f if dtype == 0 else _gpu.round_f32(f)
+        cr = c if dtype == 0 else _gpu.round_f32(c)
+        Pr = Pb if dtype == 0 else _gpu.round_f32(Pb)
+        Dr = Dc if dtype == 0 else _gpu.round_f32(Dc)
+        # restriction
+        import torch
+        fin = _gpu.to_dev(fr.reshape(nrhs, -1))
+        pf = d["g"].new_packed(dtype, nrhs)
+        d["g"].pack(dtype, nrhs, fin, pf)
+        pc = mg.new_coarse(dtype, nrhs)
+        mg.dd_restrict(dtype, nrhs, pf, pc)
+        cout = torch.zeros((nrhs, lat.Vc * 2 * n), dtype=torch.complex128, device="cuda")
+        mg.unpack_coarse(dtype, nrhs, pc, cout)
+        torch.cuda.synchronize()
+        got = _gpu.to_host(cout).reshape(nrhs, lat.Vc, 2 * n)
+        for r in range(nrhs):
+            assert _gpu.max_rel(got[r], amg.restrict(lat, Pr, fr[r])) < tol
+        # prolongation
+        cin = _gpu.to_dev(cr.reshape(nrhs, -1))
+        pc2 = mg.new_coarse(dtype, nrhs)
+        mg.pack_coarse(dtype, nrhs, cin, pc2)
+        pf2 = d["g"].new_packed(dtype, nrhs)
+        mg.dd_prolong(dtype, nrhs, pc2, pf2)
+        fout = torch.zeros((nrhs, lat.V * 12), dtype=torch.complex128, device="cuda")
+        d["g"].unpack(dtype, nrhs, pf2, fout)
+        torch.cuda.synchronize()
+        got = _gpu.to_host(fout).reshape(nrhs, lat.V, 4, 3)
+        for r in range(nrhs):
+            assert _gpu.max_rel(got[r], amg.prolong(lat, Pr, cr[r])) < tol
+        # coarse stencil
+        got = _coarse_roundtrip(mg, dtype, nrhs, cr, lambda i, o: mg.dd_coarse_apply(dtype, nrhs, i, o))
+        for r in range(nrhs):
+            err = _gpu.max_rel(got[r], amg.coarse_apply(lat, Dr, cr[r]))
+            print(f"dtype {dtype} coarse apply rhs {r}: {err:.2e}", flush=True)
+            assert err < tol
+    _close(d)
+
+
+@pytest.mark.parametrize("name", ["c1", "b4"])
+def test_coarse_solve_fixed_iterations(ctx, name):
+    """Fixed iteration count, no tolerance stop: GMRES on the even-odd Schur
+    complement and the odd reconstruction agree with the oracle in FP64."""
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_vectors
+    d = _build(ctx, name, coarse_fixed_iters=12, coarse_restart=5)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    Pb = amg.gram_schmidt(lat, d["tv0"])
+    ceo = amg.CoarseEO(lat, amg.coarse_operator(d["W"], Pb))
+    op = amg.MGParams(n_vec=n, coarse_fixed_iters=12, coarse_restart=5)
+    nrhs = 2
+    b = gauss_vectors(nrhs, lat.Vc, 41, ncomp=2 * n)
+    got = _coarse_roundtrip(mg, 0, nrhs, b, lambda i, o: mg.dd_coarse_solve(0, nrhs, i, o))
+    for r in range(nrhs):
+        err = _gpu.max_rel(got[r], ceo.solve(b[r], op))
+        print(f"coarse solve rhs {r}: {err:.2e}", flush=True)
+        assert err < 1e-10
+    _close(d)
+
+
+@pytest.mark.parametrize("name", ["c1", "b4"])
+def test_vcycle_fixed_iterations(ctx, name):
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_spinor
+    d = _build(ctx, name, coarse_fixed_iters=10, coarse_restart=10, sap_sweeps=2, sap_mr_iters=3)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    op = amg.MGParams(n_vec=n, coarse_fixed_iters=10, coarse_restart=10, sap_sweeps=2, sap_mr_iters=3)
+    two = amg.TwoLevel(d["W"], d["tv0"], op)
+    nrhs = 2
+    v = gauss_spinor(lat.L, nrhs, 51)
+    got = _gpu.fine_apply(d["g"], 0, nrhs, v, lambda i, o: mg.dd_precond_apply(nrhs, i, o))
+    for r in range(nrhs):
+        err = _gpu.max_rel(got[r], two.vcycle(v[r]))
+        print(f"V-cycle rhs {r}: {err:.2e}", flush=True)
+        assert err < 1e-10
+    _close(d)
+
+
+def test_adaptive_setup_fixed_iterations(ctx):
+    """init SAP solves + one adaptive iteration, coarse GMRES with a fixed count:
+    the produced P and D_c agree with the oracle's setup in FP64."""
+    import _gpu
+    from oracle import amg
+    d = _build(ctx, "c1", init_sap_apps=1, setup_iters=1, coarse_fixed_iters=8, coarse_restart=8)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    op = amg.MGParams(n_vec=n, init_sap_apps=1, setup_iters=1, coarse_fixed_iters=8, coarse_restart=8)
+    ref = amg.setup(d["W"], op, d["tv0"])
+    P_ref = amg.from_aggregates(lat, np.moveaxis(ref.Pb, 2, 0))
+    e1 = _gpu.max_rel(mg.export_vectors(), P_ref)
+    e2 = _gpu.max_rel(mg.export_coarse(), ref.Dc)
+    print(f"setup: P error {e1:.2e}, D_c error {e2:.2e}", flush=True)
+    assert e1 < 1e-10 and e2 < 1e-10
+    _close(d)
+
+
+@pytest.mark.parametrize("name,inner,store", [("c1", 0, 0), ("c1", 1, 1), ("b4", 1, 1), ("b4", 1, 3)])
+def test_solve_true_residual(ctx, name, inner, store):
+    """Whole solve: every RHS reaches |b - D x| / |b| <= 1e-10, recomputed with the
+    oracle's FP64 operator on the host."""
+    import torch
+    import _gpu
+    from workloads import gauss_spinor
+    d = _build(ctx, name, inner_dtype=inner, store_dtype=store, init_sap_apps=2, setup_iters=2)
+    lat, mg = d["lat"], d["mg"]
+    nrhs = 3
+    b = gauss_spinor(lat.L, nrhs, 61)
+    bd = _gpu.to_dev(b.reshape(nrhs, -1))
+    xd = torch.zeros_like(bd)
+    info, st = mg.dd_solve(nrhs, bd, xd, 1e-10)
+    torch.cuda.synchronize()
+    x = _gpu.to_host(xd).reshape(b.shape)
+    for r in range(nrhs):
+        res = np.linalg.norm(b[r] - d["W"].apply(x[r])) / np.linalg.norm(b[r])
+        print(f"{name} inner={inner} store={store} rhs {r}: iters {info[r]['outer_iters']} "
+              f"relres(lib) {info[r]['true_relres']:.2e} relres(oracle D) {res:.2e}", flush=True)
+        assert info[r]["converged"] and res <= 1e-10
+    _close(d)
