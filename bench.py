@@ -1,0 +1,203 @@
+"""Benchmark: batched 12-RHS solves of the Wilson-clover operator with the
+two-level DD-alpha-AMG solver on one MI355X.
+
+Workload (default): 32^3x64 lattice, links exp(i*0.2*H) reunitarised, c_sw = 1,
+m0 from the tuned-mass table, 4^4 aggregates/SAP domains, n = 20 test vectors,
+4 adaptive setup iterations, the 12 spin-colour point sources at the origin
+solved together to a true relative residual of 1e-10 with the FP64 operator.
+Inputs are synthetic and seeded (there is no gauge-field dataset here).
+
+A step is one batched solve of the 12 right-hand sides with the setup resident
+on the device; `value` is right-hand sides solved per second over the timed
+steps.  The line also carries the roofline of the dominant kernel (timed with
+HIP events on its launch stream over the timed steps) and the oracle's CPU
+throughput on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C3] [--store f32|f16|bf16]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-10
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, lat_shape, n_vec, gpu_outer_iters, gpu_coarse_iters_per_vcycle):
+    """Time the oracle, as it is, on a bounded sample: one outer FGMRES iteration
+    (FP64 operator apply + V-cycle with SAP(4) and the coarse even-odd GMRES) on
+    an 8^3x16 sub-volume with the workload's parameters, extrapolated to the full
+    lattice by the volume ratio and to a whole solve by the GPU's outer iteration
+    count."""
+    from threadpoolctl import threadpool_limits
+    from oracle.lattice import Lattice
+    from oracle.dirac import WilsonClover
+    from oracle import amg
+    from workloads import su3_field, gauss_vectors, gauss_spinor
+    L_s = (8, 8, 8, 16)
+    with threadpool_limits(limits=1):
+        lat = Lattice(L_s, cfg["block"])
+        U = su3_field(L_s, cfg["eps"], cfg["gauge_seed"])
+        W = WilsonClover(U, lat, cfg["m0"], cfg["c_sw"])
+        tv = gauss_vectors(n_vec, lat.V, cfg["tv_seed"]).reshape(n_vec, lat.V, 4, 3)
+        coarse_iters = max(1, int(round(gpu_coarse_iters_per_vcycle)))
+        p = amg.MGParams(n_vec=n_vec, coarse_fixed_iters=coarse_iters, coarse_restart=min(30, coarse_iters))
+        mg = amg.TwoLevel(W, tv, p)
+        v = gauss_spinor(L_s, 1, 5)[0]
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            z = mg.vcycle(v)
+            w = W.apply(z)
+            reps += 1
+            if time.perf_counter() - t0 > 8.0 or reps >= 5:
+                break
+        t_iter = (time.perf_counter() - t0) / reps
+    V_full = int(np.prod(lat_shape))
+    t_solve = t_iter * (V_full / lat.V) * gpu_outer_iters
+    return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
+                sample=(f"one outer FGMRES iteration (FP64 D + V-cycle: SAP 4x4, coarse GMRES {coarse_iters} its) "
+                        f"of the numpy oracle on an 8^3x16 sub-volume, {reps} reps, {t_iter:.2f} s/iteration; "
+                        f"scaled by volume x{V_full // lat.V} and {gpu_outer_iters:.1f} outer iterations per solve"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="C3")
+    ap.add_argument("--store", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--coarse-restart", type=int, default=30)
+    ap.add_argument("--coarse-max-iters", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the multi-GPU domain decomposition is not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1811_00355_amd import binding as B
+    from workloads import get_config, su3_field
+
+    cfg = get_config(args.config)
+    L, blk, n_vec = cfg["L"], cfg["block"], cfg["n_vec"]
+    V = int(np.prod(L))
+    nrhs = 12
+    store = B.DTYPES[args.store]
+    log(f"[bench] workload {args.config}: L={L} block={blk} n={n_vec} m0={cfg['m0']:.5f} store={args.store}")
+    t0 = time.perf_counter()
+    U = su3_field(L, cfg["eps"], cfg["gauge_seed"])
+    log(f"[bench] gauge field generated on the host in {time.perf_counter() - t0:.1f} s")
+
+    ctx = B.Context(0, hbm_budget_bytes=250 << 30)
+    g = B.Gauge(ctx, L, blk, U, cfg["m0"], cfg["c_sw"])
+    del U
+    p = B.default_params(block=blk, n_vec=n_vec, setup_iters=cfg["setup_iters"], inner_dtype=B.DD_F32,
+                         store_dtype=store, seed=cfg["tv_seed"], coarse_restart=args.coarse_restart,
+                         coarse_max_iters=args.coarse_max_iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg = B.MG(g, p)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"[bench] setup {t_setup:.2f} s")
+
+    # the 12 spin-colour point sources at the origin, canonical complex128 on the device
+    b = torch.zeros((nrhs, V * 12), dtype=torch.complex128, device="cuda")
+    for k in range(nrhs):
+        b[k, k] = 1.0
+    x = torch.zeros_like(b)
+
+    def step():
+        info, st = mg.dd_solve(nrhs, b, x, TOL, raise_on_noconv=False)
+        bad = [r for r, i in enumerate(info) if not (i["converged"] and i["true_relres"] <= TOL)]
+        if st or bad:
+            raise RuntimeError(f"solve did not converge (status {st}, rhs {bad}): {info}")
+        return info
+
+    for w in range(args.warmup):
+        info = step()
+        log(f"[bench] warmup {w}: outer iterations {[i['outer_iters'] for i in info]}, "
+            f"{info[0]['t_solve_s']:.3f} s")
+
+    B.kernel_timer_enable("*")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for s in range(args.steps):
+        infos.append(step())
+        log(f"[bench] step {s}: {infos[-1][0]['t_solve_s']:.3f} s, max relres "
+            f"{max(i['true_relres'] for i in infos[-1]):.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = nrhs * args.steps / elapsed
+
+    # dominant kernel over the timed steps
+    kstats = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
+    B.kernel_timer_enable(None)
+    dom = max(kstats, key=lambda k: kstats[k]["ms"])
+    ks = kstats[dom]
+    avg_ms = ks["ms"] / max(ks["launches"], 1)
+    achieved = ks["bytes"] / (ks["ms"] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=dom,
+                    avg_launch_ms=round(avg_ms, 4), launches=ks["launches"],
+                    share_of_step=round(ks["ms"] / (elapsed * 1e3), 3))
+    kernels = {k: dict(ms_per_step=round(v["ms"] / args.steps, 3), launches_per_step=v["launches"] // args.steps,
+                       GBs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
+               for k, v in sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])}
+    outer = np.mean([i["outer_iters"] for inf in infos for i in inf])
+    coarse_per_vcycle = np.mean([inf[0]["coarse_iters_total"] / max(max(i["outer_iters"] for i in inf), 1)
+                                 for inf in infos])
+    log(f"[bench] {value:.2f} solves/s; dominant kernel {dom}: {achieved:.0f} GB/s; kernels {kernels}")
+
+    out = {
+        "metric": "solves/s @ true rel.res 1e-10 (32^3x64, 12 RHS)",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 outer / f32 inner",
+        "data": "synthetic (seeded SU(3) links, point sources)",
+        "config": {"workload": f"{args.config}: {L[0]}^3x{L[3]} Wilson-clover, 12 point-source RHS batched, "
+                               f"2-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
+                   "lattice": list(L), "rhs": nrhs, "m0": cfg["m0"], "c_sw": cfg["c_sw"], "eps": cfg["eps"],
+                   "store_dtype": args.store, "coarse_restart": args.coarse_restart,
+                   "outer_iters_mean": round(float(outer), 2),
+                   "coarse_iters_per_vcycle": round(float(coarse_per_vcycle), 1),
+                   "setup_s": round(t_setup, 3),
+                   "solves_per_s_incl_setup": round(nrhs / (t_setup + elapsed / args.steps), 3),
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(cfg, L, n_vec, float(outer), float(coarse_per_vcycle))
+    print(json.dumps(out), flush=True)
+    mg.destroy()
+    g.destroy()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -196,6 +196,16 @@ dd_status dd_export_operands(dd_gauge* g, dd_dtype dt, void* links_host, void* c
 dd_status dd_export_coarse(const dd_mg* mg, double* dc_host /* [Vc][9][2n][2n] c128 */);
 dd_status dd_export_vectors(const dd_mg* mg, double* tv_host /* [n][V][4][3] c128 */);
 
+/* ---- per-kernel timing (benchmark support) -----------------------------------
+ * Brackets every launch of the named kernel ("*" = all instrumented kernels:
+ * k_dirac, k_sap_colour, k_restrict, k_prolong, k_coarse_mv, k_dots,
+ * k_multi_axpy) with HIP events on its launch stream and records the launch's
+ * algorithmic bytes and flops.  NULL disables timing and clears the records. */
+dd_status dd_kernel_timer_enable(const char* name);
+dd_status dd_kernel_timer_read(const char* name, double* total_ms, int64_t* launches, double* bytes,
+                               double* flops);
+dd_status dd_kernel_timer_names(char* buf, size_t cap);
+
 #ifdef __cplusplus
 }
 #endif

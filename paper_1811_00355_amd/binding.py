@@ -86,6 +86,10 @@ SIGNATURES = {
     "dd_export_operands": (_I, [_P, _I, _P, _P]),
     "dd_export_coarse": (_I, [_P, _P]),
     "dd_export_vectors": (_I, [_P, _P]),
+    "dd_kernel_timer_enable": (_I, [ctypes.c_char_p]),
+    "dd_kernel_timer_read": (_I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "dd_kernel_timer_names": (_I, [ctypes.c_char_p, ctypes.c_size_t]),
 }
 
 
@@ -321,3 +325,22 @@ class MG:
         tv = np.zeros((self.n, self.g.V, 4, 3), dtype=np.complex128)
         self.ctx.check(self.ctx.lib.dd_export_vectors(self.h, tv.ctypes.data_as(_P)))
         return tv
+
+
+def kernel_timer_enable(name="*"):
+    lib().dd_kernel_timer_enable(None if name is None else name.encode())
+
+
+def kernel_timer_read(name):
+    ms, n, by, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    st = lib().dd_kernel_timer_read(name.encode(), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by), ctypes.byref(fl))
+    if st:
+        raise DDError(st, "dd_kernel_timer_read failed")
+    return dict(ms=ms.value, launches=n.value, bytes=by.value, flops=fl.value)
+
+
+def kernel_timer_names():
+    buf = ctypes.create_string_buffer(4096)
+    lib().dd_kernel_timer_names(buf, 4096)
+    v = buf.value.decode()
+    return v.split(";") if v else []

@@ -424,8 +424,8 @@ static dd_status validate_params(dd_gauge* g, const dd_mg_params* p) {
   if (!supported_nvec(p->n_vec)) return dd_fail(g->ctx, DD_ESHAPE, "n_vec must be one of 6, 8, 12, 16, 20, 24");
   if (p->sap_sweeps < 0 || p->sap_mr_iters < 0 || p->setup_iters < 0 || p->init_sap_apps < 0)
     return dd_fail(g->ctx, DD_EINVAL, "negative iteration counts");
-  if (p->coarse_restart < 1 || p->coarse_restart > 64 || p->fgmres_restart < 1 || p->fgmres_restart > 64)
-    return dd_fail(g->ctx, DD_EINVAL, "restart lengths must be in [1, 64]");
+  if (p->coarse_restart < 1 || p->coarse_restart > 256 || p->fgmres_restart < 1 || p->fgmres_restart > 64)
+    return dd_fail(g->ctx, DD_EINVAL, "coarse restart must be in [1, 256], FGMRES restart in [1, 64]");
   if (p->coarse_max_iters < 1 || p->max_outer_iters < 1) return dd_fail(g->ctx, DD_EINVAL, "iteration caps must be >= 1");
   if (p->inner_dtype != DD_F64 && p->inner_dtype != DD_F32)
     return dd_fail(g->ctx, DD_EINVAL, "inner_dtype must be DD_F64 or DD_F32");

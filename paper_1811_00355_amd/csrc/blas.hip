@@ -7,6 +7,7 @@
 // A vector set holds nrhs vectors of `count` complex entries at stride `rs`;
 // a basis of such sets is spaced `vstride` pairs apart.
 #include "dd_internal.h"
+#include "ktimer.h"
 
 namespace {
 
@@ -241,9 +242,9 @@ inline unsigned grid1(long long n) {
 }  // namespace
 
 int dots_blocks(long long count, int nrhs) {
-  long long per = 16384;   // entries per workgroup, at least
+  long long per = 2048;    // entries per workgroup, at least
   long long nb = (count + per - 1) / per;
-  int cap = 2048 / (nrhs > 0 ? nrhs : 1);
+  int cap = 4096 / (nrhs > 0 ? nrhs : 1);
   if (cap < 8) cap = 8;
   if (nb > cap) nb = cap;
   if (nb < 1) nb = 1;
@@ -257,7 +258,11 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
     int n = nv - i0 < kMaxNv ? nv - i0 : kMaxNv;
     dim3 grid(nblk, nrhs);
     size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
+    size_t ew = wt == DD_F64 ? sizeof(double2) : sizeof(float2);
     const void* Vi = (const char*)V + (size_t)i0 * vstride * es;
+    const double bytes = (double)nrhs * count * (n * es + ew), flops = 8.0 * nrhs * count * n;
+    const bool timed = ktimer_enabled("k_dots");
+    if (timed) ktimer_begin("k_dots", st);
     if (vt == DD_F64 && wt == DD_F64)
       k_dots<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, (const double2*)w,
                                                      partial, nblk);
@@ -270,6 +275,7 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
     else
       k_dots<float2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, (const double2*)w,
                                                     partial, nblk);
+    if (timed) ktimer_end("k_dots", st, bytes, flops);
     k_reduce<<<nrhs * n, 256, 0, st>>>(n, nblk, partial, out, ldo, off + i0);
   }
 }
@@ -281,7 +287,11 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
     int n = nv - i0 < kMaxNv ? nv - i0 : kMaxNv;
     dim3 grid(grid1(count), nrhs);
     size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
+    size_t ew = wt == DD_F64 ? sizeof(double2) : sizeof(float2);
     const void* Vi = (const char*)V + (size_t)i0 * vstride * es;
+    const double bytes = (double)nrhs * count * (n * es + 2 * ew), flops = 8.0 * nrhs * count * n;
+    const bool timed = ktimer_enabled("k_multi_axpy");
+    if (timed) ktimer_begin("k_multi_axpy", st);
     if (vt == DD_F64 && wt == DD_F64)
       k_multi_axpy<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, coef, ldc,
                                                            coff + i0, sign, (double2*)w);
@@ -294,6 +304,7 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
     else
       k_multi_axpy<double2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, coef, ldc,
                                                           coff + i0, sign, (float2*)w);
+    if (timed) ktimer_end("k_multi_axpy", st, bytes, flops);
   }
 }
 

@@ -1,8 +1,6 @@
 // Coarse-grid operator apply (Eq. 2 stencil, Sec. 3: "effective links" and
-// "clover" blocks of size 2n x 2n).  One workgroup per coarse site; threads
-// run over (row, rhs) pairs, and the input vectors of the site and its eight
-// neighbours are staged in LDS.  Blocks are column major, so the threads of a
-// wave read consecutive rows of one column.
+// "clover" blocks of size 2n x 2n).  Blocks are column major, so the lanes of
+// a wave read consecutive rows of one column.
 //
 //   out(X) = a_self * M(X) xs(X) + a_hop * sum_{d=1..8} D_c(X, d) xh(X + d) + beta * z(X)
 //
@@ -10,60 +8,74 @@
 // the self block.  This covers the full stencil (xs = xh = x), the two halves
 // of the even-site Schur complement and the odd-site reconstruction.
 #include "dd_internal.h"
+#include "ktimer.h"
 
 namespace {
 
-constexpr int kLdsBytes = 40 * 1024;
+// One wave per coarse site, lane = row of the 2n x 2n blocks (2n <= 64); NR
+// right-hand sides are accumulated per lane.  The input of the site / its
+// neighbour for the current direction is staged in LDS as [col][rhs], so each
+// lane streams one column of the block (coalesced over the wave) against an
+// LDS broadcast of the inputs: every block element is read once per apply.
+constexpr int kSitesPerWG = 4;
 
-template <typename R, typename Sd, typename Tv>
-__global__ void __launch_bounds__(256) k_coarse_mv(GeomDev g, int nc, const Sd* __restrict__ Dc,
-                                                   const Sd* __restrict__ Minv, int use_inv, int nrhs, int site_begin,
-                                                   R a_self, const Tv* __restrict__ xs, R a_hop,
-                                                   const Tv* __restrict__ xh, R beta, const Tv* __restrict__ z,
-                                                   Tv* __restrict__ out) {
-  extern __shared__ unsigned char lds_raw[];
-  cx<R>* xsh = reinterpret_cast<cx<R>*>(lds_raw);
-  const int X = site_begin + blockIdx.x;
+template <typename R, typename Sd, typename Tv, int NR>
+__global__ void __launch_bounds__(64 * kSitesPerWG) k_coarse_mv(GeomDev g, int nc, const Sd* __restrict__ Dc,
+                                                              const Sd* __restrict__ Minv, int use_inv, int nrhs,
+                                                              int site_begin, int count, R a_self,
+                                                              const Tv* __restrict__ xs, R a_hop,
+                                                              const Tv* __restrict__ xh, R beta,
+                                                              const Tv* __restrict__ z, Tv* __restrict__ out) {
+  __shared__ cx<R> xsh[kSitesPerWG][64][NR];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int local = blockIdx.x * kSitesPerWG + w;
+  const bool site_ok = local < count;
+  const int X = site_begin + (site_ok ? local : 0);
   const long long vstride = (long long)g.Vc * nc;   // rhs stride of a coarse vector
-  const int ndir = (a_hop != (R)0) ? 9 : 1;
-  const bool has_self = a_self != (R)0;
-  int nb[9];
-  nb[0] = X;
+  const bool has_self = a_self != (R)0, has_hop = a_hop != (R)0;
+  const bool row_ok = site_ok && lane < nc;
+  for (int r0 = 0; r0 < nrhs; r0 += NR) {
+    const int nr = nrhs - r0 < NR ? nrhs - r0 : NR;
+    cx<R> acc_s[NR], acc_h[NR];
 #pragma unroll
-  for (int d = 1; d < 9; ++d) nb[d] = g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK;
-  const Sd* Mself = use_inv ? Minv + (long long)(X - g.Vch) * nc * nc : Dc + (long long)X * 9 * nc * nc;
-  const Sd* Dx = Dc + (long long)X * 9 * nc * nc;
-  // rhs processed in chunks that fit the LDS stage
-  int rchunk = kLdsBytes / (int)(9 * nc * sizeof(cx<R>));
-  if (rchunk < 1) rchunk = 1;
-  for (int r0 = 0; r0 < nrhs; r0 += rchunk) {
-    int nr = nrhs - r0 < rchunk ? nrhs - r0 : rchunk;
-    __syncthreads();
-    for (int e = threadIdx.x; e < ndir * nr * nc; e += blockDim.x) {
-      int d = e / (nr * nc), rem = e % (nr * nc), r = rem / nc, c = rem % nc;
-      const Tv* src = (d == 0) ? xs : xh;
-      cx<R> v = {(R)0, (R)0};
-      if (d > 0 || has_self) v = ld<R, Tv>(src + (long long)(r0 + r) * vstride + (long long)nb[d] * nc + c);
-      xsh[(d * nr + r) * nc + c] = v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
-      int r = e / nc, row = e % nc;
-      cx<R> acc_s = {(R)0, (R)0}, acc_h = {(R)0, (R)0};
-      if (has_self) {
-        const cx<R>* xv = xsh + (0 * nr + r) * nc;
-        for (int c = 0; c < nc; ++c) cfma(acc_s, ld<R, Sd>(Mself + (long long)c * nc + row), xv[c]);
+    for (int r = 0; r < NR; ++r) acc_s[r] = acc_h[r] = {(R)0, (R)0};
+    for (int d = has_self ? 0 : 1; d < (has_hop ? 9 : 1); ++d) {
+      const int Y = d == 0 ? X : (g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK);
+      const Tv* src = d == 0 ? xs : xh;
+      __syncthreads();
+      if (row_ok)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) xsh[w][lane][r] = ld<R, Tv>(src + (long long)(r0 + r) * vstride + (long long)Y * nc + lane);
+      __syncthreads();
+      if (row_ok) {
+        const Sd* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * nc * nc : Dc + (long long)X * 9 * nc * nc)
+                             : Dc + ((long long)X * 9 + d) * nc * nc;
+        cx<R> acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = {(R)0, (R)0};
+        for (int c = 0; c < nc; ++c) {
+          cx<R> m = ld<R, Sd>(B + (long long)c * nc + lane);
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+            if (r < nr) cfma(acc[r], m, xsh[w][c][r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (d == 0) acc_s[r] = acc[r];
+          else acc_h[r] = acc_h[r] + acc[r];
+        }
       }
-      for (int d = 1; d < ndir; ++d) {
-        const cx<R>* xv = xsh + (d * nr + r) * nc;
-        const Sd* B = Dx + (long long)d * nc * nc;
-        for (int c = 0; c < nc; ++c) cfma(acc_h, ld<R, Sd>(B + (long long)c * nc + row), xv[c]);
-      }
-      cx<R> o = a_self * acc_s + a_hop * acc_h;
-      long long oi = (long long)(r0 + r) * vstride + (long long)X * nc + row;
-      if (beta != (R)0) o = o + beta * ld<R, Tv>(z + oi);
-      st<Tv, R>(out + oi, o);
     }
+    if (row_ok)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nr) {
+          long long oi = (long long)(r0 + r) * vstride + (long long)X * nc + lane;
+          cx<R> o = a_self * acc_s[r] + a_hop * acc_h[r];
+          if (beta != (R)0) o = o + beta * ld<R, Tv>(z + oi);
+          st<Tv, R>(out + oi, o);
+        }
   }
 }
 
@@ -72,9 +84,21 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
         double a_self, const void* xs, double a_hop, const void* xh, double beta, const void* z, void* out,
         hipStream_t st) {
   if (count <= 0) return;
-  k_coarse_mv<R, Sd, Tv><<<(unsigned)count, 256, kLdsBytes, st>>>(
-      g, nc, (const Sd*)Dc, (const Sd*)Minv, use_inv, nrhs, site_begin, (R)a_self, (const Tv*)xs, (R)a_hop,
-      (const Tv*)xh, (R)beta, (const Tv*)z, (Tv*)out);
+  const int nblocks_read = (a_self != 0.0 ? 1 : 0) + (a_hop != 0.0 ? 8 : 0);
+  const double bytes = (double)count * nblocks_read * nc * nc * sizeof(Sd) +
+                       (double)count * nc * nrhs * sizeof(Tv) * (2 + (beta != 0.0 ? 1 : 0));
+  const double flops = 8.0 * count * nblocks_read * nc * nc * nrhs;
+  const unsigned nb = (unsigned)((count + kSitesPerWG - 1) / kSitesPerWG);
+  const dim3 blk(64 * kSitesPerWG);
+#define DD_MV(NRV)                                                                                                 \
+  DD_TIMED("k_coarse_mv", st, bytes, flops,                                                                        \
+           (k_coarse_mv<R, Sd, Tv, NRV><<<nb, blk, 0, st>>>(g, nc, (const Sd*)Dc, (const Sd*)Minv, use_inv, nrhs,   \
+                                                             site_begin, count, (R)a_self, (const Tv*)xs, (R)a_hop, \
+                                                             (const Tv*)xh, (R)beta, (const Tv*)z, (Tv*)out)))
+  if (nrhs == 1) DD_MV(1);
+  else if (nrhs <= 4) DD_MV(4);
+  else DD_MV(12);
+#undef DD_MV
 }
 
 }  // namespace

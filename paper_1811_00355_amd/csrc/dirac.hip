@@ -3,6 +3,7 @@
 // fastest, so the workgroups that share a tile of sites (and its links and
 // clover) are resident together and the operator is fetched from HBM once.
 #include "dslash.h"
+#include "ktimer.h"
 
 namespace {
 
@@ -24,8 +25,8 @@ __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ 
 
 }  // namespace
 
-void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
-                  hipStream_t st) {
+static void dirac_dispatch(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
+                           hipStream_t st) {
   unsigned nb = (unsigned)((g.V + 255) / 256) * nrhs;
   switch (dt) {
     case DD_F64:
@@ -45,4 +46,12 @@ void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, con
                                                          (const float2*)in, (float2*)out);
       break;
   }
+}
+
+void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
+                  hipStream_t st) {
+  // algorithmic traffic: spinor in + out per RHS, 4 links + packed clover once per site
+  double bytes = (double)g.V * (24.0 * vector_pair_bytes(dt) * nrhs + 72.0 * storage_pair_bytes(dt));
+  double flops = (double)g.V * nrhs * 1824.0;
+  DD_TIMED("k_dirac", st, bytes, flops, dirac_dispatch(g, dt, ops, nrhs, in, out, st));
 }

@@ -96,10 +96,13 @@ __device__ __forceinline__ void su3_dag_mul_half(const cx<R>* u, const cx<R>* h,
 // out (=|+=) C psi for a packed clover-like field (two Hermitian 6x6 blocks)
 template <typename R, typename S, bool ACC>
 __device__ __forceinline__ void clover_mul(const S* C, long long V, long long I, const cx<R>* in, cx<R>* out) {
-#pragma unroll
+  // one chirality block at a time (36 reals of operand live, not 72)
+#pragma unroll 1
   for (int c = 0; c < 2; ++c) {
     const S* B = C + (long long)(18 * c) * V + I;
-    const cx<R>* v = in + 6 * c;
+    cx<R> v[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) v[r] = c ? in[6 + r] : in[r];
     cx<R> o[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -117,7 +120,10 @@ __device__ __forceinline__ void clover_mul(const S* C, long long V, long long I,
         cfma_conj(o[q], u, v[r]);
       }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) out[6 * c + r] = ACC ? out[6 * c + r] + o[r] : o[r];
+    for (int r = 0; r < 6; ++r) {
+      if (c) out[6 + r] = ACC ? out[6 + r] + o[r] : o[r];
+      else out[r] = ACC ? out[r] + o[r] : o[r];
+    }
   }
 }
 
@@ -132,39 +138,77 @@ __device__ __forceinline__ void store_spinor(Tv* p, long long V, long long I, co
   for (int c = 0; c < 12; ++c) st<Tv, R>(p + (long long)c * V + I, psi[c]);
 }
 
-// One hop term for direction MU at site s: acc += -1/2 * phase * (1 -+ gamma) U psi(neighbour).
-// The neighbour spinor is fetched by the functor `fetch(J, inside, psi)`; a
-// hop is skipped when `dirichlet` and the neighbour lies outside the block.
-template <int MU, typename R, typename S, typename Fetch>
-__device__ __forceinline__ void hop_mu(const GeomDev& g, const S* links, const SiteLoc& s, long long I, bool dirichlet,
-                                       Fetch fetch, cx<R>* acc) {
-  bool wrap, inside;
-  cx<R> psi[12], h[6], uh[6], u[9];
-  // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
-  long long J = neighbor(g, s, MU, +1, wrap, inside);
-  if (!dirichlet || inside) {
-    fetch(J, inside, psi);
-    project<MU, -1, R>(psi, h);
-    load_link<R, S>(links, g.V, MU, I, u);
-    su3_mul_half<R>(u, h, uh);
-    reconstruct_acc<MU, -1, R>(uh, (R)(wrap ? -0.5 * g.bc_t : -0.5), acc);
-  }
-  // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
-  J = neighbor(g, s, MU, -1, wrap, inside);
-  if (!dirichlet || inside) {
-    fetch(J, inside, psi);
-    project<MU, +1, R>(psi, h);
-    load_link<R, S>(links, g.V, MU, J, u);
-    su3_dag_mul_half<R>(u, h, uh);
-    reconstruct_acc<MU, +1, R>(uh, (R)(wrap ? -0.5 * g.bc_t : -0.5), acc);
+// Runtime-direction form of the same actions.  A_mu d = (c0 d_p0, c1 d_p1) and
+// A_mu^dag h = (k0 h_q0, k1 h_q1) with unit complex coefficients; one loop body
+// serves all directions, which keeps the live register set to one hop.
+struct HopCoef {
+  int p0, q0;              // permutation: component index feeding output 0 (1 - it feeds output 1)
+  float c0r, c0i, c1r, c1i;   // A_mu coefficients
+  float k0r, k0i, k1r, k1i;   // A_mu^dag coefficients
+};
+__device__ __forceinline__ HopCoef hop_coef(int mu) {
+  switch (mu) {
+    case 0: return {1, 1, 0.f, -1.f, 0.f, -1.f, 0.f, 1.f, 0.f, 1.f};
+    case 1: return {1, 1, -1.f, 0.f, 1.f, 0.f, 1.f, 0.f, -1.f, 0.f};
+    case 2: return {0, 0, 0.f, -1.f, 0.f, 1.f, 0.f, 1.f, 0.f, -1.f};
+    default: return {0, 0, 1.f, 0.f, 1.f, 0.f, 1.f, 0.f, 1.f, 0.f};
   }
 }
 
+template <typename R>
+__device__ __forceinline__ cx<R> unit_mul(R cr, R ci, cx<R> a) {
+  return {cr * a.re - ci * a.im, cr * a.im + ci * a.re};
+}
+
+// acc += scale * phase * (-1/2) (1 + sgn gamma_mu) U psi_nb, with U = U_mu(x)
+// (forward, sgn = -1) or U_mu(x - mu)^dag (backward, sgn = +1) already loaded
+template <typename R>
+__device__ __forceinline__ void hop_rt(const HopCoef& hc, int sgn, bool dag, const cx<R>* u, const cx<R>* psi, R coef,
+                                       cx<R>* acc) {
+  cx<R> h[6], uh[6];
+  // h = psi_up + sgn * A_mu psi_dn   (selects, not indexing, keep everything in registers)
+  const R s = (R)sgn;
+  const bool swp = hc.p0 != 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> d0 = swp ? psi[9 + a] : psi[6 + a];
+    cx<R> d1 = swp ? psi[6 + a] : psi[9 + a];
+    h[a] = psi[a] + s * unit_mul<R>((R)hc.c0r, (R)hc.c0i, d0);
+    h[3 + a] = psi[3 + a] + s * unit_mul<R>((R)hc.c1r, (R)hc.c1i, d1);
+  }
+  if (dag) su3_dag_mul_half<R>(u, h, uh);
+  else su3_mul_half<R>(u, h, uh);
+  // acc += coef * (uh, sgn A_mu^dag uh)
+  const R cs = s * coef;
+  const bool swq = hc.q0 != 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> e0 = swq ? uh[3 + a] : uh[a];
+    cx<R> e1 = swq ? uh[a] : uh[3 + a];
+    acc[a] = acc[a] + coef * uh[a];
+    acc[3 + a] = acc[3 + a] + coef * uh[3 + a];
+    acc[6 + a] = acc[6 + a] + cs * unit_mul<R>((R)hc.k0r, (R)hc.k0i, e0);
+    acc[9 + a] = acc[9 + a] + cs * unit_mul<R>((R)hc.k1r, (R)hc.k1i, e1);
+  }
+}
+
+// acc += scale * (hopping term at site s).  The neighbour spinor is fetched by
+// `fetch(J, inside, psi)`; with `dirichlet`, hops to sites outside the block
+// are dropped.  One direction and sign per (rolled) loop iteration.
 template <typename R, typename S, typename Fetch>
 __device__ __forceinline__ void hop_all(const GeomDev& g, const S* links, const SiteLoc& s, long long I, bool dirichlet,
-                                        Fetch fetch, cx<R>* acc) {
-  hop_mu<0, R, S>(g, links, s, I, dirichlet, fetch, acc);
-  hop_mu<1, R, S>(g, links, s, I, dirichlet, fetch, acc);
-  hop_mu<2, R, S>(g, links, s, I, dirichlet, fetch, acc);
-  hop_mu<3, R, S>(g, links, s, I, dirichlet, fetch, acc);
+                                        Fetch fetch, cx<R>* acc, R scale = (R)1) {
+#pragma unroll 1
+  for (int k = 0; k < 8; ++k) {
+    const int mu = k >> 1;
+    const int sign = (k & 1) ? -1 : +1;
+    bool wrap, inside;
+    long long J = neighbor(g, s, mu, sign, wrap, inside);
+    if (dirichlet && !inside) continue;
+    cx<R> psi[12], u[9];
+    fetch(J, inside, psi);
+    load_link<R, S>(links, g.V, mu, sign > 0 ? I : J, u);
+    HopCoef hc = hop_coef(mu);
+    hop_rt<R>(hc, sign > 0 ? -1 : +1, sign < 0, u, psi, scale * (R)(wrap ? -0.5 * g.bc_t : -0.5), acc);
+  }
 }

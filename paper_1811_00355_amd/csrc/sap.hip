@@ -17,6 +17,7 @@
 // domain; the half-lattice vectors exchanged between the even and odd phases
 // live in LDS.  Domains hold at most 256 sites.
 #include "dslash.h"
+#include "ktimer.h"
 
 namespace {
 
@@ -55,8 +56,9 @@ template <typename R, typename S, typename Tv>
 __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
                                                      const S* __restrict__ cinv, int nrhs, int colour, int mr_iters,
                                                      const Tv* __restrict__ bvec, Tv* __restrict__ xvec) {
-  __shared__ cx<R> sh_e[12][kMaxBvh];
-  __shared__ cx<R> sh_o[12][kMaxBvh];
+  __shared__ cx<R> sh_e[12][kMaxBvh];   // even-site vector exchanged with the odd phase
+  __shared__ cx<R> sh_o[12][kMaxBvh];   // odd-site vector exchanged with the even phase
+  __shared__ cx<R> sh_r[12][kMaxBvh];   // odd-site residual r_o, kept for the reconstruction
   __shared__ R red[3 * (kMaxBvh / 64 + 1)];
 
   const int r = blockIdx.x % nrhs;
@@ -81,41 +83,39 @@ __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __re
     for (int c = 0; c < 12; ++c) p[c] = sh_o[c][jj];
   };
 
-  cx<R> re[12], ro[12], rho[12], e[12], t[12], h[12];
+  cx<R> rho[12], e[12], t[12];
   SiteLoc se, so;
   if (act) {
     se = decode_site(g, Ie);
     so = decode_site(g, Io);
-    // r = b - D x on both sites of this thread
-    load_spinor<R, Tv>(x, V, Ie, t);
-    clover_mul<R, S, false>(clov, V, Ie, t, h);
-    hop_all<R, S>(g, links, se, Ie, false, fetch_x, h);
-    load_spinor<R, Tv>(b, V, Ie, re);
+    // odd site: r_o = b - D x, kept in LDS; A_oo^-1 r_o to the exchange buffer
+    load_spinor<R, Tv>(x, V, Io, e);
+    clover_mul<R, S, false>(clov, V, Io, e, t);
+    load_spinor<R, Tv>(b, V, Io, rho);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) re[c] = re[c] - h[c];
-    load_spinor<R, Tv>(x, V, Io, t);
-    clover_mul<R, S, false>(clov, V, Io, t, h);
-    hop_all<R, S>(g, links, so, Io, false, fetch_x, h);
-    load_spinor<R, Tv>(b, V, Io, ro);
+    for (int c = 0; c < 12; ++c) rho[c] = rho[c] - t[c];
+    hop_all<R, S>(g, links, so, Io, false, fetch_x, rho, (R)-1);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) ro[c] = ro[c] - h[c];
-    // A_oo^-1 r_o
-    clover_mul<R, S, false>(cinv, V, Io, ro, t);
+    for (int c = 0; c < 12; ++c) sh_r[c][j] = rho[c];
+    clover_mul<R, S, false>(cinv, V, Io, rho, t);
 #pragma unroll
     for (int c = 0; c < 12; ++c) sh_o[c][j] = t[c];
+    // even site: r_e = b - D x
+    load_spinor<R, Tv>(x, V, Ie, e);
+    clover_mul<R, S, false>(clov, V, Ie, e, t);
+    load_spinor<R, Tv>(b, V, Ie, rho);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rho[c] = rho[c] - t[c];
+    hop_all<R, S>(g, links, se, Ie, false, fetch_x, rho, (R)-1);
   }
   __syncthreads();
   if (act) {
-    // rhs_e = r_e - H_eo A_oo^-1 r_o
+    // rhs_e = r_e - H_eo A_oo^-1 r_o ; MR starts from e_e = 0 with rho = rhs_e
+    hop_all<R, S>(g, links, se, Ie, true, fetch_o, rho, (R)-1);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) h[c] = {(R)0, (R)0};
-    hop_all<R, S>(g, links, se, Ie, true, fetch_o, h);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      rho[c] = re[c] - h[c];
-      e[c] = {(R)0, (R)0};
-    }
+    for (int c = 0; c < 12; ++c) e[c] = {(R)0, (R)0};
   }
+#pragma unroll 1
   for (int k = 0; k < mr_iters; ++k) {
     if (act) {
 #pragma unroll
@@ -125,23 +125,21 @@ __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __re
     if (act) {
       // odd: u = A_oo^-1 H_oe rho
 #pragma unroll
-      for (int c = 0; c < 12; ++c) h[c] = {(R)0, (R)0};
-      hop_all<R, S>(g, links, so, Io, true, fetch_e, h);
-      clover_mul<R, S, false>(cinv, V, Io, h, t);
+      for (int c = 0; c < 12; ++c) t[c] = {(R)0, (R)0};
+      hop_all<R, S>(g, links, so, Io, true, fetch_e, t);
+      cx<R> u[12];
+      clover_mul<R, S, false>(cinv, V, Io, t, u);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sh_o[c][j] = t[c];
+      for (int c = 0; c < 12; ++c) sh_o[c][j] = u[c];
     }
     __syncthreads();
     R pr_re = 0, pr_im = 0, pp = 0;
     if (act) {
       // even: p = A_ee rho - H_eo u   (kept in t)
       clover_mul<R, S, false>(clov, V, Ie, rho, t);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) h[c] = {(R)0, (R)0};
-      hop_all<R, S>(g, links, se, Ie, true, fetch_o, h);
+      hop_all<R, S>(g, links, se, Ie, true, fetch_o, t, (R)-1);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        t[c] = t[c] - h[c];
         cx<R> q = cmul_conj(t[c], rho[c]);   // conj(p) rho
         pr_re += q.re;
         pr_im += q.im;
@@ -165,21 +163,20 @@ __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __re
   }
   __syncthreads();
   if (act) {
-    // e_o = A_oo^-1 (r_o - H_oe e_e);  x += e
+    // x_e += e_e
+    load_spinor<R, Tv>(x, V, Ie, t);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) h[c] = {(R)0, (R)0};
-    hop_all<R, S>(g, links, so, Io, true, fetch_e, h);
+    for (int c = 0; c < 12; ++c) t[c] = t[c] + e[c];
+    store_spinor<R, Tv>(x, V, Ie, t);
+    // e_o = A_oo^-1 (r_o - H_oe e_e);  x_o += e_o
 #pragma unroll
-    for (int c = 0; c < 12; ++c) ro[c] = ro[c] - h[c];
-    clover_mul<R, S, false>(cinv, V, Io, ro, t);
-    load_spinor<R, Tv>(x, V, Io, h);
+    for (int c = 0; c < 12; ++c) rho[c] = sh_r[c][j];
+    hop_all<R, S>(g, links, so, Io, true, fetch_e, rho, (R)-1);
+    clover_mul<R, S, false>(cinv, V, Io, rho, t);
+    load_spinor<R, Tv>(x, V, Io, e);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) h[c] = h[c] + t[c];
-    store_spinor<R, Tv>(x, V, Io, h);
-    load_spinor<R, Tv>(x, V, Ie, h);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) h[c] = h[c] + e[c];
-    store_spinor<R, Tv>(x, V, Ie, h);
+    for (int c = 0; c < 12; ++c) e[c] = e[c] + t[c];
+    store_spinor<R, Tv>(x, V, Io, e);
   }
 }
 
@@ -187,10 +184,17 @@ template <typename R, typename S, typename Tv>
 void run(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const void* b, void* x, hipStream_t st) {
   int threads = ((g.Bvh + 63) / 64) * 64;
   unsigned nb = (unsigned)g.Vch * nrhs;
+  // per launch (one colour = half the sites): links, clover and odd-site inverse
+  // once, b and x read and x written per RHS
+  const double half = 0.5 * (double)g.V;
+  const double bytes = half * (90.0 * sizeof(S) + 36.0 * sizeof(Tv) * nrhs);
+  const double flops = half * nrhs * (1824.0 + (mr + 2) * 1212.0);
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour)
-      k_sap_colour<R, S, Tv><<<nb, threads, 0, st>>>(g, (const S*)ops.links, (const S*)ops.clover, (const S*)ops.cinv,
-                                                      nrhs, colour, mr, (const Tv*)b, (Tv*)x);
+      DD_TIMED("k_sap_colour", st, bytes, flops,
+               (k_sap_colour<R, S, Tv><<<nb, threads, 0, st>>>(g, (const S*)ops.links, (const S*)ops.clover,
+                                                               (const S*)ops.cinv, nrhs, colour, mr, (const Tv*)b,
+                                                               (Tv*)x)));
 }
 
 }  // namespace

@@ -9,6 +9,7 @@
 // spin components 6s..6s+5.  Coarse vectors are [rhs][Vc][2n] pairs with
 // component s*n + i; coarse-operator blocks are [Vc][9][col][row] (column major).
 #include "dslash.h"
+#include "ktimer.h"
 
 namespace {
 
@@ -304,8 +305,12 @@ struct RestrictDispatch {
   static void run(const GeomDev& g, const void* P, int nrhs, const void* fine, void* out, long long rstride,
                   long long sstride, hipStream_t st) {
     int threads = g.Bv < 64 ? 64 : g.Bv;
-    k_restrict<N, R, Sp, Tv, To><<<(unsigned)g.Vc * nrhs, threads, 0, st>>>(g, (const Sp*)P, nrhs, (const Tv*)fine,
-                                                                             (To*)out, rstride, sstride);
+    // test vectors once, fine input per RHS, coarse output per RHS
+    const double bytes = (double)g.V * 12 * (N * sizeof(Sp) + nrhs * sizeof(Tv)) + (double)g.Vc * 2 * N * nrhs * sizeof(To);
+    const double flops = 8.0 * g.V * 12 * N * nrhs;
+    DD_TIMED("k_restrict", st, bytes, flops,
+             (k_restrict<N, R, Sp, Tv, To><<<(unsigned)g.Vc * nrhs, threads, 0, st>>>(g, (const Sp*)P, nrhs, (const Tv*)fine,
+                                                                                      (To*)out, rstride, sstride)));
   }
 };
 
@@ -341,8 +346,8 @@ void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const v
   }
 }
 
-void launch_prolong(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs, const void* coarse,
-                    void* fine, hipStream_t st) {
+static void prolong_dispatch(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,
+                             const void* coarse, void* fine, hipStream_t st) {
   int threads = g.Bv < 64 ? 64 : g.Bv;
   unsigned nb = (unsigned)g.Vc * nrhs;
   if (vt == DD_F64) {
@@ -368,6 +373,14 @@ void launch_prolong(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const vo
                                                               (float2*)fine);
       break;
   }
+}
+
+void launch_prolong(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs, const void* coarse,
+                    void* fine, hipStream_t st) {
+  const size_t sp = pst == DD_F64 ? 16 : (pst == DD_F32 ? 8 : 4), sv = vt == DD_F64 ? 16 : 8;
+  const double bytes = (double)g.V * 12 * (n * sp + nrhs * sv) + (double)g.Vc * 2 * n * nrhs * sv;
+  const double flops = 8.0 * g.V * 12 * n * nrhs;
+  DD_TIMED("k_prolong", st, bytes, flops, prolong_dispatch(g, vt, pst, n, P, nrhs, coarse, fine, st));
 }
 
 void launch_gram_schmidt(const GeomDev& g, int n, double2* P, int* bad_flag, hipStream_t st) {
