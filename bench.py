@@ -79,8 +79,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C3")
     ap.add_argument("--store", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--coarse-restart", type=int, default=30)
+    ap.add_argument("--coarse-restart", type=int, default=60)
     ap.add_argument("--coarse-max-iters", type=int, default=300)
+    ap.add_argument("--coarse-cgs-passes", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -107,7 +108,7 @@ def main():
     del U
     p = B.default_params(block=blk, n_vec=n_vec, setup_iters=cfg["setup_iters"], inner_dtype=B.DD_F32,
                          store_dtype=store, seed=cfg["tv_seed"], coarse_restart=args.coarse_restart,
-                         coarse_max_iters=args.coarse_max_iters)
+                         coarse_max_iters=args.coarse_max_iters, coarse_cgs_passes=args.coarse_cgs_passes)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mg = B.MG(g, p)
@@ -181,7 +182,7 @@ def main():
         "config": {"workload": f"{args.config}: {L[0]}^3x{L[3]} Wilson-clover, 12 point-source RHS batched, "
                                f"2-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
                    "lattice": list(L), "rhs": nrhs, "m0": cfg["m0"], "c_sw": cfg["c_sw"], "eps": cfg["eps"],
-                   "store_dtype": args.store, "coarse_restart": args.coarse_restart,
+                   "store_dtype": args.store, "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
                    "outer_iters_mean": round(float(outer), 2),
                    "coarse_iters_per_vcycle": round(float(coarse_per_vcycle), 1),
                    "setup_s": round(t_setup, 3),

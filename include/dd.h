@@ -98,6 +98,7 @@ typedef struct {
   dd_dtype inner_dtype;       /* DD_F64: all-FP64 preconditioner; else FP32      */
   dd_dtype store_dtype;       /* operand storage inside M (F64/F32/F16/BF16)      */
   uint64_t seed;              /* random starting vectors of dd_setup              */
+  int32_t coarse_cgs_passes;  /* classical Gram-Schmidt passes in the coarse GMRES (1 or 2) */
 } dd_mg_params;
 
 typedef struct {

@@ -9,7 +9,8 @@
   * coarse operator, Eq. (2): D_c(X,s,i; Y,t,j) = <lambda_i(X,s)| D |lambda_j(Y,t)>,
     stored per coarse site as 9 blocks of (2n)x(2n): self, +x,+y,+z,+t, -x,-y,-z,-t
   * coarse solver: even-odd preconditioned GMRES, stopped at a relative residual
-    of 5e-2 (taken on the even-site Schur system)
+    of 5e-2 (taken on the even-site Schur system); one classical Gram-Schmidt
+    pass per Arnoldi step (the loose stop needs no re-orthogonalisation)
   * smoother: multiplicative SAP over red/black domains, each domain solved by a
     fixed number of site even-odd preconditioned minimal-residual iterations
   * preconditioner, Eq. (5): M = P D_c^-1 R + S (1 - D P D_c^-1 R), post-smoothing
@@ -36,8 +37,9 @@ class MGParams:
     sap_sweeps: int = 4           # Sec. 4: N_SAP = 4
     sap_mr_iters: int = 4         # Sec. 2: fixed MR count (value is a reading)
     coarse_tol: float = 5e-2      # Sec. 2: coarse residual condition
-    coarse_restart: int = 30
+    coarse_restart: int = 60
     coarse_max_iters: int = 300
+    coarse_cgs_passes: int = 1    # classical Gram-Schmidt passes in the coarse GMRES (reading)
     coarse_fixed_iters: int = 0   # > 0: run exactly this many coarse iterations, no tolerance stop
     fgmres_restart: int = 10
     max_outer_iters: int = 200
@@ -204,7 +206,8 @@ class CoarseEO:
         fixed = p.coarse_fixed_iters
         ye, _ = gmres(self.schur, rhs, tol=0.0 if fixed else p.coarse_tol,
                       restart=p.coarse_restart,
-                      max_iters=fixed if fixed else p.coarse_max_iters)
+                      max_iters=fixed if fixed else p.coarse_max_iters,
+                      passes=p.coarse_cgs_passes)
         yo = self.oo_inv(bo - self.hop(ye))
         return ye + yo
 
@@ -220,15 +223,16 @@ def _norm(a):
     return np.sqrt(np.real(_dot(a, a)))
 
 
-def _cgs2(Vb, w):
-    """Classical Gram-Schmidt with one re-orthogonalisation; returns h (length j)."""
-    h = np.array([_dot(v, w) for v in Vb])
-    for i, v in enumerate(Vb):
-        w -= h[i] * v
-    h2 = np.array([_dot(v, w) for v in Vb])
-    for i, v in enumerate(Vb):
-        w -= h2[i] * v
-    return h + h2
+def _cgs(Vb, w, passes=2):
+    """Classical Gram-Schmidt of w against Vb, `passes` times (2: one
+    re-orthogonalisation); returns the accumulated coefficients h."""
+    h = np.zeros(len(Vb), dtype=np.complex128)
+    for _ in range(passes):
+        hp = np.array([_dot(v, w) for v in Vb])
+        for i, v in enumerate(Vb):
+            w -= hp[i] * v
+        h += hp
+    return h
 
 
 def _givens(a, b):
@@ -243,9 +247,10 @@ def _givens(a, b):
     return c, s
 
 
-def gmres(A, b, tol, restart, max_iters, x0=None):
-    """Restarted GMRES(m) with CGS2 Arnoldi and Givens rotations.  Stops when
-    the residual estimate falls to tol*|b| or after max_iters iterations."""
+def gmres(A, b, tol, restart, max_iters, x0=None, passes=2):
+    """Restarted GMRES(m) with classical Gram-Schmidt Arnoldi (`passes` passes)
+    and Givens rotations.  Stops when the residual estimate falls to tol*|b| or
+    after max_iters iterations."""
     x = np.zeros_like(b) if x0 is None else x0.copy()
     bnorm = _norm(b)
     hist = []
@@ -267,7 +272,7 @@ def gmres(A, b, tol, restart, max_iters, x0=None):
         k = 0
         for j in range(m):
             w = A(Vb[j])
-            H[:j + 1, j] = _cgs2(Vb, w)
+            H[:j + 1, j] = _cgs(Vb, w, passes)
             H[j + 1, j] = _norm(w)
             for i in range(j):
                 a, bb = H[i, j], H[i + 1, j]
@@ -318,7 +323,7 @@ def fgmres(apply_A, precond, b, tol, restart, max_outer, x0=None):
             z = precond(Vb[j])
             Z.append(z)
             w = apply_A(z)
-            H[:j + 1, j] = _cgs2(Vb, w)
+            H[:j + 1, j] = _cgs(Vb, w, 2)
             hn = _norm(w)
             H[j + 1, j] = hn
             for i in range(j):

@@ -76,7 +76,7 @@ void dd_mg_params_default(dd_mg_params* p) {
   p->init_sap_apps = 3;
   p->sap_sweeps = 4;
   p->sap_mr_iters = 4;
-  p->coarse_restart = 30;
+  p->coarse_restart = 60;
   p->coarse_max_iters = 300;
   p->coarse_fixed_iters = 0;
   p->fgmres_restart = 10;
@@ -85,6 +85,7 @@ void dd_mg_params_default(dd_mg_params* p) {
   p->inner_dtype = DD_F32;
   p->store_dtype = DD_F32;
   p->seed = 1;
+  p->coarse_cgs_passes = 1;
 }
 
 }  // extern "C"

@@ -185,14 +185,31 @@ static void norms2(Workspace* w, dd_dtype vt, int nrhs, long long count, long lo
   launch_dots(vt, vt, nrhs, count, ld, x, 1, 0, x, w->partial, nblk, out, 1, 0, st);
 }
 
-// one CGS2 orthogonalisation of w against basis V_0..V_j, then |w|^2 -> a.nrm2
-static void cgs2(Workspace* ws, Arnoldi& a, dd_dtype vt, int nrhs, long long count, long long ld, const void* V,
-                 long long vstride, int nv, void* w, hipStream_t st) {
+// classical Gram-Schmidt of w against the basis V_0..V_{nv-1}, `passes` times
+// (h1, then h2), then |w|^2 -> a.nrm2.  With nv <= 16 the passes are fused:
+// dots, then (axpy + second dots), then (axpy + norm) -- three sweeps of V.
+static void cgs(Workspace* ws, Arnoldi& a, dd_dtype vt, int nrhs, long long count, long long ld, const void* V,
+                long long vstride, int nv, void* w, int passes, hipStream_t st) {
   int nblk = dots_blocks(count, nrhs);
   launch_dots(vt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h1, a.m + 1, 0, st);
+  if (passes == 2 && nv <= 16) {
+    launch_axpy_dots(vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, nblk, a.h2, a.m + 1, st);
+    launch_axpy_norm(vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, w, ws->partial, nblk, a.nrm2, st);
+    return;
+  }
+  if (passes == 2) {
+    launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, 0, -1.0, w, st);
+    launch_dots(vt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h2, a.m + 1, 0, st);
+    launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, 0, -1.0, w, st);
+    launch_dots(vt, vt, nrhs, count, ld, w, 1, 0, w, ws->partial, nblk, a.nrm2, 1, 0, st);
+    return;
+  }
+  (void)hipMemsetAsync(a.h2, 0, sizeof(double2) * nrhs * (a.m + 1), st);
+  if (nv <= 16) {
+    launch_axpy_norm(vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, nblk, a.nrm2, st);
+    return;
+  }
   launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, 0, -1.0, w, st);
-  launch_dots(vt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h2, a.m + 1, 0, st);
-  launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, 0, -1.0, w, st);
   launch_dots(vt, vt, nrhs, count, ld, w, 1, 0, w, ws->partial, nblk, a.nrm2, 1, 0, st);
 }
 
@@ -274,7 +291,7 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
     for (int j = 0; j < mm; ++j) {
       void* Vj = CV + (size_t)j * vs * vb;
       schur_apply(c, nrhs, Vj, w->cw, w->ct1, w->ct2, st);
-      cgs2(w, a, vt, nrhs, ce, ld, CV, vs, j + 1, w->cw, st);
+      cgs(w, a, vt, nrhs, ce, ld, CV, vs, j + 1, w->cw, mg->p.coarse_cgs_passes, st);
       launch_arnoldi(nrhs, m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est,
                      a.hnext, st);
       ++iters;
@@ -283,7 +300,8 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
         break;
       }
       launch_normalize(vt, nrhs, ce, ld, w->cw, nullptr, a.hnext, a.active, CV + (size_t)(j + 1) * vs * vb, st);
-      if (count_active(w, a.active, nrhs, st) == 0) break;
+      // converged RHS are masked on the device; the host looks every few iterations
+      if ((j + 1) % 4 == 0 && count_active(w, a.active, nrhs, st) == 0) break;
     }
     launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
     launch_multi_axpy(vt, vt, nrhs, ce, ld, CV, max_kcyc(w, a, nrhs, st), vs, a.y, m, 0, 1.0, y, st);
@@ -427,6 +445,8 @@ static dd_status validate_params(dd_gauge* g, const dd_mg_params* p) {
   if (p->coarse_restart < 1 || p->coarse_restart > 256 || p->fgmres_restart < 1 || p->fgmres_restart > 64)
     return dd_fail(g->ctx, DD_EINVAL, "coarse restart must be in [1, 256], FGMRES restart in [1, 64]");
   if (p->coarse_max_iters < 1 || p->max_outer_iters < 1) return dd_fail(g->ctx, DD_EINVAL, "iteration caps must be >= 1");
+  if (p->coarse_cgs_passes != 1 && p->coarse_cgs_passes != 2)
+    return dd_fail(g->ctx, DD_EINVAL, "coarse_cgs_passes must be 1 or 2");
   if (p->inner_dtype != DD_F64 && p->inner_dtype != DD_F32)
     return dd_fail(g->ctx, DD_EINVAL, "inner_dtype must be DD_F64 or DD_F32");
   if ((int)p->store_dtype < 0 || (int)p->store_dtype > 3) return dd_fail(g->ctx, DD_EINVAL, "unknown store_dtype");
@@ -715,7 +735,7 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
         launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->zt64, w->w64, st);
       }
       total_coarse += ci;
-      cgs2(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, st);
+      cgs(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, 2, st);
       launch_arnoldi(nrhs, m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est, a.hnext,
                      st);
       ++outer;

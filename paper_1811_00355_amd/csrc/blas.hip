@@ -103,6 +103,66 @@ __global__ void __launch_bounds__(256) k_multi_axpy(int nrhs, long long count, l
   }
 }
 
+// Fused CGS pieces for one sweep of the basis: w <- w - sum_i c_i V_i with the
+// V_i kept in registers, then either the inner products <V_i, w> (NORM = false)
+// or |w|^2 (NORM = true) of the updated w, reduced like k_dots.
+template <typename Tv, bool NORM>
+__global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
+                                                   int nv, long long vstride, const double2* __restrict__ coef, int ldc,
+                                                   Tv* __restrict__ w, double* __restrict__ partial, int nblk) {
+  __shared__ double red[4][2 * kMaxNv];
+  __shared__ cx<double> c[kMaxNv];
+  const int r = blockIdx.y, blk = blockIdx.x;
+  if (threadIdx.x < nv) {
+    double2 v = coef[(long long)r * ldc + threadIdx.x];
+    c[threadIdx.x] = {v.x, v.y};
+  }
+  __syncthreads();
+  long long chunk = (count + nblk - 1) / nblk;
+  long long e0 = (long long)blk * chunk, e1 = e0 + chunk < count ? e0 + chunk : count;
+  cx<double> acc[kMaxNv];
+#pragma unroll
+  for (int i = 0; i < kMaxNv; ++i) acc[i] = {0.0, 0.0};
+  Tv* wr = w + (long long)r * rs;
+  const Tv* vr = V + (long long)r * rs;
+  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    cx<double> x = ld<double, Tv>(wr + e);
+    cx<double> v[kMaxNv];
+#pragma unroll
+    for (int i = 0; i < kMaxNv; ++i)
+      if (i < nv) {
+        v[i] = ld<double, Tv>(vr + (long long)i * vstride + e);
+        x = x - c[i] * v[i];
+      }
+    st<Tv, double>(wr + e, x);
+    if (NORM) {
+      acc[0].re += x.re * x.re + x.im * x.im;
+    } else {
+#pragma unroll
+      for (int i = 0; i < kMaxNv; ++i)
+        if (i < nv) cfma_conj(acc[i], v[i], x);
+    }
+  }
+  const int nout = NORM ? 1 : nv;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < kMaxNv; ++i) {
+    if (i < nout) {
+      double a = wave_sum(acc[i].re), b = wave_sum(acc[i].im);
+      if (lane == 0) {
+        red[wv][2 * i] = a;
+        red[wv][2 * i + 1] = b;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * nout) {
+    double s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    int i = threadIdx.x >> 1, cc = threadIdx.x & 1;
+    partial[(((long long)r * nout + i) * nblk + blk) * 2 + cc] = s;
+  }
+}
+
 // dst[r] = src[r] / sqrt(nrm[r].x) where mask[r] != 0 (mask may be null); zero norm gives zero
 template <typename Tv>
 __global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, long long rs, const Tv* __restrict__ src,
@@ -306,6 +366,35 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
                                                           coff + i0, sign, (float2*)w);
     if (timed) ktimer_end("k_multi_axpy", st, bytes, flops);
   }
+}
+
+void launch_axpy_dots(dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv, long long vstride,
+                      const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, int ldo,
+                      hipStream_t st) {
+  dim3 grid(nblk, nrhs);
+  const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
+  const double bytes = (double)nrhs * count * (nv + 2) * es, flops = 16.0 * nrhs * count * nv;
+  DD_TIMED("k_axpy_dots", st, bytes, flops,
+           (vt == DD_F64
+                ? k_axpy_dots<double2, false><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,
+                                                                   coef, ldc, (double2*)w, partial, nblk)
+                : k_axpy_dots<float2, false><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,
+                                                                  coef, ldc, (float2*)w, partial, nblk)));
+  k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0);
+}
+
+void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv, long long vstride,
+                      const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, hipStream_t st) {
+  dim3 grid(nblk, nrhs);
+  const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
+  const double bytes = (double)nrhs * count * (nv + 2) * es, flops = 8.0 * nrhs * count * (nv + 1);
+  DD_TIMED("k_axpy_norm", st, bytes, flops,
+           (vt == DD_F64
+                ? k_axpy_dots<double2, true><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,
+                                                                  coef, ldc, (double2*)w, partial, nblk)
+                : k_axpy_dots<float2, true><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,
+                                                                 coef, ldc, (float2*)w, partial, nblk)));
+  k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0);
 }
 
 void launch_normalize(dd_dtype vt, int nrhs, long long count, long long rs, const void* src, const double2* nrm2,

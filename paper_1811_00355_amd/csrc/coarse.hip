@@ -79,6 +79,99 @@ __global__ void __launch_bounds__(64 * kSitesPerWG) k_coarse_mv(GeomDev g, int n
   }
 }
 
+// FP32 matrix-core form.  For one coarse site and one direction the stencil
+// term is a complex GEMM Y (2n x NRHS) += B (2n x 2n) X (2n x NRHS).  With
+// B = Br + i Bi, X = Xr + i Xi it is computed as four real 16x16x4 MFMA
+// products per (16-row tile, 4-deep k step): tile C0 collects Y_r = Br Xr - Bi Xi
+// and tile C1 collects Y_i = Br Xi + Bi Xr, with the right-hand side as the
+// column index of both tiles, so each lane ends with the real and imaginary
+// part of the same (row, rhs).  Lane layout of v_mfma_f32_16x16x4f32: A[i][k]
+// at lane i + 16k, B[k][j] at lane j + 16k, D[i][j] at lane j + 16(i/4), value
+// i % 4.  One wave per site, up to 16 right-hand sides per pass, 2n <= 48.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaMaxNc = 48;
+
+__global__ void __launch_bounds__(64 * kSitesPerWG) k_coarse_mfma(GeomDev g, int nc, const float2* __restrict__ Dc,
+                                                                const float2* __restrict__ Minv, int use_inv,
+                                                                int nrhs, int site_begin, int count, float a_self,
+                                                                const float2* __restrict__ xs, float a_hop,
+                                                                const float2* __restrict__ xh, float beta,
+                                                                const float2* __restrict__ z, float2* __restrict__ out) {
+  __shared__ float2 xsh[kSitesPerWG][kMfmaMaxNc][16];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int local = blockIdx.x * kSitesPerWG + w;
+  const bool site_ok = local < count;
+  const int X = site_begin + (site_ok ? local : 0);
+  const long long vstride = (long long)g.Vc * nc;
+  const bool has_self = a_self != 0.f, has_hop = a_hop != 0.f;
+  const int mtiles = (nc + 15) / 16, ksteps = nc / 4;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
+    f32x4 c0[3], c1[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) c0[t] = c1[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int d = has_self ? 0 : 1; d < (has_hop ? 9 : 1); ++d) {
+      const int Y = d == 0 ? X : (g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK);
+      const float2* src = d == 0 ? xs : xh;
+      const float sc = d == 0 ? a_self : a_hop;
+      __syncthreads();
+      // stage sc * x(Y) as [col][rhs], zero padded to 16 right-hand sides
+      for (int e = lane; e < nc * 16; e += 64) {
+        int col = e >> 4, r = e & 15;
+        float2 v = make_float2(0.f, 0.f);
+        if (site_ok && r < nr) {
+          v = src[(long long)(r0 + r) * vstride + (long long)Y * nc + col];
+          v.x *= sc;
+          v.y *= sc;
+        }
+        xsh[w][col][r] = v;
+      }
+      __syncthreads();
+      if (site_ok) {
+        const float2* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * nc * nc : Dc + (long long)X * 9 * nc * nc)
+                                 : Dc + ((long long)X * 9 + d) * nc * nc;
+        for (int ks = 0; ks < ksteps; ++ks) {
+          const int col = 4 * ks + lk;
+          const float2 xb = xsh[w][col][li];
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            if (t < mtiles) {
+              const int row = 16 * t + li;
+              const float2 m = row < nc ? B[(long long)col * nc + row] : make_float2(0.f, 0.f);
+              c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.x, xb.x, c0[t], 0, 0, 0);
+              c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.y, -xb.y, c0[t], 0, 0, 0);
+              c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.x, xb.y, c1[t], 0, 0, 0);
+              c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.y, xb.x, c1[t], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    if (site_ok && li < nr) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (t < mtiles) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * t + 4 * lk + v;
+            if (row < nc) {
+              long long oi = (long long)(r0 + li) * vstride + (long long)X * nc + row;
+              float2 o = make_float2(c0[t][v], c1[t][v]);
+              if (beta != 0.f) {
+                float2 zz = z[oi];
+                o.x += beta * zz.x;
+                o.y += beta * zz.y;
+              }
+              out[oi] = o;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 template <typename R, typename Sd, typename Tv>
 void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv, int nrhs, int site_begin, int count,
         double a_self, const void* xs, double a_hop, const void* xh, double beta, const void* z, void* out,
@@ -95,7 +188,12 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
            (k_coarse_mv<R, Sd, Tv, NRV><<<nb, blk, 0, st>>>(g, nc, (const Sd*)Dc, (const Sd*)Minv, use_inv, nrhs,   \
                                                              site_begin, count, (R)a_self, (const Tv*)xs, (R)a_hop, \
                                                              (const Tv*)xh, (R)beta, (const Tv*)z, (Tv*)out)))
-  if (nrhs == 1) DD_MV(1);
+  if (sizeof(R) == 4 && nc <= kMfmaMaxNc) {
+    DD_TIMED("k_coarse_mfma", st, bytes, flops,
+             (k_coarse_mfma<<<nb, blk, 0, st>>>(g, nc, (const float2*)Dc, (const float2*)Minv, use_inv, nrhs, site_begin,
+                                                count, (float)a_self, (const float2*)xs, (float)a_hop, (const float2*)xh,
+                                                (float)beta, (const float2*)z, (float2*)out)));
+  } else if (nrhs == 1) DD_MV(1);
   else if (nrhs <= 4) DD_MV(4);
   else DD_MV(12);
 #undef DD_MV

@@ -226,6 +226,19 @@ __host__ __device__ __forceinline__ long long neighbor(const GeomDev& g, const S
   return ((long long)slot << g.lBv) + encode_local(g, l);
 }
 
+// XCD-aware work mapping.  Consecutive workgroups are dealt round-robin to the
+// eight XCDs, each with its own L2.  Workgroups that handle the same tile for
+// different right-hand sides share the tile's operator, so they are given the
+// same XCD: workgroup b runs on XCD b % 8 and takes tile (b % 8) + 8 * (k / nrhs),
+// rhs k % nrhs, with k = b / 8.  Launch xcd_grid(ntiles, nrhs) workgroups and
+// skip tiles >= ntiles.
+__device__ __forceinline__ void xcd_tile_rhs(int nrhs, int& tile, int& rhs) {
+  const int b = blockIdx.x, x = b & 7, k = b >> 3;
+  tile = x + 8 * (k / nrhs);
+  rhs = k % nrhs;
+}
+inline unsigned xcd_grid(long long ntiles, int nrhs) { return (unsigned)(8 * ((ntiles + 7) / 8) * nrhs); }
+
 // lexicographic site index of a packed site
 __host__ __device__ __forceinline__ long long lex_site(const GeomDev& g, const SiteLoc& s) {
   int bc = g.blk_coord[s.slot];
@@ -358,6 +371,13 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
 void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long ld, const void* V, int nv,
                        long long vstride, const double2* coef, int ldc, int coff, double sign, void* w,
                        hipStream_t st);
+// w -= sum_i coef_i V_i, then out = <V_i, w> (fused, nv <= 16)
+void launch_axpy_dots(dd_dtype vt, int nrhs, long long count, long long ld, const void* V, int nv, long long vstride,
+                      const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, int ldo,
+                      hipStream_t st);
+// w -= sum_i coef_i V_i, then out[r].x = |w|^2 (fused, nv <= 16)
+void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long ld, const void* V, int nv, long long vstride,
+                      const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, hipStream_t st);
 void launch_normalize(dd_dtype vt, int nrhs, long long count, long long ld, const void* src, const double2* nrm2,
                       const double* nrm, const int* mask, void* dst, hipStream_t st);
 void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st);

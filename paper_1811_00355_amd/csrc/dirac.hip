@@ -1,7 +1,7 @@
 // Wilson-clover operator apply: out = A psi + hopping term (Sec. 3), one
-// thread per (site, right-hand side).  The workgroup index runs over the RHS
-// fastest, so the workgroups that share a tile of sites (and its links and
-// clover) are resident together and the operator is fetched from HBM once.
+// thread per (site, right-hand side).  The workgroups of one tile of sites
+// (all right-hand sides) run on the same XCD back to back, so the tile's links
+// and clover come from that XCD's L2 after the first fetch.
 #include "dslash.h"
 #include "ktimer.h"
 
@@ -10,8 +10,9 @@ namespace {
 template <typename R, typename S, typename Tv>
 __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
                                                int nrhs, const Tv* __restrict__ in, Tv* __restrict__ out) {
-  int r = blockIdx.x % nrhs;
-  long long I = (long long)(blockIdx.x / nrhs) * blockDim.x + threadIdx.x;
+  int tile, r;
+  xcd_tile_rhs(nrhs, tile, r);
+  long long I = (long long)tile * blockDim.x + threadIdx.x;
   if (I >= g.V) return;
   const Tv* x = in + (long long)r * 12 * g.V;
   SiteLoc s = decode_site(g, I);
@@ -27,7 +28,7 @@ __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ 
 
 static void dirac_dispatch(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
                            hipStream_t st) {
-  unsigned nb = (unsigned)((g.V + 255) / 256) * nrhs;
+  unsigned nb = xcd_grid((g.V + 255) / 256, nrhs);
   switch (dt) {
     case DD_F64:
       k_dirac<double, double2, double2><<<nb, 256, 0, st>>>(g, (const double2*)ops.links, (const double2*)ops.clover,

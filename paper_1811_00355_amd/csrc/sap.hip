@@ -61,8 +61,10 @@ __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __re
   __shared__ cx<R> sh_r[12][kMaxBvh];   // odd-site residual r_o, kept for the reconstruction
   __shared__ R red[3 * (kMaxBvh / 64 + 1)];
 
-  const int r = blockIdx.x % nrhs;
-  const int slot = colour * g.Vch + blockIdx.x / nrhs;
+  int tile, r;
+  xcd_tile_rhs(nrhs, tile, r);
+  if (tile >= g.Vch) return;
+  const int slot = colour * g.Vch + tile;
   const int j = threadIdx.x;
   const bool act = j < g.Bvh;
   const long long V = g.V;
@@ -183,7 +185,7 @@ __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __re
 template <typename R, typename S, typename Tv>
 void run(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const void* b, void* x, hipStream_t st) {
   int threads = ((g.Bvh + 63) / 64) * 64;
-  unsigned nb = (unsigned)g.Vch * nrhs;
+  unsigned nb = xcd_grid(g.Vch, nrhs);
   // per launch (one colour = half the sites): links, clover and odd-site inverse
   // once, b and x read and x written per RHS
   const double half = 0.5 * (double)g.V;

@@ -27,8 +27,9 @@ template <int N, typename R, typename Sp, typename Tv, typename To>
 __global__ void __launch_bounds__(256) k_restrict(GeomDev g, const Sp* __restrict__ P, int nrhs, const Tv* __restrict__ fine,
                                                   To* __restrict__ out, long long rstride, long long sstride) {
   __shared__ R red[4][4 * N];
-  const int r = blockIdx.x % nrhs;
-  const int slot = blockIdx.x / nrhs;
+  int slot, r;
+  xcd_tile_rhs(nrhs, slot, r);
+  if (slot >= g.Vc) return;
   const int j = threadIdx.x;
   const long long V = g.V;
   cx<R> d[2 * N];
@@ -76,8 +77,9 @@ template <typename R, typename Sp, typename Tv>
 __global__ void __launch_bounds__(256) k_prolong(GeomDev g, int n, const Sp* __restrict__ P, int nrhs,
                                                  const Tv* __restrict__ coarse, Tv* __restrict__ fine) {
   __shared__ cx<R> c[128];
-  const int r = blockIdx.x % nrhs;
-  const int slot = blockIdx.x / nrhs;
+  int slot, r;
+  xcd_tile_rhs(nrhs, slot, r);
+  if (slot >= g.Vc) return;
   const int j = threadIdx.x;
   const int nc = 2 * n;
   const long long V = g.V;
@@ -204,9 +206,10 @@ template <typename R, typename S, typename Sp>
 __global__ void __launch_bounds__(256) k_coarse_piece(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
                                                       const Sp* __restrict__ P, int n, int col0, int ncol, int d,
                                                       double2* __restrict__ W) {
-  const int cl = blockIdx.x % ncol;
+  int tile, cl;
+  xcd_tile_rhs(ncol, tile, cl);
   const int col = col0 + cl;
-  const long long I = (long long)(blockIdx.x / ncol) * blockDim.x + threadIdx.x;
+  const long long I = (long long)tile * blockDim.x + threadIdx.x;
   if (I >= g.V) return;
   const int t = col / n, jv = col % n;
   SiteLoc s = decode_site(g, I);
@@ -309,7 +312,7 @@ struct RestrictDispatch {
     const double bytes = (double)g.V * 12 * (N * sizeof(Sp) + nrhs * sizeof(Tv)) + (double)g.Vc * 2 * N * nrhs * sizeof(To);
     const double flops = 8.0 * g.V * 12 * N * nrhs;
     DD_TIMED("k_restrict", st, bytes, flops,
-             (k_restrict<N, R, Sp, Tv, To><<<(unsigned)g.Vc * nrhs, threads, 0, st>>>(g, (const Sp*)P, nrhs, (const Tv*)fine,
+             (k_restrict<N, R, Sp, Tv, To><<<xcd_grid(g.Vc, nrhs), threads, 0, st>>>(g, (const Sp*)P, nrhs, (const Tv*)fine,
                                                                                       (To*)out, rstride, sstride)));
   }
 };
@@ -349,7 +352,7 @@ void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const v
 static void prolong_dispatch(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,
                              const void* coarse, void* fine, hipStream_t st) {
   int threads = g.Bv < 64 ? 64 : g.Bv;
-  unsigned nb = (unsigned)g.Vc * nrhs;
+  unsigned nb = xcd_grid(g.Vc, nrhs);
   if (vt == DD_F64) {
     k_prolong<double, double2, double2><<<nb, threads, 0, st>>>(g, n, (const double2*)P, nrhs, (const double2*)coarse,
                                                                (double2*)fine);
@@ -398,7 +401,7 @@ void launch_coarse_build(const GeomDev& g, const OpSet& ops64, dd_dtype pst, int
   for (int d = 0; d < 9; ++d)
     for (int c0 = 0; c0 < nc; c0 += chunk) {
       int ncol = nc - c0 < chunk ? nc - c0 : chunk;
-      unsigned nb = (unsigned)((g.V + 255) / 256) * ncol;
+      unsigned nb = xcd_grid((g.V + 255) / 256, ncol);
       switch (pst) {
         case DD_F64:
           k_coarse_piece<double, double2, double2><<<nb, 256, 0, st>>>(g, L, C, (const double2*)P, n, c0, ncol, d, W);

@@ -212,3 +212,42 @@ def test_solve_true_residual(ctx, name, inner, store):
               f"relres(lib) {info[r]['true_relres']:.2e} relres(oracle D) {res:.2e}", flush=True)
         assert info[r]["converged"] and res <= 1e-10
     _close(d)
+
+
+@pytest.mark.parametrize("nrhs", [1, 12, 20])
+def test_coarse_apply_f32_batches(ctx, nrhs):
+    """FP32 coarse stencil (matrix-core path) over right-hand-side batches that
+    fill one, one padded and two 16-wide passes, against the oracle on the
+    FP32-rounded operator and inputs."""
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_vectors
+    d = _build(ctx, "b4")
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    Dr = _gpu.round_f32(amg.coarse_operator(d["W"], amg.gram_schmidt(lat, d["tv0"])))
+    c = _gpu.round_f32(gauss_vectors(nrhs, lat.Vc, 71, ncomp=2 * n))
+    got = _coarse_roundtrip(mg, 1, nrhs, c, lambda i, o: mg.dd_coarse_apply(1, nrhs, i, o))
+    errs = [_gpu.max_rel(got[r], amg.coarse_apply(lat, Dr, c[r])) for r in range(nrhs)]
+    print(f"FP32 coarse apply, {nrhs} rhs: max error {max(errs):.2e}", flush=True)
+    assert max(errs) < 1e-5
+    _close(d)
+
+
+def test_coarse_solve_f32_fixed_iterations(ctx):
+    """FP32 even-odd coarse GMRES (matrix-core stencil), fixed iteration count,
+    12 right-hand sides, against the oracle on the FP32-rounded operator."""
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_vectors
+    d = _build(ctx, "b4", coarse_fixed_iters=10, coarse_restart=10)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    Dr = _gpu.round_f32(amg.coarse_operator(d["W"], amg.gram_schmidt(lat, d["tv0"])))
+    ceo = amg.CoarseEO(lat, Dr)
+    op = amg.MGParams(n_vec=n, coarse_fixed_iters=10, coarse_restart=10)
+    nrhs = 12
+    b = _gpu.round_f32(gauss_vectors(nrhs, lat.Vc, 72, ncomp=2 * n))
+    got = _coarse_roundtrip(mg, 1, nrhs, b, lambda i, o: mg.dd_coarse_solve(1, nrhs, i, o))
+    errs = [_gpu.max_rel(got[r], ceo.solve(b[r], op)) for r in range(nrhs)]
+    print(f"FP32 coarse solve, 12 rhs: max error {max(errs):.2e}", flush=True)
+    assert max(errs) < 1e-4
+    _close(d)
