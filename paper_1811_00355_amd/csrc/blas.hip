@@ -301,12 +301,13 @@ inline unsigned grid1(long long n) {
 
 }  // namespace
 
-int dots_blocks(long long count, int nrhs) {
+// Workgroups per right-hand side for the two-stage reductions.  It depends on
+// the vector length only, never on the number of right-hand sides, so the
+// summation order of every RHS is the same alone and in a batch.
+int dots_blocks(long long count, int /*nrhs*/) {
   long long per = 2048;    // entries per workgroup, at least
   long long nb = (count + per - 1) / per;
-  int cap = 4096 / (nrhs > 0 ? nrhs : 1);
-  if (cap < 8) cap = 8;
-  if (nb > cap) nb = cap;
+  if (nb > 512) nb = 512;
   if (nb < 1) nb = 1;
   return (int)nb;
 }
