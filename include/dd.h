@@ -126,6 +126,11 @@ void dd_mg_params_default(dd_mg_params* p);
 dd_status dd_gauge_create(dd_ctx* ctx, const dd_problem* prob, const double* links_host,
                           dd_gauge** out);
 dd_status dd_gauge_destroy(dd_gauge* g);   /* DD_ESTATE while a dd_mg references it */
+/* New bare mass m0 (kappa = 1/(8 + 2 m0)) on the same links: rebuilds the
+ * clover term and its inverse and refreshes the storage copies.  DD_ESTATE
+ * while a dd_mg references g (use dd_setup_update_mass), DD_EINVAL for a
+ * non-finite m0. */
+dd_status dd_gauge_set_mass(dd_gauge* g, double m0);
 
 /* ---- vectors ------------------------------------------------------------------ */
 size_t dd_fine_vec_bytes(const dd_gauge* g, dd_dtype dt, int nrhs);
@@ -162,6 +167,13 @@ dd_status dd_setup(dd_gauge* g, const dd_mg_params* p, dd_mg** out);
 dd_status dd_setup_from_vectors(dd_gauge* g, const dd_mg_params* p, const double* tv_host,
                                 dd_mg** out);
 dd_status dd_mg_destroy(dd_mg* mg);
+/* "New kappa" (Sec. 4, strange-quark solves): switch the setup to bare mass m0
+ * while keeping its test vectors.  Rebuilds the clover term and inverse of the
+ * gauge field, then P (same vectors, so the same P), D_c = P^dag D P and the
+ * coarse odd-site inverses for the new operator; no adaptive iterations are
+ * run.  DD_ESTATE when another dd_mg shares the gauge field; DD_EINVAL for a
+ * singular coarse block or non-finite m0. */
+dd_status dd_setup_update_mass(dd_mg* mg, double m0);
 
 /* ---- transfer and coarse operator -------------------------------------------------------
  * DD_F64 or DD_F32 (coarse data in that precision). */

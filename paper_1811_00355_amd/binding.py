@@ -65,6 +65,7 @@ SIGNATURES = {
     "dd_mg_params_default": (None, [ctypes.POINTER(dd_mg_params)]),
     "dd_gauge_create": (_I, [_P, ctypes.POINTER(dd_problem), _P, ctypes.POINTER(_P)]),
     "dd_gauge_destroy": (_I, [_P]),
+    "dd_gauge_set_mass": (_I, [_P, ctypes.c_double]),
     "dd_fine_vec_bytes": (_S, [_P, _I, _I]),
     "dd_coarse_vec_bytes": (_S, [_P, _I, _I]),
     "dd_pack_fine": (_I, [_P, _I, _I, _P, _P, _P]),
@@ -76,6 +77,7 @@ SIGNATURES = {
     "dd_setup": (_I, [_P, ctypes.POINTER(dd_mg_params), ctypes.POINTER(_P)]),
     "dd_setup_from_vectors": (_I, [_P, ctypes.POINTER(dd_mg_params), _P, ctypes.POINTER(_P)]),
     "dd_mg_destroy": (_I, [_P]),
+    "dd_setup_update_mass": (_I, [_P, ctypes.c_double]),
     "dd_restrict": (_I, [_P, _I, _I, _P, _P, _P]),
     "dd_prolong": (_I, [_P, _I, _I, _P, _P, _P]),
     "dd_coarse_apply": (_I, [_P, _I, _I, _P, _P, _P]),
@@ -204,6 +206,9 @@ class Gauge:
             self.ctx.check(self.ctx.lib.dd_gauge_destroy(self.h))
             self.h = _P()
 
+    def dd_gauge_set_mass(self, m0):
+        self.ctx.check(self.ctx.lib.dd_gauge_set_mass(self.h, m0))
+
     # vectors ---------------------------------------------------------------------------
     def fine_vec_bytes(self, dtype, nrhs):
         return self.ctx.lib.dd_fine_vec_bytes(self.h, dtype, nrhs)
@@ -273,6 +278,9 @@ class MG:
         if self.h:
             self.ctx.check(self.ctx.lib.dd_mg_destroy(self.h))
             self.h = _P()
+
+    def dd_setup_update_mass(self, m0):
+        self.ctx.check(self.ctx.lib.dd_setup_update_mass(self.h, m0))
 
     def coarse_vec_bytes(self, dtype, nrhs):
         return self.ctx.lib.dd_coarse_vec_bytes(self.h, dtype, nrhs)

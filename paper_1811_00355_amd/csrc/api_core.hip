@@ -200,6 +200,26 @@ dd_status ensure_opset(dd_gauge* g, dd_dtype dt) {
   return DD_OK;
 }
 
+// New bare mass on the same links: the clover term's diagonal is 4 + m0, so the
+// FP64 clover and its inverse are rebuilt and every storage copy that exists is
+// converted again (links are unchanged).
+dd_status gauge_set_mass(dd_gauge* g, double m0) {
+  OpSet& m = g->ops[DD_F64];
+  g->prob.m0 = m0;
+  launch_clover_build(g->geo, (const double2*)m.links, m0, g->prob.c_sw, (double2*)m.clover, (double2*)m.cinv, 0);
+  const long long n = 36LL * g->geo.V;
+  const dd_dtype order[3] = {DD_F32, DD_F16, DD_BF16};   // half copies are rounded from the FP32 copy
+  for (dd_dtype dt : order) {
+    OpSet& o = g->ops[dt];
+    if (!o.ready) continue;
+    const OpSet& f = g->ops[DD_F32];
+    launch_convert_pairs(dt, (const double2*)m.clover, (const float2*)f.clover, o.clover, n, 0);
+    launch_convert_pairs(dt, (const double2*)m.cinv, (const float2*)f.cinv, o.cinv, n, 0);
+  }
+  DD_HIP(g->ctx, hipDeviceSynchronize());
+  return DD_OK;
+}
+
 static dd_status check_dtype(dd_ctx* ctx, dd_dtype dt) {
   if ((int)dt < 0 || (int)dt > 3) return dd_fail(ctx, DD_EINVAL, "unknown dtype");
   return DD_OK;
@@ -243,6 +263,15 @@ dd_status dd_gauge_create(dd_ctx* ctx, const dd_problem* prob, const double* lin
   m.ready = true;
   *out = g;
   return DD_OK;
+}
+
+dd_status dd_gauge_set_mass(dd_gauge* g, double m0) {
+  if (!g) return DD_EINVAL;
+  if (!std::isfinite(m0)) return dd_fail(g->ctx, DD_EINVAL, "non-finite mass");
+  if (g->refcount > 0)
+    return dd_fail(g->ctx, DD_ESTATE, "gauge field is referenced by a multigrid setup; use dd_setup_update_mass");
+  DD_HIP(g->ctx, hipSetDevice(g->ctx->device));
+  return gauge_set_mass(g, m0);
 }
 
 dd_status dd_gauge_destroy(dd_gauge* g) {

@@ -546,6 +546,17 @@ dd_status dd_setup_from_vectors(dd_gauge* g, const dd_mg_params* p, const double
   return setup_common(g, p, tv_host, out);
 }
 
+dd_status dd_setup_update_mass(dd_mg* mg, double m0) {
+  if (!mg) return DD_EINVAL;
+  if (!std::isfinite(m0)) return dd_fail(mg->ctx, DD_EINVAL, "non-finite mass");
+  if (mg->g->refcount != 1)
+    return dd_fail(mg->ctx, DD_ESTATE, "another multigrid setup references this gauge field");
+  DD_HIP(mg->ctx, hipSetDevice(mg->ctx->device));
+  dd_status s = gauge_set_mass(mg->g, m0);
+  if (s) return s;
+  return build(mg, 0);
+}
+
 dd_status dd_mg_destroy(dd_mg* mg) {
   if (!mg) return DD_EINVAL;
   (void)hipDeviceSynchronize();

@@ -391,3 +391,4 @@ void launch_lsq(int nrhs, int m, const double2* H, const double2* gv, const int*
                 hipStream_t st);
 
 dd_status ensure_opset(dd_gauge* g, dd_dtype dt);
+dd_status gauge_set_mass(dd_gauge* g, double m0);
