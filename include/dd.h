@@ -167,6 +167,14 @@ dd_status dd_setup(dd_gauge* g, const dd_mg_params* p, dd_mg** out);
 dd_status dd_setup_from_vectors(dd_gauge* g, const dd_mg_params* p, const double* tv_host,
                                 dd_mg** out);
 dd_status dd_mg_destroy(dd_mg* mg);
+/* Replay the coarse even-odd GMRES from captured HIP graphs (enable != 0) or
+ * launch its kernels one by one (0, the default).  Between two host
+ * convergence checks the solver runs four Arnoldi steps; each such chunk is
+ * captured once per (nrhs, dtype, position in the restart cycle) and then
+ * replayed.  Same kernels in the same order, so the results are bit-identical
+ * either way.  Graphs hold workspace addresses and are dropped when the
+ * workspace is reallocated.  Kernel timers do not see launches inside graphs. */
+dd_status dd_mg_set_graphs(dd_mg* mg, int enable);
 /* "New kappa" (Sec. 4, strange-quark solves): switch the setup to bare mass m0
  * while keeping its test vectors.  Rebuilds the clover term and inverse of the
  * gauge field, then P (same vectors, so the same P), D_c = P^dag D P and the

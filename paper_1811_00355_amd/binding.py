@@ -78,6 +78,7 @@ SIGNATURES = {
     "dd_setup_from_vectors": (_I, [_P, ctypes.POINTER(dd_mg_params), _P, ctypes.POINTER(_P)]),
     "dd_mg_destroy": (_I, [_P]),
     "dd_setup_update_mass": (_I, [_P, ctypes.c_double]),
+    "dd_mg_set_graphs": (_I, [_P, _I]),
     "dd_restrict": (_I, [_P, _I, _I, _P, _P, _P]),
     "dd_prolong": (_I, [_P, _I, _I, _P, _P, _P]),
     "dd_coarse_apply": (_I, [_P, _I, _I, _P, _P, _P]),
@@ -278,6 +279,9 @@ class MG:
         if self.h:
             self.ctx.check(self.ctx.lib.dd_mg_destroy(self.h))
             self.h = _P()
+
+    def dd_mg_set_graphs(self, enable):
+        self.ctx.check(self.ctx.lib.dd_mg_set_graphs(self.h, int(bool(enable))))
 
     def dd_setup_update_mass(self, m0):
         self.ctx.check(self.ctx.lib.dd_setup_update_mass(self.h, m0))

@@ -2,11 +2,14 @@
 // operator, the even-odd coarse GMRES, the preconditioner M of Eq. (5) and the
 // flexible GMRES outer solver.  Host code here only sequences kernels and
 // reads per-RHS convergence flags; all arithmetic runs on the device.
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 #include "dd_internal.h"
+#include "ktimer.h"
 
 void launch_coarse_perm(const GeomDev& g, dd_dtype vt, int nc, int nrhs, int to_packed, const void* src, void* dst,
                         hipStream_t st);
@@ -69,6 +72,10 @@ struct Workspace {
   double* partial;
   int* hflags = nullptr;   // pinned host mirror: active[nrhs], kcyc[nrhs]
   double* hvals = nullptr; // pinned host mirror: est[nrhs], tolabs[nrhs], nrm[nrhs]
+  // captured coarse GMRES chunks, keyed by (nrhs, dtype, first iteration, length, ends cycle);
+  // they hold this arena's addresses and die with it
+  hipStream_t cap = nullptr;
+  std::map<std::array<int, 5>, hipGraphExec_t> graphs;
 };
 
 static dd_dtype inner_vt(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : DD_F32; }
@@ -118,6 +125,8 @@ static void free_ws(dd_mg* mg) {
   dd_free(mg->ctx, w->arena.base, w->arena.cap);
   if (w->hflags) (void)hipHostFree(w->hflags);
   if (w->hvals) (void)hipHostFree(w->hvals);
+  for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (w->cap) (void)hipStreamDestroy(w->cap);
   delete w;
   mg->ws = nullptr;
 }
@@ -204,7 +213,7 @@ static void cgs(Workspace* ws, Arnoldi& a, dd_dtype vt, int nrhs, long long coun
     launch_dots(vt, vt, nrhs, count, ld, w, 1, 0, w, ws->partial, nblk, a.nrm2, 1, 0, st);
     return;
   }
-  (void)hipMemsetAsync(a.h2, 0, sizeof(double2) * nrhs * (a.m + 1), st);
+  launch_zero(a.h2, sizeof(double2) * nrhs * (a.m + 1), st);
   if (nv <= 16) {
     launch_axpy_norm(vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, nblk, a.nrm2, st);
     return;
@@ -239,6 +248,53 @@ static void schur_apply(const CoarseOps& c, int nrhs, const void* v, void* out, 
   launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, 1.0, v, 0.0, nullptr, t1, st);
   launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, t1, 0.0, nullptr, 0.0, nullptr, t2, st);
   launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 1.0, v, -1.0, t2, 0.0, nullptr, out, st);
+}
+
+// Arnoldi steps j0 .. j0+len-1 of one coarse GMRES cycle: w = S v_j, Gram-Schmidt,
+// Givens update, v_{j+1} = w / |w| (not after the cycle's last step).  Launches
+// only, no host synchronisation, so the sequence can be captured as a graph.
+static void issue_chunk(const CoarseOps& c, Workspace* w, Arnoldi& a, int passes, int nrhs, long long ce,
+                        long long ld, long long vs, size_t vb, char* CV, int j0, int len, bool ends, hipStream_t st) {
+  for (int j = j0; j < j0 + len; ++j) {
+    schur_apply(c, nrhs, CV + (size_t)j * vs * vb, w->cw, w->ct1, w->ct2, st);
+    cgs(w, a, c.vt, nrhs, ce, ld, CV, vs, j + 1, w->cw, passes, st);
+    launch_arnoldi(nrhs, a.m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est,
+                   a.hnext, st);
+    if (ends && j + 1 == j0 + len) break;
+    launch_normalize(c.vt, nrhs, ce, ld, w->cw, nullptr, a.hnext, a.active, CV + (size_t)(j + 1) * vs * vb, st);
+  }
+}
+
+// Run a chunk on `st`: directly, or by replaying its graph (captured on first use
+// on the workspace's own stream; capturing launches nothing).
+static dd_status run_chunk(dd_mg* mg, const CoarseOps& c, int nrhs, long long ce, long long ld, long long vs,
+                           size_t vb, int j0, int len, bool ends, hipStream_t st) {
+  Workspace* w = mg->ws;
+  Arnoldi& a = w->ca;
+  char* CV = (char*)w->CV;
+  const int passes = mg->p.coarse_cgs_passes;
+  if (!mg->use_graphs) {
+    issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, vb, CV, j0, len, ends, st);
+    return DD_OK;
+  }
+  const std::array<int, 5> key = {nrhs, (int)c.vt, j0, len, ends ? 1 : 0};
+  auto it = w->graphs.find(key);
+  if (it == w->graphs.end()) {
+    if (!w->cap) DD_HIP(mg->ctx, hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
+    DD_HIP(mg->ctx, hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
+    ktimer_suspend(true);
+    issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, vb, CV, j0, len, ends, w->cap);
+    ktimer_suspend(false);
+    hipGraph_t gr = nullptr;
+    DD_HIP(mg->ctx, hipStreamEndCapture(w->cap, &gr));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return dd_hip_check(mg->ctx, e, "hipGraphInstantiate (coarse GMRES chunk)");
+    it = w->graphs.emplace(key, ex).first;
+  }
+  DD_HIP(mg->ctx, hipGraphLaunch(it->second, st));
+  return DD_OK;
 }
 
 // y ~= D_c^-1 b by GMRES on the even-site Schur complement, then the odd sites.
@@ -288,20 +344,16 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
     if (count_active(w, a.active, nrhs, st) == 0) break;
     launch_normalize(vt, nrhs, ce, ld, w->cres, nullptr, a.beta, a.active, CV, st);
     const int mm = (cap - iters < m) ? cap - iters : m;
-    for (int j = 0; j < mm; ++j) {
-      void* Vj = CV + (size_t)j * vs * vb;
-      schur_apply(c, nrhs, Vj, w->cw, w->ct1, w->ct2, st);
-      cgs(w, a, vt, nrhs, ce, ld, CV, vs, j + 1, w->cw, mg->p.coarse_cgs_passes, st);
-      launch_arnoldi(nrhs, m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est,
-                     a.hnext, st);
-      ++iters;
-      if (j + 1 == mm) {
-        // the cycle ends here: close every RHS still active
-        break;
-      }
-      launch_normalize(vt, nrhs, ce, ld, w->cw, nullptr, a.hnext, a.active, CV + (size_t)(j + 1) * vs * vb, st);
-      // converged RHS are masked on the device; the host looks every few iterations
-      if ((j + 1) % 4 == 0 && count_active(w, a.active, nrhs, st) == 0) break;
+    // chunks of 4 Arnoldi steps; converged RHS are masked on the device and the
+    // host looks between chunks
+    for (int j = 0; j < mm;) {
+      const int len = mm - j < 4 ? mm - j : 4;
+      const bool ends = j + len == mm;
+      dd_status cs = run_chunk(mg, c, nrhs, ce, ld, vs, vb, j, len, ends, st);
+      if (cs) return cs;
+      iters += len;
+      j += len;
+      if (ends || count_active(w, a.active, nrhs, st) == 0) break;
     }
     launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
     launch_multi_axpy(vt, vt, nrhs, ce, ld, CV, max_kcyc(w, a, nrhs, st), vs, a.y, m, 0, 1.0, y, st);
@@ -555,6 +607,12 @@ dd_status dd_setup_update_mass(dd_mg* mg, double m0) {
   dd_status s = gauge_set_mass(mg->g, m0);
   if (s) return s;
   return build(mg, 0);
+}
+
+dd_status dd_mg_set_graphs(dd_mg* mg, int enable) {
+  if (!mg) return DD_EINVAL;
+  mg->use_graphs = enable != 0;
+  return DD_OK;
 }
 
 dd_status dd_mg_destroy(dd_mg* mg) {

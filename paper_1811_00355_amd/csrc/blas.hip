@@ -188,6 +188,12 @@ __global__ void k_sub(long long n, const Tv* __restrict__ a, const Tv* __restric
   }
 }
 
+// zero fill in 4-byte words (a kernel, so that it can sit inside a captured graph)
+__global__ void k_zero(long long nwords, unsigned* __restrict__ p) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwords) p[i] = 0u;
+}
+
 template <typename Tv>
 __global__ void k_add(long long n, const Tv* __restrict__ a, Tv* __restrict__ out) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -413,6 +419,12 @@ void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* ou
     k_sub<double2><<<nb, 256, 0, st>>>(n, (const double2*)a, (const double2*)b, (double2*)out);
   else
     k_sub<float2><<<nb, 256, 0, st>>>(n, (const float2*)a, (const float2*)b, (float2*)out);
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const long long nw = (long long)(bytes / 4);
+  if (nw <= 0) return;
+  k_zero<<<(unsigned)((nw + 255) / 256), 256, 0, st>>>(nw, (unsigned*)p);
 }
 
 void launch_add(dd_dtype vt, long long n, const void* a, void* out, hipStream_t st) {

@@ -299,6 +299,7 @@ struct dd_mg {
   double2* Dinv64 = nullptr;
   float2* Dinv32 = nullptr;
   Workspace* ws = nullptr;
+  bool use_graphs = false;   // coarse GMRES chunks replayed from captured HIP graphs
 };
 
 // ---------------------------------------------------------------------------
@@ -381,6 +382,7 @@ void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long ld, cons
 void launch_normalize(dd_dtype vt, int nrhs, long long count, long long ld, const void* src, const double2* nrm2,
                       const double* nrm, const int* mask, void* dst, hipStream_t st);
 void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);   // bytes: multiple of 4
 void launch_add(dd_dtype vt, long long n, const void* a, void* out, hipStream_t st);
 void launch_cycle_init(int nrhs, int m, const double2* nrm2, const double* tolabs, const int* finished,
                        double2* gv, double* beta, int* active, int* kcyc, hipStream_t st);

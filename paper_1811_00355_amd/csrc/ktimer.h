@@ -5,6 +5,7 @@
 bool ktimer_enabled(const char* tag);
 void ktimer_begin(const char* tag, hipStream_t st);
 void ktimer_end(const char* tag, hipStream_t st, double bytes, double flops);
+void ktimer_suspend(bool on);   // while on, no launch of this thread is timed
 
 // Launch `launch` (a kernel launch statement) bracketed by timing events when
 // the kernel name `tag` is being timed; `bytes` / `flops` are the launch's

@@ -39,10 +39,14 @@ Timers& T() {
 }
 
 thread_local hipEvent_t t_start = nullptr;
+thread_local bool t_suspended = false;
 
 }  // namespace
 
+void ktimer_suspend(bool on) { t_suspended = on; }
+
 bool ktimer_enabled(const char* tag) {
+  if (t_suspended) return false;   // launches being captured into a graph are not timed
   Timers& t = T();
   if (t.on.empty() && !t.all) return false;
   std::lock_guard<std::mutex> g(t.mu);
