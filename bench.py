@@ -95,6 +95,62 @@ def cpu_baseline(cfg, lat_shape, n_vec, gpu_outer_iters, gpu_coarse_iters_per_vc
                         f"scaled by volume x{V_full // lat.V} and {gpu_outer_iters:.1f} outer iterations per solve"))
 
 
+def dapply_table(B, g, reps=20):
+    """D apply throughput on this lattice for the storage forms of the operator:
+    algorithmic bytes (spinors in and out per RHS, links and clover once) over
+    the mean launch time from the library's kernel timer."""
+    import torch
+    rows = {}
+    for name, dt, nrhs in (("f64_1rhs", B.DD_F64, 1), ("f32_1rhs", B.DD_F32, 1), ("f16ops_1rhs", B.DD_F16, 1),
+                           ("bf16ops_1rhs", B.DD_BF16, 1), ("f64_12rhs", B.DD_F64, 12), ("f32_12rhs", B.DD_F32, 12),
+                           ("f16ops_12rhs", B.DD_F16, 12), ("bf16ops_12rhs", B.DD_BF16, 12)):
+        src, dst = g.new_packed(dt, nrhs), g.new_packed(dt, nrhs)
+        g.dd_dirac_apply(dt, nrhs, src, dst)
+        torch.cuda.synchronize()
+        B.kernel_timer_enable("k_dirac")
+        for _ in range(reps):
+            g.dd_dirac_apply(dt, nrhs, src, dst)
+        torch.cuda.synchronize()
+        k = B.kernel_timer_read("k_dirac")
+        B.kernel_timer_enable(None)
+        gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+        rows[name] = dict(ms=round(k["ms"] / k["launches"], 4), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+        del src, dst
+    return rows
+
+
+def fp64_single_rhs(B, g, cfg, b, args):
+    """The comparison form: an all-FP64 setup, then the 12 sources solved one at
+    a time (single-RHS FP64 solves, one after another)."""
+    import torch
+    blk, n_vec = cfg["block"], cfg["n_vec"]
+    p = B.default_params(block=blk, n_vec=n_vec, setup_iters=cfg["setup_iters"], inner_dtype=B.DD_F64,
+                         store_dtype=B.DD_F64, seed=cfg["tv_seed"], coarse_restart=args.coarse_restart,
+                         coarse_max_iters=args.coarse_max_iters, coarse_cgs_passes=args.coarse_cgs_passes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg = B.MG(g, p)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    mg.dd_mg_set_graphs(args.graphs)
+    x = torch.zeros_like(b[:1])
+    mg.dd_solve(1, b[:1].contiguous(), x, TOL)        # workspace allocation and graph capture, untimed
+    torch.cuda.synchronize()
+    iters = []
+    t0 = time.perf_counter()
+    for k in range(b.shape[0]):
+        x = torch.zeros_like(b[k:k + 1])
+        info, st = mg.dd_solve(1, b[k:k + 1].contiguous(), x, TOL, raise_on_noconv=False)
+        if st or not info[0]["converged"]:
+            raise RuntimeError(f"FP64 single-RHS solve {k} did not converge: {info}")
+        iters.append(info[0]["outer_iters"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    mg.destroy()
+    return dict(solves_per_s=round(b.shape[0] / elapsed, 3), setup_s=round(t_setup, 3),
+                outer_iters_mean=round(float(np.mean(iters)), 2), seconds=round(elapsed, 3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,7 +163,13 @@ def main():
     ap.add_argument("--coarse-cgs-passes", type=int, default=1)
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="replay the coarse GMRES from captured HIP graphs")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="time the launch-shape candidates before the timed steps")
+    ap.add_argument("--tune-cache", default=None, help="JSON cache of autotuner choices")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-single", action="store_true",
+                    help="skip the 12 sequential FP64 single-RHS solves")
+    ap.add_argument("--no-dapply", action="store_true", help="skip the D-apply bandwidth table")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -153,6 +215,13 @@ def main():
     t_setup = time.perf_counter() - t0
     log(f"[bench] setup {t_setup:.2f} s")
     mg.dd_mg_set_graphs(args.graphs)
+    tuning = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        rep = mg.dd_autotune(nrhs, args.tune_cache)
+        tuning = dict(chosen=g.dd_gauge_get_tuning(), seconds=round(time.perf_counter() - t0, 2),
+                      candidates=[l for l in rep.splitlines() if " ms" in l])
+        log(f"[bench] autotune ({tuning['seconds']} s): " + "; ".join(rep.splitlines()[1:]))
 
     # the 12 spin-colour point sources at the origin, canonical complex128 on the device
     b = torch.zeros((nrhs, V * 12), dtype=torch.complex128, device="cuda")
@@ -240,10 +309,19 @@ def main():
                    "coarse_iters_per_vcycle": round(float(coarse_per_vcycle), 1),
                    "setup_s": round(t_setup, 3),
                    "solves_per_s_incl_setup": round(nrhs / (t_setup + elapsed / args.steps), 3),
+                   "tuning": tuning,
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "kernels": kernels,
     }
+    if not args.no_dapply:
+        log("[bench] D-apply bandwidth table")
+        out["dapply"] = dapply_table(B, g)
+        log(f"[bench] D apply: {out['dapply']}")
+    if not args.no_fp64_single:
+        log("[bench] 12 sequential FP64 single-RHS solves")
+        out["config"]["fp64_single_rhs"] = fp64_single_rhs(B, g, cfg, b, args)
+        log(f"[bench] FP64 single-RHS: {out['config']['fp64_single_rhs']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg, L, n_vec, float(outer), float(coarse_per_vcycle))

@@ -116,6 +116,13 @@ const char* dd_last_error(const dd_ctx* ctx);
 size_t dd_ctx_bytes_in_use(const dd_ctx* ctx);
 void dd_mg_params_default(dd_mg_params* p);
 
+/* Launch shapes (bit-identical results for every choice; see dd_autotune). */
+typedef struct {
+  int32_t sap_wpe;        /* SAP waves per SIMD the registers allow: 2 or 3          */
+  int32_t dirac_threads;  /* D apply workgroup size: 64, 128 or 256                    */
+  int32_t coarse_spw;     /* FP32 coarse apply: coarse sites per workgroup, 2, 4 or 8  */
+} dd_tuning;
+
 /* ---- gauge field (field preparation) ---------------------------------------
  * Copies the links (host, canonical complex128), builds the clover term from
  * the four plaquette leaves of every plane and inverts its two Hermitian 6x6
@@ -175,6 +182,27 @@ dd_status dd_mg_destroy(dd_mg* mg);
  * either way.  Graphs hold workspace addresses and are dropped when the
  * workspace is reallocated.  Kernel timers do not see launches inside graphs. */
 dd_status dd_mg_set_graphs(dd_mg* mg, int enable);
+/* Free the solver workspace of a setup (Krylov bases, scratch vectors and the
+ * graphs captured on them); the next solve allocates it again.  For callers
+ * that keep many setups resident and solve on one at a time.  Synchronises
+ * the device. */
+dd_status dd_mg_release_workspace(dd_mg* mg);
+
+/* ---- autotuner --------------------------------------------------------------------------
+ * dd_autotune times every launch-shape candidate of the smoother (waves per
+ * SIMD), the FP64 D apply (workgroup size) and the FP32 coarse stencil (sites
+ * per workgroup) on this setup's own operators and workspace for nrhs
+ * right-hand sides, keeps the fastest in the gauge field (shared by every setup
+ * on it) and returns a text report (report may be NULL).  cache_path (may be
+ * NULL) names a JSON file of earlier choices keyed by device architecture,
+ * lattice, block, n, nrhs and dtypes: a hit applies the stored choice without
+ * timing; a miss times and rewrites the file.  Workspace vectors are
+ * overwritten; caller data are not touched.
+ * dd_gauge_set_tuning / dd_gauge_get_tuning set or read the choice directly
+ * (DD_EINVAL for a value outside the lists above). */
+dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report, size_t report_cap);
+dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t);
+dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t);
 /* "New kappa" (Sec. 4, strange-quark solves): switch the setup to bare mass m0
  * while keeping its test vectors.  Rebuilds the clover term and inverse of the
  * gauge field, then P (same vectors, so the same P), D_c = P^dag D P and the

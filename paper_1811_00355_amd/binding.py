@@ -43,6 +43,10 @@ class dd_mg_params(ctypes.Structure):
                 ("coarse_cgs_passes", ctypes.c_int32)]
 
 
+class dd_tuning(ctypes.Structure):
+    _fields_ = [("sap_wpe", ctypes.c_int32), ("dirac_threads", ctypes.c_int32), ("coarse_spw", ctypes.c_int32)]
+
+
 class dd_solve_info(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("coarse_iters_total", ctypes.c_int32), ("converged", ctypes.c_int32),
@@ -79,6 +83,10 @@ SIGNATURES = {
     "dd_mg_destroy": (_I, [_P]),
     "dd_setup_update_mass": (_I, [_P, ctypes.c_double]),
     "dd_mg_set_graphs": (_I, [_P, _I]),
+    "dd_mg_release_workspace": (_I, [_P]),
+    "dd_autotune": (_I, [_P, _I, ctypes.c_char_p, ctypes.c_char_p, _S]),
+    "dd_gauge_set_tuning": (_I, [_P, ctypes.POINTER(dd_tuning)]),
+    "dd_gauge_get_tuning": (_I, [_P, ctypes.POINTER(dd_tuning)]),
     "dd_restrict": (_I, [_P, _I, _I, _P, _P, _P]),
     "dd_prolong": (_I, [_P, _I, _I, _P, _P, _P]),
     "dd_coarse_apply": (_I, [_P, _I, _I, _P, _P, _P]),
@@ -207,6 +215,15 @@ class Gauge:
             self.ctx.check(self.ctx.lib.dd_gauge_destroy(self.h))
             self.h = _P()
 
+    def dd_gauge_set_tuning(self, sap_wpe, dirac_threads, coarse_spw):
+        t = dd_tuning(sap_wpe, dirac_threads, coarse_spw)
+        self.ctx.check(self.ctx.lib.dd_gauge_set_tuning(self.h, ctypes.byref(t)))
+
+    def dd_gauge_get_tuning(self):
+        t = dd_tuning()
+        self.ctx.check(self.ctx.lib.dd_gauge_get_tuning(self.h, ctypes.byref(t)))
+        return dict(sap_wpe=t.sap_wpe, dirac_threads=t.dirac_threads, coarse_spw=t.coarse_spw)
+
     def dd_gauge_set_mass(self, m0):
         self.ctx.check(self.ctx.lib.dd_gauge_set_mass(self.h, m0))
 
@@ -279,6 +296,16 @@ class MG:
         if self.h:
             self.ctx.check(self.ctx.lib.dd_mg_destroy(self.h))
             self.h = _P()
+
+    def dd_autotune(self, nrhs, cache_path=None):
+        """Time the launch-shape candidates, keep the fastest; returns the report text."""
+        buf = ctypes.create_string_buffer(4096)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self.ctx.check(self.ctx.lib.dd_autotune(self.h, nrhs, path, buf, len(buf)))
+        return buf.value.decode()
+
+    def dd_mg_release_workspace(self):
+        self.ctx.check(self.ctx.lib.dd_mg_release_workspace(self.h))
 
     def dd_mg_set_graphs(self, enable):
         self.ctx.check(self.ctx.lib.dd_mg_set_graphs(self.h, int(bool(enable))))

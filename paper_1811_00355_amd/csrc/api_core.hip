@@ -316,7 +316,7 @@ dd_status dd_dirac_apply(dd_gauge* g, dd_dtype dt, int nrhs, const void* in, voi
   if (!in || !out || nrhs < 1) return dd_fail(g->ctx, DD_EINVAL, "bad vector arguments");
   if (in == out) return dd_fail(g->ctx, DD_EINVAL, "in and out must not alias");
   if ((st = ensure_opset(g, dt))) return st;
-  launch_dirac(g->geo, dt, g->ops[dt], nrhs, in, out, (hipStream_t)stream);
+  launch_dirac(g->geo, dt, g->ops[dt], nrhs, in, out, (hipStream_t)stream, g->tune.dirac_threads);
   DD_HIP(g->ctx, hipGetLastError());
   return DD_OK;
 }
@@ -330,7 +330,8 @@ dd_status dd_sap_smooth(dd_gauge* g, const dd_mg_params* p, dd_dtype dt, int nrh
   if (p->sap_sweeps < 0 || p->sap_mr_iters < 0) return dd_fail(g->ctx, DD_EINVAL, "negative SAP iteration counts");
   if (b == x) return dd_fail(g->ctx, DD_EINVAL, "b and x must not alias");
   if ((st = ensure_opset(g, dt))) return st;
-  launch_sap(g->geo, dt, g->ops[dt], nrhs, p->sap_sweeps, p->sap_mr_iters, b, x, (hipStream_t)stream);
+  launch_sap(g->geo, dt, g->ops[dt], nrhs, p->sap_sweeps, p->sap_mr_iters, b, x, g->tune.sap_wpe,
+             (hipStream_t)stream);
   DD_HIP(g->ctx, hipGetLastError());
   return DD_OK;
 }

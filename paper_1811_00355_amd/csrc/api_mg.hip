@@ -2,8 +2,11 @@
 // operator, the even-odd coarse GMRES, the preconditioner M of Eq. (5) and the
 // flexible GMRES outer solver.  Host code here only sequences kernels and
 // reads per-RHS convergence flags; all arithmetic runs on the device.
+#include <algorithm>
 #include <array>
 #include <chrono>
+#include <cstdio>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -230,6 +233,7 @@ struct CoarseOps {
   dd_dtype vt;
   int nc;
   const void *Dc, *Dinv;
+  int spw;   // FP32 coarse apply: sites per workgroup
 };
 
 static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
@@ -239,15 +243,16 @@ static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
   c.nc = mg->nc;
   c.Dc = vt == DD_F64 ? (const void*)mg->Dc64 : (const void*)mg->Dc32;
   c.Dinv = vt == DD_F64 ? (const void*)mg->Dinv64 : (const void*)mg->Dinv32;
+  c.spw = mg->g->tune.coarse_spw;
   return c;
 }
 
 // out_e = S v_e = D_ee v_e - D_eo D_oo^-1 D_oe v_e   (t1, t2 scratch, odd parts used)
 static void schur_apply(const CoarseOps& c, int nrhs, const void* v, void* out, void* t1, void* t2, hipStream_t st) {
   const GeomDev& g = *c.g;
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, 1.0, v, 0.0, nullptr, t1, st);
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, t1, 0.0, nullptr, 0.0, nullptr, t2, st);
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 1.0, v, -1.0, t2, 0.0, nullptr, out, st);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, 1.0, v, 0.0, nullptr, t1, st, c.spw);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, t1, 0.0, nullptr, 0.0, nullptr, t2, st, c.spw);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 1.0, v, -1.0, t2, 0.0, nullptr, out, st, c.spw);
 }
 
 // Arnoldi steps j0 .. j0+len-1 of one coarse GMRES cycle: w = S v_j, Gram-Schmidt,
@@ -312,8 +317,8 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
   const int cap = fixed ? mg->p.coarse_fixed_iters : mg->p.coarse_max_iters;
   const double tol = fixed ? 0.0 : mg->p.coarse_tol;
   // rhs' = b_e - D_eo D_oo^-1 b_o
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st);
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st, c.spw);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st, c.spw);
   DD_HIP(mg->ctx, hipMemsetAsync(y, 0, (size_t)nrhs * ld * vb, st));
   // tolerance: tol * |rhs'|
   norms2(w, vt, nrhs, ce, ld, w->cr, a.nrm2, st);
@@ -371,8 +376,8 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
     if (nfin == nrhs) break;
   }
   // odd sites: y_o = D_oo^-1 (b_o - D_oe y_e)
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st);
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st, c.spw);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st, c.spw);
   DD_HIP(mg->ctx, hipGetLastError());
   if (iters_out) *iters_out = iters;
   return DD_OK;
@@ -390,7 +395,7 @@ static dd_status vcycle(dd_mg* mg, int nrhs, const void* v, void* out, int* cite
   if (s) return s;
   launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, st);
   dd_dtype od = op_dtype(mg);
-  launch_sap(g, od, mg->g->ops[od], nrhs, mg->p.sap_sweeps, mg->p.sap_mr_iters, v, out, st);
+  launch_sap(g, od, mg->g->ops[od], nrhs, mg->p.sap_sweeps, mg->p.sap_mr_iters, v, out, mg->g->tune.sap_wpe, st);
   DD_HIP(mg->ctx, hipGetLastError());
   return DD_OK;
 }
@@ -563,7 +568,7 @@ static dd_status setup_common(dd_gauge* g, const dd_mg_params* p, const double* 
   for (int k = 0; k < p->init_sap_apps; ++k) {
     DD_HIP(mg->ctx, hipMemcpyAsync(w->vin, mg->tv, fb, hipMemcpyDeviceToDevice, st));
     DD_HIP(mg->ctx, hipMemsetAsync(mg->tv, 0, fb, st));
-    launch_sap(G, od, g->ops[od], mg->n, p->sap_sweeps, p->sap_mr_iters, w->vin, mg->tv, st);
+    launch_sap(G, od, g->ops[od], mg->n, p->sap_sweeps, p->sap_mr_iters, w->vin, mg->tv, g->tune.sap_wpe, st);
     normalize_vectors(mg, mg->tv, st);
   }
   if ((s = build(mg, st))) return fail(s);
@@ -589,6 +594,50 @@ static dd_status check_mg_vec(dd_mg* mg, dd_dtype dt, int nrhs, const void* a, c
   return DD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// autotuner cache: a JSON object, one entry per line,
+//   "<device>|L=..|b=..|n=..|nrhs=..|op=..|inner=..": {"sap_wpe": 2, "dirac_threads": 256, "coarse_spw": 4}
+// Lines that do not parse are dropped (the file is rewritten on the next miss).
+// ---------------------------------------------------------------------------
+static bool tune_field(const std::string& obj, const char* name, int& v) {
+  std::string pat = std::string("\"") + name + "\":";
+  size_t p = obj.find(pat);
+  if (p == std::string::npos) return false;
+  return std::sscanf(obj.c_str() + p + pat.size(), " %d", &v) == 1;
+}
+
+static void tune_cache_read(const char* path, std::map<std::string, Tuning>& out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char buf[1024];
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string l(buf);
+    size_t a = l.find('"'), b = a == std::string::npos ? a : l.find('"', a + 1);
+    size_t o = b == std::string::npos ? b : l.find('{', b), c = o == std::string::npos ? o : l.find('}', o);
+    if (c == std::string::npos) continue;
+    std::string obj = l.substr(o, c - o + 1);
+    Tuning t;
+    if (tune_field(obj, "sap_wpe", t.sap_wpe) && tune_field(obj, "dirac_threads", t.dirac_threads) &&
+        tune_field(obj, "coarse_spw", t.coarse_spw))
+      out[l.substr(a + 1, b - a - 1)] = t;
+  }
+  std::fclose(f);
+}
+
+static bool tune_cache_write(const char* path, const std::map<std::string, Tuning>& m) {
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : m)
+    std::fprintf(f, " \"%s\": {\"sap_wpe\": %d, \"dirac_threads\": %d, \"coarse_spw\": %d}%s\n", kv.first.c_str(),
+                 kv.second.sap_wpe, kv.second.dirac_threads, kv.second.coarse_spw, ++i < m.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
 extern "C" {
 
 dd_status dd_setup(dd_gauge* g, const dd_mg_params* p, dd_mg** out) { return setup_common(g, p, nullptr, out); }
@@ -607,6 +656,132 @@ dd_status dd_setup_update_mass(dd_mg* mg, double m0) {
   dd_status s = gauge_set_mass(mg->g, m0);
   if (s) return s;
   return build(mg, 0);
+}
+
+dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t) {
+  if (!g || !t) return DD_EINVAL;
+  if ((t->sap_wpe != 2 && t->sap_wpe != 3) ||
+      (t->dirac_threads != 64 && t->dirac_threads != 128 && t->dirac_threads != 256) ||
+      (t->coarse_spw != 2 && t->coarse_spw != 4 && t->coarse_spw != 8))
+    return dd_fail(g->ctx, DD_EINVAL, "tuning: sap_wpe 2|3, dirac_threads 64|128|256, coarse_spw 2|4|8");
+  g->tune.sap_wpe = t->sap_wpe;
+  g->tune.dirac_threads = t->dirac_threads;
+  g->tune.coarse_spw = t->coarse_spw;
+  return DD_OK;
+}
+
+dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t) {
+  if (!g || !t) return DD_EINVAL;
+  t->sap_wpe = g->tune.sap_wpe;
+  t->dirac_threads = g->tune.dirac_threads;
+  t->coarse_spw = g->tune.coarse_spw;
+  return DD_OK;
+}
+
+dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report, size_t report_cap) {
+  if (!mg || nrhs < 1) return DD_EINVAL;
+  dd_gauge* g = mg->g;
+  const GeomDev& G = g->geo;
+  std::string key;
+  {
+    hipDeviceProp_t prop;
+    DD_HIP(mg->ctx, hipGetDeviceProperties(&prop, mg->ctx->device));
+    static const char* dn[4] = {"f64", "f32", "f16", "bf16"};
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s|L=%dx%dx%dx%d|b=%dx%dx%dx%d|n=%d|nrhs=%d|op=%s|inner=%s",
+                  prop.gcnArchName, G.L[0], G.L[1], G.L[2], G.L[3], G.b[0], G.b[1], G.b[2], G.b[3], mg->n, nrhs,
+                  dn[op_dtype(mg)], dn[inner_vt(mg)]);
+    key = buf;
+  }
+  std::map<std::string, Tuning> cache;
+  if (cache_path) tune_cache_read(cache_path, cache);
+  std::string rep = "key " + key + "\n";
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    g->tune = it->second;
+    rep += "cache hit\n";
+  } else {
+    dd_status s = ensure_ws(mg, nrhs, true);
+    if (s) return s;
+    Workspace* w = mg->ws;
+    hipStream_t st = 0;
+    hipEvent_t e0, e1;
+    DD_HIP(mg->ctx, hipEventCreate(&e0));
+    DD_HIP(mg->ctx, hipEventCreate(&e1));
+    // median of 3 timed runs after one warm-up
+    auto time_ms = [&](const std::function<void()>& f) {
+      f();
+      float t[3];
+      for (int k = 0; k < 3; ++k) {
+        (void)hipEventRecord(e0, st);
+        f();
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&t[k], e0, e1);
+      }
+      std::sort(t, t + 3);
+      return t[1];
+    };
+    char line[160];
+    const dd_dtype od = op_dtype(mg), vt = inner_vt(mg);
+    Tuning best = g->tune;
+    // SAP: one sweep over scratch vectors of the workspace
+    if (od != DD_F64) {
+      float bt = 1e30f;
+      for (int wpe : {2, 3}) {
+        float t = time_ms([&] { launch_sap(G, od, g->ops[od], nrhs, 1, mg->p.sap_mr_iters, w->vin, w->xs, wpe, st); });
+        std::snprintf(line, sizeof(line), "k_sap_colour sap_wpe=%d %.3f ms/sweep\n", wpe, t);
+        rep += line;
+        if (t < bt) bt = t, best.sap_wpe = wpe;
+      }
+    }
+    // FP64 D apply of the outer solver
+    {
+      float bt = 1e30f;
+      for (int th : {64, 128, 256}) {
+        float t = time_ms([&] { launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->x64, w->zt64, st, th); });
+        std::snprintf(line, sizeof(line), "k_dirac(f64) dirac_threads=%d %.3f ms\n", th, t);
+        rep += line;
+        if (t < bt) bt = t, best.dirac_threads = th;
+      }
+    }
+    // FP32 coarse stencil (matrix cores)
+    if (vt == DD_F32) {
+      float bt = 1e30f;
+      for (int spw : {2, 4, 8}) {
+        float t = time_ms([&] {
+          launch_coarse_mv(G, vt, mg->nc, mg->Dc32, mg->Dinv32, 0, nrhs, 0, G.Vc, 1.0, w->cb, 1.0, w->cb, 0.0, nullptr,
+                           w->cw, st, spw);
+        });
+        std::snprintf(line, sizeof(line), "k_coarse_mfma coarse_spw=%d %.3f ms\n", spw, t);
+        rep += line;
+        if (t < bt) bt = t, best.coarse_spw = spw;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    DD_HIP(mg->ctx, hipGetLastError());
+    g->tune = best;
+    cache[key] = best;
+    if (cache_path && !tune_cache_write(cache_path, cache))
+      rep += std::string("could not write ") + cache_path + "\n";
+  }
+  char line[128];
+  std::snprintf(line, sizeof(line), "chosen sap_wpe=%d dirac_threads=%d coarse_spw=%d\n", g->tune.sap_wpe,
+                g->tune.dirac_threads, g->tune.coarse_spw);
+  rep += line;
+  if (report && report_cap) {
+    std::strncpy(report, rep.c_str(), report_cap - 1);
+    report[report_cap - 1] = 0;
+  }
+  return DD_OK;
+}
+
+dd_status dd_mg_release_workspace(dd_mg* mg) {
+  if (!mg) return DD_EINVAL;
+  DD_HIP(mg->ctx, hipDeviceSynchronize());
+  free_ws(mg);
+  return DD_OK;
 }
 
 dd_status dd_mg_set_graphs(dd_mg* mg, int enable) {
@@ -668,7 +843,7 @@ dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
   if (s) return s;
   CoarseOps c = coarse_ops(mg, dt);
   launch_coarse_mv(mg->g->geo, dt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, mg->g->geo.Vc, 1.0, in, 1.0, in, 0.0, nullptr,
-                   out, (hipStream_t)stream);
+                   out, (hipStream_t)stream, c.spw);
   DD_HIP(mg->ctx, hipGetLastError());
   return DD_OK;
 }
@@ -770,7 +945,7 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
     if (first) {
       DD_HIP(mg->ctx, hipMemcpyAsync(w->w64, w->b64, sizeof(double2) * fine, hipMemcpyDeviceToDevice, st));
     } else {
-      launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->x64, w->zt64, st);
+      launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->x64, w->zt64, st, g->tune.dirac_threads);
       launch_sub(DD_F64, fine, w->b64, w->zt64, w->w64, st);
     }
     first = false;
@@ -796,12 +971,12 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
       int ci = 0;
       if (vt == DD_F64) {
         if ((s = vcycle(mg, nrhs, Vj, Zj, &ci, st))) return s;
-        launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, Zj, w->w64, st);
+        launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, Zj, w->w64, st, g->tune.dirac_threads);
       } else {
         launch_vec_convert(DD_F64, DD_F32, Vj, w->vin, fine, st);
         if ((s = vcycle(mg, nrhs, w->vin, Zj, &ci, st))) return s;
         launch_vec_convert(DD_F32, DD_F64, Zj, w->zt64, fine, st);
-        launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->zt64, w->w64, st);
+        launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->zt64, w->w64, st, g->tune.dirac_threads);
       }
       total_coarse += ci;
       cgs(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, 2, st);

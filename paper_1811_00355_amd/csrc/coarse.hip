@@ -91,80 +91,85 @@ __global__ void __launch_bounds__(64 * kSitesPerWG) k_coarse_mv(GeomDev g, int n
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxNc = 48;
 
-__global__ void __launch_bounds__(64 * kSitesPerWG) k_coarse_mfma(GeomDev g, int nc, const float2* __restrict__ Dc,
-                                                                const float2* __restrict__ Minv, int use_inv,
-                                                                int nrhs, int site_begin, int count, float a_self,
-                                                                const float2* __restrict__ xs, float a_hop,
-                                                                const float2* __restrict__ xh, float beta,
-                                                                const float2* __restrict__ z, float2* __restrict__ out) {
-  __shared__ float2 xsh[kSitesPerWG][kMfmaMaxNc][16];
+// NC = 2n (a multiple of 4, at most 48), SPW = sites (waves) per workgroup.  The
+// whole block of one direction is loaded into registers before the staging
+// barrier, so its HBM reads overlap the LDS traffic and every MFMA operand is
+// already in flight.
+template <int NC, int SPW>
+__global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const float2* __restrict__ Dc,
+                                                          const float2* __restrict__ Minv, int use_inv, int nrhs,
+                                                          int site_begin, int count, float a_self,
+                                                          const float2* __restrict__ xs, float a_hop,
+                                                          const float2* __restrict__ xh, float beta,
+                                                          const float2* __restrict__ z, float2* __restrict__ out) {
+  constexpr int MT = (NC + 15) / 16, KS = NC / 4;
+  __shared__ float2 xsh[SPW][NC][16];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int local = blockIdx.x * kSitesPerWG + w;
+  const int local = blockIdx.x * SPW + w;
   const bool site_ok = local < count;
   const int X = site_begin + (site_ok ? local : 0);
-  const long long vstride = (long long)g.Vc * nc;
+  const long long vstride = (long long)g.Vc * NC;
   const bool has_self = a_self != 0.f, has_hop = a_hop != 0.f;
-  const int mtiles = (nc + 15) / 16, ksteps = nc / 4;
   const int li = lane & 15, lk = lane >> 4;
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
-    f32x4 c0[3], c1[3];
+    f32x4 c0[MT], c1[MT];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) c0[t] = c1[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < MT; ++t) c0[t] = c1[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int d = has_self ? 0 : 1; d < (has_hop ? 9 : 1); ++d) {
       const int Y = d == 0 ? X : (g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK);
       const float2* src = d == 0 ? xs : xh;
       const float sc = d == 0 ? a_self : a_hop;
+      const float2* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * NC * NC : Dc + (long long)X * 9 * NC * NC)
+                               : Dc + ((long long)X * 9 + d) * NC * NC;
+      float2 m[KS][MT];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          const int row = 16 * t + li;
+          m[ks][t] = (site_ok && row < NC) ? B[(long long)(4 * ks + lk) * NC + row] : make_float2(0.f, 0.f);
+        }
       __syncthreads();
       // stage sc * x(Y) as [col][rhs], zero padded to 16 right-hand sides
-      for (int e = lane; e < nc * 16; e += 64) {
+      for (int e = lane; e < NC * 16; e += 64) {
         int col = e >> 4, r = e & 15;
         float2 v = make_float2(0.f, 0.f);
         if (site_ok && r < nr) {
-          v = src[(long long)(r0 + r) * vstride + (long long)Y * nc + col];
+          v = src[(long long)(r0 + r) * vstride + (long long)Y * NC + col];
           v.x *= sc;
           v.y *= sc;
         }
         xsh[w][col][r] = v;
       }
       __syncthreads();
-      if (site_ok) {
-        const float2* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * nc * nc : Dc + (long long)X * 9 * nc * nc)
-                                 : Dc + ((long long)X * 9 + d) * nc * nc;
-        for (int ks = 0; ks < ksteps; ++ks) {
-          const int col = 4 * ks + lk;
-          const float2 xb = xsh[w][col][li];
 #pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            if (t < mtiles) {
-              const int row = 16 * t + li;
-              const float2 m = row < nc ? B[(long long)col * nc + row] : make_float2(0.f, 0.f);
-              c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.x, xb.x, c0[t], 0, 0, 0);
-              c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.y, -xb.y, c0[t], 0, 0, 0);
-              c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.x, xb.y, c1[t], 0, 0, 0);
-              c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.y, xb.x, c1[t], 0, 0, 0);
-            }
-          }
+      for (int ks = 0; ks < KS; ++ks) {
+        const float2 xb = xsh[w][4 * ks + lk][li];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].x, xb.x, c0[t], 0, 0, 0);
+          c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].y, -xb.y, c0[t], 0, 0, 0);
+          c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].x, xb.y, c1[t], 0, 0, 0);
+          c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].y, xb.x, c1[t], 0, 0, 0);
         }
       }
     }
     if (site_ok && li < nr) {
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        if (t < mtiles) {
+      for (int t = 0; t < MT; ++t) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = 16 * t + 4 * lk + v;
-            if (row < nc) {
-              long long oi = (long long)(r0 + li) * vstride + (long long)X * nc + row;
-              float2 o = make_float2(c0[t][v], c1[t][v]);
-              if (beta != 0.f) {
-                float2 zz = z[oi];
-                o.x += beta * zz.x;
-                o.y += beta * zz.y;
-              }
-              out[oi] = o;
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + 4 * lk + v;
+          if (row < NC) {
+            long long oi = (long long)(r0 + li) * vstride + (long long)X * NC + row;
+            float2 o = make_float2(c0[t][v], c1[t][v]);
+            if (beta != 0.f) {
+              float2 zz = z[oi];
+              o.x += beta * zz.x;
+              o.y += beta * zz.y;
             }
+            out[oi] = o;
           }
         }
       }
@@ -172,10 +177,23 @@ __global__ void __launch_bounds__(64 * kSitesPerWG) k_coarse_mfma(GeomDev g, int
   }
 }
 
+template <int NC>
+void mfma_spw(int spw, unsigned count, dim3& grid, dim3& blk, void (*&fn)(GeomDev, const float2*, const float2*, int, int,
+                                                                        int, int, float, const float2*, float,
+                                                                        const float2*, float, const float2*, float2*)) {
+  switch (spw) {
+    case 2: fn = k_coarse_mfma<NC, 2>; break;
+    case 8: fn = k_coarse_mfma<NC, 8>; break;
+    default: fn = k_coarse_mfma<NC, 4>; spw = 4; break;
+  }
+  grid = dim3((count + spw - 1) / spw);
+  blk = dim3(64 * spw);
+}
+
 template <typename R, typename Sd, typename Tv>
 void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv, int nrhs, int site_begin, int count,
         double a_self, const void* xs, double a_hop, const void* xh, double beta, const void* z, void* out,
-        hipStream_t st) {
+        hipStream_t st, int spw) {
   if (count <= 0) return;
   const int nblocks_read = (a_self != 0.0 ? 1 : 0) + (a_hop != 0.0 ? 8 : 0);
   const double bytes = (double)count * nblocks_read * nc * nc * sizeof(Sd) +
@@ -189,10 +207,22 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
                                                              site_begin, count, (R)a_self, (const Tv*)xs, (R)a_hop, \
                                                              (const Tv*)xh, (R)beta, (const Tv*)z, (Tv*)out)))
   if (sizeof(R) == 4 && nc <= kMfmaMaxNc) {
+    typedef void (*Fn)(GeomDev, const float2*, const float2*, int, int, int, int, float, const float2*, float,
+                       const float2*, float, const float2*, float2*);
+    Fn fn = nullptr;
+    dim3 grid, wg;
+    switch (nc) {
+      case 12: mfma_spw<12>(spw, count, grid, wg, fn); break;
+      case 16: mfma_spw<16>(spw, count, grid, wg, fn); break;
+      case 24: mfma_spw<24>(spw, count, grid, wg, fn); break;
+      case 32: mfma_spw<32>(spw, count, grid, wg, fn); break;
+      case 40: mfma_spw<40>(spw, count, grid, wg, fn); break;
+      default: mfma_spw<48>(spw, count, grid, wg, fn); break;
+    }
     DD_TIMED("k_coarse_mfma", st, bytes, flops,
-             (k_coarse_mfma<<<nb, blk, 0, st>>>(g, nc, (const float2*)Dc, (const float2*)Minv, use_inv, nrhs, site_begin,
-                                                count, (float)a_self, (const float2*)xs, (float)a_hop, (const float2*)xh,
-                                                (float)beta, (const float2*)z, (float2*)out)));
+             (fn<<<grid, wg, 0, st>>>(g, (const float2*)Dc, (const float2*)Minv, use_inv, nrhs, site_begin, count,
+                                      (float)a_self, (const float2*)xs, (float)a_hop, (const float2*)xh, (float)beta,
+                                      (const float2*)z, (float2*)out)));
   } else if (nrhs == 1) DD_MV(1);
   else if (nrhs <= 4) DD_MV(4);
   else DD_MV(12);
@@ -203,13 +233,13 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
 
 void launch_coarse_mv(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, const void* Minv, int use_inv, int nrhs,
                       int site_begin, int count, double a_self, const void* xs, double a_hop, const void* xh,
-                      double beta, const void* z, void* out, hipStream_t st) {
+                      double beta, const void* z, void* out, hipStream_t st, int spw) {
   if (vt == DD_F64)
     mv<double, double2, double2>(g, nc, Dc, Minv, use_inv, nrhs, site_begin, count, a_self, xs, a_hop, xh, beta, z, out,
-                                 st);
+                                 st, spw);
   else
     mv<float, float2, float2>(g, nc, Dc, Minv, use_inv, nrhs, site_begin, count, a_self, xs, a_hop, xh, beta, z, out,
-                              st);
+                              st, spw);
 }
 
 // canonical coarse vectors [rhs][lex][nc] complex128 <-> packed [rhs][slot][nc]

@@ -267,8 +267,17 @@ struct OpSet {
   void* cinv = nullptr;     // [36][V]     same layout, inverse
 };
 
+// Launch shapes picked per gauge field (problem shape) by the autotuner; every
+// choice gives bit-identical results.
+struct Tuning {
+  int sap_wpe = 2;          // SAP layout: 2 (registers, 2 waves per SIMD) or 3 (lean LDS, 3)
+  int dirac_threads = 256;  // D apply workgroup size: 64, 128 or 256
+  int coarse_spw = 4;       // FP32 coarse apply: coarse sites (waves) per workgroup, 2, 4 or 8
+};
+
 struct dd_gauge {
   dd_ctx* ctx;
+  Tuning tune;
   dd_problem prob;
   GeomDev geo;
   int* d_blk_nbr = nullptr;
@@ -345,10 +354,10 @@ void launch_clover_build(const GeomDev& g, const double2* links64, double m0, do
                          double2* clover64, double2* cinv64, hipStream_t st);
 // Dirac operator
 void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
-                  hipStream_t st);
+                  hipStream_t st, int threads = 256);
 // SAP smoother
 void launch_sap(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters,
-                const void* b, void* x, hipStream_t st);
+                const void* b, void* x, int wpe, hipStream_t st);
 // transfer and coarse construction
 bool supported_nvec(int n);
 void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,
@@ -363,7 +372,7 @@ void launch_coarse_invert(const GeomDev& g, int nc, const double2* Dc64, double2
 // coarse operator: out = a_self M xs + a_hop sum_d D_c(d) xh(X+d) + beta z on sites [begin, begin+count)
 void launch_coarse_mv(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, const void* Minv, int use_inv,
                       int nrhs, int site_begin, int count, double a_self, const void* xs, double a_hop,
-                      const void* xh, double beta, const void* z, void* out, hipStream_t st);
+                      const void* xh, double beta, const void* z, void* out, hipStream_t st, int spw = 4);
 // vector kernels
 int dots_blocks(long long count, int nrhs);
 void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long ld, const void* V, int nv,

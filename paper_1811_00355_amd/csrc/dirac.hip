@@ -27,32 +27,33 @@ __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ 
 }  // namespace
 
 static void dirac_dispatch(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
-                           hipStream_t st) {
-  unsigned nb = xcd_grid((g.V + 255) / 256, nrhs);
+                           int threads, hipStream_t st) {
+  if (threads != 64 && threads != 128) threads = 256;
+  unsigned nb = xcd_grid((unsigned)((g.V + threads - 1) / threads), nrhs);
   switch (dt) {
     case DD_F64:
-      k_dirac<double, double2, double2><<<nb, 256, 0, st>>>(g, (const double2*)ops.links, (const double2*)ops.clover,
+      k_dirac<double, double2, double2><<<nb, threads, 0, st>>>(g, (const double2*)ops.links, (const double2*)ops.clover,
                                                             nrhs, (const double2*)in, (double2*)out);
       break;
     case DD_F32:
-      k_dirac<float, float2, float2><<<nb, 256, 0, st>>>(g, (const float2*)ops.links, (const float2*)ops.clover, nrhs,
+      k_dirac<float, float2, float2><<<nb, threads, 0, st>>>(g, (const float2*)ops.links, (const float2*)ops.clover, nrhs,
                                                          (const float2*)in, (float2*)out);
       break;
     case DD_F16:
-      k_dirac<float, __half2, float2><<<nb, 256, 0, st>>>(g, (const __half2*)ops.links, (const __half2*)ops.clover,
+      k_dirac<float, __half2, float2><<<nb, threads, 0, st>>>(g, (const __half2*)ops.links, (const __half2*)ops.clover,
                                                           nrhs, (const float2*)in, (float2*)out);
       break;
     case DD_BF16:
-      k_dirac<float, bf16x2, float2><<<nb, 256, 0, st>>>(g, (const bf16x2*)ops.links, (const bf16x2*)ops.clover, nrhs,
+      k_dirac<float, bf16x2, float2><<<nb, threads, 0, st>>>(g, (const bf16x2*)ops.links, (const bf16x2*)ops.clover, nrhs,
                                                          (const float2*)in, (float2*)out);
       break;
   }
 }
 
 void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
-                  hipStream_t st) {
+                  hipStream_t st, int threads) {
   // algorithmic traffic: spinor in + out per RHS, 4 links + packed clover once per site
   double bytes = (double)g.V * (24.0 * vector_pair_bytes(dt) * nrhs + 72.0 * storage_pair_bytes(dt));
   double flops = (double)g.V * nrhs * 1824.0;
-  DD_TIMED("k_dirac", st, bytes, flops, dirac_dispatch(g, dt, ops, nrhs, in, out, st));
+  DD_TIMED("k_dirac", st, bytes, flops, dirac_dispatch(g, dt, ops, nrhs, in, out, threads, st));
 }

@@ -192,9 +192,23 @@ __device__ __forceinline__ void hop_rt(const HopCoef& hc, int sgn, bool dag, con
   }
 }
 
+// One hop with compile-time direction and sign: project to the half spinor,
+// multiply by U (forward) or U^dag (backward), reconstruct into acc with coef.
+template <int MU, int SGN, bool DAG, typename R>
+__device__ __forceinline__ void hop_t(const cx<R>* u, const cx<R>* psi, R coef, cx<R>* acc) {
+  cx<R> h[6], uh[6];
+  project<MU, SGN, R>(psi, h);
+  if (DAG) su3_dag_mul_half<R>(u, h, uh);
+  else su3_mul_half<R>(u, h, uh);
+  reconstruct_acc<MU, SGN, R>(uh, coef, acc);
+}
+
 // acc += scale * (hopping term at site s).  The neighbour spinor is fetched by
 // `fetch(J, inside, psi)`; with `dirichlet`, hops to sites outside the block
-// are dropped.  One direction and sign per (rolled) loop iteration.
+// are dropped.  The loop over the 8 (direction, sign) pairs stays rolled so
+// that only one hop is live in registers; a uniform switch selects the
+// compile-time form of each hop, whose gamma-matrix factors are then plain
+// swaps and sign flips.
 template <typename R, typename S, typename Fetch>
 __device__ __forceinline__ void hop_all(const GeomDev& g, const S* links, const SiteLoc& s, long long I, bool dirichlet,
                                         Fetch fetch, cx<R>* acc, R scale = (R)1) {
@@ -208,7 +222,17 @@ __device__ __forceinline__ void hop_all(const GeomDev& g, const S* links, const 
     cx<R> psi[12], u[9];
     fetch(J, inside, psi);
     load_link<R, S>(links, g.V, mu, sign > 0 ? I : J, u);
-    HopCoef hc = hop_coef(mu);
-    hop_rt<R>(hc, sign > 0 ? -1 : +1, sign < 0, u, psi, scale * (R)(wrap ? -0.5 * g.bc_t : -0.5), acc);
+    const R coef = scale * (R)(wrap ? -0.5 * g.bc_t : -0.5);
+    // forward (1 - gamma_mu) U_mu(x) psi(x + mu); backward (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
+    switch (k) {
+      case 0: hop_t<0, -1, false, R>(u, psi, coef, acc); break;
+      case 1: hop_t<0, +1, true, R>(u, psi, coef, acc); break;
+      case 2: hop_t<1, -1, false, R>(u, psi, coef, acc); break;
+      case 3: hop_t<1, +1, true, R>(u, psi, coef, acc); break;
+      case 4: hop_t<2, -1, false, R>(u, psi, coef, acc); break;
+      case 5: hop_t<2, +1, true, R>(u, psi, coef, acc); break;
+      case 6: hop_t<3, -1, false, R>(u, psi, coef, acc); break;
+      default: hop_t<3, +1, true, R>(u, psi, coef, acc); break;
+    }
   }
 }

@@ -52,14 +52,27 @@ __device__ __forceinline__ void block_sum3(R& a, R& b, R& c, R* red) {
   }
 }
 
-template <typename R, typename S, typename Tv>
-__global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
-                                                     const S* __restrict__ cinv, int nrhs, int colour, int mr_iters,
-                                                     const Tv* __restrict__ bvec, Tv* __restrict__ xvec) {
-  __shared__ cx<R> sh_e[12][kMaxBvh];   // even-site vector exchanged with the odd phase
-  __shared__ cx<R> sh_o[12][kMaxBvh];   // odd-site vector exchanged with the even phase
-  __shared__ cx<R> sh_r[12][kMaxBvh];   // odd-site residual r_o, kept for the reconstruction
+// Two layouts of the same arithmetic (bit-identical results), picked by WPE,
+// the waves per SIMD the register allocation must allow:
+//  WPE 2: the correction e_e lives in registers; the odd residual r_o and the
+//         even and odd exchange vectors have LDS buffers of their own (36 KB
+//         in FP32, which also limits a CU to 2 waves per SIMD).
+//  WPE 3: e_e lives in LDS, one exchange buffer serves both phases (two more
+//         barriers per MR step) and r_o is recomputed for the reconstruction
+//         instead of being kept (24 KB, 3 waves per SIMD).
+template <typename R, typename S, typename Tv, int WPE>
+__global__ void __launch_bounds__(kMaxBvh) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_sap_colour(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov, const S* __restrict__ cinv, int nrhs,
+             int colour, int mr_iters, const Tv* __restrict__ bvec, Tv* __restrict__ xvec) {
+  constexpr bool kLean = WPE >= 3;
+  constexpr int kE = kLean ? kMaxBvh : 1;    // LDS slots of e_e (lean layout)
+  constexpr int kX = kLean ? 1 : kMaxBvh;    // second exchange buffer and r_o (register layout)
+  __shared__ cx<R> sh[12][kMaxBvh];    // even-phase output read by the odd phase (and, lean: both ways)
+  __shared__ cx<R> sh_o[12][kX];       // odd-phase output read by the even phase
+  __shared__ cx<R> sh_r[12][kX];       // odd residual r_o
+  __shared__ cx<R> se_acc[12][kE];     // e_e
   __shared__ R red[3 * (kMaxBvh / 64 + 1)];
+  cx<R>(*sh_odd)[kMaxBvh] = kLean ? sh : (cx<R>(*)[kMaxBvh])sh_o;
 
   int tile, r;
   xcd_tile_rhs(nrhs, tile, r);
@@ -74,37 +87,44 @@ __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __re
   const long long Io = Ie + g.Bvh;
 
   auto fetch_x = [&](long long J, bool, cx<R>* p) { load_spinor<R, Tv>(x, V, J, p); };
+  auto fetch_sh = [&](long long J, bool, cx<R>* p) {
+    int jj = (int)(J & (g.Bvh - 1));
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = sh[c][jj];
+  };
+  auto fetch_odd = [&](long long J, bool, cx<R>* p) {
+    int jj = (int)(J & (g.Bvh - 1));
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = sh_odd[c][jj];
+  };
   auto fetch_e = [&](long long J, bool, cx<R>* p) {
     int jj = (int)(J & (g.Bvh - 1));
 #pragma unroll
-    for (int c = 0; c < 12; ++c) p[c] = sh_e[c][jj];
-  };
-  auto fetch_o = [&](long long J, bool, cx<R>* p) {
-    int jj = (int)(J & (g.Bvh - 1));
-#pragma unroll
-    for (int c = 0; c < 12; ++c) p[c] = sh_o[c][jj];
+    for (int c = 0; c < 12; ++c) p[c] = se_acc[c][jj];
   };
 
-  cx<R> rho[12], e[12], t[12];
+  cx<R> rho[12], t[12], e[kLean ? 1 : 12];
   SiteLoc se, so;
   if (act) {
     se = decode_site(g, Ie);
     so = decode_site(g, Io);
-    // odd site: r_o = b - D x, kept in LDS; A_oo^-1 r_o to the exchange buffer
-    load_spinor<R, Tv>(x, V, Io, e);
-    clover_mul<R, S, false>(clov, V, Io, e, t);
+    // odd site: r_o = b - D x (kept in the register layout), A_oo^-1 r_o to the exchange buffer
+    load_spinor<R, Tv>(x, V, Io, rho);
+    clover_mul<R, S, false>(clov, V, Io, rho, t);
     load_spinor<R, Tv>(b, V, Io, rho);
 #pragma unroll
     for (int c = 0; c < 12; ++c) rho[c] = rho[c] - t[c];
     hop_all<R, S>(g, links, so, Io, false, fetch_x, rho, (R)-1);
+    if (!kLean) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) sh_r[c][j] = rho[c];
+      for (int c = 0; c < 12; ++c) sh_r[c][j] = rho[c];
+    }
     clover_mul<R, S, false>(cinv, V, Io, rho, t);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) sh_o[c][j] = t[c];
+    for (int c = 0; c < 12; ++c) sh_odd[c][j] = t[c];
     // even site: r_e = b - D x
-    load_spinor<R, Tv>(x, V, Ie, e);
-    clover_mul<R, S, false>(clov, V, Ie, e, t);
+    load_spinor<R, Tv>(x, V, Ie, rho);
+    clover_mul<R, S, false>(clov, V, Ie, rho, t);
     load_spinor<R, Tv>(b, V, Ie, rho);
 #pragma unroll
     for (int c = 0; c < 12; ++c) rho[c] = rho[c] - t[c];
@@ -113,33 +133,40 @@ __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __re
   __syncthreads();
   if (act) {
     // rhs_e = r_e - H_eo A_oo^-1 r_o ; MR starts from e_e = 0 with rho = rhs_e
-    hop_all<R, S>(g, links, se, Ie, true, fetch_o, rho, (R)-1);
+    hop_all<R, S>(g, links, se, Ie, true, fetch_odd, rho, (R)-1);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) e[c] = {(R)0, (R)0};
+    for (int c = 0; c < 12; ++c) {
+      if (kLean) se_acc[c][j] = {(R)0, (R)0};
+      else e[c] = {(R)0, (R)0};
+    }
   }
 #pragma unroll 1
   for (int k = 0; k < mr_iters; ++k) {
+    if (kLean) __syncthreads();   // every read of the shared buffer is done before it is rewritten
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sh_e[c][j] = rho[c];
+      for (int c = 0; c < 12; ++c) sh[c][j] = rho[c];
     }
     __syncthreads();
+    cx<R> u[12];
     if (act) {
       // odd: u = A_oo^-1 H_oe rho
 #pragma unroll
       for (int c = 0; c < 12; ++c) t[c] = {(R)0, (R)0};
-      hop_all<R, S>(g, links, so, Io, true, fetch_e, t);
-      cx<R> u[12];
+      hop_all<R, S>(g, links, so, Io, true, fetch_sh, t);
       clover_mul<R, S, false>(cinv, V, Io, t, u);
+    }
+    if (kLean) __syncthreads();
+    if (act) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) sh_o[c][j] = u[c];
+      for (int c = 0; c < 12; ++c) sh_odd[c][j] = u[c];
     }
     __syncthreads();
     R pr_re = 0, pr_im = 0, pp = 0;
     if (act) {
       // even: p = A_ee rho - H_eo u   (kept in t)
       clover_mul<R, S, false>(clov, V, Ie, rho, t);
-      hop_all<R, S>(g, links, se, Ie, true, fetch_o, t, (R)-1);
+      hop_all<R, S>(g, links, se, Ie, true, fetch_odd, t, (R)-1);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         cx<R> q = cmul_conj(t[c], rho[c]);   // conj(p) rho
@@ -148,41 +175,64 @@ __global__ void __launch_bounds__(kMaxBvh) k_sap_colour(GeomDev g, const S* __re
         pp += t[c].re * t[c].re + t[c].im * t[c].im;
       }
     }
-    block_sum3(pr_re, pr_im, pp, red);
+    block_sum3(pr_re, pr_im, pp, red);   // its barriers also close the reads of the exchange buffers
     if (act) {
       cx<R> alpha = {(R)0, (R)0};
       if (pp > (R)0) alpha = {pr_re / pp, pr_im / pp};
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        cfma(e[c], alpha, rho[c]);
+        if (kLean) {
+          cx<R> ev = se_acc[c][j];
+          cfma(ev, alpha, rho[c]);
+          se_acc[c][j] = ev;
+        } else {
+          cfma(e[c], alpha, rho[c]);
+        }
         rho[c] = rho[c] - alpha * t[c];
       }
     }
   }
-  if (act) {
+  if (kLean) {
+    if (act) {
+      // r_o again (x is still the old x everywhere it is read)
+      load_spinor<R, Tv>(x, V, Io, t);
+      clover_mul<R, S, false>(clov, V, Io, t, rho);
+      load_spinor<R, Tv>(b, V, Io, t);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) sh_e[c][j] = e[c];
+      for (int c = 0; c < 12; ++c) rho[c] = t[c] - rho[c];
+      hop_all<R, S>(g, links, so, Io, false, fetch_x, rho, (R)-1);
+    }
+    __syncthreads();   // all reads of the old x are done before x is written
+  } else {
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sh[c][j] = e[c];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (act) {
     // x_e += e_e
     load_spinor<R, Tv>(x, V, Ie, t);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) t[c] = t[c] + e[c];
+    for (int c = 0; c < 12; ++c) t[c] = t[c] + (kLean ? se_acc[c][j] : e[c]);
     store_spinor<R, Tv>(x, V, Ie, t);
     // e_o = A_oo^-1 (r_o - H_oe e_e);  x_o += e_o
+    if (kLean) {
+      hop_all<R, S>(g, links, so, Io, true, fetch_e, rho, (R)-1);
+    } else {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) rho[c] = sh_r[c][j];
-    hop_all<R, S>(g, links, so, Io, true, fetch_e, rho, (R)-1);
+      for (int c = 0; c < 12; ++c) rho[c] = sh_r[c][j];
+      hop_all<R, S>(g, links, so, Io, true, fetch_sh, rho, (R)-1);
+    }
     clover_mul<R, S, false>(cinv, V, Io, rho, t);
-    load_spinor<R, Tv>(x, V, Io, e);
+    load_spinor<R, Tv>(x, V, Io, rho);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) e[c] = e[c] + t[c];
-    store_spinor<R, Tv>(x, V, Io, e);
+    for (int c = 0; c < 12; ++c) rho[c] = rho[c] + t[c];
+    store_spinor<R, Tv>(x, V, Io, rho);
   }
 }
 
-template <typename R, typename S, typename Tv>
+template <typename R, typename S, typename Tv, int WPE>
 void run(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const void* b, void* x, hipStream_t st) {
   int threads = ((g.Bvh + 63) / 64) * 64;
   unsigned nb = xcd_grid(g.Vch, nrhs);
@@ -194,7 +244,7 @@ void run(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour)
       DD_TIMED("k_sap_colour", st, bytes, flops,
-               (k_sap_colour<R, S, Tv><<<nb, threads, 0, st>>>(g, (const S*)ops.links, (const S*)ops.clover,
+               (k_sap_colour<R, S, Tv, WPE><<<nb, threads, 0, st>>>(g, (const S*)ops.links, (const S*)ops.clover,
                                                                (const S*)ops.cinv, nrhs, colour, mr, (const Tv*)b,
                                                                (Tv*)x)));
 }
@@ -202,11 +252,17 @@ void run(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const
 }  // namespace
 
 void launch_sap(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters, const void* b,
-                void* x, hipStream_t st) {
-  switch (dt) {
-    case DD_F64: run<double, double2, double2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
-    case DD_F32: run<float, float2, float2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
-    case DD_F16: run<float, __half2, float2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
-    case DD_BF16: run<float, bf16x2, float2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
+                void* x, int wpe, hipStream_t st) {
+#define DD_SAP_WPE(R, S, Tv)                                                   \
+  switch (wpe) {                                                               \
+    case 3: run<R, S, Tv, 3>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break; \
+    default: run<R, S, Tv, 2>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break; \
   }
+  switch (dt) {
+    case DD_F64: run<double, double2, double2, 1>(g, ops, nrhs, sweeps, mr_iters, b, x, st); break;
+    case DD_F32: DD_SAP_WPE(float, float2, float2) break;
+    case DD_F16: DD_SAP_WPE(float, __half2, float2) break;
+    case DD_BF16: DD_SAP_WPE(float, bf16x2, float2) break;
+  }
+#undef DD_SAP_WPE
 }
