@@ -151,13 +151,112 @@ def fp64_single_rhs(B, g, cfg, b, args):
                 outer_iters_mean=round(float(np.mean(iters)), 2), seconds=round(elapsed, 3))
 
 
+def measure(B, g, cfg, args, store_name, b):
+    """Setup with operands stored as `store_name`, autotune, warm up, then time
+    args.steps solves of the 12 sources (in calls of args.rhs_batch)."""
+    import torch
+    blk, n_vec = cfg["block"], cfg["n_vec"]
+    nrhs = b.shape[0]
+    store = B.DTYPES[store_name]
+    p = B.default_params(block=blk, n_vec=n_vec, setup_iters=cfg["setup_iters"], inner_dtype=B.DD_F32,
+                         store_dtype=store, seed=cfg["tv_seed"], coarse_restart=args.coarse_restart,
+                         coarse_max_iters=args.coarse_max_iters, coarse_cgs_passes=args.coarse_cgs_passes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg = B.MG(g, p)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"[bench] store {store_name}: setup {t_setup:.2f} s")
+    mg.dd_mg_set_graphs(args.graphs)
+    kb = min(args.rhs_batch, nrhs)
+    tuning = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        rep = mg.dd_autotune(kb, args.tune_cache)
+        tuning = dict(chosen=g.dd_gauge_get_tuning(), seconds=round(time.perf_counter() - t0, 2),
+                      candidates=[l for l in rep.splitlines() if " ms" in l])
+        log(f"[bench] autotune ({tuning['seconds']} s): " + "; ".join(rep.splitlines()[1:]))
+
+    def step():
+        info = []
+        for k0 in range(0, nrhs, kb):
+            bk = b[k0:k0 + kb]
+            xk = torch.zeros_like(bk)
+            ik, st = mg.dd_solve(bk.shape[0], bk, xk, TOL, raise_on_noconv=False)
+            bad = [k0 + r for r, i in enumerate(ik) if not (i["converged"] and i["true_relres"] <= TOL)]
+            if st or bad:
+                raise RuntimeError(f"solve did not converge (status {st}, rhs {bad}): {ik}")
+            info += ik
+        return info
+
+    for w in range(args.warmup):
+        info = step()
+        log(f"[bench] warmup {w}: outer iterations {[i['outer_iters'] for i in info]}")
+
+    B.kernel_timer_enable("*")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for s in range(args.steps):
+        ts = time.perf_counter()
+        infos.append(step())
+        log(f"[bench] step {s}: {time.perf_counter() - ts:.3f} s, max relres "
+            f"{max(i['true_relres'] for i in infos[-1]):.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # dominant kernel over the timed steps.  Launches replayed from graphs are not
+    # timed; then one more (untimed) step without graphs gives the full breakdown
+    kstats = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
+    B.kernel_timer_enable(None)
+    kfull, nfull = kstats, args.steps
+    if args.graphs:
+        mg.dd_mg_set_graphs(0)
+        B.kernel_timer_enable("*")
+        step()
+        torch.cuda.synchronize()
+        kfull = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
+        B.kernel_timer_enable(None)
+        nfull = 1
+    dom = max(kfull, key=lambda k: kfull[k]["ms"] / nfull)
+    # the timed steps' own figures when they saw every launch of that kernel
+    all_seen = dom in kstats and kstats[dom]["launches"] == kfull[dom]["launches"] * args.steps // nfull
+    ks = kstats[dom] if all_seen else kfull[dom]
+    avg_ms = ks["ms"] / max(ks["launches"], 1)
+    achieved = ks["bytes"] / (ks["ms"] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(dom, args.config, store_name), kernel=dom,
+                    algorithmic_bytes_per_launch=round(ks["bytes"] / max(ks["launches"], 1)),
+                    avg_launch_ms=round(avg_ms, 4), launches=ks["launches"],
+                    share_of_step=round(ks["ms"] / (1e3 * elapsed * (1 if all_seen else nfull / args.steps)), 3),
+                    timed_in="timed steps" if all_seen else "one extra step without graphs")
+    kernels = {k: dict(ms_per_step=round(v["ms"] / nfull, 3), launches_per_step=v["launches"] // nfull,
+                       GBs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
+               for k, v in sorted(kfull.items(), key=lambda kv: -kv[1]["ms"])}
+    outer = float(np.mean([i["outer_iters"] for inf in infos for i in inf]))
+    coarse_per_vcycle = float(np.mean([sum(i["coarse_iters_total"] for i in inf[::kb]) /
+                                       max(sum(max(i["outer_iters"] for i in inf[k0:k0 + kb])
+                                               for k0 in range(0, nrhs, kb)), 1) for inf in infos]))
+    value = nrhs * args.steps / elapsed
+    log(f"[bench] store {store_name}: {value:.2f} solves/s; dominant kernel {dom}: {achieved:.0f} GB/s; "
+        f"kernels {kernels}")
+    mg.destroy()
+    return dict(value=round(value, 3), ms_per_step=round(1e3 * elapsed / args.steps, 2), elapsed=elapsed,
+                setup_s=round(t_setup, 3), outer=round(outer, 2), coarse_per_vcycle=coarse_per_vcycle,
+                tuning=tuning, roofline=roofline, kernels=kernels)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C3")
-    ap.add_argument("--store", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--store", default="f32",
+                    help="operand storage f32|f16|bf16; a comma list measures each in turn (the first is `value`)")
+    ap.add_argument("--rhs-batch", type=int, default=12,
+                    help="right-hand sides per solve call (the 12 sources go in sub-batches of this size)")
     ap.add_argument("--coarse-restart", type=int, default=60)
     ap.add_argument("--coarse-max-iters", type=int, default=300)
     ap.add_argument("--coarse-cgs-passes", type=int, default=1)
@@ -196,97 +295,23 @@ def main():
     L, blk, n_vec = cfg["L"], cfg["block"], cfg["n_vec"]
     V = int(np.prod(L))
     nrhs = 12
-    store = B.DTYPES[args.store]
     log(f"[bench] workload {args.config}: L={L} block={blk} n={n_vec} m0={cfg['m0']:.5f} store={args.store}")
     t0 = time.perf_counter()
     U = su3_field(L, cfg["eps"], cfg["gauge_seed"])
     log(f"[bench] gauge field generated on the host in {time.perf_counter() - t0:.1f} s")
 
-    ctx = B.Context(0, hbm_budget_bytes=250 << 30)
+    ctx = B.Context(0, hbm_budget_bytes=270 << 30)
     g = B.Gauge(ctx, L, blk, U, cfg["m0"], cfg["c_sw"])
     del U
-    p = B.default_params(block=blk, n_vec=n_vec, setup_iters=cfg["setup_iters"], inner_dtype=B.DD_F32,
-                         store_dtype=store, seed=cfg["tv_seed"], coarse_restart=args.coarse_restart,
-                         coarse_max_iters=args.coarse_max_iters, coarse_cgs_passes=args.coarse_cgs_passes)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mg = B.MG(g, p)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    log(f"[bench] setup {t_setup:.2f} s")
-    mg.dd_mg_set_graphs(args.graphs)
-    tuning = None
-    if args.autotune:
-        t0 = time.perf_counter()
-        rep = mg.dd_autotune(nrhs, args.tune_cache)
-        tuning = dict(chosen=g.dd_gauge_get_tuning(), seconds=round(time.perf_counter() - t0, 2),
-                      candidates=[l for l in rep.splitlines() if " ms" in l])
-        log(f"[bench] autotune ({tuning['seconds']} s): " + "; ".join(rep.splitlines()[1:]))
-
     # the 12 spin-colour point sources at the origin, canonical complex128 on the device
     b = torch.zeros((nrhs, V * 12), dtype=torch.complex128, device="cuda")
     for k in range(nrhs):
         b[k, k] = 1.0
-    x = torch.zeros_like(b)
-
-    def step():
-        info, st = mg.dd_solve(nrhs, b, x, TOL, raise_on_noconv=False)
-        bad = [r for r, i in enumerate(info) if not (i["converged"] and i["true_relres"] <= TOL)]
-        if st or bad:
-            raise RuntimeError(f"solve did not converge (status {st}, rhs {bad}): {info}")
-        return info
-
-    for w in range(args.warmup):
-        info = step()
-        log(f"[bench] warmup {w}: outer iterations {[i['outer_iters'] for i in info]}, "
-            f"{info[0]['t_solve_s']:.3f} s")
-
-    B.kernel_timer_enable("*")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for s in range(args.steps):
-        infos.append(step())
-        log(f"[bench] step {s}: {infos[-1][0]['t_solve_s']:.3f} s, max relres "
-            f"{max(i['true_relres'] for i in infos[-1]):.2e}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = nrhs * args.steps / elapsed
-
-    # dominant kernel over the timed steps.  Launches replayed from graphs are not
-    # timed; then one more (untimed) step without graphs gives the full breakdown
-    kstats = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
-    B.kernel_timer_enable(None)
-    kfull, nfull = kstats, args.steps
-    if args.graphs:
-        mg.dd_mg_set_graphs(0)
-        B.kernel_timer_enable("*")
-        step()
-        torch.cuda.synchronize()
-        kfull = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
-        B.kernel_timer_enable(None)
-        nfull = 1
-    dom = max(kfull, key=lambda k: kfull[k]["ms"] / nfull)
-    # the timed steps' own figures when they saw every launch of that kernel
-    all_seen = dom in kstats and kstats[dom]["launches"] == kfull[dom]["launches"] * args.steps // nfull
-    ks = kstats[dom] if all_seen else kfull[dom]
-    avg_ms = ks["ms"] / max(ks["launches"], 1)
-    achieved = ks["bytes"] / (ks["ms"] * 1e-3) / 1e9
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(dom, args.config, args.store), kernel=dom,
-                    algorithmic_bytes_per_launch=round(ks["bytes"] / max(ks["launches"], 1)),
-                    avg_launch_ms=round(avg_ms, 4), launches=ks["launches"],
-                    share_of_step=round(ks["ms"] / (1e3 * elapsed * (1 if all_seen else nfull / args.steps)), 3),
-                    timed_in="timed steps" if all_seen else "one extra step without graphs")
-    kernels = {k: dict(ms_per_step=round(v["ms"] / nfull, 3), launches_per_step=v["launches"] // nfull,
-                       GBs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
-               for k, v in sorted(kfull.items(), key=lambda kv: -kv[1]["ms"])}
-    outer = np.mean([i["outer_iters"] for inf in infos for i in inf])
-    coarse_per_vcycle = np.mean([inf[0]["coarse_iters_total"] / max(max(i["outer_iters"] for i in inf), 1)
-                                 for inf in infos])
-    log(f"[bench] {value:.2f} solves/s; dominant kernel {dom}: {achieved:.0f} GB/s; kernels {kernels}")
+    stores = [s_.strip() for s_ in args.store.split(",")]
+    runs = [measure(B, g, cfg, args, st_, b) for st_ in stores]
+    r0 = runs[0]
+    value, ms_per_step, elapsed = r0["value"], r0["ms_per_step"], r0["elapsed"]
+    outer, coarse_per_vcycle = r0["outer"], r0["coarse_per_vcycle"]
 
     out = {
         "metric": "solves/s @ true rel.res 1e-10 (32^3x64, 12 RHS)",
@@ -301,18 +326,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 outer / f32 inner",
         "data": "synthetic (seeded SU(3) links, point sources)",
-        "config": {"workload": f"{args.config}: {L[0]}^3x{L[3]} Wilson-clover, 12 point-source RHS batched, "
-                               f"2-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
-                   "lattice": list(L), "rhs": nrhs, "m0": cfg["m0"], "c_sw": cfg["c_sw"], "eps": cfg["eps"],
-                   "store_dtype": args.store, "graphs": bool(args.graphs), "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
+        "config": {"workload": f"{args.config}: {L[0]}^3x{L[3]} Wilson-clover, 12 point-source RHS "
+                               f"(solve calls of {args.rhs_batch}), 2-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
+                   "lattice": list(L), "rhs": nrhs, "rhs_batch": args.rhs_batch, "m0": cfg["m0"],
+                   "c_sw": cfg["c_sw"], "eps": cfg["eps"], "store_dtype": stores[0], "graphs": bool(args.graphs),
+                   "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
                    "outer_iters_mean": round(float(outer), 2),
                    "coarse_iters_per_vcycle": round(float(coarse_per_vcycle), 1),
-                   "setup_s": round(t_setup, 3),
-                   "solves_per_s_incl_setup": round(nrhs / (t_setup + elapsed / args.steps), 3),
-                   "tuning": tuning,
+                   "setup_s": r0["setup_s"],
+                   "solves_per_s_incl_setup": round(nrhs / (r0["setup_s"] + elapsed / args.steps), 3),
+                   "tuning": r0["tuning"],
+                   "other_stores": {st_: {k: r[k] for k in ("value", "ms_per_step", "setup_s", "outer")}
+                                    for st_, r in zip(stores[1:], runs[1:])},
                    "parallelism": "1 GPU"},
-        "roofline": roofline,
-        "kernels": kernels,
+        "roofline": r0["roofline"],
+        "kernels": r0["kernels"],
     }
     if not args.no_dapply:
         log("[bench] D-apply bandwidth table")
@@ -326,7 +354,6 @@ def main():
         log("[bench] timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cfg, L, n_vec, float(outer), float(coarse_per_vcycle))
     print(json.dumps(out), flush=True)
-    mg.destroy()
     g.destroy()
     ctx.close()
 

@@ -429,8 +429,21 @@ static dd_status build(dd_mg* mg, hipStream_t st) {
     if (mg->vstore == DD_F32) {
       launch_convert_pairs(DD_F32, mg->P64, nullptr, mg->Pst, nfine, st);
     } else {
-      launch_convert_pairs(DD_F32, mg->P64, nullptr, mg->Pst32tmp, nfine, st);
-      launch_convert_pairs(mg->vstore, nullptr, (const float2*)mg->Pst32tmp, mg->Pst, nfine, st);
+      // through an FP32 staging buffer of at most 2^27 pairs (1 GiB), chunk by chunk
+      const long long cap = 1LL << 27, len = nfine < cap ? nfine : cap;
+      float2* stage = nullptr;
+      if ((s = dd_alloc(mg->ctx, (void**)&stage, sizeof(float2) * len))) {
+        dd_free(mg->ctx, dflag, sizeof(int));
+        return s;
+      }
+      const size_t pb = storage_pair_bytes(mg->vstore);
+      for (long long o = 0; o < nfine; o += len) {
+        const long long cnt = nfine - o < len ? nfine - o : len;
+        launch_convert_pairs(DD_F32, mg->P64 + o, nullptr, stage, cnt, st);
+        launch_convert_pairs(mg->vstore, nullptr, stage, (char*)mg->Pst + o * pb, cnt, st);
+      }
+      DD_HIP(mg->ctx, hipStreamSynchronize(st));
+      dd_free(mg->ctx, stage, sizeof(float2) * len);
     }
   }
   // Galerkin operator from the stored P and the FP64 operator
@@ -471,9 +484,6 @@ static size_t mg_bytes_tv(const dd_mg* mg) { return vector_pair_bytes(inner_vt(m
 static size_t mg_bytes_Pst(const dd_mg* mg) {
   return mg->vstore == DD_F64 ? 0 : storage_pair_bytes(mg->vstore) * 12ULL * mg->g->geo.V * mg->n;
 }
-static size_t mg_bytes_P32tmp(const dd_mg* mg) {
-  return (mg->vstore == DD_F16 || mg->vstore == DD_BF16) ? 8ULL * 12 * mg->g->geo.V * mg->n : 0;
-}
 static size_t mg_bytes_Dc(const dd_mg* mg, size_t pb) { return pb * mg->g->geo.Vc * 9ULL * mg->nc * mg->nc; }
 static size_t mg_bytes_Dinv(const dd_mg* mg, size_t pb) { return pb * mg->g->geo.Vch * 1ULL * mg->nc * mg->nc; }
 
@@ -482,7 +492,6 @@ static void mg_free(dd_mg* mg) {
   dd_free(mg->ctx, mg->P64, mg_bytes_P64(mg));
   dd_free(mg->ctx, mg->tv, mg_bytes_tv(mg));
   dd_free(mg->ctx, mg->Pst, mg_bytes_Pst(mg));
-  dd_free(mg->ctx, mg->Pst32tmp, mg_bytes_P32tmp(mg));
   dd_free(mg->ctx, mg->Dc64, mg_bytes_Dc(mg, 16));
   dd_free(mg->ctx, mg->Dc32, mg_bytes_Dc(mg, 8));
   dd_free(mg->ctx, mg->Dinv64, mg_bytes_Dinv(mg, 16));
@@ -537,7 +546,6 @@ static dd_status setup_common(dd_gauge* g, const dd_mg_params* p, const double* 
   if ((s = dd_alloc(mg->ctx, (void**)&mg->P64, mg_bytes_P64(mg))) ||
       (s = dd_alloc(mg->ctx, (void**)&mg->tv, mg_bytes_tv(mg))) ||
       (s = dd_alloc(mg->ctx, (void**)&mg->Pst, mg_bytes_Pst(mg))) ||
-      (s = dd_alloc(mg->ctx, (void**)&mg->Pst32tmp, mg_bytes_P32tmp(mg))) ||
       (s = dd_alloc(mg->ctx, (void**)&mg->Dc64, mg_bytes_Dc(mg, 16))) ||
       (s = dd_alloc(mg->ctx, (void**)&mg->Dc32, mg_bytes_Dc(mg, 8))) ||
       (s = dd_alloc(mg->ctx, (void**)&mg->Dinv64, mg_bytes_Dinv(mg, 16))) ||

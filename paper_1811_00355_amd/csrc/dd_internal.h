@@ -299,7 +299,6 @@ struct dd_mg {
   // test vectors: FP64 master of the orthonormalised P (packed fine layout, n vectors)
   double2* P64 = nullptr;
   void* Pst = nullptr;       // P in the storage dtype (float2 / __half2 / bf16x2)
-  void* Pst32tmp = nullptr;  // FP32 staging of P for half-precision storage
   void* tv = nullptr;        // working test vectors lambda_i (inner dtype)
   // coarse operator: [Vc][9][col][row] complex (column-major blocks), FP64 master and FP32
   double2* Dc64 = nullptr;

@@ -41,21 +41,22 @@ def gauge_bytes(V, store_bytes=8, Vc=0):
     return V * 3 * 36 * (16 + 8 + (store_bytes if store_bytes != 8 else 0)) + 36 * Vc
 
 
-def setup_transient_bytes(V, Vc, n, coarse_m=60, inner_bytes=8):
+def setup_transient_bytes(V, Vc, n, coarse_m=60, inner_bytes=8, store_bytes=8):
     """Scratch that exists only while a setup runs: the V-cycle workspace for
-    the n test vectors and the coarse-build chunk (at most 4 GiB)."""
+    the n test vectors, the coarse-build chunk (at most 4 GiB) and, for half
+    storage, the FP32 staging of P (at most 1 GiB)."""
     nc = 2 * n
+    stage = min(1 << 30, 8 * 12 * V * n) if store_bytes == 4 else 0
     return (inner_bytes * 12 * V * n * 2 + inner_bytes * Vc * nc * n * (coarse_m + 8) +
-            min(4 << 30, 16 * 12 * V * nc))
+            min(4 << 30, 16 * 12 * V * nc) + stage)
 
 
 def setup_bytes(V, Vc, n, store_bytes=8, inner_bytes=8):
-    """FP64 P, working vectors (inner type), stored P, FP32 staging for half
-    storage, coarse operator and odd-site inverses in FP64 and FP32."""
+    """FP64 P, working vectors (inner type), stored P, coarse operator and
+    odd-site inverses in FP64 and FP32."""
     nc = 2 * n
     fine = 12 * V * n
-    half_stage = 8 * fine if store_bytes == 4 else 0
-    return (16 + inner_bytes + store_bytes) * fine + half_stage + (16 + 8) * Vc * nc * nc * (9 + 0.5)
+    return (16 + inner_bytes + store_bytes) * fine + (16 + 8) * Vc * nc * nc * (9 + 0.5)
 
 
 def workspace_bytes(V, Vc, n, nrhs, m=10, coarse_m=60, inner_bytes=8):
@@ -272,7 +273,7 @@ class GpuExecutor:
         return gauge_bytes(f.V, self.store_bytes, self._Vc(f)) + setup_bytes(f.V, self._Vc(f), self.n, self.store_bytes)
 
     def transient(self, f):
-        return setup_transient_bytes(f.V, self._Vc(f), self.n)
+        return setup_transient_bytes(f.V, self._Vc(f), self.n, store_bytes=self.store_bytes)
 
     def workspace(self, f, nrhs):
         return workspace_bytes(f.V, self._Vc(f), self.n, nrhs)
@@ -357,7 +358,7 @@ def main(argv=None):
     ap.add_argument("--capacity-requests", type=int, default=60)
     ap.add_argument("--per-shape", type=int, default=2)
     ap.add_argument("--load", type=float, default=0.7, help="arrival rate as a fraction of measured capacity")
-    ap.add_argument("--hbm-gib", type=float, default=250.0)
+    ap.add_argument("--hbm-gib", type=float, default=230.0)
     ap.add_argument("--store", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--shapes", default="all", help="'all' or a count of the smallest shapes to use")
     args = ap.parse_args(argv)
