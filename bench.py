@@ -5,6 +5,9 @@ Workload (default): 32^3x64 lattice, links exp(i*0.2*H) reunitarised, c_sw = 1,
 m0 from the tuned-mass table, 4^4 aggregates/SAP domains, n = 20 test vectors,
 4 adaptive setup iterations, the 12 spin-colour point sources at the origin
 solved together to a true relative residual of 1e-10 with the FP64 operator.
+Links, clover, clover inverse and test vectors are stored in BF16 for the FP32
+inner solver (--store f32 / f16 for the other forms); the outer solver, the
+Gram-Schmidt and the coarse-operator build run in FP64.
 Inputs are synthetic and seeded (there is no gauge-field dataset here).
 
 A step is one batched solve of the 12 right-hand sides with the setup resident
@@ -13,7 +16,7 @@ steps.  The line also carries the roofline of the dominant kernel (timed with
 HIP events on its launch stream over the timed steps) and the oracle's CPU
 throughput on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C3] [--store f32|f16|bf16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C3] [--store bf16|f16|f32[,...]]
 """
 import argparse
 import json
@@ -253,7 +256,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C3")
-    ap.add_argument("--store", default="f32",
+    ap.add_argument("--store", default="bf16",
                     help="operand storage f32|f16|bf16; a comma list measures each in turn (the first is `value`)")
     ap.add_argument("--rhs-batch", type=int, default=12,
                     help="right-hand sides per solve call (the 12 sources go in sub-batches of this size)")

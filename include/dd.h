@@ -121,6 +121,7 @@ typedef struct {
   int32_t sap_wpe;        /* SAP waves per SIMD the registers allow: 2 or 3          */
   int32_t dirac_threads;  /* D apply workgroup size: 64, 128 or 256                    */
   int32_t coarse_spw;     /* FP32 coarse apply: coarse sites per workgroup, 2, 4 or 8  */
+  int32_t coarse_half;    /* half-precision setups: coarse blocks in FP16/BF16 (1) or FP32 (0) */
 } dd_tuning;
 
 /* ---- gauge field (field preparation) ---------------------------------------
@@ -191,7 +192,8 @@ dd_status dd_mg_release_workspace(dd_mg* mg);
 /* ---- autotuner --------------------------------------------------------------------------
  * dd_autotune times every launch-shape candidate of the smoother (waves per
  * SIMD), the FP64 D apply (workgroup size) and the FP32 coarse stencil (sites
- * per workgroup) on this setup's own operators and workspace for nrhs
+ * per workgroup; for half-precision setups also FP32 against half blocks) on
+ * this setup's own operators and workspace for nrhs
  * right-hand sides, keeps the fastest in the gauge field (shared by every setup
  * on it) and returns a text report (report may be NULL).  cache_path (may be
  * NULL) names a JSON file of earlier choices keyed by device architecture,
@@ -212,7 +214,10 @@ dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t);
 dd_status dd_setup_update_mass(dd_mg* mg, double m0);
 
 /* ---- transfer and coarse operator -------------------------------------------------------
- * DD_F64 or DD_F32 (coarse data in that precision). */
+ * DD_F64 or DD_F32 vectors.  With DD_F32 the coarse operator is the one the
+ * FP32 inner solver uses: FP32 blocks, or, for a setup that stores its operands
+ * in a half type and whose gauge field's tuning has coarse_half = 1, FP16 /
+ * BF16 blocks rounded from the FP32 copy. */
 dd_status dd_restrict(dd_mg* mg, dd_dtype dt, int nrhs, const void* fine_in, void* coarse_out,
                       void* stream);   /* Eq. 3 */
 dd_status dd_prolong(dd_mg* mg, dd_dtype dt, int nrhs, const void* coarse_in, void* fine_out,

@@ -44,7 +44,8 @@ class dd_mg_params(ctypes.Structure):
 
 
 class dd_tuning(ctypes.Structure):
-    _fields_ = [("sap_wpe", ctypes.c_int32), ("dirac_threads", ctypes.c_int32), ("coarse_spw", ctypes.c_int32)]
+    _fields_ = [("sap_wpe", ctypes.c_int32), ("dirac_threads", ctypes.c_int32), ("coarse_spw", ctypes.c_int32),
+                ("coarse_half", ctypes.c_int32)]
 
 
 class dd_solve_info(ctypes.Structure):
@@ -215,14 +216,15 @@ class Gauge:
             self.ctx.check(self.ctx.lib.dd_gauge_destroy(self.h))
             self.h = _P()
 
-    def dd_gauge_set_tuning(self, sap_wpe, dirac_threads, coarse_spw):
-        t = dd_tuning(sap_wpe, dirac_threads, coarse_spw)
+    def dd_gauge_set_tuning(self, sap_wpe, dirac_threads, coarse_spw, coarse_half=0):
+        t = dd_tuning(sap_wpe, dirac_threads, coarse_spw, coarse_half)
         self.ctx.check(self.ctx.lib.dd_gauge_set_tuning(self.h, ctypes.byref(t)))
 
     def dd_gauge_get_tuning(self):
         t = dd_tuning()
         self.ctx.check(self.ctx.lib.dd_gauge_get_tuning(self.h, ctypes.byref(t)))
-        return dict(sap_wpe=t.sap_wpe, dirac_threads=t.dirac_threads, coarse_spw=t.coarse_spw)
+        return dict(sap_wpe=t.sap_wpe, dirac_threads=t.dirac_threads, coarse_spw=t.coarse_spw,
+                    coarse_half=t.coarse_half)
 
     def dd_gauge_set_mass(self, m0):
         self.ctx.check(self.ctx.lib.dd_gauge_set_mass(self.h, m0))

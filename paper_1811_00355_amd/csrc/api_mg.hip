@@ -233,7 +233,8 @@ struct CoarseOps {
   dd_dtype vt;
   int nc;
   const void *Dc, *Dinv;
-  int spw;   // FP32 coarse apply: sites per workgroup
+  int spw;       // FP32 coarse apply: sites per workgroup
+  dd_dtype bt;   // storage of the blocks (FP32 vectors may use FP32, FP16 or BF16 blocks)
 };
 
 static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
@@ -241,8 +242,10 @@ static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
   c.g = &mg->g->geo;
   c.vt = vt;
   c.nc = mg->nc;
-  c.Dc = vt == DD_F64 ? (const void*)mg->Dc64 : (const void*)mg->Dc32;
-  c.Dinv = vt == DD_F64 ? (const void*)mg->Dinv64 : (const void*)mg->Dinv32;
+  const bool half = vt == DD_F32 && mg->Dch && mg->g->tune.coarse_half;
+  c.Dc = vt == DD_F64 ? (const void*)mg->Dc64 : half ? (const void*)mg->Dch : (const void*)mg->Dc32;
+  c.Dinv = vt == DD_F64 ? (const void*)mg->Dinv64 : half ? (const void*)mg->Dinvh : (const void*)mg->Dinv32;
+  c.bt = vt == DD_F64 ? DD_F64 : half ? mg->vstore : DD_F32;
   c.spw = mg->g->tune.coarse_spw;
   return c;
 }
@@ -250,9 +253,9 @@ static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
 // out_e = S v_e = D_ee v_e - D_eo D_oo^-1 D_oe v_e   (t1, t2 scratch, odd parts used)
 static void schur_apply(const CoarseOps& c, int nrhs, const void* v, void* out, void* t1, void* t2, hipStream_t st) {
   const GeomDev& g = *c.g;
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, 1.0, v, 0.0, nullptr, t1, st, c.spw);
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, t1, 0.0, nullptr, 0.0, nullptr, t2, st, c.spw);
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 1.0, v, -1.0, t2, 0.0, nullptr, out, st, c.spw);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, 1.0, v, 0.0, nullptr, t1, st, c.spw, c.bt);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, t1, 0.0, nullptr, 0.0, nullptr, t2, st, c.spw, c.bt);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 1.0, v, -1.0, t2, 0.0, nullptr, out, st, c.spw, c.bt);
 }
 
 // Arnoldi steps j0 .. j0+len-1 of one coarse GMRES cycle: w = S v_j, Gram-Schmidt,
@@ -317,8 +320,8 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
   const int cap = fixed ? mg->p.coarse_fixed_iters : mg->p.coarse_max_iters;
   const double tol = fixed ? 0.0 : mg->p.coarse_tol;
   // rhs' = b_e - D_eo D_oo^-1 b_o
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st, c.spw);
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st, c.spw);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st, c.spw, c.bt);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st, c.spw, c.bt);
   DD_HIP(mg->ctx, hipMemsetAsync(y, 0, (size_t)nrhs * ld * vb, st));
   // tolerance: tol * |rhs'|
   norms2(w, vt, nrhs, ce, ld, w->cr, a.nrm2, st);
@@ -376,8 +379,8 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
     if (nfin == nrhs) break;
   }
   // odd sites: y_o = D_oo^-1 (b_o - D_oe y_e)
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st, c.spw);
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st, c.spw);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st, c.spw, c.bt);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st, c.spw, c.bt);
   DD_HIP(mg->ctx, hipGetLastError());
   if (iters_out) *iters_out = iters;
   return DD_OK;
@@ -463,6 +466,10 @@ static dd_status build(dd_mg* mg, hipStream_t st) {
   const long long ndc = (long long)G.Vc * 9 * mg->nc * mg->nc, ndi = (long long)G.Vch * mg->nc * mg->nc;
   launch_convert_pairs(DD_F32, mg->Dc64, nullptr, mg->Dc32, ndc, st);
   launch_convert_pairs(DD_F32, mg->Dinv64, nullptr, mg->Dinv32, ndi, st);
+  if (mg->Dch) {   // half copies rounded from the FP32 ones, like every other stored operand
+    launch_convert_pairs(mg->vstore, nullptr, mg->Dc32, mg->Dch, ndc, st);
+    launch_convert_pairs(mg->vstore, nullptr, mg->Dinv32, mg->Dinvh, ndi, st);
+  }
   DD_HIP(mg->ctx, hipMemcpyAsync(&bad, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
   DD_HIP(mg->ctx, hipStreamSynchronize(st));
   dd_free(mg->ctx, W, (size_t)chunk * vbytes);
@@ -496,6 +503,8 @@ static void mg_free(dd_mg* mg) {
   dd_free(mg->ctx, mg->Dc32, mg_bytes_Dc(mg, 8));
   dd_free(mg->ctx, mg->Dinv64, mg_bytes_Dinv(mg, 16));
   dd_free(mg->ctx, mg->Dinv32, mg_bytes_Dinv(mg, 8));
+  dd_free(mg->ctx, mg->Dch, mg_bytes_Dc(mg, 4));
+  dd_free(mg->ctx, mg->Dinvh, mg_bytes_Dinv(mg, 4));
   if (mg->g) mg->g->refcount--;
   delete mg;
 }
@@ -551,6 +560,10 @@ static dd_status setup_common(dd_gauge* g, const dd_mg_params* p, const double* 
       (s = dd_alloc(mg->ctx, (void**)&mg->Dinv64, mg_bytes_Dinv(mg, 16))) ||
       (s = dd_alloc(mg->ctx, (void**)&mg->Dinv32, mg_bytes_Dinv(mg, 8))))
     return fail(s);
+  if ((mg->vstore == DD_F16 || mg->vstore == DD_BF16) &&
+      ((s = dd_alloc(mg->ctx, &mg->Dch, mg_bytes_Dc(mg, 4))) ||
+       (s = dd_alloc(mg->ctx, &mg->Dinvh, mg_bytes_Dinv(mg, 4)))))
+    return fail(s);
   if ((s = ensure_ws(mg, mg->n, false))) return fail(s);
   const GeomDev& G = g->geo;
   const long long nfine = 12LL * G.V * mg->n;
@@ -604,7 +617,8 @@ static dd_status check_mg_vec(dd_mg* mg, dd_dtype dt, int nrhs, const void* a, c
 
 // ---------------------------------------------------------------------------
 // autotuner cache: a JSON object, one entry per line,
-//   "<device>|L=..|b=..|n=..|nrhs=..|op=..|inner=..": {"sap_wpe": 2, "dirac_threads": 256, "coarse_spw": 4}
+//   "<device>|L=..|b=..|n=..|nrhs=..|op=..|inner=..":
+//       {"sap_wpe": 2, "dirac_threads": 256, "coarse_spw": 4, "coarse_half": 0}
 // Lines that do not parse are dropped (the file is rewritten on the next miss).
 // ---------------------------------------------------------------------------
 static bool tune_field(const std::string& obj, const char* name, int& v) {
@@ -626,7 +640,7 @@ static void tune_cache_read(const char* path, std::map<std::string, Tuning>& out
     std::string obj = l.substr(o, c - o + 1);
     Tuning t;
     if (tune_field(obj, "sap_wpe", t.sap_wpe) && tune_field(obj, "dirac_threads", t.dirac_threads) &&
-        tune_field(obj, "coarse_spw", t.coarse_spw))
+        tune_field(obj, "coarse_spw", t.coarse_spw) && tune_field(obj, "coarse_half", t.coarse_half))
       out[l.substr(a + 1, b - a - 1)] = t;
   }
   std::fclose(f);
@@ -639,8 +653,9 @@ static bool tune_cache_write(const char* path, const std::map<std::string, Tunin
   std::fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : m)
-    std::fprintf(f, " \"%s\": {\"sap_wpe\": %d, \"dirac_threads\": %d, \"coarse_spw\": %d}%s\n", kv.first.c_str(),
-                 kv.second.sap_wpe, kv.second.dirac_threads, kv.second.coarse_spw, ++i < m.size() ? "," : "");
+    std::fprintf(f, " \"%s\": {\"sap_wpe\": %d, \"dirac_threads\": %d, \"coarse_spw\": %d, \"coarse_half\": %d}%s\n",
+                 kv.first.c_str(), kv.second.sap_wpe, kv.second.dirac_threads, kv.second.coarse_spw,
+                 kv.second.coarse_half, ++i < m.size() ? "," : "");
   std::fprintf(f, "}\n");
   bool ok = std::fclose(f) == 0;
   return ok && std::rename(tmp.c_str(), path) == 0;
@@ -670,11 +685,13 @@ dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t) {
   if (!g || !t) return DD_EINVAL;
   if ((t->sap_wpe != 2 && t->sap_wpe != 3) ||
       (t->dirac_threads != 64 && t->dirac_threads != 128 && t->dirac_threads != 256) ||
-      (t->coarse_spw != 2 && t->coarse_spw != 4 && t->coarse_spw != 8))
-    return dd_fail(g->ctx, DD_EINVAL, "tuning: sap_wpe 2|3, dirac_threads 64|128|256, coarse_spw 2|4|8");
+      (t->coarse_spw != 2 && t->coarse_spw != 4 && t->coarse_spw != 8) || (t->coarse_half != 0 && t->coarse_half != 1))
+    return dd_fail(g->ctx, DD_EINVAL,
+                   "tuning: sap_wpe 2|3, dirac_threads 64|128|256, coarse_spw 2|4|8, coarse_half 0|1");
   g->tune.sap_wpe = t->sap_wpe;
   g->tune.dirac_threads = t->dirac_threads;
   g->tune.coarse_spw = t->coarse_spw;
+  g->tune.coarse_half = t->coarse_half;
   return DD_OK;
 }
 
@@ -683,6 +700,7 @@ dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t) {
   t->sap_wpe = g->tune.sap_wpe;
   t->dirac_threads = g->tune.dirac_threads;
   t->coarse_spw = g->tune.coarse_spw;
+  t->coarse_half = g->tune.coarse_half;
   return DD_OK;
 }
 
@@ -756,14 +774,32 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
     // FP32 coarse stencil (matrix cores)
     if (vt == DD_F32) {
       float bt = 1e30f;
+      const int half_was = g->tune.coarse_half;
+      g->tune.coarse_half = 0;
       for (int spw : {2, 4, 8}) {
         float t = time_ms([&] {
-          launch_coarse_mv(G, vt, mg->nc, mg->Dc32, mg->Dinv32, 0, nrhs, 0, G.Vc, 1.0, w->cb, 1.0, w->cb, 0.0, nullptr,
-                           w->cw, st, spw);
+          CoarseOps c = coarse_ops(mg, vt);
+          launch_coarse_mv(G, vt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, G.Vc, 1.0, w->cb, 1.0, w->cb, 0.0, nullptr, w->cw,
+                           st, spw, c.bt);
         });
         std::snprintf(line, sizeof(line), "k_coarse_mfma coarse_spw=%d %.3f ms\n", spw, t);
         rep += line;
         if (t < bt) bt = t, best.coarse_spw = spw;
+      }
+      g->tune.coarse_half = half_was;
+      if (mg->Dch) {
+        const Tuning keep = g->tune;
+        g->tune.coarse_spw = best.coarse_spw;
+        g->tune.coarse_half = 1;
+        CoarseOps c = coarse_ops(mg, vt);
+        float t = time_ms([&] {
+          launch_coarse_mv(G, vt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, G.Vc, 1.0, w->cb, 1.0, w->cb, 0.0, nullptr, w->cw,
+                           st, best.coarse_spw, c.bt);
+        });
+        g->tune = keep;
+        std::snprintf(line, sizeof(line), "k_coarse_mfma coarse_half=1 coarse_spw=%d %.3f ms\n", best.coarse_spw, t);
+        rep += line;
+        best.coarse_half = t < bt ? 1 : 0;
       }
     }
     (void)hipEventDestroy(e0);
@@ -775,8 +811,8 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
       rep += std::string("could not write ") + cache_path + "\n";
   }
   char line[128];
-  std::snprintf(line, sizeof(line), "chosen sap_wpe=%d dirac_threads=%d coarse_spw=%d\n", g->tune.sap_wpe,
-                g->tune.dirac_threads, g->tune.coarse_spw);
+  std::snprintf(line, sizeof(line), "chosen sap_wpe=%d dirac_threads=%d coarse_spw=%d coarse_half=%d\n",
+                g->tune.sap_wpe, g->tune.dirac_threads, g->tune.coarse_spw, g->tune.coarse_half);
   rep += line;
   if (report && report_cap) {
     std::strncpy(report, rep.c_str(), report_cap - 1);
@@ -851,7 +887,7 @@ dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
   if (s) return s;
   CoarseOps c = coarse_ops(mg, dt);
   launch_coarse_mv(mg->g->geo, dt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, mg->g->geo.Vc, 1.0, in, 1.0, in, 0.0, nullptr,
-                   out, (hipStream_t)stream, c.spw);
+                   out, (hipStream_t)stream, c.spw, c.bt);
   DD_HIP(mg->ctx, hipGetLastError());
   return DD_OK;
 }

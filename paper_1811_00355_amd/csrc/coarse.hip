@@ -95,9 +95,9 @@ constexpr int kMfmaMaxNc = 48;
 // whole block of one direction is loaded into registers before the staging
 // barrier, so its HBM reads overlap the LDS traffic and every MFMA operand is
 // already in flight.
-template <int NC, int SPW>
-__global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const float2* __restrict__ Dc,
-                                                          const float2* __restrict__ Minv, int use_inv, int nrhs,
+template <int NC, int SPW, typename Sd>
+__global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const Sd* __restrict__ Dc,
+                                                          const Sd* __restrict__ Minv, int use_inv, int nrhs,
                                                           int site_begin, int count, float a_self,
                                                           const float2* __restrict__ xs, float a_hop,
                                                           const float2* __restrict__ xh, float beta,
@@ -120,15 +120,16 @@ __global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const float
       const int Y = d == 0 ? X : (g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK);
       const float2* src = d == 0 ? xs : xh;
       const float sc = d == 0 ? a_self : a_hop;
-      const float2* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * NC * NC : Dc + (long long)X * 9 * NC * NC)
-                               : Dc + ((long long)X * 9 + d) * NC * NC;
-      float2 m[KS][MT];
+      const Sd* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * NC * NC : Dc + (long long)X * 9 * NC * NC)
+                           : Dc + ((long long)X * 9 + d) * NC * NC;
+      cx<float> m[KS][MT];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
           const int row = 16 * t + li;
-          m[ks][t] = (site_ok && row < NC) ? B[(long long)(4 * ks + lk) * NC + row] : make_float2(0.f, 0.f);
+          m[ks][t] = (site_ok && row < NC) ? ld<float, Sd>(B + (long long)(4 * ks + lk) * NC + row)
+                                           : cx<float>{0.f, 0.f};
         }
       __syncthreads();
       // stage sc * x(Y) as [col][rhs], zero padded to 16 right-hand sides
@@ -148,10 +149,10 @@ __global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const float
         const float2 xb = xsh[w][4 * ks + lk][li];
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
-          c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].x, xb.x, c0[t], 0, 0, 0);
-          c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].y, -xb.y, c0[t], 0, 0, 0);
-          c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].x, xb.y, c1[t], 0, 0, 0);
-          c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].y, xb.x, c1[t], 0, 0, 0);
+          c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].re, xb.x, c0[t], 0, 0, 0);
+          c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].im, -xb.y, c0[t], 0, 0, 0);
+          c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].re, xb.y, c1[t], 0, 0, 0);
+          c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].im, xb.x, c1[t], 0, 0, 0);
         }
       }
     }
@@ -177,23 +178,38 @@ __global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const float
   }
 }
 
-template <int NC>
-void mfma_spw(int spw, unsigned count, dim3& grid, dim3& blk, void (*&fn)(GeomDev, const float2*, const float2*, int, int,
-                                                                        int, int, float, const float2*, float,
-                                                                        const float2*, float, const float2*, float2*)) {
+typedef void (*MfmaFn)(GeomDev, const void*, const void*, int, int, int, int, float, const float2*, float,
+                       const float2*, float, const float2*, float2*);
+
+template <int NC, typename Sd>
+MfmaFn mfma_spw(int spw, unsigned count, dim3& grid, dim3& blk) {
+  MfmaFn fn;
   switch (spw) {
-    case 2: fn = k_coarse_mfma<NC, 2>; break;
-    case 8: fn = k_coarse_mfma<NC, 8>; break;
-    default: fn = k_coarse_mfma<NC, 4>; spw = 4; break;
+    case 2: fn = (MfmaFn)k_coarse_mfma<NC, 2, Sd>; break;
+    case 8: fn = (MfmaFn)k_coarse_mfma<NC, 8, Sd>; break;
+    default: fn = (MfmaFn)k_coarse_mfma<NC, 4, Sd>; spw = 4; break;
   }
   grid = dim3((count + spw - 1) / spw);
   blk = dim3(64 * spw);
+  return fn;
+}
+
+template <typename Sd>
+MfmaFn mfma_pick(int nc, int spw, unsigned count, dim3& grid, dim3& blk) {
+  switch (nc) {
+    case 12: return mfma_spw<12, Sd>(spw, count, grid, blk);
+    case 16: return mfma_spw<16, Sd>(spw, count, grid, blk);
+    case 24: return mfma_spw<24, Sd>(spw, count, grid, blk);
+    case 32: return mfma_spw<32, Sd>(spw, count, grid, blk);
+    case 40: return mfma_spw<40, Sd>(spw, count, grid, blk);
+    default: return mfma_spw<48, Sd>(spw, count, grid, blk);
+  }
 }
 
 template <typename R, typename Sd, typename Tv>
 void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv, int nrhs, int site_begin, int count,
         double a_self, const void* xs, double a_hop, const void* xh, double beta, const void* z, void* out,
-        hipStream_t st, int spw) {
+        hipStream_t st, int spw, dd_dtype bt) {
   if (count <= 0) return;
   const int nblocks_read = (a_self != 0.0 ? 1 : 0) + (a_hop != 0.0 ? 8 : 0);
   const double bytes = (double)count * nblocks_read * nc * nc * sizeof(Sd) +
@@ -207,22 +223,14 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
                                                              site_begin, count, (R)a_self, (const Tv*)xs, (R)a_hop, \
                                                              (const Tv*)xh, (R)beta, (const Tv*)z, (Tv*)out)))
   if (sizeof(R) == 4 && nc <= kMfmaMaxNc) {
-    typedef void (*Fn)(GeomDev, const float2*, const float2*, int, int, int, int, float, const float2*, float,
-                       const float2*, float, const float2*, float2*);
-    Fn fn = nullptr;
     dim3 grid, wg;
-    switch (nc) {
-      case 12: mfma_spw<12>(spw, count, grid, wg, fn); break;
-      case 16: mfma_spw<16>(spw, count, grid, wg, fn); break;
-      case 24: mfma_spw<24>(spw, count, grid, wg, fn); break;
-      case 32: mfma_spw<32>(spw, count, grid, wg, fn); break;
-      case 40: mfma_spw<40>(spw, count, grid, wg, fn); break;
-      default: mfma_spw<48>(spw, count, grid, wg, fn); break;
-    }
-    DD_TIMED("k_coarse_mfma", st, bytes, flops,
-             (fn<<<grid, wg, 0, st>>>(g, (const float2*)Dc, (const float2*)Minv, use_inv, nrhs, site_begin, count,
-                                      (float)a_self, (const float2*)xs, (float)a_hop, (const float2*)xh, (float)beta,
-                                      (const float2*)z, (float2*)out)));
+    MfmaFn fn = bt == DD_F16    ? mfma_pick<__half2>(nc, spw, count, grid, wg)
+                : bt == DD_BF16 ? mfma_pick<bf16x2>(nc, spw, count, grid, wg)
+                                : mfma_pick<float2>(nc, spw, count, grid, wg);
+    const double hb = bt == DD_F32 ? 1.0 : 0.5;   // half-precision blocks stream half the bytes
+    DD_TIMED("k_coarse_mfma", st, bytes - (1.0 - hb) * (double)count * nblocks_read * nc * nc * sizeof(Sd), flops,
+             (fn<<<grid, wg, 0, st>>>(g, Dc, Minv, use_inv, nrhs, site_begin, count, (float)a_self, (const float2*)xs,
+                                      (float)a_hop, (const float2*)xh, (float)beta, (const float2*)z, (float2*)out)));
   } else if (nrhs == 1) DD_MV(1);
   else if (nrhs <= 4) DD_MV(4);
   else DD_MV(12);
@@ -233,13 +241,13 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
 
 void launch_coarse_mv(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, const void* Minv, int use_inv, int nrhs,
                       int site_begin, int count, double a_self, const void* xs, double a_hop, const void* xh,
-                      double beta, const void* z, void* out, hipStream_t st, int spw) {
+                      double beta, const void* z, void* out, hipStream_t st, int spw, dd_dtype bt) {
   if (vt == DD_F64)
     mv<double, double2, double2>(g, nc, Dc, Minv, use_inv, nrhs, site_begin, count, a_self, xs, a_hop, xh, beta, z, out,
-                                 st, spw);
+                                 st, spw, DD_F64);
   else
     mv<float, float2, float2>(g, nc, Dc, Minv, use_inv, nrhs, site_begin, count, a_self, xs, a_hop, xh, beta, z, out,
-                              st, spw);
+                              st, spw, bt);
 }
 
 // canonical coarse vectors [rhs][lex][nc] complex128 <-> packed [rhs][slot][nc]

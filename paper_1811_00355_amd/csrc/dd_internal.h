@@ -273,6 +273,7 @@ struct Tuning {
   int sap_wpe = 2;          // SAP layout: 2 (registers, 2 waves per SIMD) or 3 (lean LDS, 3)
   int dirac_threads = 256;  // D apply workgroup size: 64, 128 or 256
   int coarse_spw = 4;       // FP32 coarse apply: coarse sites (waves) per workgroup, 2, 4 or 8
+  int coarse_half = 0;      // with half-precision storage: 1 = coarse blocks in that type, 0 = FP32 blocks
 };
 
 struct dd_gauge {
@@ -303,9 +304,11 @@ struct dd_mg {
   // coarse operator: [Vc][9][col][row] complex (column-major blocks), FP64 master and FP32
   double2* Dc64 = nullptr;
   float2* Dc32 = nullptr;
+  void* Dch = nullptr;       // half-precision copy (storage dtype F16/BF16) used by the FP32 inner solve
   // odd-site inverses of the self blocks: [Vch][col][row]
   double2* Dinv64 = nullptr;
   float2* Dinv32 = nullptr;
+  void* Dinvh = nullptr;
   Workspace* ws = nullptr;
   bool use_graphs = false;   // coarse GMRES chunks replayed from captured HIP graphs
 };
@@ -371,7 +374,8 @@ void launch_coarse_invert(const GeomDev& g, int nc, const double2* Dc64, double2
 // coarse operator: out = a_self M xs + a_hop sum_d D_c(d) xh(X+d) + beta z on sites [begin, begin+count)
 void launch_coarse_mv(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, const void* Minv, int use_inv,
                       int nrhs, int site_begin, int count, double a_self, const void* xs, double a_hop,
-                      const void* xh, double beta, const void* z, void* out, hipStream_t st, int spw = 4);
+                      const void* xh, double beta, const void* z, void* out, hipStream_t st, int spw = 4,
+                      dd_dtype bt = DD_F32);
 // vector kernels
 int dots_blocks(long long count, int nrhs);
 void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long ld, const void* V, int nv,

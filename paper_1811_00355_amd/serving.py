@@ -53,10 +53,12 @@ def setup_transient_bytes(V, Vc, n, coarse_m=60, inner_bytes=8, store_bytes=8):
 
 def setup_bytes(V, Vc, n, store_bytes=8, inner_bytes=8):
     """FP64 P, working vectors (inner type), stored P, coarse operator and
-    odd-site inverses in FP64 and FP32."""
+    odd-site inverses in FP64 and FP32 (and in the storage type when it is a
+    half type)."""
     nc = 2 * n
     fine = 12 * V * n
-    return (16 + inner_bytes + store_bytes) * fine + (16 + 8) * Vc * nc * nc * (9 + 0.5)
+    half = store_bytes if store_bytes != 8 else 0     # half storage keeps a half copy of D_c too
+    return (16 + inner_bytes + store_bytes) * fine + (16 + 8 + half) * Vc * nc * nc * (9 + 0.5)
 
 
 def workspace_bytes(V, Vc, n, nrhs, m=10, coarse_m=60, inner_bytes=8):

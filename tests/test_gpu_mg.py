@@ -337,3 +337,36 @@ def test_batch_invariance(ctx, inner, store):
         assert same
     assert len({i["outer_iters"] for i in info}) >= 2, "every source converged together: masking not exercised"
     _close(d)
+
+
+@pytest.mark.parametrize("store", [2, 3])
+def test_coarse_half_blocks(ctx, store):
+    """Half-precision storage also keeps D_c (and the odd-site inverses) in
+    FP16 / BF16; with coarse_half tuning the FP32 inner solve uses them: the stencil matches the oracle on the
+    rounded operator (P rounded to FP32 before and to the half type after
+    Gram-Schmidt, D_c rounded through FP32), and the fixed-iteration coarse
+    solve matches the oracle's even-odd GMRES with the same rounded blocks."""
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_vectors
+    d = _build(ctx, "b4", inner_dtype=1, store_dtype=store, coarse_fixed_iters=10, coarse_restart=10)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    d["g"].dd_gauge_set_tuning(2, 256, 4, coarse_half=1)
+    Pb = _gpu.round_store(amg.gram_schmidt(lat, _gpu.round_f32(d["tv0"])), store)
+    Dc = amg.coarse_operator(d["W"], Pb)
+    Dr = _gpu.round_store(Dc, store)
+    nrhs = 12
+    c = _gpu.round_f32(gauss_vectors(nrhs, lat.Vc, 73, ncomp=2 * n))
+    got = _coarse_roundtrip(mg, 1, nrhs, c, lambda i, o: mg.dd_coarse_apply(1, nrhs, i, o))
+    errs = [_gpu.max_rel(got[r], amg.coarse_apply(lat, Dr, c[r])) for r in range(nrhs)]
+    print(f"store {store}: coarse apply with half blocks, max error {max(errs):.2e}", flush=True)
+    assert max(errs) < 1e-5
+    ceo = amg.CoarseEO(lat, Dr)
+    odd = ceo.odd
+    ceo.Doo_inv[odd] = _gpu.round_store(np.linalg.inv(Dc[odd, 0]), store)   # the library rounds the FP64 inverse
+    op = amg.MGParams(n_vec=n, coarse_fixed_iters=10, coarse_restart=10)
+    got = _coarse_roundtrip(mg, 1, nrhs, c, lambda i, o: mg.dd_coarse_solve(1, nrhs, i, o))
+    errs = [_gpu.max_rel(got[r], ceo.solve(c[r], op)) for r in range(nrhs)]
+    print(f"store {store}: coarse solve with half blocks, max error {max(errs):.2e}", flush=True)
+    assert max(errs) < 1e-4
+    _close(d)

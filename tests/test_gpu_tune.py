@@ -42,6 +42,8 @@ def test_tuning_choices_bit_identical(ctx, tmp_path):
         assert same
     with pytest.raises(Exception):
         g.dd_gauge_set_tuning(4, 256, 4)
+    with pytest.raises(Exception):
+        g.dd_gauge_set_tuning(2, 256, 4, coarse_half=2)
     cache = tmp_path / "tune.json"
     rep = mg.dd_autotune(nrhs, str(cache))
     print(rep, flush=True)
