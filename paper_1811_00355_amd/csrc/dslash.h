@@ -66,6 +66,24 @@ __device__ __forceinline__ void load_link(const S* L, long long V, int mu, long 
   for (int k = 0; k < 9; ++k) u[k] = ld<R, S>(L + (long long)(mu * 9 + k) * V + I);
 }
 
+// acc += a * b and acc += conj(a) * b as four chained fused multiply-adds (one
+// rounding each, 4 VALU operations instead of 6 for sum-then-accumulate); used
+// where the hop and clover arithmetic is the bottleneck.
+template <typename R>
+__device__ __forceinline__ void cfma4(cx<R>& acc, cx<R> a, cx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+template <typename R>
+__device__ __forceinline__ void cfma4_conj(cx<R>& acc, cx<R> a, cx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+}
+
 // o = U h on both spin components of a half spinor
 template <typename R>
 __device__ __forceinline__ void su3_mul_half(const cx<R>* u, const cx<R>* h, cx<R>* o) {
@@ -74,8 +92,8 @@ __device__ __forceinline__ void su3_mul_half(const cx<R>* u, const cx<R>* h, cx<
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       cx<R> acc = u[3 * a] * h[3 * s];
-      cfma(acc, u[3 * a + 1], h[3 * s + 1]);
-      cfma(acc, u[3 * a + 2], h[3 * s + 2]);
+      cfma4(acc, u[3 * a + 1], h[3 * s + 1]);
+      cfma4(acc, u[3 * a + 2], h[3 * s + 2]);
       o[3 * s + a] = acc;
     }
 }
@@ -87,8 +105,8 @@ __device__ __forceinline__ void su3_dag_mul_half(const cx<R>* u, const cx<R>* h,
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       cx<R> acc = cmul_conj(u[a], h[3 * s]);
-      cfma_conj(acc, u[3 + a], h[3 * s + 1]);
-      cfma_conj(acc, u[6 + a], h[3 * s + 2]);
+      cfma4_conj(acc, u[3 + a], h[3 * s + 1]);
+      cfma4_conj(acc, u[6 + a], h[3 * s + 2]);
       o[3 * s + a] = acc;
     }
 }
@@ -116,8 +134,8 @@ __device__ __forceinline__ void clover_mul(const S* C, long long V, long long I,
 #pragma unroll
       for (int q = r + 1; q < 6; ++q) {
         cx<R> u = ld<R, S>(B + (long long)(k++) * V);
-        cfma(o[r], u, v[q]);
-        cfma_conj(o[q], u, v[r]);
+        cfma4(o[r], u, v[q]);
+        cfma4_conj(o[q], u, v[r]);
       }
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
