@@ -30,23 +30,30 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s for
+# non-packed instructions; the published 157.3 TFLOP/s counts packed FP32 (2 per lane), which
+# this library does not emit.  Kernels whose arithmetic intensity at the workload's batch is above
+# the FP32 ridge (157.3 / 8 = 19.7 flop/byte) are rated against the FP32 peak ("alu").
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 78.6
+ALU_BOUND = {"k_sap_colour"}
 TOL = 1e-10
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this workload
 # (scaled by the copy-kernel calibration: FETCH_SIZE x2.000, WRITE_SIZE x1.000; see
-# profiles/k_sap_colour_c3_pmc.md).  Reported only while the kernel's sources are
-# unchanged since the measurement.
+# profiles/k_sap_colour_c3_pmc.md), per SAP layout (the autotuner's sap_wpe).  Reported
+# only while the kernel's sources are unchanged since the measurement.
+_SAP_SOURCES = ["paper_1811_00355_amd/csrc/sap.hip", "paper_1811_00355_amd/csrc/dslash.h",
+                "paper_1811_00355_amd/csrc/dd_internal.h"]
 MEASURED_TRAFFIC = {
-    ("k_sap_colour", "C3", "f32"): dict(bytes=12.263e9 + 1.208e9, sha="a4a782c762fb31b3",
-                                        sources=["paper_1811_00355_amd/csrc/sap.hip",
-                                                 "paper_1811_00355_amd/csrc/dslash.h",
-                                                 "paper_1811_00355_amd/csrc/dd_internal.h"]),
+    ("k_sap_colour", "C3", "bf16", 3): dict(bytes=16.791e9 + 1.208e9, sha="69d054152903f6e1", sources=_SAP_SOURCES),
+    ("k_sap_colour", "C3", "bf16", 2): dict(bytes=11.040e9 + 1.208e9, sha="69d054152903f6e1", sources=_SAP_SOURCES),
 }
 
 
-def measured_traffic(kernel, config, store):
+def measured_traffic(kernel, config, store, sap_wpe):
     import hashlib
-    m = MEASURED_TRAFFIC.get((kernel, config, store))
+    m = MEASURED_TRAFFIC.get((kernel, config, store, sap_wpe))
     if m is None:
         return None
     h = hashlib.sha256()
@@ -226,14 +233,24 @@ def measure(B, g, cfg, args, store_name, b):
     all_seen = dom in kstats and kstats[dom]["launches"] == kfull[dom]["launches"] * args.steps // nfull
     ks = kstats[dom] if all_seen else kfull[dom]
     avg_ms = ks["ms"] / max(ks["launches"], 1)
-    achieved = ks["bytes"] / (ks["ms"] * 1e-3) / 1e9
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=measured_traffic(dom, args.config, store_name), kernel=dom,
+    gbs = ks["bytes"] / (ks["ms"] * 1e-3) / 1e9
+    tfs = ks["flops"] / (ks["ms"] * 1e-3) / 1e12
+    ai = ks["flops"] / max(ks["bytes"], 1.0)
+    if dom in ALU_BOUND and ai > FP32_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS:
+        roofline = dict(bound="alu", achieved=round(tfs, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=round(tfs / FP32_PEAK_TFLOPS, 4), frac_of_nonpacked_peak=round(tfs / FP32_NONPACKED_TFLOPS, 4),
+                        algorithmic_flops_per_launch=round(ks["flops"] / max(ks["launches"], 1)))
+    else:
+        roofline = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(gbs / HBM_PEAK_GBS, 4))
+    sap_wpe = g.dd_gauge_get_tuning()["sap_wpe"]
+    roofline.update(traffic=measured_traffic(dom, args.config, store_name, sap_wpe), kernel=dom,
                     algorithmic_bytes_per_launch=round(ks["bytes"] / max(ks["launches"], 1)),
+                    hbm_GBs_algorithmic=round(gbs, 1), arithmetic_intensity=round(ai, 2),
                     avg_launch_ms=round(avg_ms, 4), launches=ks["launches"],
                     share_of_step=round(ks["ms"] / (1e3 * elapsed * (1 if all_seen else nfull / args.steps)), 3),
                     timed_in="timed steps" if all_seen else "one extra step without graphs")
+    achieved = gbs
     kernels = {k: dict(ms_per_step=round(v["ms"] / nfull, 3), launches_per_step=v["launches"] // nfull,
                        GBs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
                for k, v in sorted(kfull.items(), key=lambda kv: -kv[1]["ms"])}
