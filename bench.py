@@ -94,7 +94,7 @@ def cpu_baseline(cfg, lat_shape, n_vec, gpu_outer_iters, gpu_coarse_iters_per_vc
             z = mg.vcycle(v)
             w = W.apply(z)
             reps += 1
-            if time.perf_counter() - t0 > 8.0 or reps >= 5:
+            if time.perf_counter() - t0 > 12.0 or reps >= 10:
                 break
         t_iter = (time.perf_counter() - t0) / reps
     V_full = int(np.prod(lat_shape))

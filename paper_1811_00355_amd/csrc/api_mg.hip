@@ -464,12 +464,11 @@ static dd_status build(dd_mg* mg, hipStream_t st) {
   DD_HIP(mg->ctx, hipMemcpyAsync(dflag, &neg, sizeof(int), hipMemcpyHostToDevice, st));
   launch_coarse_invert(G, mg->nc, mg->Dc64, mg->Dinv64, dflag, st);
   const long long ndc = (long long)G.Vc * 9 * mg->nc * mg->nc, ndi = (long long)G.Vch * mg->nc * mg->nc;
-  launch_convert_pairs(DD_F32, mg->Dc64, nullptr, mg->Dc32, ndc, st);
-  launch_convert_pairs(DD_F32, mg->Dinv64, nullptr, mg->Dinv32, ndi, st);
-  if (mg->Dch) {   // half copies rounded from the FP32 ones, like every other stored operand
-    launch_convert_pairs(mg->vstore, nullptr, mg->Dc32, mg->Dch, ndc, st);
-    launch_convert_pairs(mg->vstore, nullptr, mg->Dinv32, mg->Dinvh, ndi, st);
-  }
+  // FP32 copies (and half copies rounded from them) in the matrix-core order
+  const dd_dtype half = mg->Dch ? mg->vstore : DD_F64;
+  const long long nn = (long long)mg->nc * mg->nc;
+  launch_coarse_tile(mg->nc, mg->Dc64, ndc / nn, mg->Dc32, half, mg->Dch, st);
+  launch_coarse_tile(mg->nc, mg->Dinv64, ndi / nn, mg->Dinv32, half, mg->Dinvh, st);
   DD_HIP(mg->ctx, hipMemcpyAsync(&bad, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
   DD_HIP(mg->ctx, hipStreamSynchronize(st));
   dd_free(mg->ctx, W, (size_t)chunk * vbytes);

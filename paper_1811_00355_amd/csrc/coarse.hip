@@ -7,6 +7,8 @@
 // with M(X) = D_c(X, 0) (self block) or, for odd sites, the stored inverse of
 // the self block.  This covers the full stencil (xs = xh = x), the two halves
 // of the even-site Schur complement and the odd-site reconstruction.
+#include <type_traits>
+
 #include "dd_internal.h"
 #include "ktimer.h"
 
@@ -88,6 +90,50 @@ __global__ void __launch_bounds__(64 * kSitesPerWG) k_coarse_mv(GeomDev g, int n
 // part of the same (row, rhs).  Lane layout of v_mfma_f32_16x16x4f32: A[i][k]
 // at lane i + 16k, B[k][j] at lane j + 16k, D[i][j] at lane j + 16(i/4), value
 // i % 4.  One wave per site, up to 16 right-hand sides per pass, 2n <= 48.
+// Matrix-core order of one NC x NC block (the FP32 and half copies the FP32
+// apply reads).  Element (row, col) lies in row tile t = row / 16 (RT = min(16,
+// NC - 16 t) rows) and k-step ks = col / 4 (lane group lk = col % 4); P
+// consecutive k-steps form a group q = ks / P.  Within a tile the order is
+// [q][lk][li][e]: lane (li, lk) of the MFMA operand reads its P k-steps of row
+// 16 t + li with one load of P elements, and a wave reads one contiguous stretch.
+// No padding: a block still holds NC * NC elements.
+__host__ __device__ inline long long tiled_off(int row, int col, int NC, int P) {
+  const int t = row >> 4, li = row & 15, RT = NC - 16 * t < 16 ? NC - 16 * t : 16;
+  const int ks = col >> 2, lk = col & 3, q = ks / P, e = ks % P;
+  return (long long)16 * t * NC + ((long long)(q * 4 + lk) * RT + li) * P + e;
+}
+// P: the largest power of two k-steps per load (at most 16 bytes) that divides NC / 4
+__host__ __device__ constexpr int tile_group(int NC, int elem_bytes) {
+  return ((NC / 4) % (16 / elem_bytes) == 0) ? 16 / elem_bytes : (((NC / 4) % 2 == 0 && 16 / elem_bytes >= 2) ? 2 : 1);
+}
+
+// FP64 column-major blocks -> FP32 blocks in matrix-core order
+__global__ void k_tile_f32(const double2* __restrict__ src, float2* __restrict__ dst, long long nblk, int NC) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)NC * NC;
+  if (i >= nblk * per) return;
+  const long long b = i / per, w = i % per;
+  const int row = (int)(w % NC), col = (int)(w / NC);
+  const double2 v = src[i];
+  dst[b * per + tiled_off(row, col, NC, tile_group(NC, 8))] = make_float2((float)v.x, (float)v.y);
+}
+// FP32 matrix-core blocks -> half matrix-core blocks (rounded from the FP32 values)
+template <typename H>
+__global__ void k_tile_half(const float2* __restrict__ src, H* __restrict__ dst, long long nblk, int NC) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)NC * NC;
+  if (i >= nblk * per) return;
+  const long long b = i / per, w = i % per;
+  const int row = (int)(w % NC), col = (int)(w / NC);
+  const float2 v = src[b * per + tiled_off(row, col, NC, tile_group(NC, 8))];
+  H* d = dst + b * per + tiled_off(row, col, NC, tile_group(NC, 4));
+  if constexpr (sizeof(H) == 4 && std::is_same<H, __half2>::value) {
+    *d = __floats2half2_rn(v.x, v.y);
+  } else {
+    d->u = f32_to_bf16_bits(v.x) | (f32_to_bf16_bits(v.y) << 16);
+  }
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxNc = 48;
 
@@ -122,15 +168,24 @@ __global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const Sd* _
       const float sc = d == 0 ? a_self : a_hop;
       const Sd* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * NC * NC : Dc + (long long)X * 9 * NC * NC)
                            : Dc + ((long long)X * 9 + d) * NC * NC;
+      // P k-steps per load from the matrix-core order (see tiled_off)
+      constexpr int P = tile_group(NC, (int)sizeof(Sd));
+      struct alignas(P * sizeof(Sd)) Pack {
+        Sd v[P];
+      };
       cx<float> m[KS][MT];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
+      for (int t = 0; t < MT; ++t) {
+        const int RT = NC - 16 * t < 16 ? NC - 16 * t : 16;
+        const bool ok = site_ok && li < RT;
 #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          const int row = 16 * t + li;
-          m[ks][t] = (site_ok && row < NC) ? ld<float, Sd>(B + (long long)(4 * ks + lk) * NC + row)
-                                           : cx<float>{0.f, 0.f};
+        for (int q = 0; q < KS / P; ++q) {
+          Pack pk;
+          if (ok) pk = *reinterpret_cast<const Pack*>(B + (long long)16 * t * NC + ((long long)(q * 4 + lk) * RT + li) * P);
+#pragma unroll
+          for (int e = 0; e < P; ++e) m[q * P + e][t] = ok ? ld<float, Sd>(&pk.v[e]) : cx<float>{0.f, 0.f};
         }
+      }
       __syncthreads();
       // stage sc * x(Y) as [col][rhs], zero padded to 16 right-hand sides
       for (int e = lane; e < NC * 16; e += 64) {
@@ -238,6 +293,15 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
 }
 
 }  // namespace
+
+void launch_coarse_tile(int nc, const double2* src64, long long nblk, float2* dst32, dd_dtype half, void* dsth,
+                        hipStream_t st) {
+  const long long n = nblk * nc * nc;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  k_tile_f32<<<nb, 256, 0, st>>>(src64, dst32, nblk, nc);
+  if (half == DD_F16) k_tile_half<__half2><<<nb, 256, 0, st>>>(dst32, (__half2*)dsth, nblk, nc);
+  if (half == DD_BF16) k_tile_half<bf16x2><<<nb, 256, 0, st>>>(dst32, (bf16x2*)dsth, nblk, nc);
+}
 
 void launch_coarse_mv(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, const void* Minv, int use_inv, int nrhs,
                       int site_begin, int count, double a_self, const void* xs, double a_hop, const void* xh,

@@ -395,6 +395,10 @@ void launch_normalize(dd_dtype vt, int nrhs, long long count, long long ld, cons
                       const double* nrm, const int* mask, void* dst, hipStream_t st);
 void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);   // bytes: multiple of 4
+// FP32 (and, when half is DD_F16 / DD_BF16, half) copies of nblk FP64 coarse
+// blocks in the order the matrix-core apply reads
+void launch_coarse_tile(int nc, const double2* src64, long long nblk, float2* dst32, dd_dtype half, void* dsth,
+                        hipStream_t st);
 void launch_add(dd_dtype vt, long long n, const void* a, void* out, hipStream_t st);
 void launch_cycle_init(int nrhs, int m, const double2* nrm2, const double* tolabs, const int* finished,
                        double2* gv, double* beta, int* active, int* kcyc, hipStream_t st);
