@@ -129,6 +129,36 @@ def dapply_table(B, g, reps=20):
     return rows
 
 
+def baseline_dd(B, g, b, args, store_name):
+    """The paper's comparison solver on the same 12 sources: FP64 defect
+    correction around an FP32 BiCGstab right-preconditioned by SAP with
+    N_SAP = 5.  Run one defect-correction step per call (each continuing from
+    the previous iterate) so that every step reports its progress; the timed
+    figure is the sum of the calls."""
+    import torch
+    p = B.bicgstab_params(store_dtype=B.DTYPES[store_name], max_outer_iters=1, use_x0=1)
+    x = torch.zeros_like(b)
+    total, inner, outer = 0.0, 0, 0
+    info = None
+    for step in range(20):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info, st = g.dd_solve_bicgstab(p, b.shape[0], b, x, TOL, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        total += dt
+        inner += info[0]["inner_iters"]
+        outer += info[0]["outer_iters"]
+        log(f"[bench] baseline step {step}: {dt:.2f} s, inner steps {info[0]['inner_iters']}, "
+            f"max true relres {max(i['true_relres'] for i in info):.2e}")
+        if st == 0:
+            break
+    ok = all(i["converged"] and i["true_relres"] <= TOL for i in info)
+    return dict(solves_per_s=round(b.shape[0] / total, 4), seconds=round(total, 3), converged=ok,
+                outer_iters=outer, inner_iters=inner, max_true_relres=max(i["true_relres"] for i in info),
+                sap_sweeps=p.sap_sweeps, inner_tol=p.inner_tol, store_dtype=store_name)
+
+
 def fp64_single_rhs(B, g, cfg, b, args):
     """The comparison form: an all-FP64 setup, then the 12 sources solved one at
     a time (single-RHS FP64 solves, one after another)."""
@@ -289,6 +319,8 @@ def main():
     ap.add_argument("--no-fp64-single", action="store_true",
                     help="skip the 12 sequential FP64 single-RHS solves")
     ap.add_argument("--no-dapply", action="store_true", help="skip the D-apply bandwidth table")
+    ap.add_argument("--no-baseline-dd", action="store_true",
+                    help="skip the paper's comparison solver (SAP-preconditioned BiCGstab)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -366,6 +398,12 @@ def main():
         log("[bench] D-apply bandwidth table")
         out["dapply"] = dapply_table(B, g)
         log(f"[bench] D apply: {out['dapply']}")
+    if not args.no_baseline_dd:
+        log("[bench] the paper's comparison solver (SAP-preconditioned BiCGstab)")
+        dd = baseline_dd(B, g, b, args, stores[0])
+        dd["amg_speedup"] = round(value / dd["solves_per_s"], 2)
+        out["config"]["baseline_dd_bicgstab"] = dd
+        log(f"[bench] baseline: {dd}")
     if not args.no_fp64_single:
         log("[bench] 12 sequential FP64 single-RHS solves")
         out["config"]["fp64_single_rhs"] = fp64_single_rhs(B, g, cfg, b, args)

@@ -189,6 +189,30 @@ dd_status dd_mg_set_graphs(dd_mg* mg, int enable);
  * the device. */
 dd_status dd_mg_release_workspace(dd_mg* mg);
 
+/* ---- the paper's comparison solver -----------------------------------------------------
+ * Sec. 4 "baseline": a mixed-precision nested BiCGstab whose single-precision
+ * level is preconditioned by domain decomposition (SAP, N_SAP = 5).  The paper
+ * does not give the outer iteration; here it is a defect correction with the
+ * FP64 operator (r = b - D x, x += e), and the inner level is an FP32 BiCGstab
+ * on D e = r, right preconditioned by SAP over the field's blocks (even-odd
+ * minimal-residual domain solves, as in the multigrid smoother), stopped at a
+ * relative residual inner_tol.  The paper's domains are 12^4 with SSOR inside;
+ * here they are the field's power-of-two blocks.  Right-hand sides advance
+ * together; a converged one is not changed any more.  Same vector layout,
+ * statuses and info as dd_solve (info.coarse_iters_total = inner steps). */
+typedef struct {
+  int32_t sap_sweeps;       /* N_SAP (5)                                  */
+  int32_t sap_mr_iters;     /* MR steps per domain solve (4)              */
+  int32_t inner_max_iters;  /* cap on one inner solve (500)               */
+  int32_t max_outer_iters;  /* cap on defect-correction steps (20)        */
+  double inner_tol;         /* relative residual of one inner solve (1e-4) */
+  dd_dtype store_dtype;     /* operands of the inner level: F32, F16, BF16 */
+  int32_t use_x0;           /* 1: x_canon holds the starting guess; 0: start from zero */
+} dd_bicgstab_params;
+void dd_bicgstab_params_default(dd_bicgstab_params* p);
+dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, const double* b_canon_dev,
+                            double* x_canon_dev, double tol, dd_solve_info* info, void* stream);
+
 /* ---- autotuner --------------------------------------------------------------------------
  * dd_autotune times every launch-shape candidate of the smoother (waves per
  * SIMD), the FP64 D apply (workgroup size) and the FP32 coarse stencil (sites

@@ -48,6 +48,12 @@ class dd_tuning(ctypes.Structure):
                 ("coarse_half", ctypes.c_int32)]
 
 
+class dd_bicgstab_params(ctypes.Structure):
+    _fields_ = [("sap_sweeps", ctypes.c_int32), ("sap_mr_iters", ctypes.c_int32),
+                ("inner_max_iters", ctypes.c_int32), ("max_outer_iters", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("store_dtype", ctypes.c_int32), ("use_x0", ctypes.c_int32)]
+
+
 class dd_solve_info(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("coarse_iters_total", ctypes.c_int32), ("converged", ctypes.c_int32),
@@ -84,6 +90,9 @@ SIGNATURES = {
     "dd_mg_destroy": (_I, [_P]),
     "dd_setup_update_mass": (_I, [_P, ctypes.c_double]),
     "dd_mg_set_graphs": (_I, [_P, _I]),
+    "dd_bicgstab_params_default": (None, [ctypes.POINTER(dd_bicgstab_params)]),
+    "dd_solve_bicgstab": (_I, [_P, ctypes.POINTER(dd_bicgstab_params), _I, _P, _P, ctypes.c_double,
+                               ctypes.POINTER(dd_solve_info), _P]),
     "dd_mg_release_workspace": (_I, [_P]),
     "dd_autotune": (_I, [_P, _I, ctypes.c_char_p, ctypes.c_char_p, _S]),
     "dd_gauge_set_tuning": (_I, [_P, ctypes.POINTER(dd_tuning)]),
@@ -178,6 +187,14 @@ class Context:
             self.h = _P()
 
 
+def bicgstab_params(**kw):
+    p = dd_bicgstab_params()
+    lib().dd_bicgstab_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
 def default_params(**kw):
     p = dd_mg_params()
     lib().dd_mg_params_default(ctypes.byref(p))
@@ -225,6 +242,16 @@ class Gauge:
         self.ctx.check(self.ctx.lib.dd_gauge_get_tuning(self.h, ctypes.byref(t)))
         return dict(sap_wpe=t.sap_wpe, dirac_threads=t.dirac_threads, coarse_spw=t.coarse_spw,
                     coarse_half=t.coarse_half)
+
+    def dd_solve_bicgstab(self, params, nrhs, b_canon, x_canon, tol, stream=None, raise_on_noconv=True):
+        """The paper's comparison solver (SAP-preconditioned FP32 BiCGstab in an FP64 defect correction)."""
+        info = (dd_solve_info * nrhs)()
+        st = self.ctx.lib.dd_solve_bicgstab(self.h, ctypes.byref(params), nrhs, _ptr(b_canon), _ptr(x_canon), tol, info,
+                                            _stream(stream))
+        if st and not (st == 5 and not raise_on_noconv):
+            self.ctx.check(st)
+        return [dict(outer_iters=i.outer_iters, inner_iters=i.coarse_iters_total, converged=bool(i.converged),
+                     true_relres=i.true_relres, t_solve_s=i.t_solve_s) for i in info], st
 
     def dd_gauge_set_mass(self, m0):
         self.ctx.check(self.ctx.lib.dd_gauge_set_mass(self.h, m0))
