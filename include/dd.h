@@ -198,8 +198,10 @@ dd_status dd_mg_release_workspace(dd_mg* mg);
  * minimal-residual domain solves, as in the multigrid smoother), stopped at a
  * relative residual inner_tol.  The paper's domains are 12^4 with SSOR inside;
  * here they are the field's power-of-two blocks.  Right-hand sides advance
- * together; a converged one is not changed any more.  Same vector layout,
- * statuses and info as dd_solve (info.coarse_iters_total = inner steps). */
+ * together; a converged one is not changed any more.  The correction stops with
+ * DD_ENOCONV at max_outer_iters or as soon as a step increases the residual of
+ * an unconverged right-hand side (x then holds that iterate).  Same vector
+ * layout, statuses and info as dd_solve (info.coarse_iters_total = inner steps). */
 typedef struct {
   int32_t sap_sweeps;       /* N_SAP (5)                                  */
   int32_t sap_mr_iters;     /* MR steps per domain solve (4)              */

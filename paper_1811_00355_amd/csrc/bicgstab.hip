@@ -163,13 +163,16 @@ dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, 
     launch_dots(DD_F64, DD_F64, nrhs, cnt, cnt, r64, 1, 0, r64, partial, nblk, dots, 1, 0, st);
     if ((s = read_dots(1))) return s;
     int nfin = 0;
+    bool grew = false;
     for (int q = 0; q < nrhs; ++q) {
+      const double before = relres[q];
       if (bnorm[q] > 0.0) relres[q] = std::sqrt(hd[q].x) / bnorm[q];
       if (!std::isfinite(relres[q])) return dd_fail(ctx, DD_ENAN, "breakdown: non-finite residual");
       if (relres[q] <= tol) fin[q] = 1;
+      if (outer > 0 && !fin[q] && relres[q] > before) grew = true;   // the inner solve made it worse
       nfin += fin[q];
     }
-    if (nfin == nrhs || outer >= p->max_outer_iters) break;
+    if (nfin == nrhs || outer >= p->max_outer_iters || grew) break;
     ++outer;
     // inner right-hand side: r in FP32, zero for finished right-hand sides
     launch_vec_convert(DD_F64, DD_F32, r64, r, fine, st);
@@ -262,7 +265,10 @@ dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, 
       info[q].flops_model = 0;
     }
   }
-  if (!all) return dd_fail(ctx, DD_ENOCONV, "max_outer_iters reached before every right-hand side converged");
+  if (!all)
+    return dd_fail(ctx, DD_ENOCONV,
+                   "defect correction stopped (max_outer_iters, or a step increased the residual) before every "
+                   "right-hand side converged");
   return DD_OK;
 }
 

@@ -311,9 +311,9 @@ inline unsigned grid1(long long n) {
 // the vector length only, never on the number of right-hand sides, so the
 // summation order of every RHS is the same alone and in a batch.
 int dots_blocks(long long count, int /*nrhs*/) {
-  long long per = 2048;    // entries per workgroup, at least
+  long long per = 512;     // entries per workgroup, at least (2 per thread): short coarse vectors still fill the chip
   long long nb = (count + per - 1) / per;
-  if (nb > 512) nb = 512;
+  if (nb > 1024) nb = 1024;
   if (nb < 1) nb = 1;
   return (int)nb;
 }
