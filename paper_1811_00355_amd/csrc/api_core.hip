@@ -156,10 +156,13 @@ static dd_status build_geometry(dd_gauge* g) {
   dd_status st;
   if ((st = dd_alloc(g->ctx, (void**)&g->d_blk_nbr, sizeof(int) * 8 * G.Vc))) return st;
   if ((st = dd_alloc(g->ctx, (void**)&g->d_blk_coord, sizeof(int) * G.Vc))) return st;
+  if ((st = dd_alloc(g->ctx, (void**)&g->d_lex_slot, sizeof(int) * G.Vc))) return st;
   DD_HIP(g->ctx, hipMemcpy(g->d_blk_nbr, g->h_blk_nbr.data(), sizeof(int) * 8 * G.Vc, hipMemcpyHostToDevice));
   DD_HIP(g->ctx, hipMemcpy(g->d_blk_coord, g->h_blk_coord.data(), sizeof(int) * G.Vc, hipMemcpyHostToDevice));
+  DD_HIP(g->ctx, hipMemcpy(g->d_lex_slot, slot_of_lex.data(), sizeof(int) * G.Vc, hipMemcpyHostToDevice));
   G.blk_nbr = g->d_blk_nbr;
   G.blk_coord = g->d_blk_coord;
+  G.lex_slot = g->d_lex_slot;
   return DD_OK;
 }
 
@@ -280,6 +283,7 @@ dd_status dd_gauge_destroy(dd_gauge* g) {
   for (int d = 0; d < 4; ++d) free_opset(g, (dd_dtype)d);
   dd_free(g->ctx, g->d_blk_nbr, sizeof(int) * 8 * g->geo.Vc);
   dd_free(g->ctx, g->d_blk_coord, sizeof(int) * g->geo.Vc);
+  dd_free(g->ctx, g->d_lex_slot, sizeof(int) * g->geo.Vc);
   delete g;
   return DD_OK;
 }

@@ -35,6 +35,7 @@ struct GeomDev {
   long long V;
   const int* blk_nbr;    // [8][Vc]: slot of the neighbouring block; bit 30 set when the hop wraps in t
   const int* blk_coord;  // [Vc]: block coordinates packed as bx | by<<8 | bz<<16 | bt<<24
+  const int* lex_slot;   // [Vc]: slot of the block with lexicographic block index l (x fastest)
   double bc_t;
 };
 
@@ -239,6 +240,35 @@ __device__ __forceinline__ void xcd_tile_rhs(int nrhs, int& tile, int& rhs) {
 }
 inline unsigned xcd_grid(long long ntiles, int nrhs) { return (unsigned)(8 * ((ntiles + 7) / 8) * nrhs); }
 
+// Contiguous ranges per XCD: the k-th workgroup of XCD x = b % 8 takes right-hand
+// side k % nrhs of tile x * (ntiles / 8) + k / nrhs (ntiles a multiple of 8), so
+// each XCD works through one contiguous eighth of the tiles.  Launch
+// xcd_grid(ntiles, nrhs) workgroups.
+__device__ __forceinline__ void xcd_range_tile(int ntiles, int nrhs, int& tile, int& rhs) {
+  const int b = blockIdx.x, x = b & 7, k = b >> 3;
+  rhs = k % nrhs;
+  tile = x * (ntiles / 8) + k / nrhs;
+}
+
+// Slab order for kernels whose halo comes from neighbouring blocks.  The tiles
+// (per_blk of them per block) are taken in lexicographic block order, both
+// colours interleaved, and each XCD gets a contiguous eighth of that order (a
+// slab of the lattice): the k-th workgroup of XCD x = b % 8 takes right-hand
+// side k % nrhs of tile x * (ntiles / 8) + k / nrhs of the order.  Neighbouring
+// blocks are then processed together on one L2.  Launch xcd_grid(Vc * per_blk,
+// nrhs) workgroups; Vc is a multiple of 16.  Returns false for workgroups past
+// the end.
+__device__ __forceinline__ bool xcd_slab_tile(const GeomDev& g, int per_blk, int nrhs, int& tile, int& rhs) {
+  const int b = blockIdx.x, x = b & 7, k = b >> 3;
+  const int per_x = g.Vc * per_blk / 8;
+  const int kk = k / nrhs;
+  rhs = k % nrhs;
+  if (kk >= per_x) return false;
+  const int tl = x * per_x + kk;
+  tile = g.lex_slot[tl / per_blk] * per_blk + tl % per_blk;
+  return true;
+}
+
 // lexicographic site index of a packed site
 __host__ __device__ __forceinline__ long long lex_site(const GeomDev& g, const SiteLoc& s) {
   int bc = g.blk_coord[s.slot];
@@ -283,6 +313,7 @@ struct dd_gauge {
   GeomDev geo;
   int* d_blk_nbr = nullptr;
   int* d_blk_coord = nullptr;
+  int* d_lex_slot = nullptr;
   std::vector<int> h_blk_nbr, h_blk_coord;
   OpSet ops[4];   // indexed by dd_dtype: F64 master, F32, F16, BF16
   int refcount = 0;

@@ -1,7 +1,9 @@
 // Wilson-clover operator apply: out = A psi + hopping term (Sec. 3), one
-// thread per (site, right-hand side).  The workgroups of one tile of sites
-// (all right-hand sides) run on the same XCD back to back, so the tile's links
-// and clover come from that XCD's L2 after the first fetch.
+// thread per (site, right-hand side).  Tiles are visited in slab order: the
+// workgroups of one tile (all right-hand sides) run on the same XCD back to back,
+// so its links and clover come from that XCD's L2 after the first fetch, and
+// neighbouring blocks run together on that XCD, so halo spinors and backward
+// links are shared through the same L2.
 #include "dslash.h"
 #include "ktimer.h"
 
@@ -11,7 +13,11 @@ template <typename R, typename S, typename Tv>
 __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
                                                int nrhs, const Tv* __restrict__ in, Tv* __restrict__ out) {
   int tile, r;
-  xcd_tile_rhs(nrhs, tile, r);
+  if (g.Bv >= (int)blockDim.x) {   // whole blocks per tile range: slab order (see xcd_slab_tile)
+    if (!xcd_slab_tile(g, g.Bv / blockDim.x, nrhs, tile, r)) return;
+  } else {
+    xcd_tile_rhs(nrhs, tile, r);
+  }
   long long I = (long long)tile * blockDim.x + threadIdx.x;
   if (I >= g.V) return;
   const Tv* x = in + (long long)r * 12 * g.V;

@@ -74,8 +74,11 @@ k_sap_colour(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
   __shared__ R red[3 * (kMaxBvh / 64 + 1)];
   cx<R>(*sh_odd)[kMaxBvh] = kLean ? sh : (cx<R>(*)[kMaxBvh])sh_o;
 
+  // domains of one colour are numbered in lexicographic block order; each XCD
+  // takes a contiguous range of them, so the 8 domains around a block of the
+  // other colour (whose x is their halo) run on one L2
   int tile, r;
-  xcd_tile_rhs(nrhs, tile, r);
+  xcd_range_tile(g.Vch, nrhs, tile, r);
   if (tile >= g.Vch) return;
   const int slot = colour * g.Vch + tile;
   const int j = threadIdx.x;

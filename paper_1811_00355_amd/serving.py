@@ -37,8 +37,9 @@ def gauge_bytes(V, store_bytes=8, Vc=0):
     """FP64 links, clover and clover inverse (3 x 36 complex pairs), plus their
     copies in the storage type (same three fields); half-precision copies are
     rounded from an FP32 copy, which stays resident too.  The block tables take
-    36 B per coarse site (8 neighbour slots and the packed coordinates)."""
-    return V * 3 * 36 * (16 + 8 + (store_bytes if store_bytes != 8 else 0)) + 36 * Vc
+    40 B per coarse site (8 neighbour slots, the packed coordinates, the slot of
+    each lexicographic block index)."""
+    return V * 3 * 36 * (16 + 8 + (store_bytes if store_bytes != 8 else 0)) + 40 * Vc
 
 
 def setup_transient_bytes(V, Vc, n, coarse_m=60, inner_bytes=8, store_bytes=8):
