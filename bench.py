@@ -338,8 +338,8 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU domain decomposition is not part of it", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for {args.gpus}); "
+              "the multi-GPU domain decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
