@@ -211,6 +211,10 @@ def measure(B, g, cfg, args, store_name, b):
     t_setup = time.perf_counter() - t0
     log(f"[bench] store {store_name}: setup {t_setup:.2f} s")
     mg.dd_mg_set_graphs(args.graphs)
+    if args.coarse_basis_half:
+        t = g.dd_gauge_get_tuning()
+        t["coarse_basis_half"] = 1
+        g.dd_gauge_set_tuning(**t)
     kb = min(args.rhs_batch, nrhs)
     tuning = None
     if args.autotune:
@@ -318,6 +322,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="time the launch-shape candidates before the timed steps")
     ap.add_argument("--tune-cache", default=None, help="JSON cache of autotuner choices")
+    ap.add_argument("--coarse-basis-half", type=int, default=0, choices=[0, 1],
+                    help="store the FP32 coarse GMRES basis in FP16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-single", action="store_true",
                     help="skip the 12 sequential FP64 single-RHS solves")
@@ -386,6 +392,7 @@ def main():
                    "lattice": list(L), "rhs": nrhs, "rhs_batch": args.rhs_batch, "m0": cfg["m0"],
                    "c_sw": cfg["c_sw"], "eps": cfg["eps"], "store_dtype": stores[0], "graphs": bool(args.graphs),
                    "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
+                   "coarse_basis": "f16" if args.coarse_basis_half else "f32",
                    "outer_iters_mean": round(float(outer), 2),
                    "coarse_iters_per_vcycle": round(float(coarse_per_vcycle), 1),
                    "setup_s": r0["setup_s"],

@@ -67,6 +67,7 @@ struct Workspace {
   void *vin = nullptr, *xs = nullptr;
   // coarse vectors (inner dtype) and the coarse Krylov basis
   void *cb, *cy, *cr, *cw, *ct1, *ct2, *cres, *CV;
+  void* cv32;   // FP32 copy of the current basis vector when the basis is stored in FP16
   Arnoldi ca;
   // outer solver
   double2 *b64, *x64, *w64, *zt64, *V64;
@@ -75,10 +76,10 @@ struct Workspace {
   double* partial;
   int* hflags = nullptr;   // pinned host mirror: active[nrhs], kcyc[nrhs]
   double* hvals = nullptr; // pinned host mirror: est[nrhs], tolabs[nrhs], nrm[nrhs]
-  // captured coarse GMRES chunks, keyed by (nrhs, dtype, first iteration, length, ends cycle);
+  // captured coarse GMRES chunks, keyed by (nrhs, dtype, basis dtype, first iteration, length, ends cycle);
   // they hold this arena's addresses and die with it
   hipStream_t cap = nullptr;
-  std::map<std::array<int, 5>, hipGraphExec_t> graphs;
+  std::map<std::array<int, 6>, hipGraphExec_t> graphs;
 };
 
 static dd_dtype inner_vt(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : DD_F32; }
@@ -102,6 +103,7 @@ static void carve_ws(Workspace& w, const dd_mg* mg, int nrhs, bool outer) {
   w.ct1 = a.take<char>(coarse * vb);
   w.ct2 = a.take<char>(coarse * vb);
   w.cres = a.take<char>(coarse * vb);
+  w.cv32 = a.take<char>(coarse * sizeof(float2));
   w.CV = a.take<char>((size_t)(mc + 1) * coarse * vb);
   w.ca.carve(a, nrhs, mc);
   int nblk = dots_blocks(12LL * V, nrhs);
@@ -201,27 +203,28 @@ static void norms2(Workspace* w, dd_dtype vt, int nrhs, long long count, long lo
 // (h1, then h2), then |w|^2 -> a.nrm2.  With nv <= 16 the passes are fused:
 // dots, then (axpy + second dots), then (axpy + norm) -- three sweeps of V.
 static void cgs(Workspace* ws, Arnoldi& a, dd_dtype vt, int nrhs, long long count, long long ld, const void* V,
-                long long vstride, int nv, void* w, int passes, hipStream_t st) {
+                long long vstride, int nv, void* w, int passes, hipStream_t st, dd_dtype bt) {
+  // bt: dtype of the basis V (vt, or DD_F16 for an FP16 basis with FP32 vectors)
   int nblk = dots_blocks(count, nrhs);
-  launch_dots(vt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h1, a.m + 1, 0, st);
+  launch_dots(bt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h1, a.m + 1, 0, st);
   if (passes == 2 && nv <= 16) {
-    launch_axpy_dots(vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, nblk, a.h2, a.m + 1, st);
-    launch_axpy_norm(vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, w, ws->partial, nblk, a.nrm2, st);
+    launch_axpy_dots(vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, nblk, a.h2, a.m + 1, st, bt);
+    launch_axpy_norm(vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, w, ws->partial, nblk, a.nrm2, st, bt);
     return;
   }
   if (passes == 2) {
-    launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, 0, -1.0, w, st);
-    launch_dots(vt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h2, a.m + 1, 0, st);
-    launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, 0, -1.0, w, st);
+    launch_multi_axpy(bt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, 0, -1.0, w, st);
+    launch_dots(bt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h2, a.m + 1, 0, st);
+    launch_multi_axpy(bt, vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, 0, -1.0, w, st);
     launch_dots(vt, vt, nrhs, count, ld, w, 1, 0, w, ws->partial, nblk, a.nrm2, 1, 0, st);
     return;
   }
   launch_zero(a.h2, sizeof(double2) * nrhs * (a.m + 1), st);
   if (nv <= 16) {
-    launch_axpy_norm(vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, nblk, a.nrm2, st);
+    launch_axpy_norm(vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, nblk, a.nrm2, st, bt);
     return;
   }
-  launch_multi_axpy(vt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, 0, -1.0, w, st);
+  launch_multi_axpy(bt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, 0, -1.0, w, st);
   launch_dots(vt, vt, nrhs, count, ld, w, 1, 0, w, ws->partial, nblk, a.nrm2, 1, 0, st);
 }
 
@@ -235,6 +238,8 @@ struct CoarseOps {
   const void *Dc, *Dinv;
   int spw;       // FP32 coarse apply: sites per workgroup
   dd_dtype bt;   // storage of the blocks (FP32 vectors may use FP32, FP16 or BF16 blocks)
+  dd_dtype basis;   // storage of the GMRES basis: vt, or DD_F16 with FP32 vectors
+  size_t bb;        // bytes of one basis element
 };
 
 static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
@@ -247,6 +252,8 @@ static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
   c.Dinv = vt == DD_F64 ? (const void*)mg->Dinv64 : half ? (const void*)mg->Dinvh : (const void*)mg->Dinv32;
   c.bt = vt == DD_F64 ? DD_F64 : half ? mg->vstore : DD_F32;
   c.spw = mg->g->tune.coarse_spw;
+  c.basis = (vt == DD_F32 && mg->g->tune.coarse_basis_half) ? DD_F16 : vt;
+  c.bb = c.basis == DD_F16 ? sizeof(__half2) : vector_pair_bytes(vt);
   return c;
 }
 
@@ -262,36 +269,38 @@ static void schur_apply(const CoarseOps& c, int nrhs, const void* v, void* out, 
 // Givens update, v_{j+1} = w / |w| (not after the cycle's last step).  Launches
 // only, no host synchronisation, so the sequence can be captured as a graph.
 static void issue_chunk(const CoarseOps& c, Workspace* w, Arnoldi& a, int passes, int nrhs, long long ce,
-                        long long ld, long long vs, size_t vb, char* CV, int j0, int len, bool ends, hipStream_t st) {
+                        long long ld, long long vs, char* CV, int j0, int len, bool ends, hipStream_t st) {
+  const bool half = c.basis == DD_F16;   // the operator then reads v_j from its FP32 copy (w->cv32)
   for (int j = j0; j < j0 + len; ++j) {
-    schur_apply(c, nrhs, CV + (size_t)j * vs * vb, w->cw, w->ct1, w->ct2, st);
-    cgs(w, a, c.vt, nrhs, ce, ld, CV, vs, j + 1, w->cw, passes, st);
+    schur_apply(c, nrhs, half ? w->cv32 : CV + (size_t)j * vs * c.bb, w->cw, w->ct1, w->ct2, st);
+    cgs(w, a, c.vt, nrhs, ce, ld, CV, vs, j + 1, w->cw, passes, st, c.basis);
     launch_arnoldi(nrhs, a.m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est,
                    a.hnext, st);
     if (ends && j + 1 == j0 + len) break;
-    launch_normalize(c.vt, nrhs, ce, ld, w->cw, nullptr, a.hnext, a.active, CV + (size_t)(j + 1) * vs * vb, st);
+    launch_normalize(c.vt, nrhs, ce, ld, w->cw, nullptr, a.hnext, a.active, CV + (size_t)(j + 1) * vs * c.bb, st,
+                     c.basis, half ? w->cv32 : nullptr);
   }
 }
 
 // Run a chunk on `st`: directly, or by replaying its graph (captured on first use
 // on the workspace's own stream; capturing launches nothing).
 static dd_status run_chunk(dd_mg* mg, const CoarseOps& c, int nrhs, long long ce, long long ld, long long vs,
-                           size_t vb, int j0, int len, bool ends, hipStream_t st) {
+                           int j0, int len, bool ends, hipStream_t st) {
   Workspace* w = mg->ws;
   Arnoldi& a = w->ca;
   char* CV = (char*)w->CV;
   const int passes = mg->p.coarse_cgs_passes;
   if (!mg->use_graphs) {
-    issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, vb, CV, j0, len, ends, st);
+    issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, CV, j0, len, ends, st);
     return DD_OK;
   }
-  const std::array<int, 5> key = {nrhs, (int)c.vt, j0, len, ends ? 1 : 0};
+  const std::array<int, 6> key = {nrhs, (int)c.vt, (int)c.basis, j0, len, ends ? 1 : 0};
   auto it = w->graphs.find(key);
   if (it == w->graphs.end()) {
     if (!w->cap) DD_HIP(mg->ctx, hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
     DD_HIP(mg->ctx, hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
     ktimer_suspend(true);
-    issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, vb, CV, j0, len, ends, w->cap);
+    issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, CV, j0, len, ends, w->cap);
     ktimer_suspend(false);
     hipGraph_t gr = nullptr;
     DD_HIP(mg->ctx, hipStreamEndCapture(w->cap, &gr));
@@ -350,21 +359,22 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
     norms2(w, vt, nrhs, ce, ld, w->cres, a.nrm2, st);
     launch_cycle_init(nrhs, m, a.nrm2, a.tolabs, a.finished, a.gv, a.beta, a.active, a.kcyc, st);
     if (count_active(w, a.active, nrhs, st) == 0) break;
-    launch_normalize(vt, nrhs, ce, ld, w->cres, nullptr, a.beta, a.active, CV, st);
+    launch_normalize(vt, nrhs, ce, ld, w->cres, nullptr, a.beta, a.active, CV, st, c.basis,
+                     c.basis == DD_F16 ? w->cv32 : nullptr);
     const int mm = (cap - iters < m) ? cap - iters : m;
     // chunks of 4 Arnoldi steps; converged RHS are masked on the device and the
     // host looks between chunks
     for (int j = 0; j < mm;) {
       const int len = mm - j < 4 ? mm - j : 4;
       const bool ends = j + len == mm;
-      dd_status cs = run_chunk(mg, c, nrhs, ce, ld, vs, vb, j, len, ends, st);
+      dd_status cs = run_chunk(mg, c, nrhs, ce, ld, vs, j, len, ends, st);
       if (cs) return cs;
       iters += len;
       j += len;
       if (ends || count_active(w, a.active, nrhs, st) == 0) break;
     }
     launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
-    launch_multi_axpy(vt, vt, nrhs, ce, ld, CV, max_kcyc(w, a, nrhs, st), vs, a.y, m, 0, 1.0, y, st);
+    launch_multi_axpy(c.basis, vt, nrhs, ce, ld, CV, max_kcyc(w, a, nrhs, st), vs, a.y, m, 0, 1.0, y, st);
     // RHS whose estimate met the tolerance are finished
     DD_HIP(mg->ctx, hipMemcpyAsync(w->hvals, a.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     DD_HIP(mg->ctx, hipMemcpyAsync(w->hvals + nrhs, a.tolabs, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
@@ -684,13 +694,16 @@ dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t) {
   if (!g || !t) return DD_EINVAL;
   if ((t->sap_wpe != 2 && t->sap_wpe != 3) ||
       (t->dirac_threads != 64 && t->dirac_threads != 128 && t->dirac_threads != 256) ||
-      (t->coarse_spw != 2 && t->coarse_spw != 4 && t->coarse_spw != 8) || (t->coarse_half != 0 && t->coarse_half != 1))
+      (t->coarse_spw != 2 && t->coarse_spw != 4 && t->coarse_spw != 8) || (t->coarse_half != 0 && t->coarse_half != 1) ||
+      (t->coarse_basis_half != 0 && t->coarse_basis_half != 1))
     return dd_fail(g->ctx, DD_EINVAL,
-                   "tuning: sap_wpe 2|3, dirac_threads 64|128|256, coarse_spw 2|4|8, coarse_half 0|1");
+                   "tuning: sap_wpe 2|3, dirac_threads 64|128|256, coarse_spw 2|4|8, coarse_half 0|1, "
+                   "coarse_basis_half 0|1");
   g->tune.sap_wpe = t->sap_wpe;
   g->tune.dirac_threads = t->dirac_threads;
   g->tune.coarse_spw = t->coarse_spw;
   g->tune.coarse_half = t->coarse_half;
+  g->tune.coarse_basis_half = t->coarse_basis_half;
   return DD_OK;
 }
 
@@ -700,6 +713,7 @@ dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t) {
   t->dirac_threads = g->tune.dirac_threads;
   t->coarse_spw = g->tune.coarse_spw;
   t->coarse_half = g->tune.coarse_half;
+  t->coarse_basis_half = g->tune.coarse_basis_half;
   return DD_OK;
 }
 
@@ -722,8 +736,10 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
   if (cache_path) tune_cache_read(cache_path, cache);
   std::string rep = "key " + key + "\n";
   auto it = cache.find(key);
+  const int basis_half = g->tune.coarse_basis_half;   // a numerical choice of the caller, not a launch shape
   if (it != cache.end()) {
     g->tune = it->second;
+    g->tune.coarse_basis_half = basis_half;
     rep += "cache hit\n";
   } else {
     dd_status s = ensure_ws(mg, nrhs, true);
@@ -1022,7 +1038,7 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
         launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->zt64, w->w64, st, g->tune.dirac_threads);
       }
       total_coarse += ci;
-      cgs(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, 2, st);
+      cgs(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, 2, st, DD_F64);
       launch_arnoldi(nrhs, m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est, a.hnext,
                      st);
       ++outer;

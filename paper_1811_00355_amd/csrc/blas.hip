@@ -106,10 +106,10 @@ __global__ void __launch_bounds__(256) k_multi_axpy(int nrhs, long long count, l
 // Fused CGS pieces for one sweep of the basis: w <- w - sum_i c_i V_i with the
 // V_i kept in registers, then either the inner products <V_i, w> (NORM = false)
 // or |w|^2 (NORM = true) of the updated w, reduced like k_dots.
-template <typename Tv, bool NORM>
+template <typename Tv, typename Tw, bool NORM>
 __global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
                                                    int nv, long long vstride, const double2* __restrict__ coef, int ldc,
-                                                   Tv* __restrict__ w, double* __restrict__ partial, int nblk) {
+                                                   Tw* __restrict__ w, double* __restrict__ partial, int nblk) {
   __shared__ double red[4][2 * kMaxNv];
   __shared__ cx<double> c[kMaxNv];
   const int r = blockIdx.y, blk = blockIdx.x;
@@ -123,10 +123,10 @@ __global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, lo
   cx<double> acc[kMaxNv];
 #pragma unroll
   for (int i = 0; i < kMaxNv; ++i) acc[i] = {0.0, 0.0};
-  Tv* wr = w + (long long)r * rs;
+  Tw* wr = w + (long long)r * rs;
   const Tv* vr = V + (long long)r * rs;
   for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    cx<double> x = ld<double, Tv>(wr + e);
+    cx<double> x = ld<double, Tw>(wr + e);
     cx<double> v[kMaxNv];
 #pragma unroll
     for (int i = 0; i < kMaxNv; ++i)
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, lo
         v[i] = ld<double, Tv>(vr + (long long)i * vstride + e);
         x = x - c[i] * v[i];
       }
-    st<Tv, double>(wr + e, x);
+    st<Tw, double>(wr + e, x);
     if (NORM) {
       acc[0].re += x.re * x.re + x.im * x.im;
     } else {
@@ -164,17 +164,24 @@ __global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, lo
 }
 
 // dst[r] = src[r] / sqrt(nrm[r].x) where mask[r] != 0 (mask may be null); zero norm gives zero
-template <typename Tv>
-__global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, long long rs, const Tv* __restrict__ src,
+template <typename Ts, typename Td>
+__global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, long long rs, const Ts* __restrict__ src,
                                                    const double2* __restrict__ nrm2, const double* __restrict__ nrm,
-                                                   const int* __restrict__ mask, Tv* __restrict__ dst) {
+                                                   const int* __restrict__ mask, Td* __restrict__ dst,
+                                                   float2* __restrict__ copy32) {
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
   double n = nrm ? nrm[r] : sqrt(nrm2[r].x);
   double s = n > 0.0 ? 1.0 / n : 0.0;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x) {
-    cx<double> v = ld<double, Tv>(src + (long long)r * rs + e);
-    st<Tv, double>(dst + (long long)r * rs + e, s * v);
+    cx<double> v = ld<double, Ts>(src + (long long)r * rs + e);
+    Td q;
+    st<Td, double>(&q, s * v);
+    dst[(long long)r * rs + e] = q;
+    if (copy32) {   // the stored (rounded) value, widened to FP32
+      const cx<float> f = ld<float, Td>(&q);
+      copy32[(long long)r * rs + e] = make_float2(f.re, f.im);
+    }
   }
 }
 
@@ -324,7 +331,7 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
   for (int i0 = 0; i0 < nv; i0 += kMaxNv) {
     int n = nv - i0 < kMaxNv ? nv - i0 : kMaxNv;
     dim3 grid(nblk, nrhs);
-    size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
+    size_t es = vt == DD_F64 ? sizeof(double2) : vt == DD_F16 ? sizeof(__half2) : sizeof(float2);
     size_t ew = wt == DD_F64 ? sizeof(double2) : sizeof(float2);
     const void* Vi = (const char*)V + (size_t)i0 * vstride * es;
     const double bytes = (double)nrhs * count * (n * es + ew), flops = 8.0 * nrhs * count * n;
@@ -333,6 +340,9 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
     if (vt == DD_F64 && wt == DD_F64)
       k_dots<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, (const double2*)w,
                                                      partial, nblk);
+    else if (vt == DD_F16 && wt == DD_F32)
+      k_dots<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)Vi, n, vstride, (const float2*)w,
+                                                    partial, nblk);
     else if (vt != DD_F64 && wt != DD_F64)
       k_dots<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, (const float2*)w,
                                                    partial, nblk);
@@ -353,7 +363,7 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
   for (int i0 = 0; i0 < nv; i0 += kMaxNv) {
     int n = nv - i0 < kMaxNv ? nv - i0 : kMaxNv;
     dim3 grid(grid1(count), nrhs);
-    size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
+    size_t es = vt == DD_F64 ? sizeof(double2) : vt == DD_F16 ? sizeof(__half2) : sizeof(float2);
     size_t ew = wt == DD_F64 ? sizeof(double2) : sizeof(float2);
     const void* Vi = (const char*)V + (size_t)i0 * vstride * es;
     const double bytes = (double)nrhs * count * (n * es + 2 * ew), flops = 8.0 * nrhs * count * n;
@@ -362,6 +372,9 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
     if (vt == DD_F64 && wt == DD_F64)
       k_multi_axpy<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, coef, ldc,
                                                            coff + i0, sign, (double2*)w);
+    else if (vt == DD_F16 && wt == DD_F32)
+      k_multi_axpy<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)Vi, n, vstride, coef, ldc,
+                                                          coff + i0, sign, (float2*)w);
     else if (vt != DD_F64 && wt != DD_F64)
       k_multi_axpy<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, coef, ldc,
                                                          coff + i0, sign, (float2*)w);
@@ -375,42 +388,51 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
   }
 }
 
+// basis V of dtype bt (DD_F16 only with FP32 vectors), vectors w of dtype vt
+#define DD_BASIS_DISPATCH(KERNEL, NORMV)                                                                          \
+  if (vt == DD_F64)                                                                                                \
+    KERNEL<double2, double2, NORMV><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride, coef,   \
+                                                          ldc, (double2*)w, partial, nblk);                        \
+  else if (bt == DD_F16)                                                                                           \
+    KERNEL<__half2, float2, NORMV><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride, coef,    \
+                                                         ldc, (float2*)w, partial, nblk);                          \
+  else                                                                                                             \
+    KERNEL<float2, float2, NORMV><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride, coef, ldc, \
+                                                        (float2*)w, partial, nblk);
+
 void launch_axpy_dots(dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv, long long vstride,
                       const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, int ldo,
-                      hipStream_t st) {
+                      hipStream_t st, dd_dtype bt) {
   dim3 grid(nblk, nrhs);
-  const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
-  const double bytes = (double)nrhs * count * (nv + 2) * es, flops = 16.0 * nrhs * count * nv;
-  DD_TIMED("k_axpy_dots", st, bytes, flops,
-           (vt == DD_F64
-                ? k_axpy_dots<double2, false><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,
-                                                                   coef, ldc, (double2*)w, partial, nblk)
-                : k_axpy_dots<float2, false><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,
-                                                                  coef, ldc, (float2*)w, partial, nblk)));
+  const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
+  const double bytes = (double)nrhs * count * (nv * eb + 2 * es), flops = 16.0 * nrhs * count * nv;
+  DD_TIMED("k_axpy_dots", st, bytes, flops, DD_BASIS_DISPATCH(k_axpy_dots, false));
   k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0);
 }
 
 void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv, long long vstride,
-                      const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, hipStream_t st) {
+                      const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, hipStream_t st,
+                      dd_dtype bt) {
   dim3 grid(nblk, nrhs);
-  const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2);
-  const double bytes = (double)nrhs * count * (nv + 2) * es, flops = 8.0 * nrhs * count * (nv + 1);
-  DD_TIMED("k_axpy_norm", st, bytes, flops,
-           (vt == DD_F64
-                ? k_axpy_dots<double2, true><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,
-                                                                  coef, ldc, (double2*)w, partial, nblk)
-                : k_axpy_dots<float2, true><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,
-                                                                 coef, ldc, (float2*)w, partial, nblk)));
+  const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
+  const double bytes = (double)nrhs * count * (nv * eb + 2 * es), flops = 8.0 * nrhs * count * (nv + 1);
+  DD_TIMED("k_axpy_norm", st, bytes, flops, DD_BASIS_DISPATCH(k_axpy_dots, true));
   k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0);
 }
+#undef DD_BASIS_DISPATCH
 
 void launch_normalize(dd_dtype vt, int nrhs, long long count, long long rs, const void* src, const double2* nrm2,
-                      const double* nrm, const int* mask, void* dst, hipStream_t st) {
+                      const double* nrm, const int* mask, void* dst, hipStream_t st, dd_dtype dt, void* copy32) {
   dim3 grid(grid1(count), nrhs);
   if (vt == DD_F64)
-    k_normalize<double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)src, nrm2, nrm, mask, (double2*)dst);
+    k_normalize<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)src, nrm2, nrm, mask,
+                                                        (double2*)dst, nullptr);
+  else if (dt == DD_F16)
+    k_normalize<float2, __half2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)src, nrm2, nrm, mask,
+                                                       (__half2*)dst, (float2*)copy32);
   else
-    k_normalize<float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)src, nrm2, nrm, mask, (float2*)dst);
+    k_normalize<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)src, nrm2, nrm, mask,
+                                                      (float2*)dst, (float2*)copy32);
 }
 
 void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st) {

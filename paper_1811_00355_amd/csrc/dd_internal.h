@@ -168,6 +168,10 @@ __device__ __forceinline__ void st<float2, double>(float2* p, cx<double> v) {
   *p = make_float2((float)v.re, (float)v.im);
 }
 template <>
+__device__ __forceinline__ void st<__half2, double>(__half2* p, cx<double> v) {
+  *p = __floats2half2_rn((float)v.re, (float)v.im);
+}
+template <>
 __device__ __forceinline__ void st<double2, float>(double2* p, cx<float> v) {
   *p = make_double2((double)v.re, (double)v.im);
 }
@@ -304,6 +308,7 @@ struct Tuning {
   int dirac_threads = 256;  // D apply workgroup size: 64, 128 or 256
   int coarse_spw = 4;       // FP32 coarse apply: coarse sites (waves) per workgroup, 2, 4 or 8
   int coarse_half = 0;      // with half-precision storage: 1 = coarse blocks in that type, 0 = FP32 blocks
+  int coarse_basis_half = 0;  // FP32 coarse GMRES: Krylov basis stored in FP16 (1) or FP32 (0)
 };
 
 struct dd_gauge {
@@ -418,12 +423,15 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
 // w -= sum_i coef_i V_i, then out = <V_i, w> (fused, nv <= 16)
 void launch_axpy_dots(dd_dtype vt, int nrhs, long long count, long long ld, const void* V, int nv, long long vstride,
                       const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, int ldo,
-                      hipStream_t st);
+                      hipStream_t st,
+                      dd_dtype bt = DD_F32);
 // w -= sum_i coef_i V_i, then out[r].x = |w|^2 (fused, nv <= 16)
 void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long ld, const void* V, int nv, long long vstride,
-                      const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, hipStream_t st);
+                      const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, hipStream_t st,
+                      dd_dtype bt = DD_F32);
 void launch_normalize(dd_dtype vt, int nrhs, long long count, long long ld, const void* src, const double2* nrm2,
-                      const double* nrm, const int* mask, void* dst, hipStream_t st);
+                      const double* nrm, const int* mask, void* dst, hipStream_t st,
+                      dd_dtype dt = DD_F32, void* copy32 = nullptr);   // dt: dtype of dst (F16 basis)
 void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);   // bytes: multiple of 4
 // FP32 (and, when half is DD_F16 / DD_BF16, half) copies of nblk FP64 coarse

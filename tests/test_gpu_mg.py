@@ -370,3 +370,57 @@ def test_coarse_half_blocks(ctx, store):
     print(f"store {store}: coarse solve with half blocks, max error {max(errs):.2e}", flush=True)
     assert max(errs) < 1e-4
     _close(d)
+
+
+def test_coarse_basis_half(ctx):
+    """FP16 storage of the FP32 coarse GMRES basis (coarse_basis_half).  The
+    Arnoldi relation is formed with the rounded basis, so the method stays a
+    residual-minimising GMRES over a slightly perturbed Krylov space: (1) in
+    fixed-iteration mode its residual |b - D_c y| (oracle's FP64 stencil on
+    the FP32-rounded operator) is at most 1% above the oracle's own GMRES
+    residual plus the attainable accuracy of a basis known to FP16 unit
+    roundoff (2 u16, u16 = 4.9e-4), and y is within 1e-2 of the oracle's
+    (u16 times the small least-squares condition); (2) a whole solve
+    still reaches |b - D x| / |b| <= 1e-10 with at most two more outer
+    iterations than the FP32 basis."""
+    import torch
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_vectors, gauss_spinor
+    d = _build(ctx, "b4", coarse_fixed_iters=10, coarse_restart=10)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    d["g"].dd_gauge_set_tuning(2, 256, 4, coarse_basis_half=1)
+    Dr = _gpu.round_f32(amg.coarse_operator(d["W"], amg.gram_schmidt(lat, d["tv0"])))
+    ceo = amg.CoarseEO(lat, Dr)
+    op = amg.MGParams(n_vec=n, coarse_fixed_iters=10, coarse_restart=10)
+    nrhs = 12
+    b = _gpu.round_f32(gauss_vectors(nrhs, lat.Vc, 74, ncomp=2 * n))
+    got = _coarse_roundtrip(mg, 1, nrhs, b, lambda i, o: mg.dd_coarse_solve(1, nrhs, i, o))
+    for r in range(nrhs):
+        ref = ceo.solve(b[r], op)
+        nb = np.linalg.norm(b[r])
+        res_got = np.linalg.norm(b[r] - amg.coarse_apply(lat, Dr, got[r])) / nb
+        res_ref = np.linalg.norm(b[r] - amg.coarse_apply(lat, Dr, ref)) / nb
+        err = _gpu.max_rel(got[r], ref)
+        print(f"rhs {r}: residual FP16 basis {res_got:.4e} oracle {res_ref:.4e} solution diff {err:.2e}", flush=True)
+        assert res_got <= 1.01 * res_ref + 2 * 2.0 ** -11 and err < 1e-2
+    _close(d)
+    its = {}
+    for half in (0, 1):
+        d = _build(ctx, "b4", inner_dtype=1, store_dtype=1, init_sap_apps=2, setup_iters=2)
+        d["g"].dd_gauge_set_tuning(2, 256, 4, coarse_basis_half=half)
+        lat, mg = d["lat"], d["mg"]
+        nrhs = 3
+        bs = gauss_spinor(lat.L, nrhs, 62)
+        bd = _gpu.to_dev(bs.reshape(nrhs, -1))
+        xd = torch.zeros_like(bd)
+        info, _ = mg.dd_solve(nrhs, bd, xd, 1e-10)
+        torch.cuda.synchronize()
+        x = _gpu.to_host(xd).reshape(bs.shape)
+        its[half] = [i["outer_iters"] for i in info]
+        for r in range(nrhs):
+            res = np.linalg.norm(bs[r] - d["W"].apply(x[r])) / np.linalg.norm(bs[r])
+            print(f"coarse_basis_half={half} rhs {r}: iters {info[r]['outer_iters']} relres {res:.2e}", flush=True)
+            assert info[r]["converged"] and res <= 1e-10
+        _close(d)
+    assert all(h <= f + 2 for h, f in zip(its[1], its[0]))
