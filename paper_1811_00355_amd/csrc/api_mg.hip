@@ -109,7 +109,10 @@ static void carve_ws(Workspace& w, const dd_mg* mg, int nrhs, bool outer) {
   int nblk = dots_blocks(12LL * V, nrhs);
   int nblk_c = dots_blocks((long long)mg->g->geo.Vc * mg->nc, nrhs);
   if (nblk_c > nblk) nblk = nblk_c;
-  w.partial = a.take<double>((size_t)nrhs * 16 * nblk * 2);
+  size_t np = (size_t)nrhs * 16 * nblk * 2;   // launch_dots: 16 vectors per launch
+  const size_t np_gs = (size_t)nrhs * mc * gs_blocks(mg->g->geo.Vch * (long long)mg->nc) * 2;
+  if (np_gs > np) np = np_gs;
+  w.partial = a.take<double>(np);
   w.b64 = w.x64 = w.w64 = w.zt64 = w.V64 = nullptr;
   w.Z = nullptr;
   if (outer) {
@@ -200,11 +203,18 @@ static void norms2(Workspace* w, dd_dtype vt, int nrhs, long long count, long lo
 }
 
 // classical Gram-Schmidt of w against the basis V_0..V_{nv-1}, `passes` times
-// (h1, then h2), then |w|^2 -> a.nrm2.  With nv <= 16 the passes are fused:
-// dots, then (axpy + second dots), then (axpy + norm) -- three sweeps of V.
+// (h1, then h2), then |w|^2 -> a.nrm2.  One pass: the whole basis in two sweeps
+// (dots, then axpy + norm).  Two passes with nv <= 16: dots, then (axpy +
+// second dots), then (axpy + norm) -- three sweeps of V.  After one pass the
+// step's Arnoldi kernel reads no second-pass coefficients (h2 = null).
 static void cgs(Workspace* ws, Arnoldi& a, dd_dtype vt, int nrhs, long long count, long long ld, const void* V,
                 long long vstride, int nv, void* w, int passes, hipStream_t st, dd_dtype bt) {
   // bt: dtype of the basis V (vt, or DD_F16 for an FP16 basis with FP32 vectors)
+  if (passes == 1 && nv <= gs_max_nv()) {
+    launch_gs_dots(bt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, a.h1, a.m + 1, st);
+    launch_gs_axpy_norm(bt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, a.nrm2, st);
+    return;
+  }
   int nblk = dots_blocks(count, nrhs);
   launch_dots(bt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h1, a.m + 1, 0, st);
   if (passes == 2 && nv <= 16) {
@@ -217,11 +227,6 @@ static void cgs(Workspace* ws, Arnoldi& a, dd_dtype vt, int nrhs, long long coun
     launch_dots(bt, vt, nrhs, count, ld, V, nv, vstride, w, ws->partial, nblk, a.h2, a.m + 1, 0, st);
     launch_multi_axpy(bt, vt, nrhs, count, ld, V, nv, vstride, a.h2, a.m + 1, 0, -1.0, w, st);
     launch_dots(vt, vt, nrhs, count, ld, w, 1, 0, w, ws->partial, nblk, a.nrm2, 1, 0, st);
-    return;
-  }
-  launch_zero(a.h2, sizeof(double2) * nrhs * (a.m + 1), st);
-  if (nv <= 16) {
-    launch_axpy_norm(vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, w, ws->partial, nblk, a.nrm2, st, bt);
     return;
   }
   launch_multi_axpy(bt, vt, nrhs, count, ld, V, nv, vstride, a.h1, a.m + 1, 0, -1.0, w, st);
@@ -274,8 +279,8 @@ static void issue_chunk(const CoarseOps& c, Workspace* w, Arnoldi& a, int passes
   for (int j = j0; j < j0 + len; ++j) {
     schur_apply(c, nrhs, half ? w->cv32 : CV + (size_t)j * vs * c.bb, w->cw, w->ct1, w->ct2, st);
     cgs(w, a, c.vt, nrhs, ce, ld, CV, vs, j + 1, w->cw, passes, st, c.basis);
-    launch_arnoldi(nrhs, a.m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est,
-                   a.hnext, st);
+    launch_arnoldi(nrhs, a.m, j, a.h1, passes == 2 ? a.h2 : nullptr, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs,
+                   a.active, a.kcyc, a.est, a.hnext, st);
     if (ends && j + 1 == j0 + len) break;
     launch_normalize(c.vt, nrhs, ce, ld, w->cw, nullptr, a.hnext, a.active, CV + (size_t)(j + 1) * vs * c.bb, st,
                      c.basis, half ? w->cv32 : nullptr);

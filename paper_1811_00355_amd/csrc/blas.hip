@@ -163,6 +163,151 @@ __global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, lo
   }
 }
 
+// Classical Gram-Schmidt against a whole basis (nv <= kGsMaxNv) in two passes:
+// k_gs_dots forms <V_i, w> for every i, k_gs_axpy_norm then w <- w - sum c_i V_i
+// and |w|^2.  A workgroup owns a fixed tile of kGsTile entries (so the
+// reduction tree depends on the vector length only); each thread keeps
+// kGsEpt entries of w in registers and streams kGsGroup basis vectors at a
+// time, and a wave folds the 2 kGsGroup sums of its lanes with a butterfly
+// that halves the set at every exchange.
+constexpr int kGsEpt = 8, kGsTile = 256 * kGsEpt, kGsGroup = 4, kGsMaxNv = 128;
+
+// a[0..7] of every lane -> value (lane >> 3) summed over the wave (10 exchanges)
+__device__ __forceinline__ double fold8(double* a, int lane) {
+  {
+    const bool hi = lane & 32;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double keep = hi ? a[4 + j] : a[j], send = hi ? a[j] : a[4 + j];
+      a[j] = keep + __shfl_xor(send, 32, 64);
+    }
+  }
+  {
+    const bool hi = lane & 16;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double keep = hi ? a[2 + j] : a[j], send = hi ? a[j] : a[2 + j];
+      a[j] = keep + __shfl_xor(send, 16, 64);
+    }
+  }
+  {
+    const bool hi = lane & 8;
+    const double keep = hi ? a[1] : a[0], send = hi ? a[0] : a[1];
+    a[0] = keep + __shfl_xor(send, 8, 64);
+  }
+  double v = a[0];
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  return v;
+}
+
+// The loads of a group carry no conditions (indices are clamped into the
+// vectors and out-of-range terms are multiplied by zero), so a thread has all
+// kGsEpt * kGsGroup of them in flight at once.
+template <typename Tv, typename Tw>
+__global__ void __launch_bounds__(256) k_gs_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
+                                                 int nv, long long vstride, const Tw* __restrict__ w,
+                                                 double* __restrict__ partial, int nblk) {
+  static_assert(kGsGroup == 4, "fold8 folds 2 x 4 values");
+  __shared__ double red[4][2 * kGsMaxNv];
+  const int r = blockIdx.y, blk = blockIdx.x, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long e0 = (long long)blk * kGsTile + threadIdx.x;
+  const Tw* wr = w + (long long)r * rs;
+  const Tv* vr = V + (long long)r * rs;
+  cx<double> x[kGsEpt];
+  long long ek[kGsEpt];
+#pragma unroll
+  for (int k = 0; k < kGsEpt; ++k) {
+    const long long e = e0 + 256LL * k;
+    ek[k] = e < count ? e : count - 1;
+    const cx<double> v = ld<double, Tw>(wr + ek[k]);
+    x[k] = e < count ? v : cx<double>{0.0, 0.0};   // entries past the end contribute zero
+  }
+  for (int i0 = 0; i0 < nv; i0 += kGsGroup) {
+    Tv raw[kGsGroup][kGsEpt];
+#pragma unroll
+    for (int g = 0; g < kGsGroup; ++g) {
+      const Tv* vi = vr + (long long)(i0 + g < nv ? i0 + g : nv - 1) * vstride;   // past nv: discarded below
+#pragma unroll
+      for (int k = 0; k < kGsEpt; ++k) raw[g][k] = vi[ek[k]];
+    }
+    double a[2 * kGsGroup];
+#pragma unroll
+    for (int g = 0; g < kGsGroup; ++g) {
+      cx<double> acc = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < kGsEpt; ++k) cfma_conj(acc, ld<double, Tv>(&raw[g][k]), x[k]);
+      a[2 * g] = acc.re;
+      a[2 * g + 1] = acc.im;
+    }
+    const double s = fold8(a, lane);
+    const int t = 2 * i0 + (lane >> 3);
+    if ((lane & 7) == 0 && t < 2 * nv) red[wv][t] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 2 * nv; t += blockDim.x)
+    partial[(((long long)r * nv + (t >> 1)) * nblk + blk) * 2 + (t & 1)] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+// w[r] <- w[r] - sum_{i < nv} coef[r * ldc + i] V_i[r], partial sums of |w|^2 over the same tiles
+template <typename Tv, typename Tw>
+__global__ void __launch_bounds__(256) k_gs_axpy_norm(int nrhs, long long count, long long rs,
+                                                      const Tv* __restrict__ V, int nv, long long vstride,
+                                                      const double2* __restrict__ coef, int ldc, Tw* __restrict__ w,
+                                                      double* __restrict__ partial, int nblk) {
+  __shared__ cx<double> c[kGsMaxNv + kGsGroup];
+  __shared__ double red[4];
+  const int r = blockIdx.y, blk = blockIdx.x, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nvp = (nv + kGsGroup - 1) / kGsGroup * kGsGroup;
+  for (int i = threadIdx.x; i < nvp; i += blockDim.x) {
+    const double2 v = i < nv ? coef[(long long)r * ldc + i] : make_double2(0.0, 0.0);   // padding: zero weight
+    c[i] = {v.x, v.y};
+  }
+  __syncthreads();
+  const long long e0 = (long long)blk * kGsTile + threadIdx.x;
+  Tw* wr = w + (long long)r * rs;
+  const Tv* vr = V + (long long)r * rs;
+  cx<double> x[kGsEpt];
+  long long ek[kGsEpt];
+#pragma unroll
+  for (int k = 0; k < kGsEpt; ++k) {
+    const long long e = e0 + 256LL * k;
+    ek[k] = e < count ? e : count - 1;
+    x[k] = ld<double, Tw>(wr + ek[k]);
+  }
+  for (int i0 = 0; i0 < nv; i0 += kGsGroup) {
+    Tv raw[kGsGroup][kGsEpt];
+#pragma unroll
+    for (int g = 0; g < kGsGroup; ++g) {
+      const Tv* vi = vr + (long long)(i0 + g < nv ? i0 + g : nv - 1) * vstride;   // past nv: weight zero
+#pragma unroll
+      for (int k = 0; k < kGsEpt; ++k) raw[g][k] = vi[ek[k]];
+    }
+#pragma unroll
+    for (int g = 0; g < kGsGroup; ++g) {
+      const cx<double> cg = c[i0 + g];
+#pragma unroll
+      for (int k = 0; k < kGsEpt; ++k) x[k] = x[k] - cg * ld<double, Tv>(&raw[g][k]);
+    }
+  }
+  double n2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < kGsEpt; ++k) {
+    const long long e = e0 + 256LL * k;
+    if (e < count) {
+      st<Tw, double>(wr + e, x[k]);
+      n2 += x[k].re * x[k].re + x[k].im * x[k].im;
+    }
+  }
+  n2 = wave_sum(n2);
+  if (lane == 0) red[wv] = n2;
+  __syncthreads();
+  if (threadIdx.x < 2)
+    partial[((long long)r * nblk + blk) * 2 + threadIdx.x] =
+        threadIdx.x == 0 ? red[0] + red[1] + red[2] + red[3] : 0.0;
+}
+
 // dst[r] = src[r] / sqrt(nrm[r].x) where mask[r] != 0 (mask may be null); zero norm gives zero
 template <typename Ts, typename Td>
 __global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, long long rs, const Ts* __restrict__ src,
@@ -236,7 +381,7 @@ __global__ void k_arnoldi(int nrhs, int m, int j, const double2* __restrict__ h1
   if (r >= nrhs || !active[r]) return;
   double2* Hc = H + ((long long)r * m + j) * (m + 1);   // column j
   for (int i = 0; i <= j; ++i) {
-    double2 a = h1[r * (m + 1) + i], b = h2[r * (m + 1) + i];
+    double2 a = h1[r * (m + 1) + i], b = h2 ? h2[r * (m + 1) + i] : make_double2(0.0, 0.0);
     Hc[i] = make_double2(a.x + b.x, a.y + b.y);
   }
   double hn = sqrt(nrm2[r].x);
@@ -420,6 +565,54 @@ void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long rs, cons
   k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0);
 }
 #undef DD_BASIS_DISPATCH
+
+int gs_max_nv() { return kGsMaxNv; }
+int gs_blocks(long long count) { return (int)((count + kGsTile - 1) / kGsTile); }
+
+// basis V of dtype bt (DD_F16 only with FP32 vectors), vector w of dtype vt
+#define DD_GS_DISPATCH(KERNEL, ...)                                                                  \
+  if (vt == DD_F64)                                                                                   \
+    KERNEL<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,   \
+                                                   __VA_ARGS__, (double2*)w, partial, nblk);          \
+  else if (bt == DD_F16)                                                                              \
+    KERNEL<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride,    \
+                                                  __VA_ARGS__, (float2*)w, partial, nblk);            \
+  else                                                                                                \
+    KERNEL<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,      \
+                                                 __VA_ARGS__, (float2*)w, partial, nblk);
+
+void launch_gs_dots(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv,
+                    long long vstride, const void* w, double* partial, double2* out, int ldo, hipStream_t st) {
+  const int nblk = gs_blocks(count);
+  dim3 grid(nblk, nrhs);
+  const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
+  const double bytes = (double)nrhs * count * (nv * eb + es), flops = 8.0 * nrhs * count * nv;
+  if (vt == DD_F64)
+    DD_TIMED("k_gs_dots", st, bytes, flops,
+             (k_gs_dots<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,
+                                                                (const double2*)w, partial, nblk)));
+  else if (bt == DD_F16)
+    DD_TIMED("k_gs_dots", st, bytes, flops,
+             (k_gs_dots<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride,
+                                                               (const float2*)w, partial, nblk)));
+  else
+    DD_TIMED("k_gs_dots", st, bytes, flops,
+             (k_gs_dots<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,
+                                                              (const float2*)w, partial, nblk)));
+  k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0);
+}
+
+void launch_gs_axpy_norm(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv,
+                         long long vstride, const double2* coef, int ldc, void* w, double* partial, double2* out,
+                         hipStream_t st) {
+  const int nblk = gs_blocks(count);
+  dim3 grid(nblk, nrhs);
+  const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
+  const double bytes = (double)nrhs * count * (nv * eb + 2 * es), flops = 8.0 * nrhs * count * (nv + 1);
+  DD_TIMED("k_gs_axpy_norm", st, bytes, flops, DD_GS_DISPATCH(k_gs_axpy_norm, coef, ldc));
+  k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0);
+}
+#undef DD_GS_DISPATCH
 
 void launch_normalize(dd_dtype vt, int nrhs, long long count, long long rs, const void* src, const double2* nrm2,
                       const double* nrm, const int* mask, void* dst, hipStream_t st, dd_dtype dt, void* copy32) {

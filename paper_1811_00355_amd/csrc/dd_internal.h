@@ -429,6 +429,16 @@ void launch_axpy_dots(dd_dtype vt, int nrhs, long long count, long long ld, cons
 void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long ld, const void* V, int nv, long long vstride,
                       const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, hipStream_t st,
                       dd_dtype bt = DD_F32);
+// whole-basis classical Gram-Schmidt (nv <= gs_max_nv()), partial sums over gs_blocks(count) tiles:
+// out[r * ldo + i] = <V_i, w> for i < nv
+int gs_max_nv();
+int gs_blocks(long long count);
+void launch_gs_dots(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long long ld, const void* V, int nv,
+                    long long vstride, const void* w, double* partial, double2* out, int ldo, hipStream_t st);
+// w -= sum_{i < nv} coef_i V_i, then out[r].x = |w|^2
+void launch_gs_axpy_norm(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long long ld, const void* V, int nv,
+                         long long vstride, const double2* coef, int ldc, void* w, double* partial, double2* out,
+                         hipStream_t st);
 void launch_normalize(dd_dtype vt, int nrhs, long long count, long long ld, const void* src, const double2* nrm2,
                       const double* nrm, const int* mask, void* dst, hipStream_t st,
                       dd_dtype dt = DD_F32, void* copy32 = nullptr);   // dt: dtype of dst (F16 basis)
@@ -441,6 +451,7 @@ void launch_coarse_tile(int nc, const double2* src64, long long nblk, float2* ds
 void launch_add(dd_dtype vt, long long n, const void* a, void* out, hipStream_t st);
 void launch_cycle_init(int nrhs, int m, const double2* nrm2, const double* tolabs, const int* finished,
                        double2* gv, double* beta, int* active, int* kcyc, hipStream_t st);
+// h2: second Gram-Schmidt pass, or null after a single pass
 void launch_arnoldi(int nrhs, int m, int j, const double2* h1, const double2* h2, const double2* nrm2,
                     double2* H, double* cs, double2* sn, double2* gv, const double* tolabs, int* active,
                     int* kcyc, double* est, double* hnext, hipStream_t st);
