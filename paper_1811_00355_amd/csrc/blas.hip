@@ -19,28 +19,53 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <typename Tv, typename Tw>
+// The basis kernels take the vector count nv at run time and a compile-time
+// bound NV in {1, 2, 4, 8, 16}: loads of vectors past nv are clamped to vector
+// nv - 1 (same cache lines) and their results discarded or weighted by zero,
+// and each thread handles U = 8 / NV entries per trip (at least one), so all
+// NV * U loads of a trip are issued before the first wait.
+template <int NV>
+constexpr int nv_unroll() { return NV >= 8 ? 1 : 8 / NV; }
+
+// partial[r][i][blk] = <V_i[r], w[r]> over the blk-th of nblk equal chunks
+template <int NV, typename Tv, typename Tw>
 __global__ void __launch_bounds__(256) k_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V, int nv,
                                               long long vstride, const Tw* __restrict__ w, double* __restrict__ partial,
                                               int nblk) {
-  __shared__ double red[4][2 * kMaxNv];
+  constexpr int U = nv_unroll<NV>();
+  __shared__ double red[4][2 * NV];
   const int r = blockIdx.y, blk = blockIdx.x;
-  long long chunk = (count + nblk - 1) / nblk;
-  long long e0 = (long long)blk * chunk, e1 = e0 + chunk < count ? e0 + chunk : count;
-  cx<double> acc[kMaxNv];
+  const long long chunk = (count + nblk - 1) / nblk;
+  const long long e0 = (long long)blk * chunk, e1 = e0 + chunk < count ? e0 + chunk : count;
+  cx<double> acc[NV];
 #pragma unroll
-  for (int i = 0; i < kMaxNv; ++i) acc[i] = {0.0, 0.0};
+  for (int i = 0; i < NV; ++i) acc[i] = {0.0, 0.0};
   const Tw* wr = w + (long long)r * rs;
   const Tv* vr = V + (long long)r * rs;
-  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    cx<double> x = ld<double, Tw>(wr + e);
+  for (long long b = e0 + threadIdx.x; b < e1; b += 256LL * U) {
+    long long ek[U];
+    Tw wraw[U];
+    Tv vraw[NV][U];
 #pragma unroll
-    for (int i = 0; i < kMaxNv; ++i)
-      if (i < nv) cfma_conj(acc[i], ld<double, Tv>(vr + (long long)i * vstride + e), x);
+    for (int u = 0; u < U; ++u) ek[u] = b + 256LL * u < e1 ? b + 256LL * u : e1 - 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) wraw[u] = wr[ek[u]];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const Tv* vi = vr + (long long)(i < nv ? i : nv - 1) * vstride;
+#pragma unroll
+      for (int u = 0; u < U; ++u) vraw[i][u] = vi[ek[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const cx<double> x = b + 256LL * u < e1 ? ld<double, Tw>(&wraw[u]) : cx<double>{0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < NV; ++i) cfma_conj(acc[i], ld<double, Tv>(&vraw[i][u]), x);
+    }
   }
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int i = 0; i < kMaxNv; ++i) {
+  for (int i = 0; i < NV; ++i) {
     if (i < nv) {
       double a = wave_sum(acc[i].re), b = wave_sum(acc[i].im);
       if (lane == 0) {
@@ -81,72 +106,103 @@ __global__ void __launch_bounds__(256) k_reduce(int nv, int nblk, const double* 
   if (threadIdx.x == 0) out[(long long)r * ldo + off + i] = make_double2(red[0][0], red[1][0]);
 }
 
-// w[r] += sign * sum_i coef[r * ldc + coff + i] * V_i[r]
-template <typename Tv, typename Tw>
+// w[r] += sign * sum_{i < nv} coef[r * ldc + coff + i] * V_i[r]
+template <int NV, typename Tv, typename Tw>
 __global__ void __launch_bounds__(256) k_multi_axpy(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
                                                     int nv, long long vstride, const double2* __restrict__ coef, int ldc,
                                                     int coff, double sign, Tw* __restrict__ w) {
-  __shared__ cx<double> c[kMaxNv];
+  constexpr int U = nv_unroll<NV>();
+  __shared__ cx<double> c[NV];
   const int r = blockIdx.y;
-  if (threadIdx.x < nv) {
-    double2 v = coef[(long long)r * ldc + coff + threadIdx.x];
+  if (threadIdx.x < NV) {
+    const double2 v = threadIdx.x < nv ? coef[(long long)r * ldc + coff + threadIdx.x] : make_double2(0.0, 0.0);
     c[threadIdx.x] = {sign * v.x, sign * v.y};
   }
   __syncthreads();
   const Tv* vr = V + (long long)r * rs;
   Tw* wr = w + (long long)r * rs;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x) {
-    cx<double> acc = ld<double, Tw>(wr + e);
-    for (int i = 0; i < nv; ++i)
-      if (c[i].re != 0.0 || c[i].im != 0.0) cfma(acc, c[i], ld<double, Tv>(vr + (long long)i * vstride + e));
-    st<Tw, double>(wr + e, acc);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < count; b += stride * U) {
+    long long ek[U];
+    Tw wraw[U];
+    Tv vraw[NV][U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) ek[u] = b + stride * u < count ? b + stride * u : count - 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) wraw[u] = wr[ek[u]];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const Tv* vi = vr + (long long)(i < nv ? i : nv - 1) * vstride;
+#pragma unroll
+      for (int u = 0; u < U; ++u) vraw[i][u] = vi[ek[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cx<double> acc = ld<double, Tw>(&wraw[u]);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) cfma(acc, c[i], ld<double, Tv>(&vraw[i][u]));
+      if (b + stride * u < count) st<Tw, double>(wr + ek[u], acc);
+    }
   }
 }
 
 // Fused CGS pieces for one sweep of the basis: w <- w - sum_i c_i V_i with the
 // V_i kept in registers, then either the inner products <V_i, w> (NORM = false)
 // or |w|^2 (NORM = true) of the updated w, reduced like k_dots.
-template <typename Tv, typename Tw, bool NORM>
+template <int NV, typename Tv, typename Tw, bool NORM>
 __global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
                                                    int nv, long long vstride, const double2* __restrict__ coef, int ldc,
                                                    Tw* __restrict__ w, double* __restrict__ partial, int nblk) {
-  __shared__ double red[4][2 * kMaxNv];
-  __shared__ cx<double> c[kMaxNv];
+  constexpr int U = nv_unroll<NV>();
+  __shared__ double red[4][2 * NV];
+  __shared__ cx<double> c[NV];
   const int r = blockIdx.y, blk = blockIdx.x;
-  if (threadIdx.x < nv) {
-    double2 v = coef[(long long)r * ldc + threadIdx.x];
+  if (threadIdx.x < NV) {
+    const double2 v = threadIdx.x < nv ? coef[(long long)r * ldc + threadIdx.x] : make_double2(0.0, 0.0);
     c[threadIdx.x] = {v.x, v.y};
   }
   __syncthreads();
-  long long chunk = (count + nblk - 1) / nblk;
-  long long e0 = (long long)blk * chunk, e1 = e0 + chunk < count ? e0 + chunk : count;
-  cx<double> acc[kMaxNv];
+  const long long chunk = (count + nblk - 1) / nblk;
+  const long long e0 = (long long)blk * chunk, e1 = e0 + chunk < count ? e0 + chunk : count;
+  cx<double> acc[NV];
 #pragma unroll
-  for (int i = 0; i < kMaxNv; ++i) acc[i] = {0.0, 0.0};
+  for (int i = 0; i < NV; ++i) acc[i] = {0.0, 0.0};
   Tw* wr = w + (long long)r * rs;
   const Tv* vr = V + (long long)r * rs;
-  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    cx<double> x = ld<double, Tw>(wr + e);
-    cx<double> v[kMaxNv];
+  for (long long b = e0 + threadIdx.x; b < e1; b += 256LL * U) {
+    long long ek[U];
+    Tw wraw[U];
+    Tv vraw[NV][U];
 #pragma unroll
-    for (int i = 0; i < kMaxNv; ++i)
-      if (i < nv) {
-        v[i] = ld<double, Tv>(vr + (long long)i * vstride + e);
-        x = x - c[i] * v[i];
+    for (int u = 0; u < U; ++u) ek[u] = b + 256LL * u < e1 ? b + 256LL * u : e1 - 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) wraw[u] = wr[ek[u]];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const Tv* vi = vr + (long long)(i < nv ? i : nv - 1) * vstride;
+#pragma unroll
+      for (int u = 0; u < U; ++u) vraw[i][u] = vi[ek[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = b + 256LL * u < e1;
+      cx<double> x = ld<double, Tw>(&wraw[u]);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) x = x - c[i] * ld<double, Tv>(&vraw[i][u]);
+      if (ok) st<Tw, double>(wr + ek[u], x);
+      if (!ok) x = {0.0, 0.0};
+      if (NORM) {
+        acc[0].re += x.re * x.re + x.im * x.im;
+      } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cfma_conj(acc[i], ld<double, Tv>(&vraw[i][u]), x);
       }
-    st<Tw, double>(wr + e, x);
-    if (NORM) {
-      acc[0].re += x.re * x.re + x.im * x.im;
-    } else {
-#pragma unroll
-      for (int i = 0; i < kMaxNv; ++i)
-        if (i < nv) cfma_conj(acc[i], v[i], x);
     }
   }
   const int nout = NORM ? 1 : nv;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int i = 0; i < kMaxNv; ++i) {
+  for (int i = 0; i < NV; ++i) {
     if (i < nout) {
       double a = wave_sum(acc[i].re), b = wave_sum(acc[i].im);
       if (lane == 0) {
@@ -470,6 +526,52 @@ int dots_blocks(long long count, int /*nrhs*/) {
   return (int)nb;
 }
 
+namespace {
+// BODY(NV) for the smallest bucket NV >= n (n <= 16)
+#define DD_NV_BUCKET(n, BODY) \
+  if ((n) <= 1) {             \
+    BODY(1);                  \
+  } else if ((n) <= 2) {      \
+    BODY(2);                  \
+  } else if ((n) <= 4) {      \
+    BODY(4);                  \
+  } else if ((n) <= 8) {      \
+    BODY(8);                  \
+  } else {                    \
+    BODY(16);                 \
+  }
+
+template <typename Tv, typename Tw>
+void dots_typed(dim3 grid, hipStream_t st, int nrhs, long long count, long long rs, const void* V, int n,
+                long long vstride, const void* w, double* partial, int nblk) {
+#define DD_DOTS(NV) \
+  k_dots<NV, Tv, Tw><<<grid, 256, 0, st>>>(nrhs, count, rs, (const Tv*)V, n, vstride, (const Tw*)w, partial, nblk)
+  DD_NV_BUCKET(n, DD_DOTS)
+#undef DD_DOTS
+}
+
+template <typename Tv, typename Tw>
+void multi_axpy_typed(dim3 grid, hipStream_t st, int nrhs, long long count, long long rs, const void* V, int n,
+                      long long vstride, const double2* coef, int ldc, int coff, double sign, void* w) {
+#define DD_MAXPY(NV)                                                                                          \
+  k_multi_axpy<NV, Tv, Tw><<<grid, 256, 0, st>>>(nrhs, count, rs, (const Tv*)V, n, vstride, coef, ldc, coff, sign, \
+                                                  (Tw*)w)
+  DD_NV_BUCKET(n, DD_MAXPY)
+#undef DD_MAXPY
+}
+
+template <typename Tv, typename Tw, bool NORM>
+void axpy_dots_typed(dim3 grid, hipStream_t st, int nrhs, long long count, long long rs, const void* V, int n,
+                     long long vstride, const double2* coef, int ldc, void* w, double* partial, int nblk) {
+#define DD_AXD(NV)                                                                                                \
+  k_axpy_dots<NV, Tv, Tw, NORM><<<grid, 256, 0, st>>>(nrhs, count, rs, (const Tv*)V, n, vstride, coef, ldc, (Tw*)w, \
+                                                       partial, nblk)
+  DD_NV_BUCKET(n, DD_AXD)
+#undef DD_AXD
+}
+#undef DD_NV_BUCKET
+}  // namespace
+
 void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long rs, const void* V, int nv,
                  long long vstride, const void* w, double* partial, int nblk, double2* out, int ldo, int off,
                  hipStream_t st) {
@@ -483,20 +585,15 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
     const bool timed = ktimer_enabled("k_dots");
     if (timed) ktimer_begin("k_dots", st);
     if (vt == DD_F64 && wt == DD_F64)
-      k_dots<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, (const double2*)w,
-                                                     partial, nblk);
+      dots_typed<double2, double2>(grid, st, nrhs, count, rs, Vi, n, vstride, w, partial, nblk);
     else if (vt == DD_F16 && wt == DD_F32)
-      k_dots<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)Vi, n, vstride, (const float2*)w,
-                                                    partial, nblk);
+      dots_typed<__half2, float2>(grid, st, nrhs, count, rs, Vi, n, vstride, w, partial, nblk);
     else if (vt != DD_F64 && wt != DD_F64)
-      k_dots<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, (const float2*)w,
-                                                   partial, nblk);
+      dots_typed<float2, float2>(grid, st, nrhs, count, rs, Vi, n, vstride, w, partial, nblk);
     else if (vt == DD_F64)
-      k_dots<double2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, (const float2*)w,
-                                                    partial, nblk);
+      dots_typed<double2, float2>(grid, st, nrhs, count, rs, Vi, n, vstride, w, partial, nblk);
     else
-      k_dots<float2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, (const double2*)w,
-                                                    partial, nblk);
+      dots_typed<float2, double2>(grid, st, nrhs, count, rs, Vi, n, vstride, w, partial, nblk);
     if (timed) ktimer_end("k_dots", st, bytes, flops);
     k_reduce<<<nrhs * n, 256, 0, st>>>(n, nblk, partial, out, ldo, off + i0);
   }
@@ -515,35 +612,27 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
     const bool timed = ktimer_enabled("k_multi_axpy");
     if (timed) ktimer_begin("k_multi_axpy", st);
     if (vt == DD_F64 && wt == DD_F64)
-      k_multi_axpy<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, coef, ldc,
-                                                           coff + i0, sign, (double2*)w);
+      multi_axpy_typed<double2, double2>(grid, st, nrhs, count, rs, Vi, n, vstride, coef, ldc, coff + i0, sign, w);
     else if (vt == DD_F16 && wt == DD_F32)
-      k_multi_axpy<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)Vi, n, vstride, coef, ldc,
-                                                          coff + i0, sign, (float2*)w);
+      multi_axpy_typed<__half2, float2>(grid, st, nrhs, count, rs, Vi, n, vstride, coef, ldc, coff + i0, sign, w);
     else if (vt != DD_F64 && wt != DD_F64)
-      k_multi_axpy<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, coef, ldc,
-                                                         coff + i0, sign, (float2*)w);
+      multi_axpy_typed<float2, float2>(grid, st, nrhs, count, rs, Vi, n, vstride, coef, ldc, coff + i0, sign, w);
     else if (vt != DD_F64)
-      k_multi_axpy<float2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)Vi, n, vstride, coef, ldc,
-                                                          coff + i0, sign, (double2*)w);
+      multi_axpy_typed<float2, double2>(grid, st, nrhs, count, rs, Vi, n, vstride, coef, ldc, coff + i0, sign, w);
     else
-      k_multi_axpy<double2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)Vi, n, vstride, coef, ldc,
-                                                          coff + i0, sign, (float2*)w);
+      multi_axpy_typed<double2, float2>(grid, st, nrhs, count, rs, Vi, n, vstride, coef, ldc, coff + i0, sign, w);
     if (timed) ktimer_end("k_multi_axpy", st, bytes, flops);
   }
 }
 
 // basis V of dtype bt (DD_F16 only with FP32 vectors), vectors w of dtype vt
-#define DD_BASIS_DISPATCH(KERNEL, NORMV)                                                                          \
-  if (vt == DD_F64)                                                                                                \
-    KERNEL<double2, double2, NORMV><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride, coef,   \
-                                                          ldc, (double2*)w, partial, nblk);                        \
-  else if (bt == DD_F16)                                                                                           \
-    KERNEL<__half2, float2, NORMV><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride, coef,    \
-                                                         ldc, (float2*)w, partial, nblk);                          \
-  else                                                                                                             \
-    KERNEL<float2, float2, NORMV><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride, coef, ldc, \
-                                                        (float2*)w, partial, nblk);
+#define DD_BASIS_DISPATCH(NORMV)                                                                                    \
+  if (vt == DD_F64)                                                                                                  \
+    axpy_dots_typed<double2, double2, NORMV>(grid, st, nrhs, count, rs, V, nv, vstride, coef, ldc, w, partial, nblk); \
+  else if (bt == DD_F16)                                                                                             \
+    axpy_dots_typed<__half2, float2, NORMV>(grid, st, nrhs, count, rs, V, nv, vstride, coef, ldc, w, partial, nblk);  \
+  else                                                                                                               \
+    axpy_dots_typed<float2, float2, NORMV>(grid, st, nrhs, count, rs, V, nv, vstride, coef, ldc, w, partial, nblk);
 
 void launch_axpy_dots(dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv, long long vstride,
                       const double2* coef, int ldc, void* w, double* partial, int nblk, double2* out, int ldo,
@@ -551,7 +640,7 @@ void launch_axpy_dots(dd_dtype vt, int nrhs, long long count, long long rs, cons
   dim3 grid(nblk, nrhs);
   const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
   const double bytes = (double)nrhs * count * (nv * eb + 2 * es), flops = 16.0 * nrhs * count * nv;
-  DD_TIMED("k_axpy_dots", st, bytes, flops, DD_BASIS_DISPATCH(k_axpy_dots, false));
+  DD_TIMED("k_axpy_dots", st, bytes, flops, DD_BASIS_DISPATCH(false));
   k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0);
 }
 
@@ -561,7 +650,7 @@ void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long rs, cons
   dim3 grid(nblk, nrhs);
   const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
   const double bytes = (double)nrhs * count * (nv * eb + 2 * es), flops = 8.0 * nrhs * count * (nv + 1);
-  DD_TIMED("k_axpy_norm", st, bytes, flops, DD_BASIS_DISPATCH(k_axpy_dots, true));
+  DD_TIMED("k_axpy_norm", st, bytes, flops, DD_BASIS_DISPATCH(true));
   k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0);
 }
 #undef DD_BASIS_DISPATCH
