@@ -137,96 +137,104 @@ __global__ void k_tile_half(const float2* __restrict__ src, H* __restrict__ dst,
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxNc = 48;
 
-// NC = 2n (a multiple of 4, at most 48), SPW = sites (waves) per workgroup.  The
-// whole block of one direction is loaded into registers before the staging
-// barrier, so its HBM reads overlap the LDS traffic and every MFMA operand is
-// already in flight.
-template <int NC, int SPW, typename Sd>
-__global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const Sd* __restrict__ Dc,
-                                                          const Sd* __restrict__ Minv, int use_inv, int nrhs,
-                                                          int site_begin, int count, float a_self,
-                                                          const float2* __restrict__ xs, float a_hop,
-                                                          const float2* __restrict__ xh, float beta,
-                                                          const float2* __restrict__ z, float2* __restrict__ out) {
-  constexpr int MT = (NC + 15) / 16, KS = NC / 4;
-  __shared__ float2 xsh[SPW][NC][16];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int local = blockIdx.x * SPW + w;
-  const bool site_ok = local < count;
+// NC = 2n (a multiple of 4, at most 48).  A workgroup takes S coarse sites with
+// MT = ceil(NC / 16) waves per site, one per 16-row tile of the NC rows: each
+// wave streams its rows of the site's 9 (or 1, or 8) blocks into registers,
+// while the MT waves of the site stage sc * x(Y) for 16 right-hand sides (zero
+// weight past nrhs) in LDS with loads along the columns, one barrier per
+// direction (double-buffered staging).  Complex products use three real MFMAs
+// (Gauss): with A = a + ib and x = c + id,
+//   k1 += a (c + d),  k2 += (a + b)(-d),  k3 += (b - a) c,
+//   Re(A x) = k1 + k2,  Im(A x) = k1 + k3.
+// Site groups are dealt to the XCDs in contiguous eighths, so the neighbours'
+// x of one range come from the same L2.
+template <int NC, int S, typename Sd>
+__global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) k_coarse_mfma(
+    GeomDev g, const Sd* __restrict__ Dc, const Sd* __restrict__ Minv, int use_inv, int nrhs, int site_begin,
+    int count, float a_self, const float2* __restrict__ xs, float a_hop, const float2* __restrict__ xh, float beta,
+    const float2* __restrict__ z, float2* __restrict__ out) {
+  constexpr int MT = (NC + 15) / 16, KS = NC / 4, XP = 17;
+  constexpr int P = tile_group(NC, (int)sizeof(Sd));
+  struct alignas(P * sizeof(Sd)) Pack {
+    Sd v[P];
+  };
+  __shared__ float2 xsh[S][2][NC][XP];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s_in = wv / MT, t = wv % MT, tid_site = threadIdx.x - 64 * MT * s_in;
+  const int ngroups = (count + S - 1) / S, per_x = (ngroups + 7) / 8;
+  const int group = (blockIdx.x & 7) * per_x + (blockIdx.x >> 3);
+  if (group >= ngroups) return;   // uniform per workgroup
+  const int local = group * S + s_in;
+  const bool site_ok = local < count;   // S > 1: the last group may be short (its waves still reach the barriers)
   const int X = site_begin + (site_ok ? local : 0);
+  const int RT = NC - 16 * t < 16 ? NC - 16 * t : 16;
   const long long vstride = (long long)g.Vc * NC;
   const bool has_self = a_self != 0.f, has_hop = a_hop != 0.f;
   const int li = lane & 15, lk = lane >> 4;
+  const bool row_ok = li < RT;
+  int buf = 0;
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
-    f32x4 c0[MT], c1[MT];
-#pragma unroll
-    for (int t = 0; t < MT; ++t) c0[t] = c1[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const bool rhs_ok = li < nr;
+    f32x4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1;
     for (int d = has_self ? 0 : 1; d < (has_hop ? 9 : 1); ++d) {
       const int Y = d == 0 ? X : (g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK);
       const float2* src = d == 0 ? xs : xh;
       const float sc = d == 0 ? a_self : a_hop;
       const Sd* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * NC * NC : Dc + (long long)X * 9 * NC * NC)
                            : Dc + ((long long)X * 9 + d) * NC * NC;
-      // P k-steps per load from the matrix-core order (see tiled_off)
-      constexpr int P = tile_group(NC, (int)sizeof(Sd));
-      struct alignas(P * sizeof(Sd)) Pack {
-        Sd v[P];
-      };
-      cx<float> m[KS][MT];
+      const Sd* Bt = B + (long long)16 * t * NC;
+      // x(Y) first (consecutive threads of the site take consecutive columns; the
+      // loads are clamped into the nr right-hand sides), then this wave's rows of
+      // the block (rows 16t + li, columns 4 ks + lk, P k-steps per load, see
+      // tiled_off), so the staging waits for the x loads only
+      constexpr int XI = (16 * NC + 64 * MT - 1) / (64 * MT);
+      const int nx = nr * NC;
+      float2 xv[XI];
 #pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        const int RT = NC - 16 * t < 16 ? NC - 16 * t : 16;
-        const bool ok = site_ok && li < RT;
-#pragma unroll
-        for (int q = 0; q < KS / P; ++q) {
-          Pack pk;
-          if (ok) pk = *reinterpret_cast<const Pack*>(B + (long long)16 * t * NC + ((long long)(q * 4 + lk) * RT + li) * P);
-#pragma unroll
-          for (int e = 0; e < P; ++e) m[q * P + e][t] = ok ? ld<float, Sd>(&pk.v[e]) : cx<float>{0.f, 0.f};
-        }
+      for (int i = 0; i < XI; ++i) {
+        const int e = tid_site + 64 * MT * i, ec = e < nx ? e : nx - 1;
+        const int r = ec / NC, col = ec - r * NC;
+        xv[i] = src[(long long)(r0 + r) * vstride + (long long)Y * NC + col];
       }
-      __syncthreads();
-      // stage sc * x(Y) as [col][rhs], zero padded to 16 right-hand sides
-      for (int e = lane; e < NC * 16; e += 64) {
-        int col = e >> 4, r = e & 15;
-        float2 v = make_float2(0.f, 0.f);
-        if (site_ok && r < nr) {
-          v = src[(long long)(r0 + r) * vstride + (long long)Y * NC + col];
-          v.x *= sc;
-          v.y *= sc;
+      Pack pk[KS / P];
+#pragma unroll
+      for (int q = 0; q < KS / P; ++q)
+        pk[q] = *reinterpret_cast<const Pack*>(Bt + ((long long)(q * 4 + lk) * RT + (row_ok ? li : 0)) * P);
+      // stage sc * x(Y) as [col][rhs]
+#pragma unroll
+      for (int i = 0; i < XI; ++i) {
+        const int e = tid_site + 64 * MT * i;
+        if (e < nx) {
+          const int r = e / NC, col = e - r * NC;
+          xsh[s_in][buf][col][r] = make_float2(sc * xv[i].x, sc * xv[i].y);
         }
-        xsh[w][col][r] = v;
       }
       __syncthreads();
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const float2 xb = xsh[w][4 * ks + lk][li];
-#pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].re, xb.x, c0[t], 0, 0, 0);
-          c0[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].im, -xb.y, c0[t], 0, 0, 0);
-          c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].re, xb.y, c1[t], 0, 0, 0);
-          c1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(m[ks][t].im, xb.x, c1[t], 0, 0, 0);
-        }
+        const cx<float> m = row_ok ? ld<float, Sd>(&pk[ks / P].v[ks % P]) : cx<float>{0.f, 0.f};
+        const float2 xb = xsh[s_in][buf][4 * ks + lk][li];
+        const float c = rhs_ok ? xb.x : 0.f, dd = rhs_ok ? xb.y : 0.f;
+        k1 = __builtin_amdgcn_mfma_f32_16x16x4f32(m.re, c + dd, k1, 0, 0, 0);
+        k2 = __builtin_amdgcn_mfma_f32_16x16x4f32(m.re + m.im, -dd, k2, 0, 0, 0);
+        k3 = __builtin_amdgcn_mfma_f32_16x16x4f32(m.im - m.re, c, k3, 0, 0, 0);
       }
+      buf ^= 1;
     }
-    if (site_ok && li < nr) {
+    if (site_ok && rhs_ok) {
 #pragma unroll
-      for (int t = 0; t < MT; ++t) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 16 * t + 4 * lk + v;
-          if (row < NC) {
-            long long oi = (long long)(r0 + li) * vstride + (long long)X * NC + row;
-            float2 o = make_float2(c0[t][v], c1[t][v]);
-            if (beta != 0.f) {
-              float2 zz = z[oi];
-              o.x += beta * zz.x;
-              o.y += beta * zz.y;
-            }
-            out[oi] = o;
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + 4 * lk + v;
+        if (row < NC) {
+          long long oi = (long long)(r0 + li) * vstride + (long long)X * NC + row;
+          float2 o = make_float2(k1[v] + k2[v], k1[v] + k3[v]);
+          if (beta != 0.f) {
+            float2 zz = z[oi];
+            o.x += beta * zz.x;
+            o.y += beta * zz.y;
           }
+          out[oi] = o;
         }
       }
     }
@@ -236,16 +244,25 @@ __global__ void __launch_bounds__(64 * SPW) k_coarse_mfma(GeomDev g, const Sd* _
 typedef void (*MfmaFn)(GeomDev, const void*, const void*, int, int, int, int, float, const float2*, float,
                        const float2*, float, const float2*, float2*);
 
+// spw: target waves per workgroup; sites per workgroup S = max(1, spw / MT), at most 4
 template <int NC, typename Sd>
 MfmaFn mfma_spw(int spw, unsigned count, dim3& grid, dim3& blk) {
+  constexpr int MT = (NC + 15) / 16;
+  int S = spw / MT;
   MfmaFn fn;
-  switch (spw) {
-    case 2: fn = (MfmaFn)k_coarse_mfma<NC, 2, Sd>; break;
-    case 8: fn = (MfmaFn)k_coarse_mfma<NC, 8, Sd>; break;
-    default: fn = (MfmaFn)k_coarse_mfma<NC, 4, Sd>; spw = 4; break;
+  if (S >= 4) {
+    fn = (MfmaFn)k_coarse_mfma<NC, 4, Sd>;
+    S = 4;
+  } else if (S >= 2) {
+    fn = (MfmaFn)k_coarse_mfma<NC, 2, Sd>;
+    S = 2;
+  } else {
+    fn = (MfmaFn)k_coarse_mfma<NC, 1, Sd>;
+    S = 1;
   }
-  grid = dim3((count + spw - 1) / spw);
-  blk = dim3(64 * spw);
+  const unsigned per_x = ((count + S - 1) / S + 7) / 8;   // see k_coarse_mfma
+  grid = dim3(8 * per_x);
+  blk = dim3(64 * S * MT);
   return fn;
 }
 
