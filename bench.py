@@ -169,7 +169,8 @@ def fp64_single_rhs(B, g, cfg, b, args):
     blk, n_vec = cfg["block"], cfg["n_vec"]
     p = B.default_params(block=blk, n_vec=n_vec, setup_iters=cfg["setup_iters"], inner_dtype=B.DD_F64,
                          store_dtype=B.DD_F64, seed=cfg["tv_seed"], coarse_restart=args.coarse_restart,
-                         coarse_max_iters=args.coarse_max_iters, coarse_cgs_passes=args.coarse_cgs_passes)
+                         coarse_max_iters=args.coarse_max_iters, coarse_cgs_passes=args.coarse_cgs_passes,
+                         outer_cgs_passes=args.outer_cgs_passes)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mg = B.MG(g, p)
@@ -203,7 +204,8 @@ def measure(B, g, cfg, args, store_name, b):
     store = B.DTYPES[store_name]
     p = B.default_params(block=blk, n_vec=n_vec, setup_iters=cfg["setup_iters"], inner_dtype=B.DD_F32,
                          store_dtype=store, seed=cfg["tv_seed"], coarse_restart=args.coarse_restart,
-                         coarse_max_iters=args.coarse_max_iters, coarse_cgs_passes=args.coarse_cgs_passes)
+                         coarse_max_iters=args.coarse_max_iters, coarse_cgs_passes=args.coarse_cgs_passes,
+                         outer_cgs_passes=args.outer_cgs_passes)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mg = B.MG(g, p)
@@ -317,12 +319,14 @@ def main():
     ap.add_argument("--coarse-restart", type=int, default=60)
     ap.add_argument("--coarse-max-iters", type=int, default=300)
     ap.add_argument("--coarse-cgs-passes", type=int, default=1)
+    ap.add_argument("--outer-cgs-passes", type=int, default=1, choices=[1, 2],
+                    help="classical Gram-Schmidt passes of the FP64 outer FGMRES")
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="replay the coarse GMRES from captured HIP graphs")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="time the launch-shape candidates before the timed steps")
     ap.add_argument("--tune-cache", default=None, help="JSON cache of autotuner choices")
-    ap.add_argument("--coarse-basis-half", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--coarse-basis-half", type=int, default=1, choices=[0, 1],
                     help="store the FP32 coarse GMRES basis in FP16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-single", action="store_true",
@@ -392,6 +396,7 @@ def main():
                    "lattice": list(L), "rhs": nrhs, "rhs_batch": args.rhs_batch, "m0": cfg["m0"],
                    "c_sw": cfg["c_sw"], "eps": cfg["eps"], "store_dtype": stores[0], "graphs": bool(args.graphs),
                    "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
+                   "outer_cgs_passes": args.outer_cgs_passes,
                    "coarse_basis": "f16" if args.coarse_basis_half else "f32",
                    "outer_iters_mean": round(float(outer), 2),
                    "coarse_iters_per_vcycle": round(float(coarse_per_vcycle), 1),

@@ -99,6 +99,7 @@ typedef struct {
   dd_dtype store_dtype;       /* operand storage inside M (F64/F32/F16/BF16)      */
   uint64_t seed;              /* random starting vectors of dd_setup              */
   int32_t coarse_cgs_passes;  /* classical Gram-Schmidt passes in the coarse GMRES (1 or 2) */
+  int32_t outer_cgs_passes;   /* classical Gram-Schmidt passes in the FP64 outer FGMRES (1 or 2; default 2) */
 } dd_mg_params;
 
 typedef struct {

@@ -40,7 +40,7 @@ class dd_mg_params(ctypes.Structure):
                 ("fgmres_restart", ctypes.c_int32), ("max_outer_iters", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("inner_dtype", ctypes.c_int32),
                 ("store_dtype", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("coarse_cgs_passes", ctypes.c_int32)]
+                ("coarse_cgs_passes", ctypes.c_int32), ("outer_cgs_passes", ctypes.c_int32)]
 
 
 class dd_tuning(ctypes.Structure):

@@ -86,6 +86,7 @@ void dd_mg_params_default(dd_mg_params* p) {
   p->store_dtype = DD_F32;
   p->seed = 1;
   p->coarse_cgs_passes = 1;
+  p->outer_cgs_passes = 2;
 }
 
 }  // extern "C"

@@ -110,7 +110,12 @@ static void carve_ws(Workspace& w, const dd_mg* mg, int nrhs, bool outer) {
   int nblk_c = dots_blocks((long long)mg->g->geo.Vc * mg->nc, nrhs);
   if (nblk_c > nblk) nblk = nblk_c;
   size_t np = (size_t)nrhs * 16 * nblk * 2;   // launch_dots: 16 vectors per launch
-  const size_t np_gs = (size_t)nrhs * mc * gs_blocks(mg->g->geo.Vch * (long long)mg->nc) * 2;
+  // one-pass Gram-Schmidt: nv <= restart vectors over gs_blocks(count) tiles
+  size_t np_gs = (size_t)nrhs * mc * gs_blocks(mg->g->geo.Vch * (long long)mg->nc) * 2;
+  if (outer) {
+    const size_t np_outer = (size_t)nrhs * mg->p.fgmres_restart * gs_blocks(12LL * V) * 2;
+    if (np_outer > np_gs) np_gs = np_outer;
+  }
   if (np_gs > np) np = np_gs;
   w.partial = a.take<double>(np);
   w.b64 = w.x64 = w.w64 = w.zt64 = w.V64 = nullptr;
@@ -536,6 +541,8 @@ static dd_status validate_params(dd_gauge* g, const dd_mg_params* p) {
   if (p->coarse_max_iters < 1 || p->max_outer_iters < 1) return dd_fail(g->ctx, DD_EINVAL, "iteration caps must be >= 1");
   if (p->coarse_cgs_passes != 1 && p->coarse_cgs_passes != 2)
     return dd_fail(g->ctx, DD_EINVAL, "coarse_cgs_passes must be 1 or 2");
+  if (p->outer_cgs_passes != 1 && p->outer_cgs_passes != 2)
+    return dd_fail(g->ctx, DD_EINVAL, "outer_cgs_passes must be 1 or 2");
   if (p->inner_dtype != DD_F64 && p->inner_dtype != DD_F32)
     return dd_fail(g->ctx, DD_EINVAL, "inner_dtype must be DD_F64 or DD_F32");
   if ((int)p->store_dtype < 0 || (int)p->store_dtype > 3) return dd_fail(g->ctx, DD_EINVAL, "unknown store_dtype");
@@ -1043,9 +1050,10 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
         launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->zt64, w->w64, st, g->tune.dirac_threads);
       }
       total_coarse += ci;
-      cgs(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, 2, st, DD_F64);
-      launch_arnoldi(nrhs, m, j, a.h1, a.h2, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est, a.hnext,
-                     st);
+      const int op = mg->p.outer_cgs_passes;
+      cgs(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, op, st, DD_F64);
+      launch_arnoldi(nrhs, m, j, a.h1, op == 2 ? a.h2 : nullptr, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active,
+                     a.kcyc, a.est, a.hnext, st);
       ++outer;
       if (j + 1 == mm) break;
       launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.hnext, a.active, w->V64 + (size_t)(j + 1) * vs64, st);

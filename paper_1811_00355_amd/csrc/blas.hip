@@ -581,7 +581,8 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
     size_t es = vt == DD_F64 ? sizeof(double2) : vt == DD_F16 ? sizeof(__half2) : sizeof(float2);
     size_t ew = wt == DD_F64 ? sizeof(double2) : sizeof(float2);
     const void* Vi = (const char*)V + (size_t)i0 * vstride * es;
-    const double bytes = (double)nrhs * count * (n * es + ew), flops = 8.0 * nrhs * count * n;
+    // a norm (V = w, one vector) reads the vector once
+    const double bytes = (double)nrhs * count * (Vi == w && n == 1 ? ew : n * es + ew), flops = 8.0 * nrhs * count * n;
     const bool timed = ktimer_enabled("k_dots");
     if (timed) ktimer_begin("k_dots", st);
     if (vt == DD_F64 && wt == DD_F64)

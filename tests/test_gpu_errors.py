@@ -49,7 +49,7 @@ def test_bad_parameters(ctx):
     g = Gauge(ctx, L4, B2, _links(), -0.4, 1.0)
     before = ctx.bytes_in_use()
     bad = [dict(n_vec=7), dict(n_vec=10), dict(coarse_restart=0), dict(fgmres_restart=65),
-           dict(inner_dtype=1, store_dtype=0), dict(inner_dtype=0, store_dtype=3), dict(coarse_cgs_passes=3),
+           dict(inner_dtype=1, store_dtype=0), dict(inner_dtype=0, store_dtype=3), dict(coarse_cgs_passes=3), dict(outer_cgs_passes=0),
            dict(max_outer_iters=0)]
     want = ["DD_ESHAPE", "DD_ESHAPE", "DD_EINVAL", "DD_EINVAL", "DD_EINVAL", "DD_EINVAL", "DD_EINVAL", "DD_EINVAL"]
     for kw, w in zip(bad, want):

@@ -190,14 +190,18 @@ def test_adaptive_setup_fixed_iterations(ctx):
     _close(d)
 
 
-@pytest.mark.parametrize("name,inner,store", [("c1", 0, 0), ("c1", 1, 1), ("b4", 1, 1), ("b4", 1, 3)])
-def test_solve_true_residual(ctx, name, inner, store):
+@pytest.mark.parametrize("name,inner,store,outer_passes",
+                         [("c1", 0, 0, 2), ("c1", 1, 1, 2), ("b4", 1, 1, 2), ("b4", 1, 3, 2), ("b4", 1, 3, 1),
+                          ("c1", 0, 0, 1)])
+def test_solve_true_residual(ctx, name, inner, store, outer_passes):
     """Whole solve: every RHS reaches |b - D x| / |b| <= 1e-10, recomputed with the
-    oracle's FP64 operator on the host."""
+    oracle's FP64 operator on the host (outer FGMRES with one or two classical
+    Gram-Schmidt passes)."""
     import torch
     import _gpu
     from workloads import gauss_spinor
-    d = _build(ctx, name, inner_dtype=inner, store_dtype=store, init_sap_apps=2, setup_iters=2)
+    d = _build(ctx, name, inner_dtype=inner, store_dtype=store, init_sap_apps=2, setup_iters=2,
+               outer_cgs_passes=outer_passes)
     lat, mg = d["lat"], d["mg"]
     nrhs = 3
     b = gauss_spinor(lat.L, nrhs, 61)
@@ -208,7 +212,7 @@ def test_solve_true_residual(ctx, name, inner, store):
     x = _gpu.to_host(xd).reshape(b.shape)
     for r in range(nrhs):
         res = np.linalg.norm(b[r] - d["W"].apply(x[r])) / np.linalg.norm(b[r])
-        print(f"{name} inner={inner} store={store} rhs {r}: iters {info[r]['outer_iters']} "
+        print(f"{name} inner={inner} store={store} outer passes {outer_passes} rhs {r}: iters {info[r]['outer_iters']} "
               f"relres(lib) {info[r]['true_relres']:.2e} relres(oracle D) {res:.2e}", flush=True)
         assert info[r]["converged"] and res <= 1e-10
     _close(d)
