@@ -1033,7 +1033,9 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
     if (nfin == nrhs || outer >= mg->p.max_outer_iters) break;
     DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
     launch_cycle_init(nrhs, m, a.nrm2, a.tolabs, a.finished, a.gv, a.beta, a.active, a.kcyc, st);
-    launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.beta, a.active, w->V64, st);
+    // with an FP32 preconditioner the normalisation also writes v_j rounded to FP32 (its input)
+    void* vin32 = vt == DD_F64 ? nullptr : w->vin;
+    launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.beta, a.active, w->V64, st, DD_F64, vin32);
     int mm = mg->p.max_outer_iters - outer < m ? mg->p.max_outer_iters - outer : m;
     for (int j = 0; j < mm; ++j) {
       double2* Vj = w->V64 + (size_t)j * vs64;
@@ -1044,10 +1046,8 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
         if ((s = vcycle(mg, nrhs, Vj, Zj, &ci, st))) return s;
         launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, Zj, w->w64, st, g->tune.dirac_threads);
       } else {
-        launch_vec_convert(DD_F64, DD_F32, Vj, w->vin, fine, st);
         if ((s = vcycle(mg, nrhs, w->vin, Zj, &ci, st))) return s;
-        launch_vec_convert(DD_F32, DD_F64, Zj, w->zt64, fine, st);
-        launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->zt64, w->w64, st, g->tune.dirac_threads);
+        launch_dirac_f32_in(G, g->ops[DD_F64], nrhs, (const float2*)Zj, w->w64, st, g->tune.dirac_threads);
       }
       total_coarse += ci;
       const int op = mg->p.outer_cgs_passes;
@@ -1056,7 +1056,8 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
                      a.kcyc, a.est, a.hnext, st);
       ++outer;
       if (j + 1 == mm) break;
-      launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.hnext, a.active, w->V64 + (size_t)(j + 1) * vs64, st);
+      launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.hnext, a.active, w->V64 + (size_t)(j + 1) * vs64, st,
+                       DD_F64, vin32);
       if (count_active(w, a.active, nrhs, st) == 0) break;
     }
     launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);

@@ -508,6 +508,104 @@ __global__ void k_lsq(int nrhs, int m, const double2* __restrict__ H, const doub
   }
 }
 
+// Wave-per-RHS forms of k_arnoldi and k_lsq for m <= 64: lane i holds entry i
+// of the column, the rotations and the right-hand side, so the column is read
+// and written once in parallel and only the recurrences run lane by lane
+// (register exchanges instead of dependent global loads).
+__device__ __forceinline__ cx<double> lane_get(cx<double> v, int i) {
+  return {__shfl(v.re, i, 64), __shfl(v.im, i, 64)};
+}
+
+__global__ void __launch_bounds__(64) k_arnoldi_w(int m, int j, const double2* __restrict__ h1,
+                                                  const double2* __restrict__ h2, const double2* __restrict__ nrm2,
+                                                  double2* __restrict__ H, double* __restrict__ cs,
+                                                  double2* __restrict__ sn, double2* __restrict__ gv,
+                                                  const double* __restrict__ tolabs, int* __restrict__ active,
+                                                  int* __restrict__ kcyc, double* __restrict__ est,
+                                                  double* __restrict__ hnext) {
+  const int r = blockIdx.x, lane = threadIdx.x;
+  if (!active[r]) return;   // uniform per wave
+  double2* Hc = H + ((long long)r * m + j) * (m + 1);   // column j
+  cx<double> hc = {0.0, 0.0}, sl = {0.0, 0.0};
+  double cl = 1.0;
+  if (lane <= j) {
+    const double2 a = h1[r * (m + 1) + lane], b = h2 ? h2[r * (m + 1) + lane] : make_double2(0.0, 0.0);
+    hc = {a.x + b.x, a.y + b.y};
+  }
+  if (lane < j) {
+    cl = cs[r * m + lane];
+    const double2 v = sn[r * m + lane];
+    sl = {v.x, v.y};
+  }
+  const double hn = sqrt(nrm2[r].x);
+  // previous rotations, in order: (H_i, H_{i+1}) <- (c H_i + s H_{i+1}, c H_{i+1} - conj(s) H_i)
+  cx<double> carry = lane_get(hc, 0), res = hc;
+  for (int i = 0; i < j; ++i) {
+    const cx<double> b = lane_get(hc, i + 1), s = lane_get(sl, i);
+    const double c = __shfl(cl, i, 64);
+    const cx<double> na = c * carry + s * b;
+    carry = c * b - conj(s) * carry;
+    if (lane == i) res = na;
+  }
+  // new rotation zeroing H[j+1][j]: c real, [c s; -conj(s) c] [a; b] = [rho; 0]
+  const cx<double> a = carry;
+  const double bn = hn;
+  double c;
+  cx<double> s;
+  const double aa = sqrt(a.re * a.re + a.im * a.im);
+  if (bn == 0.0) {
+    c = 1.0;
+    s = {0.0, 0.0};
+  } else if (aa == 0.0) {
+    c = 0.0;
+    s = {1.0, 0.0};
+  } else {
+    const double t = sqrt(aa * aa + bn * bn);
+    c = aa / t;
+    s = (bn / t) * cx<double>{a.re / aa, a.im / aa};
+  }
+  const cx<double> rho = c * a + s * cx<double>{bn, 0.0};
+  if (lane == j) res = rho;
+  if (lane <= j) Hc[lane] = make_double2(res.re, res.im);
+  if (lane == 0) {
+    hnext[r] = hn;
+    Hc[j + 1] = make_double2(0.0, 0.0);
+    cs[r * m + j] = c;
+    sn[r * m + j] = make_double2(s.re, s.im);
+    const cx<double> gj = {gv[r * (m + 1) + j].x, gv[r * (m + 1) + j].y};
+    const cx<double> g1 = -(conj(s) * gj);
+    const cx<double> g0 = c * gj;
+    gv[r * (m + 1) + j] = make_double2(g0.re, g0.im);
+    gv[r * (m + 1) + j + 1] = make_double2(g1.re, g1.im);
+    const double e = sqrt(g1.re * g1.re + g1.im * g1.im);
+    est[r] = e;
+    kcyc[r] = j + 1;
+    if (e <= tolabs[r] || hn == 0.0 || j + 1 == m) active[r] = 0;
+  }
+}
+
+// y = R^-1 g over the kcyc[r] leading entries (column-oriented back substitution); y beyond kcyc is zero
+__global__ void __launch_bounds__(64) k_lsq_w(int m, const double2* __restrict__ H, const double2* __restrict__ gv,
+                                              const int* __restrict__ kcyc, double2* __restrict__ y) {
+  const int r = blockIdx.x, lane = threadIdx.x;
+  const int k = kcyc[r];
+  cx<double> g = {0.0, 0.0}, yl = {0.0, 0.0};
+  if (lane < k) g = {gv[r * (m + 1) + lane].x, gv[r * (m + 1) + lane].y};
+  for (int i = k - 1; i >= 0; --i) {
+    const double2* Hi = H + ((long long)r * m + i) * (m + 1);   // column i
+    const double2 d = Hi[i];
+    const double den = d.x * d.x + d.y * d.y;
+    const cx<double> inv = den > 0.0 ? cx<double>{d.x / den, -d.y / den} : cx<double>{0.0, 0.0};
+    const cx<double> yi = lane_get(g, i) * inv;
+    if (lane == i) yl = yi;
+    if (lane < i) {
+      const double2 h = Hi[lane];
+      g = g - cx<double>{h.x, h.y} * yi;
+    }
+  }
+  if (lane < m) y[r * m + lane] = make_double2(yl.re, yl.im);
+}
+
 inline unsigned grid1(long long n) {
   long long b = (n + 255) / 256;
   return (unsigned)(b > 65535 ? 65535 : b);
@@ -709,7 +807,7 @@ void launch_normalize(dd_dtype vt, int nrhs, long long count, long long rs, cons
   dim3 grid(grid1(count), nrhs);
   if (vt == DD_F64)
     k_normalize<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)src, nrm2, nrm, mask,
-                                                        (double2*)dst, nullptr);
+                                                        (double2*)dst, (float2*)copy32);
   else if (dt == DD_F16)
     k_normalize<float2, __half2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)src, nrm2, nrm, mask,
                                                        (__half2*)dst, (float2*)copy32);
@@ -748,9 +846,15 @@ void launch_cycle_init(int nrhs, int m, const double2* nrm2, const double* tolab
 void launch_arnoldi(int nrhs, int m, int j, const double2* h1, const double2* h2, const double2* nrm2, double2* H,
                     double* cs, double2* sn, double2* gv, const double* tolabs, int* active, int* kcyc, double* est,
                     double* hnext, hipStream_t st) {
-  k_arnoldi<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, j, h1, h2, nrm2, H, cs, sn, gv, tolabs, active, kcyc, est, hnext);
+  if (m <= 64)
+    k_arnoldi_w<<<nrhs, 64, 0, st>>>(m, j, h1, h2, nrm2, H, cs, sn, gv, tolabs, active, kcyc, est, hnext);
+  else
+    k_arnoldi<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, j, h1, h2, nrm2, H, cs, sn, gv, tolabs, active, kcyc, est, hnext);
 }
 
 void launch_lsq(int nrhs, int m, const double2* H, const double2* gv, const int* kcyc, double2* y, hipStream_t st) {
-  k_lsq<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, H, gv, kcyc, y);
+  if (m <= 64)
+    k_lsq_w<<<nrhs, 64, 0, st>>>(m, H, gv, kcyc, y);
+  else
+    k_lsq<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, H, gv, kcyc, y);
 }

@@ -393,6 +393,9 @@ void launch_clover_build(const GeomDev& g, const double2* links64, double m0, do
 // Dirac operator
 void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
                   hipStream_t st, int threads = 256);
+// FP64 operator applied to an FP32 vector (FP64 result)
+void launch_dirac_f32_in(const GeomDev& g, const OpSet& ops64, int nrhs, const float2* in, double2* out,
+                         hipStream_t st, int threads = 256);
 // SAP smoother
 void launch_sap(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters,
                 const void* b, void* x, int wpe, hipStream_t st);

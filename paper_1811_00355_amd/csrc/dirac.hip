@@ -9,9 +9,9 @@
 
 namespace {
 
-template <typename R, typename S, typename Tv>
+template <typename R, typename S, typename Tv, typename To = Tv>
 __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov,
-                                               int nrhs, const Tv* __restrict__ in, Tv* __restrict__ out) {
+                                               int nrhs, const Tv* __restrict__ in, To* __restrict__ out) {
   int tile, r;
   if (g.Bv >= (int)blockDim.x) {   // whole blocks per tile range: slab order (see xcd_slab_tile)
     if (!xcd_slab_tile(g, g.Bv / blockDim.x, nrhs, tile, r)) return;
@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ 
   clover_mul<R, S, false>(clov, g.V, I, psi, acc);
   auto fetch = [&](long long J, bool, cx<R>* p) { load_spinor<R, Tv>(x, g.V, J, p); };
   hop_all<R, S>(g, links, s, I, false, fetch, acc);
-  store_spinor<R, Tv>(out + (long long)r * 12 * g.V, g.V, I, acc);
+  store_spinor<R, To>(out + (long long)r * 12 * g.V, g.V, I, acc);
 }
 
 // Block form (4^4 blocks: one workgroup of Bv = 256 threads per block and
@@ -35,10 +35,10 @@ __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ 
 // of the same block read them there, so memory sees one read of every spinor
 // plus the hops across the block faces (a quarter of the sites per direction),
 // instead of eight gathers per site that the L2 cannot hold between hops.
-template <typename R, typename S, typename Tv>
+template <typename R, typename S, typename Tv, typename To = Tv>
 __global__ void __launch_bounds__(256) k_dirac_blk(GeomDev g, const S* __restrict__ links,
                                                    const S* __restrict__ clov, int nrhs, const Tv* __restrict__ in,
-                                                   Tv* __restrict__ out) {
+                                                   To* __restrict__ out) {
   __shared__ cx<R> sp[12][256];
   int tile, r;
   if (!xcd_slab_tile(g, 1, nrhs, tile, r)) return;   // uniform per workgroup
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_dirac_blk(GeomDev g, const S* __restric
     }
   };
   hop_all<R, S>(g, links, s, I, false, fetch, acc);
-  store_spinor<R, Tv>(out + (long long)r * 12 * g.V, g.V, I, acc);
+  store_spinor<R, To>(out + (long long)r * 12 * g.V, g.V, I, acc);
 }
 
 }  // namespace
@@ -121,4 +121,23 @@ void launch_dirac(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, con
   double bytes = (double)g.V * (24.0 * vector_pair_bytes(dt) * nrhs + 72.0 * storage_pair_bytes(dt));
   double flops = (double)g.V * nrhs * 1824.0;
   DD_TIMED("k_dirac", st, bytes, flops, dirac_dispatch(g, dt, ops, nrhs, in, out, threads, st));
+}
+
+void launch_dirac_f32_in(const GeomDev& g, const OpSet& ops64, int nrhs, const float2* in, double2* out,
+                         hipStream_t st, int threads) {
+  // FP64 operator on an FP32 input (widened exactly on load), FP64 output
+  const double bytes = (double)g.V * (12.0 * (sizeof(float2) + sizeof(double2)) * nrhs + 72.0 * sizeof(double2));
+  const double flops = (double)g.V * nrhs * 1824.0;
+  const double2* L = (const double2*)ops64.links;
+  const double2* C = (const double2*)ops64.clover;
+  if (g.Bv == 256 && g.Vc % 16 == 0) {
+    DD_TIMED("k_dirac", st, bytes, flops,
+             (k_dirac_blk<double, double2, float2, double2><<<xcd_grid(g.Vc, nrhs), 256, 0, st>>>(g, L, C, nrhs, in,
+                                                                                               out)));
+    return;
+  }
+  if (threads != 64 && threads != 128) threads = 256;
+  const unsigned nb = xcd_grid((unsigned)((g.V + threads - 1) / threads), nrhs);
+  DD_TIMED("k_dirac", st, bytes, flops,
+           (k_dirac<double, double2, float2, double2><<<nb, threads, 0, st>>>(g, L, C, nrhs, in, out)));
 }
