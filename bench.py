@@ -213,9 +213,10 @@ def measure(B, g, cfg, args, store_name, b):
     t_setup = time.perf_counter() - t0
     log(f"[bench] store {store_name}: setup {t_setup:.2f} s")
     mg.dd_mg_set_graphs(args.graphs)
-    if args.coarse_basis_half:
+    if args.coarse_basis_half or args.coarse_mfma_half:
         t = g.dd_gauge_get_tuning()
-        t["coarse_basis_half"] = 1
+        t["coarse_basis_half"] = args.coarse_basis_half
+        t["coarse_mfma_half"] = args.coarse_mfma_half
         g.dd_gauge_set_tuning(**t)
     kb = min(args.rhs_batch, nrhs)
     tuning = None
@@ -300,10 +301,26 @@ def measure(B, g, cfg, args, store_name, b):
     value = nrhs * args.steps / elapsed
     log(f"[bench] store {store_name}: {value:.2f} solves/s; dominant kernel {dom}: {achieved:.0f} GB/s; "
         f"kernels {kernels}")
+    fp32_coarse = None
+    if (args.coarse_basis_half or args.coarse_mfma_half) and not args.no_fp32_coarse:
+        # the same setup with the coarse GMRES basis and coarse products in FP32, same step count
+        t = g.dd_gauge_get_tuning()
+        g.dd_gauge_set_tuning(**dict(t, coarse_basis_half=0, coarse_mfma_half=0))
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf32 = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t0
+        g.dd_gauge_set_tuning(**t)
+        fp32_coarse = dict(value=round(nrhs * args.steps / el32, 3), ms_per_step=round(1e3 * el32 / args.steps, 2),
+                           outer_iters_mean=round(float(np.mean([i["outer_iters"] for inf in inf32 for i in inf])), 2),
+                           max_true_relres=float(max(i["true_relres"] for inf in inf32 for i in inf)))
+        log(f"[bench] store {store_name}, FP32 coarse basis and products: {fp32_coarse}")
     mg.destroy()
     return dict(value=round(value, 3), ms_per_step=round(1e3 * elapsed / args.steps, 2), elapsed=elapsed,
                 setup_s=round(t_setup, 3), outer=round(outer, 2), coarse_per_vcycle=coarse_per_vcycle,
-                tuning=tuning, roofline=roofline, kernels=kernels)
+                tuning=tuning, roofline=roofline, kernels=kernels, fp32_coarse=fp32_coarse)
 
 
 def main():
@@ -328,6 +345,10 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="JSON cache of autotuner choices")
     ap.add_argument("--coarse-basis-half", type=int, default=1, choices=[0, 1],
                     help="store the FP32 coarse GMRES basis in FP16")
+    ap.add_argument("--coarse-mfma-half", type=int, default=1, choices=[0, 1],
+                    help="half-precision coarse blocks on FP16/BF16 matrix cores (x rounded to that type)")
+    ap.add_argument("--no-fp32-coarse", action="store_true",
+                    help="skip the second timing with the coarse basis and products in FP32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-single", action="store_true",
                     help="skip the 12 sequential FP64 single-RHS solves")
@@ -389,7 +410,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 outer / f32 inner",
+        "dtype": "f64 outer / f32 inner" + (f" ({stores[0]} coarse products, f32 accumulation)"
+                                            if args.coarse_mfma_half and stores[0] in ("f16", "bf16") else ""),
         "data": "synthetic (seeded SU(3) links, point sources)",
         "config": {"workload": f"{args.config}: {L[0]}^3x{L[3]} Wilson-clover, 12 point-source RHS "
                                f"(solve calls of {args.rhs_batch}), 2-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
@@ -398,11 +420,13 @@ def main():
                    "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
                    "outer_cgs_passes": args.outer_cgs_passes,
                    "coarse_basis": "f16" if args.coarse_basis_half else "f32",
+                   "coarse_mfma_half": bool(args.coarse_mfma_half),
                    "outer_iters_mean": round(float(outer), 2),
                    "coarse_iters_per_vcycle": round(float(coarse_per_vcycle), 1),
                    "setup_s": r0["setup_s"],
                    "solves_per_s_incl_setup": round(nrhs / (r0["setup_s"] + elapsed / args.steps), 3),
                    "tuning": r0["tuning"],
+                   "fp32_coarse_arithmetic": r0["fp32_coarse"],
                    "other_stores": {st_: {k: r[k] for k in ("value", "ms_per_step", "setup_s", "outer")}
                                     for st_, r in zip(stores[1:], runs[1:])},
                    "parallelism": "1 GPU"},

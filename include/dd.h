@@ -119,7 +119,8 @@ void dd_mg_params_default(dd_mg_params* p);
 
 /* Launch shapes and coarse storage.  The first three give bit-identical results
  * for every choice (see dd_autotune); coarse_half and coarse_basis_half change
- * the rounding of the coarse-level arithmetic, which only the FGMRES outer
+ * the rounding of the coarse-level arithmetic (as do coarse_basis_half and
+ * coarse_mfma_half), which only the FGMRES outer
  * iteration count can see (the outer solver is flexible, Sec. 2). */
 typedef struct {
   int32_t sap_wpe;        /* SAP waves per SIMD the registers allow: 2 or 3          */
@@ -128,6 +129,10 @@ typedef struct {
   int32_t coarse_half;    /* half-precision setups: coarse blocks in FP16/BF16 (1) or FP32 (0) */
   int32_t coarse_basis_half; /* FP32 coarse GMRES: Krylov basis stored in FP16 (1) or FP32 (0);
                                 never changed by dd_autotune */
+  int32_t coarse_mfma_half;  /* with half-precision coarse blocks (coarse_half = 1): multiply them on
+                                FP16 / BF16 matrix cores with x rounded to the same type and FP32
+                                accumulation (1), or convert them to FP32 (0); never changed by
+                                dd_autotune */
 } dd_tuning;
 
 /* ---- gauge field (field preparation) ---------------------------------------

@@ -248,6 +248,7 @@ struct CoarseOps {
   const void *Dc, *Dinv;
   int spw;       // FP32 coarse apply: sites per workgroup
   dd_dtype bt;   // storage of the blocks (FP32 vectors may use FP32, FP16 or BF16 blocks)
+  bool hm;          // half blocks on half-precision MFMA
   dd_dtype basis;   // storage of the GMRES basis: vt, or DD_F16 with FP32 vectors
   size_t bb;        // bytes of one basis element
 };
@@ -262,6 +263,7 @@ static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
   c.Dinv = vt == DD_F64 ? (const void*)mg->Dinv64 : half ? (const void*)mg->Dinvh : (const void*)mg->Dinv32;
   c.bt = vt == DD_F64 ? DD_F64 : half ? mg->vstore : DD_F32;
   c.spw = mg->g->tune.coarse_spw;
+  c.hm = mg->g->tune.coarse_mfma_half != 0;
   c.basis = (vt == DD_F32 && mg->g->tune.coarse_basis_half) ? DD_F16 : vt;
   c.bb = c.basis == DD_F16 ? sizeof(__half2) : vector_pair_bytes(vt);
   return c;
@@ -270,9 +272,9 @@ static CoarseOps coarse_ops(const dd_mg* mg, dd_dtype vt) {
 // out_e = S v_e = D_ee v_e - D_eo D_oo^-1 D_oe v_e   (t1, t2 scratch, odd parts used)
 static void schur_apply(const CoarseOps& c, int nrhs, const void* v, void* out, void* t1, void* t2, hipStream_t st) {
   const GeomDev& g = *c.g;
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, 1.0, v, 0.0, nullptr, t1, st, c.spw, c.bt);
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, t1, 0.0, nullptr, 0.0, nullptr, t2, st, c.spw, c.bt);
-  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 1.0, v, -1.0, t2, 0.0, nullptr, out, st, c.spw, c.bt);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, 1.0, v, 0.0, nullptr, t1, st, c.spw, c.bt, c.hm);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, t1, 0.0, nullptr, 0.0, nullptr, t2, st, c.spw, c.bt, c.hm);
+  launch_coarse_mv(g, c.vt, c.nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 1.0, v, -1.0, t2, 0.0, nullptr, out, st, c.spw, c.bt, c.hm);
 }
 
 // Arnoldi steps j0 .. j0+len-1 of one coarse GMRES cycle: w = S v_j, Gram-Schmidt,
@@ -339,8 +341,8 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
   const int cap = fixed ? mg->p.coarse_fixed_iters : mg->p.coarse_max_iters;
   const double tol = fixed ? 0.0 : mg->p.coarse_tol;
   // rhs' = b_e - D_eo D_oo^-1 b_o
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st, c.spw, c.bt);
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st, c.spw, c.bt);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st, c.spw, c.bt, c.hm);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st, c.spw, c.bt, c.hm);
   DD_HIP(mg->ctx, hipMemsetAsync(y, 0, (size_t)nrhs * ld * vb, st));
   // tolerance: tol * |rhs'|
   norms2(w, vt, nrhs, ce, ld, w->cr, a.nrm2, st);
@@ -399,8 +401,8 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
     if (nfin == nrhs) break;
   }
   // odd sites: y_o = D_oo^-1 (b_o - D_oe y_e)
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st, c.spw, c.bt);
-  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st, c.spw, c.bt);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st, c.spw, c.bt, c.hm);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st, c.spw, c.bt, c.hm);
   DD_HIP(mg->ctx, hipGetLastError());
   if (iters_out) *iters_out = iters;
   return DD_OK;
@@ -707,15 +709,16 @@ dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t) {
   if ((t->sap_wpe != 2 && t->sap_wpe != 3) ||
       (t->dirac_threads != 64 && t->dirac_threads != 128 && t->dirac_threads != 256) ||
       (t->coarse_spw != 2 && t->coarse_spw != 4 && t->coarse_spw != 8) || (t->coarse_half != 0 && t->coarse_half != 1) ||
-      (t->coarse_basis_half != 0 && t->coarse_basis_half != 1))
+      (t->coarse_basis_half != 0 && t->coarse_basis_half != 1) || (t->coarse_mfma_half != 0 && t->coarse_mfma_half != 1))
     return dd_fail(g->ctx, DD_EINVAL,
                    "tuning: sap_wpe 2|3, dirac_threads 64|128|256, coarse_spw 2|4|8, coarse_half 0|1, "
-                   "coarse_basis_half 0|1");
+                   "coarse_basis_half 0|1, coarse_mfma_half 0|1");
   g->tune.sap_wpe = t->sap_wpe;
   g->tune.dirac_threads = t->dirac_threads;
   g->tune.coarse_spw = t->coarse_spw;
   g->tune.coarse_half = t->coarse_half;
   g->tune.coarse_basis_half = t->coarse_basis_half;
+  g->tune.coarse_mfma_half = t->coarse_mfma_half;
   return DD_OK;
 }
 
@@ -726,6 +729,7 @@ dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t) {
   t->coarse_spw = g->tune.coarse_spw;
   t->coarse_half = g->tune.coarse_half;
   t->coarse_basis_half = g->tune.coarse_basis_half;
+  t->coarse_mfma_half = g->tune.coarse_mfma_half;
   return DD_OK;
 }
 
@@ -748,10 +752,12 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
   if (cache_path) tune_cache_read(cache_path, cache);
   std::string rep = "key " + key + "\n";
   auto it = cache.find(key);
-  const int basis_half = g->tune.coarse_basis_half;   // a numerical choice of the caller, not a launch shape
+  // numerical choices of the caller, not launch shapes
+  const int basis_half = g->tune.coarse_basis_half, mfma_half = g->tune.coarse_mfma_half;
   if (it != cache.end()) {
     g->tune = it->second;
     g->tune.coarse_basis_half = basis_half;
+    g->tune.coarse_mfma_half = mfma_half;
     rep += "cache hit\n";
   } else {
     dd_status s = ensure_ws(mg, nrhs, true);
@@ -807,7 +813,7 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
         float t = time_ms([&] {
           CoarseOps c = coarse_ops(mg, vt);
           launch_coarse_mv(G, vt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, G.Vc, 1.0, w->cb, 1.0, w->cb, 0.0, nullptr, w->cw,
-                           st, spw, c.bt);
+                           st, spw, c.bt, c.hm);
         });
         std::snprintf(line, sizeof(line), "k_coarse_mfma coarse_spw=%d %.3f ms\n", spw, t);
         rep += line;
@@ -821,7 +827,7 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
         CoarseOps c = coarse_ops(mg, vt);
         float t = time_ms([&] {
           launch_coarse_mv(G, vt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, G.Vc, 1.0, w->cb, 1.0, w->cb, 0.0, nullptr, w->cw,
-                           st, best.coarse_spw, c.bt);
+                           st, best.coarse_spw, c.bt, c.hm);
         });
         g->tune = keep;
         std::snprintf(line, sizeof(line), "k_coarse_mfma coarse_half=1 coarse_spw=%d %.3f ms\n", best.coarse_spw, t);
@@ -914,7 +920,7 @@ dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
   if (s) return s;
   CoarseOps c = coarse_ops(mg, dt);
   launch_coarse_mv(mg->g->geo, dt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, mg->g->geo.Vc, 1.0, in, 1.0, in, 0.0, nullptr,
-                   out, (hipStream_t)stream, c.spw, c.bt);
+                   out, (hipStream_t)stream, c.spw, c.bt, c.hm);
   DD_HIP(mg->ctx, hipGetLastError());
   return DD_OK;
 }

@@ -241,24 +241,178 @@ __global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) k_coarse_mfma(
   }
 }
 
+// Half-precision matrix-core form (opt-in, half-precision blocks only): the
+// blocks feed 16x16x16 FP16 / BF16 MFMAs directly and sc * x(Y) is rounded to
+// the same type when staged; products accumulate in FP32 (four real MFMAs per
+// complex product: k1 = a c, k2 = b d, k3 = a d, k4 = b c).  MFMA K-slot
+// (lk, v) of K-step s takes column 4 (4 s + v) + lk, so every lane's four A
+// values sit at one (row, lk) of the tiled block layout (see tiled_off);
+// columns past NC are zero on both sides.
+typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
+typedef short b16x4 __attribute__((ext_vector_type(4)));
+
+template <typename Sd> struct HalfOp;
+template <> struct HalfOp<__half2> {
+  typedef h16x4 vec;
+  typedef _Float16 elem;
+  __device__ static elem from_f32(float f) { return (_Float16)f; }
+  __device__ static void split(const __half2& v, elem& re, elem& im) {
+    const __half2_raw r = v;
+    re = __builtin_bit_cast(_Float16, r.x);
+    im = __builtin_bit_cast(_Float16, r.y);
+  }
+  __device__ static f32x4 mfma(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+};
+template <> struct HalfOp<bf16x2> {
+  typedef b16x4 vec;
+  typedef short elem;
+  __device__ static elem from_f32(float f) { return (short)f32_to_bf16_bits(f); }
+  __device__ static void split(const bf16x2& v, elem& re, elem& im) {
+    re = (short)(v.u & 0xffffu);
+    im = (short)(v.u >> 16);
+  }
+  __device__ static f32x4 mfma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int NC, int S, typename Sd>
+__global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) k_coarse_mfma_h(
+    GeomDev g, const Sd* __restrict__ Dc, const Sd* __restrict__ Minv, int use_inv, int nrhs, int site_begin,
+    int count, float a_self, const float2* __restrict__ xs, float a_hop, const float2* __restrict__ xh, float beta,
+    const float2* __restrict__ z, float2* __restrict__ out) {
+  typedef HalfOp<Sd> H;
+  typedef typename H::vec vec;
+  typedef typename H::elem elem;
+  constexpr int MT = (NC + 15) / 16, KS = NC / 4, NS = (KS + 3) / 4;
+  constexpr int P = tile_group(NC, (int)sizeof(Sd));
+  // staged x: [site][buffer][s][lk][rhs][v], real and imaginary parts
+  __shared__ alignas(16) elem xc[S][2][NS][4][16][4];
+  __shared__ alignas(16) elem xd[S][2][NS][4][16][4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s_in = wv / MT, t = wv % MT, tid_site = threadIdx.x - 64 * MT * s_in;
+  const int ngroups = (count + S - 1) / S, per_x = (ngroups + 7) / 8;
+  const int group = (blockIdx.x & 7) * per_x + (blockIdx.x >> 3);
+  if (group >= ngroups) return;   // uniform per workgroup
+  const int local = group * S + s_in;
+  const bool site_ok = local < count;
+  const int X = site_begin + (site_ok ? local : 0);
+  const int RT = NC - 16 * t < 16 ? NC - 16 * t : 16;
+  const long long vstride = (long long)g.Vc * NC;
+  const bool has_self = a_self != 0.f, has_hop = a_hop != 0.f;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool row_ok = li < RT;
+  // K-slots past NC stay zero in both buffers
+  {
+    elem* pc = &xc[s_in][0][0][0][0][0];
+    elem* pd = &xd[s_in][0][0][0][0][0];
+    for (int e = tid_site; e < 2 * NS * 4 * 16 * 4; e += 64 * MT) {
+      pc[e] = H::from_f32(0.f);
+      pd[e] = H::from_f32(0.f);
+    }
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
+    const bool rhs_ok = li < nr;
+    f32x4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1, k4 = k1;
+    for (int d = has_self ? 0 : 1; d < (has_hop ? 9 : 1); ++d) {
+      const int Y = d == 0 ? X : (g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK);
+      const float2* src = d == 0 ? xs : xh;
+      const float sc = d == 0 ? a_self : a_hop;
+      const Sd* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * NC * NC : Dc + (long long)X * 9 * NC * NC)
+                           : Dc + ((long long)X * 9 + d) * NC * NC;
+      const Sd* Bt = B + (long long)16 * t * NC;
+      constexpr int XI = (16 * NC + 64 * MT - 1) / (64 * MT);
+      const int nx = nr * NC;
+      float2 xv[XI];
+#pragma unroll
+      for (int i = 0; i < XI; ++i) {
+        const int e = tid_site + 64 * MT * i, ec = e < nx ? e : nx - 1;
+        const int r = ec / NC, col = ec - r * NC;
+        xv[i] = src[(long long)(r0 + r) * vstride + (long long)Y * NC + col];
+      }
+      // this wave's rows: K-step s, slot v -> tiled column group ks = 4 s + v at this lane's lk
+      Sd av[NS][4];
+#pragma unroll
+      for (int st = 0; st < NS; ++st)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ks = 4 * st + v;
+          if (ks < KS) av[st][v] = Bt[((long long)((ks / P) * 4 + lk) * RT + (row_ok ? li : 0)) * P + ks % P];
+        }
+#pragma unroll
+      for (int i = 0; i < XI; ++i) {
+        const int e = tid_site + 64 * MT * i;
+        if (e < nx) {
+          const int r = e / NC, col = e - r * NC;
+          const int ks = col >> 2, cl = col & 3;
+          xc[s_in][buf][ks >> 2][cl][r][ks & 3] = H::from_f32(sc * xv[i].x);
+          xd[s_in][buf][ks >> 2][cl][r][ks & 3] = H::from_f32(sc * xv[i].y);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        vec a, b;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          elem re = H::from_f32(0.f), im = H::from_f32(0.f);
+          if (4 * st + v < KS && row_ok) H::split(av[st][v], re, im);
+          a[v] = re;
+          b[v] = im;
+        }
+        vec c = *reinterpret_cast<const vec*>(&xc[s_in][buf][st][lk][li][0]);
+        vec dd = *reinterpret_cast<const vec*>(&xd[s_in][buf][st][lk][li][0]);
+        if (!rhs_ok) {
+          c = vec{};
+          dd = vec{};
+        }
+        k1 = H::mfma(a, c, k1);
+        k2 = H::mfma(b, dd, k2);
+        k3 = H::mfma(a, dd, k3);
+        k4 = H::mfma(b, c, k4);
+      }
+      buf ^= 1;
+    }
+    if (site_ok && rhs_ok) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + 4 * lk + v;
+        if (row < NC) {
+          long long oi = (long long)(r0 + li) * vstride + (long long)X * NC + row;
+          float2 o = make_float2(k1[v] - k2[v], k3[v] + k4[v]);
+          if (beta != 0.f) {
+            float2 zz = z[oi];
+            o.x += beta * zz.x;
+            o.y += beta * zz.y;
+          }
+          out[oi] = o;
+        }
+      }
+    }
+  }
+}
+
 typedef void (*MfmaFn)(GeomDev, const void*, const void*, int, int, int, int, float, const float2*, float,
                        const float2*, float, const float2*, float2*);
 
 // spw: target waves per workgroup; sites per workgroup S = max(1, spw / MT), at most 4
-template <int NC, typename Sd>
+template <int NC, typename Sd, bool HM = false>
 MfmaFn mfma_spw(int spw, unsigned count, dim3& grid, dim3& blk) {
   constexpr int MT = (NC + 15) / 16;
   int S = spw / MT;
   MfmaFn fn;
-  if (S >= 4) {
-    fn = (MfmaFn)k_coarse_mfma<NC, 4, Sd>;
-    S = 4;
-  } else if (S >= 2) {
-    fn = (MfmaFn)k_coarse_mfma<NC, 2, Sd>;
-    S = 2;
+  if (S >= 4) S = 4;
+  else if (S >= 2) S = 2;
+  else S = 1;
+  if constexpr (HM) {
+    fn = S == 4 ? (MfmaFn)k_coarse_mfma_h<NC, 4, Sd> : S == 2 ? (MfmaFn)k_coarse_mfma_h<NC, 2, Sd>
+                                                              : (MfmaFn)k_coarse_mfma_h<NC, 1, Sd>;
   } else {
-    fn = (MfmaFn)k_coarse_mfma<NC, 1, Sd>;
-    S = 1;
+    fn = S == 4 ? (MfmaFn)k_coarse_mfma<NC, 4, Sd> : S == 2 ? (MfmaFn)k_coarse_mfma<NC, 2, Sd>
+                                                            : (MfmaFn)k_coarse_mfma<NC, 1, Sd>;
   }
   const unsigned per_x = ((count + S - 1) / S + 7) / 8;   // see k_coarse_mfma
   grid = dim3(8 * per_x);
@@ -266,22 +420,22 @@ MfmaFn mfma_spw(int spw, unsigned count, dim3& grid, dim3& blk) {
   return fn;
 }
 
-template <typename Sd>
+template <typename Sd, bool HM = false>
 MfmaFn mfma_pick(int nc, int spw, unsigned count, dim3& grid, dim3& blk) {
   switch (nc) {
-    case 12: return mfma_spw<12, Sd>(spw, count, grid, blk);
-    case 16: return mfma_spw<16, Sd>(spw, count, grid, blk);
-    case 24: return mfma_spw<24, Sd>(spw, count, grid, blk);
-    case 32: return mfma_spw<32, Sd>(spw, count, grid, blk);
-    case 40: return mfma_spw<40, Sd>(spw, count, grid, blk);
-    default: return mfma_spw<48, Sd>(spw, count, grid, blk);
+    case 12: return mfma_spw<12, Sd, HM>(spw, count, grid, blk);
+    case 16: return mfma_spw<16, Sd, HM>(spw, count, grid, blk);
+    case 24: return mfma_spw<24, Sd, HM>(spw, count, grid, blk);
+    case 32: return mfma_spw<32, Sd, HM>(spw, count, grid, blk);
+    case 40: return mfma_spw<40, Sd, HM>(spw, count, grid, blk);
+    default: return mfma_spw<48, Sd, HM>(spw, count, grid, blk);
   }
 }
 
 template <typename R, typename Sd, typename Tv>
 void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv, int nrhs, int site_begin, int count,
         double a_self, const void* xs, double a_hop, const void* xh, double beta, const void* z, void* out,
-        hipStream_t st, int spw, dd_dtype bt) {
+        hipStream_t st, int spw, dd_dtype bt, bool hm) {
   if (count <= 0) return;
   const int nblocks_read = (a_self != 0.0 ? 1 : 0) + (a_hop != 0.0 ? 8 : 0);
   const double bytes = (double)count * nblocks_read * nc * nc * sizeof(Sd) +
@@ -296,8 +450,10 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
                                                              (const Tv*)xh, (R)beta, (const Tv*)z, (Tv*)out)))
   if (sizeof(R) == 4 && nc <= kMfmaMaxNc) {
     dim3 grid, wg;
-    MfmaFn fn = bt == DD_F16    ? mfma_pick<__half2>(nc, spw, count, grid, wg)
-                : bt == DD_BF16 ? mfma_pick<bf16x2>(nc, spw, count, grid, wg)
+    MfmaFn fn = bt == DD_F16    ? (hm ? mfma_pick<__half2, true>(nc, spw, count, grid, wg)
+                                      : mfma_pick<__half2>(nc, spw, count, grid, wg))
+                : bt == DD_BF16 ? (hm ? mfma_pick<bf16x2, true>(nc, spw, count, grid, wg)
+                                      : mfma_pick<bf16x2>(nc, spw, count, grid, wg))
                                 : mfma_pick<float2>(nc, spw, count, grid, wg);
     const double hb = bt == DD_F32 ? 1.0 : 0.5;   // half-precision blocks stream half the bytes
     DD_TIMED("k_coarse_mfma", st, bytes - (1.0 - hb) * (double)count * nblocks_read * nc * nc * sizeof(Sd), flops,
@@ -322,13 +478,13 @@ void launch_coarse_tile(int nc, const double2* src64, long long nblk, float2* ds
 
 void launch_coarse_mv(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, const void* Minv, int use_inv, int nrhs,
                       int site_begin, int count, double a_self, const void* xs, double a_hop, const void* xh,
-                      double beta, const void* z, void* out, hipStream_t st, int spw, dd_dtype bt) {
+                      double beta, const void* z, void* out, hipStream_t st, int spw, dd_dtype bt, bool hm) {
   if (vt == DD_F64)
     mv<double, double2, double2>(g, nc, Dc, Minv, use_inv, nrhs, site_begin, count, a_self, xs, a_hop, xh, beta, z, out,
-                                 st, spw, DD_F64);
+                                 st, spw, DD_F64, false);
   else
     mv<float, float2, float2>(g, nc, Dc, Minv, use_inv, nrhs, site_begin, count, a_self, xs, a_hop, xh, beta, z, out,
-                              st, spw, bt);
+                              st, spw, bt, hm && (bt == DD_F16 || bt == DD_BF16));
 }
 
 // canonical coarse vectors [rhs][lex][nc] complex128 <-> packed [rhs][slot][nc]

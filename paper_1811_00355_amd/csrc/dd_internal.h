@@ -308,7 +308,8 @@ struct Tuning {
   int dirac_threads = 256;  // D apply workgroup size: 64, 128 or 256
   int coarse_spw = 4;       // FP32 coarse apply: coarse sites (waves) per workgroup, 2, 4 or 8
   int coarse_half = 0;      // with half-precision storage: 1 = coarse blocks in that type, 0 = FP32 blocks
-  int coarse_basis_half = 0;  // FP32 coarse GMRES: Krylov basis stored in FP16 (1) or FP32 (0)
+  int coarse_basis_half = 0;
+  int coarse_mfma_half = 0;   // half-precision blocks: FP16 / BF16 MFMA with x rounded to that type  // FP32 coarse GMRES: Krylov basis stored in FP16 (1) or FP32 (0)
 };
 
 struct dd_gauge {
@@ -414,7 +415,7 @@ void launch_coarse_invert(const GeomDev& g, int nc, const double2* Dc64, double2
 void launch_coarse_mv(const GeomDev& g, dd_dtype vt, int nc, const void* Dc, const void* Minv, int use_inv,
                       int nrhs, int site_begin, int count, double a_self, const void* xs, double a_hop,
                       const void* xh, double beta, const void* z, void* out, hipStream_t st, int spw = 4,
-                      dd_dtype bt = DD_F32);
+                      dd_dtype bt = DD_F32, bool hmfma = false);   // hmfma: half blocks on half-precision MFMA
 // vector kernels
 int dots_blocks(long long count, int nrhs);
 void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long ld, const void* V, int nv,

@@ -428,3 +428,40 @@ def test_coarse_basis_half(ctx):
             assert info[r]["converged"] and res <= 1e-10
         _close(d)
     assert all(h <= f + 2 for h, f in zip(its[1], its[0]))
+
+
+@pytest.mark.parametrize("store", [2, 3])
+def test_coarse_mfma_half(ctx, store):
+    """Half-precision coarse blocks on FP16 / BF16 matrix cores (coarse_mfma_half):
+    x is rounded to the block type before the products, which accumulate in FP32.
+    Against the oracle's stencil on the same rounded blocks the normwise error
+    is bounded by a few unit roundoffs of that type (FP16 u = 2^-11, BF16
+    u = 2^-8; bar 4u).  A whole solve on this path still reaches
+    |b - D x| / |b| <= 1e-10 (the outer FGMRES is flexible)."""
+    import torch
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_vectors, gauss_spinor
+    d = _build(ctx, "b4", inner_dtype=1, store_dtype=store, init_sap_apps=2, setup_iters=2)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    d["g"].dd_gauge_set_tuning(2, 256, 4, coarse_half=1, coarse_mfma_half=1)
+    # the library's D_c (its build is checked elsewhere), rounded as the half blocks are: FP64 -> FP32 -> half
+    Dr = _gpu.round_store(_gpu.round_f32(mg.export_coarse()), store)
+    nrhs = 12
+    c = _gpu.round_f32(gauss_vectors(nrhs, lat.Vc, 75, ncomp=2 * n))
+    got = _coarse_roundtrip(mg, 1, nrhs, c, lambda i, o: mg.dd_coarse_apply(1, nrhs, i, o))
+    errs = [_gpu.max_rel(got[r], amg.coarse_apply(lat, Dr, c[r])) for r in range(nrhs)]
+    u = 2.0 ** -11 if store == 2 else 2.0 ** -8
+    print(f"store {store}: coarse apply on half matrix cores, max error {max(errs):.2e} (bar {4 * u:.1e})", flush=True)
+    assert max(errs) < 4 * u
+    bs = gauss_spinor(lat.L, 3, 63)
+    bd = _gpu.to_dev(bs.reshape(3, -1))
+    xd = torch.zeros_like(bd)
+    info, _ = mg.dd_solve(3, bd, xd, 1e-10)
+    torch.cuda.synchronize()
+    x = _gpu.to_host(xd).reshape(bs.shape)
+    for r in range(3):
+        res = np.linalg.norm(bs[r] - d["W"].apply(x[r])) / np.linalg.norm(bs[r])
+        print(f"store {store} rhs {r}: iters {info[r]['outer_iters']} relres {res:.2e}", flush=True)
+        assert info[r]["converged"] and res <= 1e-10
+    _close(d)
