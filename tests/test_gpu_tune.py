@@ -49,15 +49,18 @@ def test_tuning_choices_bit_identical(ctx, tmp_path):
     print(rep, flush=True)
     with pytest.raises(Exception):
         g.dd_gauge_set_tuning(2, 256, 4, coarse_basis_half=2)
+    with pytest.raises(Exception):
+        g.dd_gauge_set_tuning(2, 256, 4, coarse_mfma_half=2)
     chosen = g.dd_gauge_get_tuning()
-    assert chosen["coarse_basis_half"] == 0
-    launch = {k: v for k, v in chosen.items() if k != "coarse_basis_half"}
+    numeric = ("coarse_basis_half", "coarse_mfma_half")   # the caller's numerical choices, not launch shapes
+    assert all(chosen[k] == 0 for k in numeric)
+    launch = {k: v for k, v in chosen.items() if k not in numeric}
     data = json.loads(cache.read_text())
     assert len(data) == 1 and list(data.values())[0] == launch
-    # the cache holds launch shapes only: the caller's basis storage survives a hit
-    g.dd_gauge_set_tuning(3, 64, 2, coarse_basis_half=1)
+    # the cache holds launch shapes only: the caller's numerical choices survive a hit
+    g.dd_gauge_set_tuning(3, 64, 2, coarse_basis_half=1, coarse_mfma_half=1)
     rep2 = mg.dd_autotune(nrhs, str(cache))
-    assert "cache hit" in rep2 and g.dd_gauge_get_tuning() == dict(launch, coarse_basis_half=1)
+    assert "cache hit" in rep2 and g.dd_gauge_get_tuning() == dict(launch, coarse_basis_half=1, coarse_mfma_half=1)
     g.dd_gauge_set_tuning(**launch)
     x = torch.zeros_like(bd)
     mg.dd_solve(nrhs, bd, x, 1e-10)
