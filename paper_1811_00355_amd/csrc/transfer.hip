@@ -71,6 +71,147 @@ __global__ void __launch_bounds__(256) k_restrict(GeomDev g, const Sp* __restric
 }
 
 // ---------------------------------------------------------------------------
+// restriction on matrix cores (4^4 aggregates, FP32 vectors): one workgroup per
+// aggregate for up to 16 right-hand sides at a time, so the aggregate's test
+// vectors are read once.  Per chirality s the result is the complex product
+// (n x 6*256) . (6*256 x rhs) of conj(lambda) and the fine vector.  Wave w takes
+// sites 64w .. 64w+63; per spin-colour component c the wave stages the 64 sites
+// of v (16 RHS) and of the n test vectors in LDS with coalesced loads, then runs
+// 16 k-steps of v_mfma_f32_16x16x4f32 over the sites, three real products per
+// complex one (Gauss: with conj(lambda) = a + ib, v = c + id: a (c + d),
+// (a + b)(-d), (b - a) c).  The four waves' partial sums are added in wave order.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int N, typename Sp>
+__global__ void __launch_bounds__(256) k_restrict_mfma(GeomDev g, const Sp* __restrict__ P, int nrhs,
+                                                       const float2* __restrict__ fine, float2* __restrict__ out,
+                                                       long long rstride, long long sstride) {
+  constexpr int MT = (N + 15) / 16, SP = 65;   // row tiles of the n test vectors; padded site stride
+  __shared__ float2 vs[4][16][SP];
+  __shared__ Sp ps[4][N][SP];
+  __shared__ float2 red[4][2 * N][16];
+  const int slot = blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const long long V = g.V, site = ((long long)slot << g.lBv) + 64 * w + lane;
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
+    const bool rhs_ok = li < nr;
+    for (int s = 0; s < 2; ++s) {
+      f32x4 k1[MT], k2[MT], k3[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) k1[t] = k2[t] = k3[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      for (int cc = 0; cc < 6; ++cc) {
+        const int c = 6 * s + cc;
+        float2 xv[16];
+        Sp pv[N];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xv[r] = fine[(long long)(r0 + (r < nr ? r : 0)) * 12 * V + (long long)c * V + site];
+#pragma unroll
+        for (int i = 0; i < N; ++i) pv[i] = P[((long long)i * 12 + c) * V + site];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) vs[w][r][lane] = xv[r];
+#pragma unroll
+        for (int i = 0; i < N; ++i) ps[w][i][lane] = pv[i];
+        __syncthreads();
+#pragma unroll 4
+        for (int ks = 0; ks < 16; ++ks) {
+          const float2 xb = vs[w][li][4 * ks + lk];
+          const float xc = rhs_ok ? xb.x : 0.f, xd = rhs_ok ? xb.y : 0.f;
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            const int i = 16 * t + li;
+            const cx<float> l = i < N ? ld<float, Sp>(&ps[w][i < N ? i : 0][4 * ks + lk]) : cx<float>{0.f, 0.f};
+            const float a = l.re, b = -l.im;   // conj(lambda)
+            k1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xc + xd, k1[t], 0, 0, 0);
+            k2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a + b, -xd, k2[t], 0, 0, 0);
+            k3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b - a, xc, k3[t], 0, 0, 0);
+          }
+        }
+        __syncthreads();   // every read of the staging is done before it is refilled
+      }
+      // this wave's partial result: lane holds rows 16t + 4lk + v of right-hand side li
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + 4 * lk + v;
+          if (row < N) red[w][s * N + row][li] = make_float2(k1[t][v] + k2[t][v], k1[t][v] + k3[t][v]);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * N * 16; e += blockDim.x) {
+      const int r = e / (2 * N), k = e - r * (2 * N);
+      if (r < nr) {
+        const float2 a = red[0][k][r], b = red[1][k][r], c = red[2][k][r], d = red[3][k][r];
+        out[(long long)(r0 + r) * rstride + (long long)slot * sstride + k] =
+            make_float2(((a.x + b.x) + c.x) + d.x, ((a.y + b.y) + c.y) + d.y);
+      }
+    }
+    __syncthreads();   // red is rewritten by the next pass
+  }
+}
+
+// ---------------------------------------------------------------------------
+// prolongation on matrix cores (4^4 aggregates, FP32 vectors): one workgroup per
+// aggregate for up to 16 right-hand sides at a time.  Per spin-colour component
+// c (chirality s = c / 6) the fine values of the aggregate's sites are the
+// complex product (sites x n) . (n x rhs) of lambda_i(site, c) and the coarse
+// vector's chirality-s block.  Wave w takes sites 64w .. 64w+63 as four 16-row
+// tiles; the n test-vector values of its sites are staged in LDS per component
+// (coalesced), the coarse vectors once per pass.  Three real MFMAs per complex
+// product as in the restriction.
+// ---------------------------------------------------------------------------
+template <int N, typename Sp>
+__global__ void __launch_bounds__(256) k_prolong_mfma(GeomDev g, const Sp* __restrict__ P, int nrhs,
+                                                      const float2* __restrict__ coarse, float2* __restrict__ fine) {
+  constexpr int KS = (N + 3) / 4, SP = 65;
+  __shared__ Sp ps[4][N][SP];
+  __shared__ float2 xs[16][2 * N + 1];
+  const int slot = blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const long long V = g.V, base = ((long long)slot << g.lBv) + 64 * w;
+  const int nc = 2 * N;
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
+    __syncthreads();   // the previous pass's reads of xs are done
+    for (int e = threadIdx.x; e < 16 * nc; e += blockDim.x) {
+      const int r = e / nc, k = e - r * nc;
+      xs[r][k] = r < nr ? coarse[((long long)(r0 + r) * g.Vc + slot) * nc + k] : make_float2(0.f, 0.f);
+    }
+    for (int c = 0; c < 12; ++c) {
+      const int s = c / 6;
+      Sp pv[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) pv[i] = P[((long long)i * 12 + c) * V + base + lane];
+      __syncthreads();   // xs is written (first component); the previous component's reads of ps are done
+#pragma unroll
+      for (int i = 0; i < N; ++i) ps[w][i][lane] = pv[i];
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        f32x4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int i = 4 * ks + lk;
+          const cx<float> l = i < N ? ld<float, Sp>(&ps[w][i < N ? i : 0][16 * t + li]) : cx<float>{0.f, 0.f};
+          const float2 xb = i < N ? xs[li][s * N + i] : make_float2(0.f, 0.f);
+          k1 = __builtin_amdgcn_mfma_f32_16x16x4f32(l.re, xb.x + xb.y, k1, 0, 0, 0);
+          k2 = __builtin_amdgcn_mfma_f32_16x16x4f32(l.re + l.im, -xb.y, k2, 0, 0, 0);
+          k3 = __builtin_amdgcn_mfma_f32_16x16x4f32(l.im - l.re, xb.x, k3, 0, 0, 0);
+        }
+        // lane holds sites 16t + 4lk + v of right-hand side li
+        if (li < nr) {
+          float2* o = fine + (long long)(r0 + li) * 12 * V + (long long)c * V + base + 16 * t + 4 * lk;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) o[v] = make_float2(k1[v] + k2[v], k1[v] + k3[v]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // prolongation: one workgroup per (aggregate, rhs), one thread per site
 // ---------------------------------------------------------------------------
 template <typename R, typename Sp, typename Tv>
@@ -341,6 +482,32 @@ void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const v
     restrict_n<double, double2, double2, double2>(g, n, P, nrhs, fine, coarse, rs, nc, st);
     return;
   }
+  if (g.Bv == 256 && pst != DD_F64) {   // matrix-core form
+    const double bytes = (double)g.V * 12 * (n * storage_pair_bytes(pst) + nrhs * sizeof(float2)) +
+                         (double)g.Vc * 2 * n * nrhs * sizeof(float2);
+    const double flops = 8.0 * g.V * 12 * n * nrhs;
+#define DD_RM(NN, SP)                                                                                     \
+  DD_TIMED("k_restrict", st, bytes, flops,                                                                \
+           (k_restrict_mfma<NN, SP><<<g.Vc, 256, 0, st>>>(g, (const SP*)P, nrhs, (const float2*)fine,     \
+                                                          (float2*)coarse, rs, nc)))
+#define DD_RMN(SP)                  \
+  switch (n) {                      \
+    case 6: DD_RM(6, SP); break;    \
+    case 8: DD_RM(8, SP); break;    \
+    case 12: DD_RM(12, SP); break;  \
+    case 16: DD_RM(16, SP); break;  \
+    case 20: DD_RM(20, SP); break;  \
+    default: DD_RM(24, SP); break;  \
+  }
+    switch (pst) {
+      case DD_F32: DD_RMN(float2) break;
+      case DD_F16: DD_RMN(__half2) break;
+      default: DD_RMN(bf16x2) break;
+    }
+#undef DD_RMN
+#undef DD_RM
+    return;
+  }
   switch (pst) {
     case DD_F64: restrict_n<float, double2, float2, float2>(g, n, P, nrhs, fine, coarse, rs, nc, st); break;
     case DD_F32: restrict_n<float, float2, float2, float2>(g, n, P, nrhs, fine, coarse, rs, nc, st); break;
@@ -351,6 +518,27 @@ void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const v
 
 static void prolong_dispatch(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,
                              const void* coarse, void* fine, hipStream_t st) {
+  if (vt != DD_F64 && g.Bv == 256 && pst != DD_F64) {   // matrix-core form
+#define DD_PM(NN, SP)                                                                                        \
+  k_prolong_mfma<NN, SP><<<g.Vc, 256, 0, st>>>(g, (const SP*)P, nrhs, (const float2*)coarse, (float2*)fine)
+#define DD_PMN(SP)                  \
+  switch (n) {                      \
+    case 6: DD_PM(6, SP); break;    \
+    case 8: DD_PM(8, SP); break;    \
+    case 12: DD_PM(12, SP); break;  \
+    case 16: DD_PM(16, SP); break;  \
+    case 20: DD_PM(20, SP); break;  \
+    default: DD_PM(24, SP); break;  \
+  }
+    switch (pst) {
+      case DD_F32: DD_PMN(float2) break;
+      case DD_F16: DD_PMN(__half2) break;
+      default: DD_PMN(bf16x2) break;
+    }
+#undef DD_PMN
+#undef DD_PM
+    return;
+  }
   int threads = g.Bv < 64 ? 64 : g.Bv;
   unsigned nb = xcd_grid(g.Vc, nrhs);
   if (vt == DD_F64) {

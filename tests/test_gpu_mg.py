@@ -465,3 +465,46 @@ def test_coarse_mfma_half(ctx, store):
         print(f"store {store} rhs {r}: iters {info[r]['outer_iters']} relres {res:.2e}", flush=True)
         assert info[r]["converged"] and res <= 1e-10
     _close(d)
+
+
+@pytest.mark.parametrize("store,nrhs", [(1, 12), (2, 20), (3, 1)])
+def test_restrict_prolong_inner(ctx, store, nrhs):
+    """Restriction and prolongation of the FP32 inner solve with the stored test
+    vectors (FP32, FP16, BF16; 4^4 aggregates take the matrix-core forms), over
+    one, a padded and two 16-wide right-hand-side passes, against the oracle on
+    the same rounded vectors: P rounded to FP32 before and to the storage type
+    after Gram-Schmidt, inputs rounded to FP32."""
+    import torch
+    import _gpu
+    from oracle import amg
+    from workloads import gauss_spinor, gauss_vectors
+    d = _build(ctx, "b4", inner_dtype=1, store_dtype=store)
+    lat, mg, n = d["lat"], d["mg"], d["n"]
+    Pr = _gpu.round_store(amg.gram_schmidt(lat, _gpu.round_f32(d["tv0"])), store)
+    f = _gpu.round_f32(gauss_spinor(lat.L, nrhs, 33))
+    c = _gpu.round_f32(gauss_vectors(nrhs, lat.Vc, 34, ncomp=2 * n))
+    fin = _gpu.to_dev(f.reshape(nrhs, -1))
+    pf = d["g"].new_packed(1, nrhs)
+    d["g"].pack(1, nrhs, fin, pf)
+    pc = mg.new_coarse(1, nrhs)
+    mg.dd_restrict(1, nrhs, pf, pc)
+    cout = torch.zeros((nrhs, lat.Vc * 2 * n), dtype=torch.complex128, device="cuda")
+    mg.unpack_coarse(1, nrhs, pc, cout)
+    torch.cuda.synchronize()
+    got = _gpu.to_host(cout).reshape(nrhs, lat.Vc, 2 * n)
+    errs = [_gpu.max_rel(got[r], amg.restrict(lat, Pr, f[r])) for r in range(nrhs)]
+    print(f"store {store}, {nrhs} rhs: restriction max error {max(errs):.2e}", flush=True)
+    assert max(errs) < 1e-5
+    cin = _gpu.to_dev(c.reshape(nrhs, -1))
+    pc2 = mg.new_coarse(1, nrhs)
+    mg.pack_coarse(1, nrhs, cin, pc2)
+    pf2 = d["g"].new_packed(1, nrhs)
+    mg.dd_prolong(1, nrhs, pc2, pf2)
+    fout = torch.zeros((nrhs, lat.V * 12), dtype=torch.complex128, device="cuda")
+    d["g"].unpack(1, nrhs, pf2, fout)
+    torch.cuda.synchronize()
+    got = _gpu.to_host(fout).reshape(nrhs, lat.V, 4, 3)
+    errs = [_gpu.max_rel(got[r], amg.prolong(lat, Pr, c[r])) for r in range(nrhs)]
+    print(f"store {store}, {nrhs} rhs: prolongation max error {max(errs):.2e}", flush=True)
+    assert max(errs) < 1e-5
+    _close(d)
