@@ -118,14 +118,16 @@ size_t dd_ctx_bytes_in_use(const dd_ctx* ctx);
 void dd_mg_params_default(dd_mg_params* p);
 
 /* Launch shapes and coarse storage.  The first three give bit-identical results
- * for every choice (see dd_autotune); coarse_half and coarse_basis_half change
- * the rounding of the coarse-level arithmetic (as do coarse_basis_half and
- * coarse_mfma_half), which only the FGMRES outer
- * iteration count can see (the outer solver is flexible, Sec. 2). */
+ * for every choice (see dd_autotune).  coarse_half, coarse_basis_half and
+ * coarse_mfma_half change the rounding of the coarse-level arithmetic, which
+ * only the FGMRES outer iteration count can see (the outer solver is flexible,
+ * Sec. 2). */
 typedef struct {
   int32_t sap_wpe;        /* SAP waves per SIMD the registers allow: 2 or 3          */
-  int32_t dirac_threads;  /* D apply workgroup size: 64, 128 or 256                    */
-  int32_t coarse_spw;     /* FP32 coarse apply: coarse sites per workgroup, 2, 4 or 8  */
+  int32_t dirac_threads;  /* D apply workgroup size, 64, 128 or 256 (blocks other than 4^4; 4^4 blocks
+                             take one 256-thread workgroup per block)                */
+  int32_t coarse_spw;     /* coarse apply: target waves per workgroup, 2, 4 or 8 (sites per workgroup =
+                             max(1, coarse_spw / ceil(2n / 16)), at most 4)          */
   int32_t coarse_half;    /* half-precision setups: coarse blocks in FP16/BF16 (1) or FP32 (0) */
   int32_t coarse_basis_half; /* FP32 coarse GMRES: Krylov basis stored in FP16 (1) or FP32 (0);
                                 never changed by dd_autotune */

@@ -8,6 +8,8 @@
 // aggregate X is the contiguous site range of block slot X, chirality s covers
 // spin components 6s..6s+5.  Coarse vectors are [rhs][Vc][2n] pairs with
 // component s*n + i; coarse-operator blocks are [Vc][9][col][row] (column major).
+#include <type_traits>
+
 #include "dslash.h"
 #include "ktimer.h"
 
@@ -82,73 +84,109 @@ __global__ void __launch_bounds__(256) k_restrict(GeomDev g, const Sp* __restric
 // (a + b)(-d), (b - a) c).  The four waves' partial sums are added in wave order.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename R> struct Mfma4;
+// Output layouts differ: element v of lane group lk holds row 4 lk + v (FP32 form)
+// or row lk + 4 v (FP64 form) of column lane % 16.
+template <> struct Mfma4<float> {
+  typedef f32x4 acc;
+  typedef float2 vec;
+  __device__ static acc op(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int v) { return 4 * lk + v; }
+};
+template <> struct Mfma4<double> {
+  typedef f64x4 acc;
+  typedef double2 vec;
+  __device__ static acc op(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int v) { return lk + 4 * v; }
+};
 
-template <int N, typename Sp>
+// R: FP32 (inner solve) or FP64 (Galerkin build); SW: sites per staging step of a wave
+template <int N, typename Sp, typename R, int SW>
 __global__ void __launch_bounds__(256) k_restrict_mfma(GeomDev g, const Sp* __restrict__ P, int nrhs,
-                                                       const float2* __restrict__ fine, float2* __restrict__ out,
-                                                       long long rstride, long long sstride) {
-  constexpr int MT = (N + 15) / 16, SP = 65;   // row tiles of the n test vectors; padded site stride
-  __shared__ float2 vs[4][16][SP];
-  __shared__ Sp ps[4][N][SP];
-  __shared__ float2 red[4][2 * N][16];
+                                                       const typename Mfma4<R>::vec* __restrict__ fine,
+                                                       typename Mfma4<R>::vec* __restrict__ out, long long rstride,
+                                                       long long sstride) {
+  typedef Mfma4<R> M;
+  typedef typename M::acc acc_t;
+  typedef typename M::vec Tv;
+  constexpr int MT = (N + 15) / 16, SP = SW + 1;   // row tiles of the n test vectors; padded site stride
+  // staging of v and lambda; after both chiralities the same bytes hold the waves' partial sums [w][k][rhs]
+  constexpr size_t kVs = sizeof(Tv) * 4 * 16 * SP, kPs = sizeof(Sp) * 4 * N * SP, kRed = sizeof(Tv) * 4 * 2 * N * 16;
+  __shared__ __align__(16) char smem[kVs + kPs > kRed ? kVs + kPs : kRed];
+  Tv(*vs)[16][SP] = reinterpret_cast<Tv(*)[16][SP]>(smem);
+  Sp(*ps)[N][SP] = reinterpret_cast<Sp(*)[N][SP]>(smem + kVs);
+  Tv(*red)[2 * N][16] = reinterpret_cast<Tv(*)[2 * N][16]>(smem);
   const int slot = blockIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  const long long V = g.V, site = ((long long)slot << g.lBv) + 64 * w + lane;
+  const long long V = g.V, base = ((long long)slot << g.lBv) + 64 * w;
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
     const bool rhs_ok = li < nr;
+    cx<R> res[2][MT][4];
     for (int s = 0; s < 2; ++s) {
-      f32x4 k1[MT], k2[MT], k3[MT];
+      acc_t k1[MT], k2[MT], k3[MT];
 #pragma unroll
-      for (int t = 0; t < MT; ++t) k1[t] = k2[t] = k3[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < MT; ++t) k1[t] = k2[t] = k3[t] = acc_t{0, 0, 0, 0};
       for (int cc = 0; cc < 6; ++cc) {
         const int c = 6 * s + cc;
-        float2 xv[16];
-        Sp pv[N];
+        for (int h = 0; h < 64 / SW; ++h) {
+          const long long site = base + h * SW + (lane < SW ? lane : 0);
+          Tv xv[16];
+          Sp pv[N];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) xv[r] = fine[(long long)(r0 + (r < nr ? r : 0)) * 12 * V + (long long)c * V + site];
+          for (int r = 0; r < 16; ++r) xv[r] = fine[(long long)(r0 + (r < nr ? r : 0)) * 12 * V + (long long)c * V + site];
 #pragma unroll
-        for (int i = 0; i < N; ++i) pv[i] = P[((long long)i * 12 + c) * V + site];
+          for (int i = 0; i < N; ++i) pv[i] = P[((long long)i * 12 + c) * V + site];
+          if (lane < SW) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) vs[w][r][lane] = xv[r];
+            for (int r = 0; r < 16; ++r) vs[w][r][lane] = xv[r];
 #pragma unroll
-        for (int i = 0; i < N; ++i) ps[w][i][lane] = pv[i];
-        __syncthreads();
-#pragma unroll 4
-        for (int ks = 0; ks < 16; ++ks) {
-          const float2 xb = vs[w][li][4 * ks + lk];
-          const float xc = rhs_ok ? xb.x : 0.f, xd = rhs_ok ? xb.y : 0.f;
-#pragma unroll
-          for (int t = 0; t < MT; ++t) {
-            const int i = 16 * t + li;
-            const cx<float> l = i < N ? ld<float, Sp>(&ps[w][i < N ? i : 0][4 * ks + lk]) : cx<float>{0.f, 0.f};
-            const float a = l.re, b = -l.im;   // conj(lambda)
-            k1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xc + xd, k1[t], 0, 0, 0);
-            k2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a + b, -xd, k2[t], 0, 0, 0);
-            k3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(b - a, xc, k3[t], 0, 0, 0);
+            for (int i = 0; i < N; ++i) ps[w][i][lane] = pv[i];
           }
+          __syncthreads();
+#pragma unroll 4
+          for (int ks = 0; ks < SW / 4; ++ks) {
+            const Tv xb = vs[w][li][4 * ks + lk];
+            const R xc = rhs_ok ? xb.x : (R)0, xd = rhs_ok ? xb.y : (R)0;
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+              const int i = 16 * t + li;
+              const cx<R> l = i < N ? ld<R, Sp>(&ps[w][i < N ? i : 0][4 * ks + lk]) : cx<R>{(R)0, (R)0};
+              const R a = l.re, b = -l.im;   // conj(lambda)
+              k1[t] = M::op(a, xc + xd, k1[t]);
+              k2[t] = M::op(a + b, -xd, k2[t]);
+              k3[t] = M::op(b - a, xc, k3[t]);
+            }
+          }
+          __syncthreads();   // every read of the staging is done before it is refilled
         }
-        __syncthreads();   // every read of the staging is done before it is refilled
       }
-      // this wave's partial result: lane holds rows 16t + 4lk + v of right-hand side li
+      // this wave's partial result: lane holds rows 16t + M::row(lk, v) of right-hand side li
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) res[s][t][v] = {k1[t][v] + k2[t][v], k1[t][v] + k3[t][v]};
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int t = 0; t < MT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = 16 * t + 4 * lk + v;
-          if (row < N) red[w][s * N + row][li] = make_float2(k1[t][v] + k2[t][v], k1[t][v] + k3[t][v]);
+          const int row = 16 * t + M::row(lk, v);
+          if (row < N) red[w][s * N + row][li] = Tv{res[s][t][v].re, res[s][t][v].im};
         }
-    }
     __syncthreads();
     for (int e = threadIdx.x; e < 2 * N * 16; e += blockDim.x) {
       const int r = e / (2 * N), k = e - r * (2 * N);
       if (r < nr) {
-        const float2 a = red[0][k][r], b = red[1][k][r], c = red[2][k][r], d = red[3][k][r];
+        const Tv a = red[0][k][r], b = red[1][k][r], c = red[2][k][r], d = red[3][k][r];
         out[(long long)(r0 + r) * rstride + (long long)slot * sstride + k] =
-            make_float2(((a.x + b.x) + c.x) + d.x, ((a.y + b.y) + c.y) + d.y);
+            Tv{((a.x + b.x) + c.x) + d.x, ((a.y + b.y) + c.y) + d.y};
       }
     }
-    __syncthreads();   // red is rewritten by the next pass
+    __syncthreads();   // the staging buffer is refilled by the next pass
   }
 }
 
@@ -452,6 +490,14 @@ struct RestrictDispatch {
     // test vectors once, fine input per RHS, coarse output per RHS
     const double bytes = (double)g.V * 12 * (N * sizeof(Sp) + nrhs * sizeof(Tv)) + (double)g.Vc * 2 * N * nrhs * sizeof(To);
     const double flops = 8.0 * g.V * 12 * N * nrhs;
+    if constexpr (std::is_same<R, double>::value && std::is_same<Tv, double2>::value && std::is_same<To, double2>::value) {
+      if (g.Bv == 256) {   // FP64 matrix cores, 32 sites per staging step (two workgroups per CU)
+        DD_TIMED("k_restrict", st, bytes, flops,
+                 (k_restrict_mfma<N, Sp, double, 32><<<g.Vc, 256, 0, st>>>(g, (const Sp*)P, nrhs, (const double2*)fine,
+                                                                           (double2*)out, rstride, sstride)));
+        return;
+      }
+    }
     DD_TIMED("k_restrict", st, bytes, flops,
              (k_restrict<N, R, Sp, Tv, To><<<xcd_grid(g.Vc, nrhs), threads, 0, st>>>(g, (const Sp*)P, nrhs, (const Tv*)fine,
                                                                                       (To*)out, rstride, sstride)));
@@ -488,8 +534,8 @@ void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const v
     const double flops = 8.0 * g.V * 12 * n * nrhs;
 #define DD_RM(NN, SP)                                                                                     \
   DD_TIMED("k_restrict", st, bytes, flops,                                                                \
-           (k_restrict_mfma<NN, SP><<<g.Vc, 256, 0, st>>>(g, (const SP*)P, nrhs, (const float2*)fine,     \
-                                                          (float2*)coarse, rs, nc)))
+           (k_restrict_mfma<NN, SP, float, 64><<<g.Vc, 256, 0, st>>>(g, (const SP*)P, nrhs,                \
+                                                                     (const float2*)fine, (float2*)coarse, rs, nc)))
 #define DD_RMN(SP)                  \
   switch (n) {                      \
     case 6: DD_RM(6, SP); break;    \
