@@ -76,10 +76,11 @@ struct Workspace {
   double* partial;
   int* hflags = nullptr;   // pinned host mirror: active[nrhs], kcyc[nrhs]
   double* hvals = nullptr; // pinned host mirror: est[nrhs], tolabs[nrhs], nrm[nrhs]
-  // captured coarse GMRES chunks, keyed by (nrhs, dtype, basis dtype, first iteration, length, ends cycle);
+  // captured coarse GMRES chunks, keyed by (nrhs, dtype, basis dtype, block dtype, waves per workgroup,
+  // half matrix cores, first iteration, length, ends cycle), i.e. every launch choice baked into a capture;
   // they hold this arena's addresses and die with it
   hipStream_t cap = nullptr;
-  std::map<std::array<int, 6>, hipGraphExec_t> graphs;
+  std::map<std::array<int, 9>, hipGraphExec_t> graphs;
 };
 
 static dd_dtype inner_vt(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : DD_F32; }
@@ -306,7 +307,7 @@ static dd_status run_chunk(dd_mg* mg, const CoarseOps& c, int nrhs, long long ce
     issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, CV, j0, len, ends, st);
     return DD_OK;
   }
-  const std::array<int, 6> key = {nrhs, (int)c.vt, (int)c.basis, j0, len, ends ? 1 : 0};
+  const std::array<int, 9> key = {nrhs, (int)c.vt, (int)c.basis, (int)c.bt, c.spw, c.hm ? 1 : 0, j0, len, ends ? 1 : 0};
   auto it = w->graphs.find(key);
   if (it == w->graphs.end()) {
     if (!w->cap) DD_HIP(mg->ctx, hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));

@@ -3,7 +3,8 @@
 // workgroups of one tile (all right-hand sides) run on the same XCD back to back,
 // so its links and clover come from that XCD's L2 after the first fetch, and
 // neighbouring blocks run together on that XCD, so halo spinors and backward
-// links are shared through the same L2.
+// links are shared through the same L2.  Lattices with 4^4 blocks take the
+// block form (k_dirac_blk), whose in-block hops read spinors staged in LDS.
 #include "dslash.h"
 #include "ktimer.h"
 

@@ -91,3 +91,46 @@ def test_solve_with_graphs_matches_eager(ctx):
         assert torch.equal(xe, x0)
     mg.destroy()
     g.destroy()
+
+
+def test_graphs_follow_tuning_changes(ctx):
+    """A captured chunk is keyed by every launch choice in it: after the coarse
+    tuning changes (waves per workgroup, half blocks, half matrix cores, FP16
+    basis) the graph path gives the same bits as the eager path under the new
+    tuning, not a replay of the old capture."""
+    import torch
+    import _gpu
+    from paper_1811_00355_amd import Gauge, MG, default_params
+    from oracle.lattice import Lattice
+    from workloads import su3_field, gauss_vectors
+    L, blk, n = (8, 8, 8, 16), (4, 4, 4, 4), 20
+    lat = Lattice(L, blk)
+    g = Gauge(ctx, L, blk, su3_field(L, 0.2, 23), -0.1, 1.0)
+    p = default_params(block=blk, n_vec=n, inner_dtype=1, store_dtype=3, init_sap_apps=2, setup_iters=1)
+    mg = MG(g, p, tv_host=gauss_vectors(n, lat.V, 30).reshape(n, lat.V, 4, 3))
+    nrhs = 3
+    cin = _gpu.to_dev(gauss_vectors(nrhs, lat.Vc, 85, ncomp=2 * n).reshape(nrhs, -1))
+    pin, pout = mg.new_coarse(1, nrhs), mg.new_coarse(1, nrhs)
+    mg.pack_coarse(1, nrhs, cin, pin)
+    results = []
+    for tune in (dict(), dict(coarse_spw=8), dict(coarse_half=1), dict(coarse_half=1, coarse_mfma_half=1),
+                 dict(coarse_half=1, coarse_mfma_half=1, coarse_basis_half=1)):
+        t = dict(sap_wpe=2, dirac_threads=256, coarse_spw=4)
+        t.update(tune)
+        g.dd_gauge_set_tuning(**t)
+        mg.dd_mg_set_graphs(False)
+        pout.zero_()
+        it0 = mg.dd_coarse_solve(1, nrhs, pin, pout)
+        ref = pout.clone()
+        mg.dd_mg_set_graphs(True)
+        pout.zero_()
+        it = mg.dd_coarse_solve(1, nrhs, pin, pout)
+        torch.cuda.synchronize()
+        same = torch.equal(pout, ref)
+        print(f"tuning {tune}: iters {it} (eager {it0}) bitwise {same}", flush=True)
+        assert it == it0 and same
+        results.append(ref)
+    # the half-precision choices really changed the arithmetic (so the check above is not vacuous)
+    assert not torch.equal(results[0], results[3]) and not torch.equal(results[3], results[4])
+    mg.destroy()
+    g.destroy()
