@@ -111,19 +111,18 @@ __global__ void __launch_bounds__(256) k_restrict_mfma(GeomDev g, const Sp* __re
   typedef typename M::acc acc_t;
   typedef typename M::vec Tv;
   constexpr int MT = (N + 15) / 16, SP = SW + 1;   // row tiles of the n test vectors; padded site stride
-  // staging of v and lambda; after both chiralities the same bytes hold the waves' partial sums [w][k][rhs]
-  constexpr size_t kVs = sizeof(Tv) * 4 * 16 * SP, kPs = sizeof(Sp) * 4 * N * SP, kRed = sizeof(Tv) * 4 * 2 * N * 16;
+  // staging of v and lambda; after each chirality the same bytes hold the waves' partial sums [w][row][rhs]
+  constexpr size_t kVs = sizeof(Tv) * 4 * 16 * SP, kPs = sizeof(Sp) * 4 * N * SP, kRed = sizeof(Tv) * 4 * N * 16;
   __shared__ __align__(16) char smem[kVs + kPs > kRed ? kVs + kPs : kRed];
   Tv(*vs)[16][SP] = reinterpret_cast<Tv(*)[16][SP]>(smem);
   Sp(*ps)[N][SP] = reinterpret_cast<Sp(*)[N][SP]>(smem + kVs);
-  Tv(*red)[2 * N][16] = reinterpret_cast<Tv(*)[2 * N][16]>(smem);
+  Tv(*red)[N][16] = reinterpret_cast<Tv(*)[N][16]>(smem);
   const int slot = blockIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const long long V = g.V, base = ((long long)slot << g.lBv) + 64 * w;
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
     const bool rhs_ok = li < nr;
-    cx<R> res[2][MT][4];
     for (int s = 0; s < 2; ++s) {
       acc_t k1[MT], k2[MT], k3[MT];
 #pragma unroll
@@ -159,34 +158,28 @@ __global__ void __launch_bounds__(256) k_restrict_mfma(GeomDev g, const Sp* __re
               k3[t] = M::op(b - a, xc, k3[t]);
             }
           }
-          __syncthreads();   // every read of the staging is done before it is refilled
+          __syncthreads();   // every read of the staging is done before it is refilled (or reused below)
         }
       }
       // this wave's partial result: lane holds rows 16t + M::row(lk, v) of right-hand side li
 #pragma unroll
       for (int t = 0; t < MT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) res[s][t][v] = {k1[t][v] + k2[t][v], k1[t][v] + k3[t][v]};
-    }
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int t = 0; t < MT; ++t)
-#pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = 16 * t + M::row(lk, v);
-          if (row < N) red[w][s * N + row][li] = Tv{res[s][t][v].re, res[s][t][v].im};
+          if (row < N) red[w][row][li] = Tv{k1[t][v] + k2[t][v], k1[t][v] + k3[t][v]};
         }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 2 * N * 16; e += blockDim.x) {
-      const int r = e / (2 * N), k = e - r * (2 * N);
-      if (r < nr) {
-        const Tv a = red[0][k][r], b = red[1][k][r], c = red[2][k][r], d = red[3][k][r];
-        out[(long long)(r0 + r) * rstride + (long long)slot * sstride + k] =
-            Tv{((a.x + b.x) + c.x) + d.x, ((a.y + b.y) + c.y) + d.y};
+      __syncthreads();
+      for (int e = threadIdx.x; e < N * 16; e += blockDim.x) {
+        const int r = e / N, row = e - r * N;
+        if (r < nr) {
+          const Tv a = red[0][row][r], b = red[1][row][r], c = red[2][row][r], d = red[3][row][r];
+          out[(long long)(r0 + r) * rstride + (long long)slot * sstride + s * N + row] =
+              Tv{((a.x + b.x) + c.x) + d.x, ((a.y + b.y) + c.y) + d.y};
+        }
       }
+      __syncthreads();   // the staging buffer is refilled next
     }
-    __syncthreads();   // the staging buffer is refilled by the next pass
   }
 }
 
