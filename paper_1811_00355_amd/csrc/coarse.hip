@@ -276,19 +276,25 @@ template <> struct HalfOp<bf16x2> {
   }
 };
 
+// Two directions per barrier phase: the loads of both directions' blocks and
+// inputs are in flight together (five phases for the nine-block stencil
+// instead of nine), which matters because one apply is a single round of
+// workgroups whose time is the chain of load latencies.  The directions are
+// still accumulated in order, so the result is that of one direction per phase.
 template <int NC, int S, typename Sd>
-__global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) k_coarse_mfma_h(
+__global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_mfma_h(
     GeomDev g, const Sd* __restrict__ Dc, const Sd* __restrict__ Minv, int use_inv, int nrhs, int site_begin,
     int count, float a_self, const float2* __restrict__ xs, float a_hop, const float2* __restrict__ xh, float beta,
     const float2* __restrict__ z, float2* __restrict__ out) {
   typedef HalfOp<Sd> H;
   typedef typename H::vec vec;
   typedef typename H::elem elem;
-  constexpr int MT = (NC + 15) / 16, KS = NC / 4, NS = (KS + 3) / 4;
+  constexpr int MT = (NC + 15) / 16, KS = NC / 4, NS = (KS + 3) / 4, DP = 2;
   constexpr int P = tile_group(NC, (int)sizeof(Sd));
-  // staged x: [site][buffer][s][lk][rhs][v], real and imaginary parts
-  __shared__ alignas(16) elem xc[S][2][NS][4][16][4];
-  __shared__ alignas(16) elem xd[S][2][NS][4][16][4];
+  constexpr int XI = (16 * NC + 64 * MT - 1) / (64 * MT);
+  // staged x: [site][buffer][direction of the phase][s][lk][rhs][v], real and imaginary parts
+  __shared__ alignas(16) elem xc[S][2][DP][NS][4][16][4];
+  __shared__ alignas(16) elem xd[S][2][DP][NS][4][16][4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int s_in = wv / MT, t = wv % MT, tid_site = threadIdx.x - 64 * MT * s_in;
   const int ngroups = (count + S - 1) / S, per_x = (ngroups + 7) / 8;
@@ -296,17 +302,20 @@ __global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) k_coarse_mfma_h(
   if (group >= ngroups) return;   // uniform per workgroup
   const int local = group * S + s_in;
   const bool site_ok = local < count;
-  const int X = site_begin + (site_ok ? local : 0);
+  // the site is the same on every lane of a wave: keep it (and the block and
+  // neighbour addresses derived from it) in scalar registers
+  const int X = __builtin_amdgcn_readfirstlane(site_begin + (site_ok ? local : 0));
   const int RT = NC - 16 * t < 16 ? NC - 16 * t : 16;
   const long long vstride = (long long)g.Vc * NC;
   const bool has_self = a_self != 0.f, has_hop = a_hop != 0.f;
+  const int d_begin = has_self ? 0 : 1, d_end = has_hop ? 9 : 1;
   const int li = lane & 15, lk = lane >> 4;
   const bool row_ok = li < RT;
-  // K-slots past NC stay zero in both buffers
+  // K-slots past NC stay zero in every buffer
   {
-    elem* pc = &xc[s_in][0][0][0][0][0];
-    elem* pd = &xd[s_in][0][0][0][0][0];
-    for (int e = tid_site; e < 2 * NS * 4 * 16 * 4; e += 64 * MT) {
+    elem* pc = &xc[s_in][0][0][0][0][0][0];
+    elem* pd = &xd[s_in][0][0][0][0][0][0];
+    for (int e = tid_site; e < 2 * DP * NS * 4 * 16 * 4; e += 64 * MT) {
       pc[e] = H::from_f32(0.f);
       pd[e] = H::from_f32(0.f);
     }
@@ -316,63 +325,76 @@ __global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) k_coarse_mfma_h(
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
     const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
     const bool rhs_ok = li < nr;
+    const int nx = nr * NC;
     f32x4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1, k4 = k1;
-    for (int d = has_self ? 0 : 1; d < (has_hop ? 9 : 1); ++d) {
-      const int Y = d == 0 ? X : (g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK);
-      const float2* src = d == 0 ? xs : xh;
-      const float sc = d == 0 ? a_self : a_hop;
-      const Sd* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * NC * NC : Dc + (long long)X * 9 * NC * NC)
-                           : Dc + ((long long)X * 9 + d) * NC * NC;
-      const Sd* Bt = B + (long long)16 * t * NC;
-      constexpr int XI = (16 * NC + 64 * MT - 1) / (64 * MT);
-      const int nx = nr * NC;
-      float2 xv[XI];
+    for (int d0 = d_begin; d0 < d_end; d0 += DP) {
+      const int nd = d_end - d0 < DP ? d_end - d0 : DP;   // uniform
+      float2 xv[DP][XI];
+      Sd av[DP][NS][4];
 #pragma unroll
-      for (int i = 0; i < XI; ++i) {
-        const int e = tid_site + 64 * MT * i, ec = e < nx ? e : nx - 1;
-        const int r = ec / NC, col = ec - r * NC;
-        xv[i] = src[(long long)(r0 + r) * vstride + (long long)Y * NC + col];
-      }
-      // this wave's rows: K-step s, slot v -> tiled column group ks = 4 s + v at this lane's lk
-      Sd av[NS][4];
+      for (int q = 0; q < DP; ++q) {
+        if (q >= nd) break;
+        const int d = d0 + q;
+        const int Y = d == 0 ? X : __builtin_amdgcn_readfirstlane(g.blk_nbr[(d - 1) * g.Vc + X] & DD_SLOT_MASK);
+        const float2* xsrc = (d == 0 ? xs : xh) + (long long)r0 * vstride + (long long)Y * NC;
+        const Sd* B = d == 0 ? (use_inv ? Minv + (long long)(X - g.Vch) * NC * NC : Dc + (long long)X * 9 * NC * NC)
+                             : Dc + ((long long)X * 9 + d) * NC * NC;
+        const Sd* Bt = B + 16 * t * NC;
 #pragma unroll
-      for (int st = 0; st < NS; ++st)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int ks = 4 * st + v;
-          if (ks < KS) av[st][v] = Bt[((long long)((ks / P) * 4 + lk) * RT + (row_ok ? li : 0)) * P + ks % P];
+        for (int i = 0; i < XI; ++i) {
+          const int e = tid_site + 64 * MT * i, ec = e < nx ? e : nx - 1;
+          const int r = ec / NC, col = ec - r * NC;
+          xv[q][i] = xsrc[(unsigned)(r * (int)vstride + col)];   // < 16 * Vc * NC elements
         }
+        // this wave's rows: K-step s, slot v -> tiled column group ks = 4 s + v at this lane's lk
 #pragma unroll
-      for (int i = 0; i < XI; ++i) {
-        const int e = tid_site + 64 * MT * i;
-        if (e < nx) {
-          const int r = e / NC, col = e - r * NC;
-          const int ks = col >> 2, cl = col & 3;
-          xc[s_in][buf][ks >> 2][cl][r][ks & 3] = H::from_f32(sc * xv[i].x);
-          xd[s_in][buf][ks >> 2][cl][r][ks & 3] = H::from_f32(sc * xv[i].y);
+        for (int st = 0; st < NS; ++st)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ks = 4 * st + v;
+            if (ks < KS) av[q][st][v] = Bt[(unsigned)((((ks / P) * 4 + lk) * RT + (row_ok ? li : 0)) * P + ks % P)];
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < DP; ++q) {
+        if (q >= nd) break;
+        const float sc = d0 + q == 0 ? a_self : a_hop;
+#pragma unroll
+        for (int i = 0; i < XI; ++i) {
+          const int e = tid_site + 64 * MT * i;
+          if (e < nx) {
+            const int r = e / NC, col = e - r * NC;
+            const int ks = col >> 2, cl = col & 3;
+            xc[s_in][buf][q][ks >> 2][cl][r][ks & 3] = H::from_f32(sc * xv[q][i].x);
+            xd[s_in][buf][q][ks >> 2][cl][r][ks & 3] = H::from_f32(sc * xv[q][i].y);
+          }
         }
       }
       __syncthreads();
 #pragma unroll
-      for (int st = 0; st < NS; ++st) {
-        vec a, b;
+      for (int q = 0; q < DP; ++q) {
+        if (q >= nd) break;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          elem re = H::from_f32(0.f), im = H::from_f32(0.f);
-          if (4 * st + v < KS && row_ok) H::split(av[st][v], re, im);
-          a[v] = re;
-          b[v] = im;
+        for (int st = 0; st < NS; ++st) {
+          vec a, b;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            elem re = H::from_f32(0.f), im = H::from_f32(0.f);
+            if (4 * st + v < KS && row_ok) H::split(av[q][st][v], re, im);
+            a[v] = re;
+            b[v] = im;
+          }
+          vec c = *reinterpret_cast<const vec*>(&xc[s_in][buf][q][st][lk][li][0]);
+          vec dd = *reinterpret_cast<const vec*>(&xd[s_in][buf][q][st][lk][li][0]);
+          if (!rhs_ok) {
+            c = vec{};
+            dd = vec{};
+          }
+          k1 = H::mfma(a, c, k1);
+          k2 = H::mfma(b, dd, k2);
+          k3 = H::mfma(a, dd, k3);
+          k4 = H::mfma(b, c, k4);
         }
-        vec c = *reinterpret_cast<const vec*>(&xc[s_in][buf][st][lk][li][0]);
-        vec dd = *reinterpret_cast<const vec*>(&xd[s_in][buf][st][lk][li][0]);
-        if (!rhs_ok) {
-          c = vec{};
-          dd = vec{};
-        }
-        k1 = H::mfma(a, c, k1);
-        k2 = H::mfma(b, dd, k2);
-        k3 = H::mfma(a, dd, k3);
-        k4 = H::mfma(b, c, k4);
       }
       buf ^= 1;
     }
