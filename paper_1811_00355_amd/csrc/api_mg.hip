@@ -472,11 +472,17 @@ static dd_status build(dd_mg* mg, hipStream_t st) {
       dd_free(mg->ctx, stage, sizeof(float2) * len);
     }
   }
-  // Galerkin operator from the stored P and the FP64 operator
+  // Galerkin operator from the stored P and the FP64 operator.  W holds `chunk`
+  // FP64 fine vectors (columns of D_c built per pass over P): as many as fit in
+  // 4 GiB, or in half of the budget still free up to 32 GiB, whichever is larger,
+  // rounded down to whole 16-column passes of the restriction.  Every column is
+  // computed on its own, so the chunk changes the number of passes, not the result.
   const long long vbytes = 12LL * G.V * (long long)sizeof(double2);
-  int chunk = (int)((4LL << 30) / vbytes);
+  const size_t free_b = mg->ctx->budget > mg->ctx->in_use ? mg->ctx->budget - mg->ctx->in_use : 0;
+  const size_t wcap = std::max<size_t>(4ULL << 30, std::min<size_t>(free_b / 2, 32ULL << 30));
+  int chunk = (int)std::min<long long>((long long)(wcap / (size_t)vbytes), mg->nc);
+  if (chunk >= 16 && chunk < mg->nc) chunk -= chunk % 16;
   if (chunk < 1) chunk = 1;
-  if (chunk > mg->nc) chunk = mg->nc;
   double2* W = nullptr;
   if ((s = dd_alloc(mg->ctx, (void**)&W, (size_t)chunk * vbytes))) {
     dd_free(mg->ctx, dflag, sizeof(int));

@@ -13,6 +13,8 @@ CASES = {
     "asym": ((8, 4, 4, 8), (2, 2, 2, 4), 0.25, -0.2, 1.3, 17, 6),
     "b4": ((8, 8, 8, 16), (4, 4, 4, 4), 0.2, -0.1, 1.0, 23, 20),
 }
+# 2n = 48, the largest coarse block the matrix-core applies take (the 48^3x96 workload's n = 24)
+EXTRA = {"b4n24": ((8, 8, 8, 16), (4, 4, 4, 4), 0.2, -0.1, 1.0, 23, 24)}
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +30,7 @@ def _build(ctx, name, **pkw):
     from oracle.lattice import Lattice
     from oracle.dirac import WilsonClover
     from workloads import su3_field, gauss_vectors
-    L, blk, eps, m0, csw, seed, n = CASES[name]
+    L, blk, eps, m0, csw, seed, n = {**CASES, **EXTRA}[name]
     U = su3_field(L, eps, seed)
     lat = Lattice(L, blk)
     W = WilsonClover(U, lat, m0, csw)
@@ -430,8 +432,8 @@ def test_coarse_basis_half(ctx):
     assert all(h <= f + 2 for h, f in zip(its[1], its[0]))
 
 
-@pytest.mark.parametrize("store", [2, 3])
-def test_coarse_mfma_half(ctx, store):
+@pytest.mark.parametrize("store,name", [(2, "b4"), (3, "b4"), (3, "b4n24")])
+def test_coarse_mfma_half(ctx, store, name):
     """Half-precision coarse blocks on FP16 / BF16 matrix cores (coarse_mfma_half):
     x is rounded to the block type before the products, which accumulate in FP32.
     Against the oracle's stencil on the same rounded blocks the normwise error
@@ -442,7 +444,7 @@ def test_coarse_mfma_half(ctx, store):
     import _gpu
     from oracle import amg
     from workloads import gauss_vectors, gauss_spinor
-    d = _build(ctx, "b4", inner_dtype=1, store_dtype=store, init_sap_apps=2, setup_iters=2)
+    d = _build(ctx, name, inner_dtype=1, store_dtype=store, init_sap_apps=2, setup_iters=2)
     lat, mg, n = d["lat"], d["mg"], d["n"]
     d["g"].dd_gauge_set_tuning(2, 256, 4, coarse_half=1, coarse_mfma_half=1)
     # the library's D_c (its build is checked elsewhere), rounded as the half blocks are: FP64 -> FP32 -> half
@@ -452,7 +454,7 @@ def test_coarse_mfma_half(ctx, store):
     got = _coarse_roundtrip(mg, 1, nrhs, c, lambda i, o: mg.dd_coarse_apply(1, nrhs, i, o))
     errs = [_gpu.max_rel(got[r], amg.coarse_apply(lat, Dr, c[r])) for r in range(nrhs)]
     u = 2.0 ** -11 if store == 2 else 2.0 ** -8
-    print(f"store {store}: coarse apply on half matrix cores, max error {max(errs):.2e} (bar {4 * u:.1e})", flush=True)
+    print(f"{name} store {store}: coarse apply on half matrix cores, max error {max(errs):.2e} (bar {4 * u:.1e})", flush=True)
     assert max(errs) < 4 * u
     bs = gauss_spinor(lat.L, 3, 63)
     bd = _gpu.to_dev(bs.reshape(3, -1))
