@@ -44,8 +44,11 @@ def gauge_bytes(V, store_bytes=8, Vc=0):
 
 def setup_transient_bytes(V, Vc, n, coarse_m=60, inner_bytes=8, store_bytes=8):
     """Scratch that exists only while a setup runs: the V-cycle workspace for
-    the n test vectors, the coarse-build chunk (at most 4 GiB) and, for half
-    storage, the FP32 staging of P (at most 1 GiB)."""
+    the n test vectors, the coarse-build chunk and, for half storage, the FP32
+    staging of P (at most 1 GiB).  The chunk counted here is the least the
+    library takes (all columns, or 4 GiB of them); with more of the budget free
+    it takes up to half of that free part (at most 32 GiB), so admission on
+    this figure never sends a setup over the budget."""
     nc = 2 * n
     stage = min(1 << 30, 8 * 12 * V * n) if store_bytes == 4 else 0
     return (inner_bytes * 12 * V * n * 2 + inner_bytes * Vc * nc * n * (coarse_m + 8) +
