@@ -409,3 +409,24 @@ def test_solution_gauge_covariance(c1, c1_mg, c1_dense):
     kappa = np.linalg.cond(D)
     assert info["converged"]
     assert rel(xg, x @ np.swapaxes(Om, 1, 2)) <= kappa * 1e-10
+
+
+def test_sampled_aggregates_match_full():
+    """Gram-Schmidt, restriction and prolongation evaluated on a subset of the
+    aggregates (a lattice view holding only those aggregates' sites, as the
+    full-size GPU checks use it) equal the whole-lattice evaluation there."""
+    from types import SimpleNamespace
+    lat = Lattice((8, 8, 8, 16), (4, 4, 4, 4))
+    n = 20
+    tv = gauss_vectors(n, lat.V, 5).reshape(n, lat.V, 4, 3)
+    P = amg.gram_schmidt(lat, tv)
+    aggs = np.array([0, 3, 7, lat.Vc - 1])
+    k = len(aggs)
+    sites = lat.sites_of_agg[aggs].reshape(-1)
+    sub = SimpleNamespace(sites_of_agg=np.arange(k * lat.Bv).reshape(k, lat.Bv), Vc=k, Bv=lat.Bv, V=k * lat.Bv)
+    Ps = amg.gram_schmidt(sub, tv[:, sites])
+    assert np.array_equal(Ps, P[aggs])
+    f = gauss_spinor(lat.L, 1, 3)[0]
+    assert np.array_equal(amg.restrict(sub, Ps, f[sites]), amg.restrict(lat, P, f)[aggs])
+    c = gauss_vectors(1, lat.Vc, 4, ncomp=2 * n)[0]
+    assert np.array_equal(amg.prolong(sub, Ps, c[aggs]), amg.prolong(lat, P, c)[sites])
