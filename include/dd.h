@@ -183,7 +183,11 @@ dd_status dd_sap_smooth(dd_gauge* g, const dd_mg_params* p, dd_dtype dt, int nrh
  * caller's starting vectors (host, canonical complex128 [n][V][4][3]).  Both then
  * run init_sap_apps SAP solves, build (per-aggregate Gram-Schmidt in FP64, P,
  * D_c = P^dag D P, coarse odd-site inverses) and setup_iters adaptive
- * iterations lambda_i <- M lambda_i (Sec. 2). */
+ * iterations lambda_i <- M lambda_i (Sec. 2).  While D_c is built the setup
+ * holds a scratch of FP64 fine vectors, one per column of D_c built in a pass:
+ * all 2n columns or 4 GiB of them, or up to half of the budget then free (at
+ * most 32 GiB) when that is more.  DD_EBUDGET if even the first figure does
+ * not fit; nothing of the setup stays allocated then. */
 dd_status dd_setup(dd_gauge* g, const dd_mg_params* p, dd_mg** out);
 dd_status dd_setup_from_vectors(dd_gauge* g, const dd_mg_params* p, const double* tv_host,
                                 dd_mg** out);
