@@ -281,6 +281,9 @@ template <> struct HalfOp<bf16x2> {
 // instead of nine), which matters because one apply is a single round of
 // workgroups whose time is the chain of load latencies.  The directions are
 // still accumulated in order, so the result is that of one direction per phase.
+// With both directions' operands live the compiler would take about 164
+// registers (two waves per SIMD); the register budget is capped at four waves
+// per SIMD instead (the BF16 form then spills 12 bytes per lane).
 template <int NC, int S, typename Sd>
 __global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_mfma_h(
     GeomDev g, const Sd* __restrict__ Dc, const Sd* __restrict__ Minv, int use_inv, int nrhs, int site_begin,
