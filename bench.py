@@ -195,9 +195,31 @@ def fp64_single_rhs(B, g, cfg, b, args):
                 outer_iters_mean=round(float(np.mean(iters)), 2), seconds=round(elapsed, 3))
 
 
+def _roofline(kernel, ks, elapsed_ms_per_launch_set, args, store_name, sap_wpe):
+    """Roofline entry of one kernel from its kernel-timer record (algorithmic
+    bytes and flops per launch over the mean event-timed launch duration)."""
+    avg_ms = ks["ms"] / max(ks["launches"], 1)
+    gbs = ks["bytes"] / (ks["ms"] * 1e-3) / 1e9
+    tfs = ks["flops"] / (ks["ms"] * 1e-3) / 1e12
+    ai = ks["flops"] / max(ks["bytes"], 1.0)
+    if kernel in ALU_BOUND and ai > FP32_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS:
+        r = dict(bound="alu", achieved=round(tfs, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                 frac=round(tfs / FP32_PEAK_TFLOPS, 4), frac_of_nonpacked_peak=round(tfs / FP32_NONPACKED_TFLOPS, 4),
+                 algorithmic_flops_per_launch=round(ks["flops"] / max(ks["launches"], 1)))
+    else:
+        r = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4))
+    r.update(traffic=measured_traffic(kernel, args.config, store_name, sap_wpe), kernel=kernel,
+             algorithmic_bytes_per_launch=round(ks["bytes"] / max(ks["launches"], 1)),
+             hbm_GBs_algorithmic=round(gbs, 1), arithmetic_intensity=round(ai, 2),
+             avg_launch_ms=round(avg_ms, 4), launches=ks["launches"])
+    return r
+
+
 def measure(B, g, cfg, args, store_name, b):
-    """Setup with operands stored as `store_name`, autotune, warm up, then time
-    args.steps solves of the 12 sources (in calls of args.rhs_batch)."""
+    """Setup with operands stored as `store_name`, autotune, warm up, one
+    untimed step with every kernel timed (the breakdown, which names the
+    dominant kernel), then args.steps timed solves of the 12 sources (in calls
+    of args.rhs_batch) with only the dominant kernel bracketed by events."""
     import torch
     blk, n_vec = cfg["block"], cfg["n_vec"]
     nrhs = b.shape[0]
@@ -213,11 +235,11 @@ def measure(B, g, cfg, args, store_name, b):
     t_setup = time.perf_counter() - t0
     log(f"[bench] store {store_name}: setup {t_setup:.2f} s")
     mg.dd_mg_set_graphs(args.graphs)
-    if args.coarse_basis_half or args.coarse_mfma_half:
-        t = g.dd_gauge_get_tuning()
-        t["coarse_basis_half"] = args.coarse_basis_half
-        t["coarse_mfma_half"] = args.coarse_mfma_half
-        g.dd_gauge_set_tuning(**t)
+    half_store = store_name in ("f16", "bf16")
+    t = g.dd_gauge_get_tuning()
+    t.update(coarse_half=args.coarse_half if half_store else 0, coarse_basis_half=args.coarse_basis_half,
+             coarse_mfma_half=args.coarse_mfma_half if half_store else 0)
+    g.dd_gauge_set_tuning(**t)
     kb = min(args.rhs_batch, nrhs)
     tuning = None
     if args.autotune:
@@ -243,84 +265,76 @@ def measure(B, g, cfg, args, store_name, b):
         info = step()
         log(f"[bench] warmup {w}: outer iterations {[i['outer_iters'] for i in info]}")
 
+    # breakdown: one untimed step, graphs off so that every launch is seen, every kernel timed
+    mg.dd_mg_set_graphs(0)
     B.kernel_timer_enable("*")
+    binfo = step()
+    torch.cuda.synchronize()
+    kfull = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
+    B.kernel_timer_enable(None)
+    mg.dd_mg_set_graphs(args.graphs)
+    dom = max(kfull, key=lambda k: kfull[k]["ms"])
+    model_bytes = sum(v["bytes"] for v in kfull.values())
+    model_flops = sum(v["flops"] for v in kfull.values())
+    kernels = {k: dict(ms_per_step=round(v["ms"], 3), launches_per_step=v["launches"],
+                       GBs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
+               for k, v in sorted(kfull.items(), key=lambda kv: -kv[1]["ms"])}
+
+    # timed steps: only the dominant kernel carries events
+    B.kernel_timer_enable(dom)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
-    for s in range(args.steps):
+    for s_ in range(args.steps):
         ts = time.perf_counter()
         infos.append(step())
-        log(f"[bench] step {s}: {time.perf_counter() - ts:.3f} s, max relres "
+        log(f"[bench] step {s_}: {time.perf_counter() - ts:.3f} s, max relres "
             f"{max(i['true_relres'] for i in infos[-1]):.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-
-    # dominant kernel over the timed steps.  Launches replayed from graphs are not
-    # timed; then one more (untimed) step without graphs gives the full breakdown
-    kstats = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
+    kd = B.kernel_timer_read(dom)
     B.kernel_timer_enable(None)
-    kfull, nfull = kstats, args.steps
-    if args.graphs:
-        mg.dd_mg_set_graphs(0)
-        B.kernel_timer_enable("*")
-        step()
-        torch.cuda.synchronize()
-        kfull = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
-        B.kernel_timer_enable(None)
-        nfull = 1
-    dom = max(kfull, key=lambda k: kfull[k]["ms"] / nfull)
-    # the timed steps' own figures when they saw every launch of that kernel
-    all_seen = dom in kstats and kstats[dom]["launches"] == kfull[dom]["launches"] * args.steps // nfull
-    ks = kstats[dom] if all_seen else kfull[dom]
-    avg_ms = ks["ms"] / max(ks["launches"], 1)
-    gbs = ks["bytes"] / (ks["ms"] * 1e-3) / 1e9
-    tfs = ks["flops"] / (ks["ms"] * 1e-3) / 1e12
-    ai = ks["flops"] / max(ks["bytes"], 1.0)
-    if dom in ALU_BOUND and ai > FP32_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS:
-        roofline = dict(bound="alu", achieved=round(tfs, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                        frac=round(tfs / FP32_PEAK_TFLOPS, 4), frac_of_nonpacked_peak=round(tfs / FP32_NONPACKED_TFLOPS, 4),
-                        algorithmic_flops_per_launch=round(ks["flops"] / max(ks["launches"], 1)))
-    else:
-        roofline = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(gbs / HBM_PEAK_GBS, 4))
     sap_wpe = g.dd_gauge_get_tuning()["sap_wpe"]
-    roofline.update(traffic=measured_traffic(dom, args.config, store_name, sap_wpe), kernel=dom,
-                    algorithmic_bytes_per_launch=round(ks["bytes"] / max(ks["launches"], 1)),
-                    hbm_GBs_algorithmic=round(gbs, 1), arithmetic_intensity=round(ai, 2),
-                    avg_launch_ms=round(avg_ms, 4), launches=ks["launches"],
-                    share_of_step=round(ks["ms"] / (1e3 * elapsed * (1 if all_seen else nfull / args.steps)), 3),
-                    timed_in="timed steps" if all_seen else "one extra step without graphs")
-    achieved = gbs
-    kernels = {k: dict(ms_per_step=round(v["ms"] / nfull, 3), launches_per_step=v["launches"] // nfull,
-                       GBs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
-               for k, v in sorted(kfull.items(), key=lambda kv: -kv[1]["ms"])}
+    seen = kd["launches"] == kfull[dom]["launches"] * args.steps
+    roofline = _roofline(dom, kd if seen else kfull[dom], None, args, store_name, sap_wpe)
+    roofline.update(share_of_step=round((kd["ms"] if seen else kfull[dom]["ms"] * args.steps) / (1e3 * elapsed), 3),
+                    timed_in="timed steps" if seen else "the breakdown step (launches inside graphs)")
     outer = float(np.mean([i["outer_iters"] for inf in infos for i in inf]))
     coarse_per_vcycle = float(np.mean([sum(i["coarse_iters_total"] for i in inf[::kb]) /
                                        max(sum(max(i["outer_iters"] for i in inf[k0:k0 + kb])
                                                for k0 in range(0, nrhs, kb)), 1) for inf in infos]))
     value = nrhs * args.steps / elapsed
-    log(f"[bench] store {store_name}: {value:.2f} solves/s; dominant kernel {dom}: {achieved:.0f} GB/s; "
-        f"kernels {kernels}")
-    fp32_coarse = None
-    if (args.coarse_basis_half or args.coarse_mfma_half) and not args.no_fp32_coarse:
-        # the same setup with the coarse GMRES basis and coarse products in FP32, same step count
+    V = int(np.prod(cfg["L"]))
+    # whole-step model (the breakdown step's launches): algorithmic bytes and flops of every kernel
+    step_model = dict(GB=round(model_bytes / 1e9, 2), GFLOP=round(model_flops / 1e9, 1),
+                      mflop_per_site_per_solve=round(model_flops / (V * nrhs) / 1e6, 2),
+                      hbm_frac_of_step=round(model_bytes / (elapsed / args.steps) / (HBM_PEAK_GBS * 1e9), 4),
+                      info_flops_model=int(binfo[0]["flops_model"]), info_bytes_model=int(binfo[0]["bytes_model"]))
+    log(f"[bench] store {store_name}: {value:.2f} solves/s; dominant kernel {dom}: {roofline}; kernels {kernels}")
+    log(f"[bench] step model {step_model}")
+    half_coarse = None
+    if half_store and not args.no_half_coarse and not (args.coarse_half and args.coarse_mfma_half and args.coarse_basis_half):
+        # the same setup with half-precision coarse blocks on half matrix cores and an FP16 coarse basis
         t = g.dd_gauge_get_tuning()
-        g.dd_gauge_set_tuning(**dict(t, coarse_basis_half=0, coarse_mfma_half=0))
+        g.dd_gauge_set_tuning(**dict(t, coarse_half=1, coarse_basis_half=1, coarse_mfma_half=1))
+        if args.autotune:
+            mg.dd_autotune(kb, args.tune_cache)
         step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        inf32 = [step() for _ in range(args.steps)]
+        infh = [step() for _ in range(args.steps)]
         torch.cuda.synchronize()
-        el32 = time.perf_counter() - t0
+        elh = time.perf_counter() - t0
         g.dd_gauge_set_tuning(**t)
-        fp32_coarse = dict(value=round(nrhs * args.steps / el32, 3), ms_per_step=round(1e3 * el32 / args.steps, 2),
-                           outer_iters_mean=round(float(np.mean([i["outer_iters"] for inf in inf32 for i in inf])), 2),
-                           max_true_relres=float(max(i["true_relres"] for inf in inf32 for i in inf)))
-        log(f"[bench] store {store_name}, FP32 coarse basis and products: {fp32_coarse}")
+        half_coarse = dict(value=round(nrhs * args.steps / elh, 3), ms_per_step=round(1e3 * elh / args.steps, 2),
+                           coarse=f"{store_name} blocks on {store_name} matrix cores, f16 basis",
+                           outer_iters_mean=round(float(np.mean([i["outer_iters"] for inf in infh for i in inf])), 2),
+                           max_true_relres=float(max(i["true_relres"] for inf in infh for i in inf)))
+        log(f"[bench] store {store_name}, half-precision coarse arithmetic: {half_coarse}")
     mg.destroy()
     return dict(value=round(value, 3), ms_per_step=round(1e3 * elapsed / args.steps, 2), elapsed=elapsed,
                 setup_s=round(t_setup, 3), outer=round(outer, 2), coarse_per_vcycle=coarse_per_vcycle,
-                tuning=tuning, roofline=roofline, kernels=kernels, fp32_coarse=fp32_coarse)
+                tuning=tuning, roofline=roofline, kernels=kernels, half_coarse=half_coarse, step_model=step_model)
 
 
 def main():
@@ -343,12 +357,14 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="time the launch-shape candidates before the timed steps")
     ap.add_argument("--tune-cache", default=None, help="JSON cache of autotuner choices")
-    ap.add_argument("--coarse-basis-half", type=int, default=1, choices=[0, 1],
+    ap.add_argument("--coarse-half", type=int, default=0, choices=[0, 1],
+                    help="half-precision storage: keep the coarse blocks in that type (0: FP32 blocks)")
+    ap.add_argument("--coarse-basis-half", type=int, default=0, choices=[0, 1],
                     help="store the FP32 coarse GMRES basis in FP16")
-    ap.add_argument("--coarse-mfma-half", type=int, default=1, choices=[0, 1],
+    ap.add_argument("--coarse-mfma-half", type=int, default=0, choices=[0, 1],
                     help="half-precision coarse blocks on FP16/BF16 matrix cores (x rounded to that type)")
-    ap.add_argument("--no-fp32-coarse", action="store_true",
-                    help="skip the second timing with the coarse basis and products in FP32")
+    ap.add_argument("--no-half-coarse", action="store_true",
+                    help="skip the second timing with half-precision coarse blocks, products and basis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-single", action="store_true",
                     help="skip the 12 sequential FP64 single-RHS solves")
@@ -418,7 +434,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64 outer / f32 inner" + (f" ({stores[0]} coarse products, f32 accumulation)"
-                                            if args.coarse_mfma_half and stores[0] in ("f16", "bf16") else ""),
+                                            if args.coarse_mfma_half and args.coarse_half and stores[0] in ("f16", "bf16")
+                                            else " (f32 coarse blocks and products on matrix cores)"),
         "data": "synthetic (seeded SU(3) links, point sources)",
         "config": {"workload": f"{args.config}: {L[0]}^3x{L[3]} Wilson-clover, 12 point-source RHS "
                                f"(solve calls of {args.rhs_batch}), 2-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
@@ -426,14 +443,16 @@ def main():
                    "c_sw": cfg["c_sw"], "eps": cfg["eps"], "store_dtype": stores[0], "graphs": bool(args.graphs),
                    "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
                    "outer_cgs_passes": args.outer_cgs_passes,
+                   "coarse_blocks": stores[0] if args.coarse_half and stores[0] in ("f16", "bf16") else "f32",
                    "coarse_basis": "f16" if args.coarse_basis_half else "f32",
-                   "coarse_mfma_half": bool(args.coarse_mfma_half),
+                   "coarse_mfma_half": bool(args.coarse_mfma_half and args.coarse_half),
                    "outer_iters_mean": round(float(outer), 2),
                    "coarse_iters_per_vcycle": round(float(coarse_per_vcycle), 1),
                    "setup_s": r0["setup_s"],
                    "solves_per_s_incl_setup": round(nrhs / (r0["setup_s"] + elapsed / args.steps), 3),
                    "tuning": r0["tuning"],
-                   "fp32_coarse_arithmetic": r0["fp32_coarse"],
+                   "half_coarse_arithmetic": r0["half_coarse"],
+                   "step_model": r0["step_model"],
                    "other_stores": {st_: {k: r[k] for k in ("value", "ms_per_step", "setup_s", "outer")}
                                     for st_, r in zip(stores[1:], runs[1:])},
                    "parallelism": "1 GPU"},

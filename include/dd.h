@@ -106,6 +106,9 @@ typedef struct {
   int32_t outer_iters, restarts, coarse_iters_total, converged;
   double true_relres;          /* |b - D x| / |b| with the FP64 operator */
   double t_setup_s, t_solve_s;
+  /* algorithmic HBM bytes and flops of the whole call (all right-hand sides):
+   * the sum over its instrumented kernel launches of each launch's model
+   * (operands and vectors read once, outputs written once; useful flops) */
   int64_t bytes_model, flops_model;
 } dd_solve_info;
 
@@ -128,7 +131,8 @@ typedef struct {
                              take one 256-thread workgroup per block)                */
   int32_t coarse_spw;     /* coarse apply: target waves per workgroup, 2, 4 or 8 (sites per workgroup =
                              max(1, coarse_spw / ceil(2n / 16)), at most 4)          */
-  int32_t coarse_half;    /* half-precision setups: coarse blocks in FP16/BF16 (1) or FP32 (0) */
+  int32_t coarse_half;    /* half-precision setups: coarse blocks in FP16/BF16 (1) or FP32 (0);
+                             never changed by dd_autotune */
   int32_t coarse_basis_half; /* FP32 coarse GMRES: Krylov basis stored in FP16 (1) or FP32 (0);
                                 never changed by dd_autotune */
   int32_t coarse_mfma_half;  /* with half-precision coarse blocks (coarse_half = 1): multiply them on
@@ -206,6 +210,26 @@ dd_status dd_mg_set_graphs(dd_mg* mg, int enable);
  * the device. */
 dd_status dd_mg_release_workspace(dd_mg* mg);
 
+/* ---- device footprint --------------------------------------------------------------------
+ * The device bytes the library allocates for a problem shape and parameter set,
+ * for callers that admit work by HBM budget.  Host arithmetic only: nothing is
+ * allocated and no device is touched.
+ *   gauge_bytes     : dd_gauge_create plus the storage copies a setup with p adds
+ *                     (FP64 links, clover and inverse; FP32 copy; half copy; block tables)
+ *   setup_bytes     : what dd_setup keeps resident (P in FP64 and in the storage
+ *                     type, working vectors, D_c and odd-site inverses in FP64,
+ *                     FP32 and, for half storage, the half type)
+ *   scratch_bytes   : the most held on top of those two while dd_gauge_create or
+ *                     dd_setup runs, with the Galerkin build at its least column
+ *                     chunk (the build takes a larger chunk only out of half of
+ *                     the budget then free, so this figure is a sufficient margin)
+ *   workspace_bytes : the dd_solve workspace for nrhs right-hand sides
+ * DD_ESHAPE / DD_EINVAL as dd_gauge_create and dd_setup would return them. */
+typedef struct {
+  size_t gauge_bytes, setup_bytes, scratch_bytes, workspace_bytes;
+} dd_footprint;
+dd_status dd_footprint_bytes(const dd_problem* prob, const dd_mg_params* p, int nrhs, dd_footprint* out);
+
 /* ---- the paper's comparison solver -----------------------------------------------------
  * Sec. 4 "baseline": a mixed-precision nested BiCGstab whose single-precision
  * level is preconditioned by domain decomposition (SAP, N_SAP = 5).  The paper
@@ -234,15 +258,17 @@ dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, 
 
 /* ---- autotuner --------------------------------------------------------------------------
  * dd_autotune times every launch-shape candidate of the smoother (waves per
- * SIMD), the FP64 D apply (workgroup size) and the FP32 coarse stencil (sites
- * per workgroup; for half-precision setups also FP32 against half blocks) on
- * this setup's own operators and workspace for nrhs
- * right-hand sides, keeps the fastest in the gauge field (shared by every setup
- * on it) and returns a text report (report may be NULL).  cache_path (may be
- * NULL) names a JSON file of earlier choices keyed by device architecture,
- * lattice, block, n, nrhs and dtypes: a hit applies the stored choice without
- * timing; a miss times and rewrites the file.  Workspace vectors are
- * overwritten; caller data are not touched.
+ * SIMD), the FP64 D apply (workgroup size) and the coarse stencil on matrix
+ * cores (sites per workgroup, in the coarse block type the tuning already
+ * selects) on this setup's own operators and workspace for nrhs right-hand
+ * sides, keeps the fastest in the gauge field (shared by every setup on it)
+ * and returns a text report (report may be NULL).  The numerical choices
+ * coarse_half, coarse_basis_half and coarse_mfma_half are the caller's and are
+ * never changed.  cache_path (may be NULL) names a JSON file of earlier choices
+ * keyed by device architecture, lattice, block, n, nrhs, dtypes and coarse
+ * block type: a hit applies the stored launch shapes without timing; a miss
+ * times and rewrites the file.  Workspace vectors are overwritten; caller data
+ * are not touched.
  * dd_gauge_set_tuning / dd_gauge_get_tuning set or read the choice directly
  * (DD_EINVAL for a value outside the lists above). */
 dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report, size_t report_cap);

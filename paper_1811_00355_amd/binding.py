@@ -63,6 +63,11 @@ class dd_solve_info(ctypes.Structure):
                 ("flops_model", ctypes.c_int64)]
 
 
+class dd_footprint(ctypes.Structure):
+    _fields_ = [("gauge_bytes", ctypes.c_size_t), ("setup_bytes", ctypes.c_size_t),
+                ("scratch_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _S = ctypes.c_size_t
@@ -95,6 +100,8 @@ SIGNATURES = {
     "dd_solve_bicgstab": (_I, [_P, ctypes.POINTER(dd_bicgstab_params), _I, _P, _P, ctypes.c_double,
                                ctypes.POINTER(dd_solve_info), _P]),
     "dd_mg_release_workspace": (_I, [_P]),
+    "dd_footprint_bytes": (_I, [ctypes.POINTER(dd_problem), ctypes.POINTER(dd_mg_params), _I,
+                                ctypes.POINTER(dd_footprint)]),
     "dd_autotune": (_I, [_P, _I, ctypes.c_char_p, ctypes.c_char_p, _S]),
     "dd_gauge_set_tuning": (_I, [_P, ctypes.POINTER(dd_tuning)]),
     "dd_gauge_get_tuning": (_I, [_P, ctypes.POINTER(dd_tuning)]),
@@ -194,6 +201,18 @@ def bicgstab_params(**kw):
     for k, v in kw.items():
         setattr(p, k, v)
     return p
+
+
+def footprint(L, block, params, nrhs, bc_t=-1):
+    """Device bytes the library allocates for this shape (dd_footprint_bytes):
+    dict with gauge, setup, scratch and workspace figures.  Host arithmetic only."""
+    prob = dd_problem((ctypes.c_int32 * 4)(*L), (ctypes.c_int32 * 4)(*block), bc_t, 0.0, 1.0)
+    out = dd_footprint()
+    st = lib().dd_footprint_bytes(ctypes.byref(prob), ctypes.byref(params), nrhs, ctypes.byref(out))
+    if st:
+        raise DDError(st, f"dd_footprint_bytes(L={tuple(L)}, block={tuple(block)}, nrhs={nrhs})")
+    return dict(gauge=out.gauge_bytes, setup=out.setup_bytes, scratch=out.scratch_bytes,
+                workspace=out.workspace_bytes)
 
 
 def default_params(**kw):

@@ -80,7 +80,11 @@ struct Workspace {
   // half matrix cores, first iteration, length, ends cycle), i.e. every launch choice baked into a capture;
   // they hold this arena's addresses and die with it
   hipStream_t cap = nullptr;
-  std::map<std::array<int, 9>, hipGraphExec_t> graphs;
+  struct Captured {
+    hipGraphExec_t exec;
+    double bytes, flops;   // algorithmic work of the captured launches, added at every replay
+  };
+  std::map<std::array<int, 9>, Captured> graphs;
 };
 
 static dd_dtype inner_vt(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : DD_F32; }
@@ -88,13 +92,27 @@ static dd_dtype op_dtype(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ?
 static const void* P_inner(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? (const void*)mg->P64 : mg->Pst; }
 static dd_dtype P_inner_dt(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : mg->vstore; }
 
-static void carve_ws(Workspace& w, const dd_mg* mg, int nrhs, bool outer) {
+// Sizes that fix the workspace layout (also computed without a setup, for the
+// footprint query).
+struct WsShape {
+  long long V, Vc, Vch;
+  int nc;        // coarse components per site (2n)
+  int mc, m;     // coarse GMRES restart, outer FGMRES restart
+  dd_dtype vt;   // inner vector dtype
+};
+
+static WsShape ws_shape(const dd_mg* mg) {
+  const GeomDev& G = mg->g->geo;
+  return {G.V, G.Vc, G.Vch, mg->nc, mg->p.coarse_restart, mg->p.fgmres_restart, inner_vt(mg)};
+}
+
+static void carve_ws(Workspace& w, const WsShape& sh, int nrhs, bool outer) {
   Arena& a = w.arena;
-  const long long V = mg->g->geo.V;
+  const long long V = sh.V;
   const long long fine = 12LL * V * nrhs;
-  const long long coarse = (long long)mg->g->geo.Vc * mg->nc * nrhs;
-  const size_t vb = vector_pair_bytes(inner_vt(mg));
-  const int mc = mg->p.coarse_restart;
+  const long long coarse = sh.Vc * sh.nc * nrhs;
+  const size_t vb = vector_pair_bytes(sh.vt);
+  const int mc = sh.mc;
   w.vin = a.take<char>(fine * vb);
   w.xs = a.take<char>(fine * vb);
   w.cb = a.take<char>(coarse * vb);
@@ -108,13 +126,13 @@ static void carve_ws(Workspace& w, const dd_mg* mg, int nrhs, bool outer) {
   w.CV = a.take<char>((size_t)(mc + 1) * coarse * vb);
   w.ca.carve(a, nrhs, mc);
   int nblk = dots_blocks(12LL * V, nrhs);
-  int nblk_c = dots_blocks((long long)mg->g->geo.Vc * mg->nc, nrhs);
+  int nblk_c = dots_blocks(sh.Vc * sh.nc, nrhs);
   if (nblk_c > nblk) nblk = nblk_c;
   size_t np = (size_t)nrhs * 16 * nblk * 2;   // launch_dots: 16 vectors per launch
   // one-pass Gram-Schmidt: nv <= restart vectors over gs_blocks(count) tiles
-  size_t np_gs = (size_t)nrhs * mc * gs_blocks(mg->g->geo.Vch * (long long)mg->nc) * 2;
+  size_t np_gs = (size_t)nrhs * mc * gs_blocks(sh.Vch * (long long)sh.nc) * 2;
   if (outer) {
-    const size_t np_outer = (size_t)nrhs * mg->p.fgmres_restart * gs_blocks(12LL * V) * 2;
+    const size_t np_outer = (size_t)nrhs * sh.m * gs_blocks(12LL * V) * 2;
     if (np_outer > np_gs) np_gs = np_outer;
   }
   if (np_gs > np) np = np_gs;
@@ -122,7 +140,7 @@ static void carve_ws(Workspace& w, const dd_mg* mg, int nrhs, bool outer) {
   w.b64 = w.x64 = w.w64 = w.zt64 = w.V64 = nullptr;
   w.Z = nullptr;
   if (outer) {
-    const int m = mg->p.fgmres_restart;
+    const int m = sh.m;
     w.b64 = a.take<double2>(fine);
     w.x64 = a.take<double2>(fine);
     w.w64 = a.take<double2>(fine);
@@ -133,13 +151,21 @@ static void carve_ws(Workspace& w, const dd_mg* mg, int nrhs, bool outer) {
   }
 }
 
+// device bytes of the workspace for nrhs right-hand sides (the arena plus its alignment slack)
+static size_t ws_bytes(const WsShape& sh, int nrhs, bool outer) {
+  Workspace w;
+  w.arena.sizing = true;
+  carve_ws(w, sh, nrhs, outer);
+  return w.arena.used + 256;
+}
+
 static void free_ws(dd_mg* mg) {
   Workspace* w = mg->ws;
   if (!w) return;
   dd_free(mg->ctx, w->arena.base, w->arena.cap);
   if (w->hflags) (void)hipHostFree(w->hflags);
   if (w->hvals) (void)hipHostFree(w->hvals);
-  for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   if (w->cap) (void)hipStreamDestroy(w->cap);
   delete w;
   mg->ws = nullptr;
@@ -157,9 +183,8 @@ static dd_status ensure_ws(dd_mg* mg, int nrhs, bool outer) {
   w->nrhs = nrhs;
   w->outer = outer;
   w->arena.ctx = mg->ctx;
-  w->arena.sizing = true;
-  carve_ws(*w, mg, nrhs, outer);
-  size_t bytes = w->arena.used + 256;
+  const WsShape sh = ws_shape(mg);
+  const size_t bytes = ws_bytes(sh, nrhs, outer);
   dd_status st = dd_alloc(mg->ctx, (void**)&w->arena.base, bytes);
   if (st) {
     delete w;
@@ -170,7 +195,7 @@ static dd_status ensure_ws(dd_mg* mg, int nrhs, bool outer) {
   // start from finite values everywhere (Krylov bases are read up to the longest cycle)
   (void)hipMemset(w->arena.base, 0, bytes);
   w->arena.used = 0;
-  carve_ws(*w, mg, nrhs, outer);
+  carve_ws(*w, sh, nrhs, outer);
   if (hipHostMalloc((void**)&w->hflags, sizeof(int) * 2 * nrhs) != hipSuccess ||
       hipHostMalloc((void**)&w->hvals, sizeof(double) * 3 * nrhs) != hipSuccess) {
     mg->ws = w;
@@ -312,18 +337,23 @@ static dd_status run_chunk(dd_mg* mg, const CoarseOps& c, int nrhs, long long ce
   if (it == w->graphs.end()) {
     if (!w->cap) DD_HIP(mg->ctx, hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
     DD_HIP(mg->ctx, hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
+    double b0, f0, b1, f1;
+    ktimer_model(&b0, &f0);
     ktimer_suspend(true);
     issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, CV, j0, len, ends, w->cap);
     ktimer_suspend(false);
+    ktimer_model(&b1, &f1);
+    ktimer_model_set(b0, f0);   // capturing executes nothing; the replay below accounts for it
     hipGraph_t gr = nullptr;
     DD_HIP(mg->ctx, hipStreamEndCapture(w->cap, &gr));
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
     if (e != hipSuccess) return dd_hip_check(mg->ctx, e, "hipGraphInstantiate (coarse GMRES chunk)");
-    it = w->graphs.emplace(key, ex).first;
+    it = w->graphs.emplace(key, Workspace::Captured{ex, b1 - b0, f1 - f0}).first;
   }
-  DD_HIP(mg->ctx, hipGraphLaunch(it->second, st));
+  DD_HIP(mg->ctx, hipGraphLaunch(it->second.exec, st));
+  ktimer_account(it->second.bytes, it->second.flops);
   return DD_OK;
 }
 
@@ -597,21 +627,19 @@ static dd_status setup_common(dd_gauge* g, const dd_mg_params* p, const double* 
   if ((s = ensure_ws(mg, mg->n, false))) return fail(s);
   const GeomDev& G = g->geo;
   const long long nfine = 12LL * G.V * mg->n;
-  // starting vectors, canonical FP64 -> packed working dtype (P64 is the staging buffer)
-  double2* canon = nullptr;
-  if ((s = dd_alloc(mg->ctx, (void**)&canon, sizeof(double2) * nfine))) return fail(s);
+  // starting vectors, canonical FP64 -> packed working dtype.  P64 (exactly n
+  // canonical FP64 fine vectors in size) is the staging buffer: build()
+  // overwrites it with the orthonormalised vectors, so the setup allocates no
+  // second copy.
+  double2* canon = mg->P64;
   if (tv_host) {
     hipError_t e = hipMemcpy(canon, tv_host, sizeof(double2) * nfine, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      dd_free(mg->ctx, canon, sizeof(double2) * nfine);
-      return fail(dd_hip_check(mg->ctx, e, "test vector upload"));
-    }
+    if (e != hipSuccess) return fail(dd_hip_check(mg->ctx, e, "test vector upload"));
   } else {
     launch_gauss(p->seed, nfine, canon, st);
   }
   launch_pack_fine(G, inner_vt(mg), mg->n, canon, mg->tv, st);
   hipError_t e = hipStreamSynchronize(st);
-  dd_free(mg->ctx, canon, sizeof(double2) * nfine);
   if (e != hipSuccess) return fail(dd_hip_check(mg->ctx, e, "starting vectors"));
   Workspace* w = mg->ws;
   const size_t fb = vector_pair_bytes(inner_vt(mg)) * (size_t)nfine;
@@ -647,7 +675,7 @@ static dd_status check_mg_vec(dd_mg* mg, dd_dtype dt, int nrhs, const void* a, c
 
 // ---------------------------------------------------------------------------
 // autotuner cache: a JSON object, one entry per line,
-//   "<device>|L=..|b=..|n=..|nrhs=..|op=..|inner=..":
+//   "<device>|L=..|b=..|n=..|nrhs=..|op=..|inner=..|cblk=..":
 //       {"sap_wpe": 2, "dirac_threads": 256, "coarse_spw": 4, "coarse_half": 0}
 // Lines that do not parse are dropped (the file is rewritten on the next miss).
 // ---------------------------------------------------------------------------
@@ -750,19 +778,24 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
     DD_HIP(mg->ctx, hipGetDeviceProperties(&prop, mg->ctx->device));
     static const char* dn[4] = {"f64", "f32", "f16", "bf16"};
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s|L=%dx%dx%dx%d|b=%dx%dx%dx%d|n=%d|nrhs=%d|op=%s|inner=%s",
+    // the coarse block type the caller chose is part of the key: the coarse launch shape is tuned for it
+    std::snprintf(buf, sizeof(buf), "%s|L=%dx%dx%dx%d|b=%dx%dx%dx%d|n=%d|nrhs=%d|op=%s|inner=%s|cblk=%s",
                   prop.gcnArchName, G.L[0], G.L[1], G.L[2], G.L[3], G.b[0], G.b[1], G.b[2], G.b[3], mg->n, nrhs,
-                  dn[op_dtype(mg)], dn[inner_vt(mg)]);
+                  dn[op_dtype(mg)], dn[inner_vt(mg)],
+                  (g->tune.coarse_half && mg->Dch) ? (g->tune.coarse_mfma_half ? "half-mfma" : "half") : "f32");
     key = buf;
   }
   std::map<std::string, Tuning> cache;
   if (cache_path) tune_cache_read(cache_path, cache);
   std::string rep = "key " + key + "\n";
   auto it = cache.find(key);
-  // numerical choices of the caller, not launch shapes
-  const int basis_half = g->tune.coarse_basis_half, mfma_half = g->tune.coarse_mfma_half;
+  // numerical choices of the caller (which coarse blocks, basis and products
+  // the solve uses), not launch shapes: kept on a hit and on a miss
+  const int coarse_half = g->tune.coarse_half, basis_half = g->tune.coarse_basis_half,
+            mfma_half = g->tune.coarse_mfma_half;
   if (it != cache.end()) {
     g->tune = it->second;
+    g->tune.coarse_half = coarse_half;
     g->tune.coarse_basis_half = basis_half;
     g->tune.coarse_mfma_half = mfma_half;
     rep += "cache hit\n";
@@ -811,40 +844,27 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
         if (t < bt) bt = t, best.dirac_threads = th;
       }
     }
-    // FP32 coarse stencil (matrix cores)
+    // coarse stencil on matrix cores, in the block type the caller chose
     if (vt == DD_F32) {
       float bt = 1e30f;
-      const int half_was = g->tune.coarse_half;
-      g->tune.coarse_half = 0;
       for (int spw : {2, 4, 8}) {
         float t = time_ms([&] {
           CoarseOps c = coarse_ops(mg, vt);
           launch_coarse_mv(G, vt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, G.Vc, 1.0, w->cb, 1.0, w->cb, 0.0, nullptr, w->cw,
                            st, spw, c.bt, c.hm);
         });
-        std::snprintf(line, sizeof(line), "k_coarse_mfma coarse_spw=%d %.3f ms\n", spw, t);
+        std::snprintf(line, sizeof(line), "k_coarse_mfma coarse_spw=%d%s %.3f ms\n", spw,
+                      g->tune.coarse_half && mg->Dch ? " (half blocks)" : "", t);
         rep += line;
         if (t < bt) bt = t, best.coarse_spw = spw;
-      }
-      g->tune.coarse_half = half_was;
-      if (mg->Dch) {
-        const Tuning keep = g->tune;
-        g->tune.coarse_spw = best.coarse_spw;
-        g->tune.coarse_half = 1;
-        CoarseOps c = coarse_ops(mg, vt);
-        float t = time_ms([&] {
-          launch_coarse_mv(G, vt, mg->nc, c.Dc, c.Dinv, 0, nrhs, 0, G.Vc, 1.0, w->cb, 1.0, w->cb, 0.0, nullptr, w->cw,
-                           st, best.coarse_spw, c.bt, c.hm);
-        });
-        g->tune = keep;
-        std::snprintf(line, sizeof(line), "k_coarse_mfma coarse_half=1 coarse_spw=%d %.3f ms\n", best.coarse_spw, t);
-        rep += line;
-        best.coarse_half = t < bt ? 1 : 0;
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     DD_HIP(mg->ctx, hipGetLastError());
+    best.coarse_half = coarse_half;
+    best.coarse_basis_half = basis_half;
+    best.coarse_mfma_half = mfma_half;
     g->tune = best;
     cache[key] = best;
     if (cache_path && !tune_cache_write(cache_path, cache))
@@ -858,6 +878,51 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
     std::strncpy(report, rep.c_str(), report_cap - 1);
     report[report_cap - 1] = 0;
   }
+  return DD_OK;
+}
+
+dd_status dd_footprint_bytes(const dd_problem* prob, const dd_mg_params* p, int nrhs, dd_footprint* out) {
+  if (!prob || !p || !out || nrhs < 1) return DD_EINVAL;
+  long long V = 1, Vc = 1;
+  for (int m = 0; m < 4; ++m) {
+    const int L = prob->L[m], b = prob->block[m];
+    if (b < 2 || (b & (b - 1)) || L < b || L % b || (L / b) % 2) return DD_ESHAPE;
+    if (p->agg_block[m] != b || p->sap_block[m] != b) return DD_ESHAPE;
+    V *= L;
+    Vc *= L / b;
+  }
+  if (p->n_vec % 2 || !supported_nvec(p->n_vec)) return DD_ESHAPE;
+  if (p->inner_dtype != DD_F64 && p->inner_dtype != DD_F32) return DD_EINVAL;
+  if ((int)p->store_dtype < 0 || (int)p->store_dtype > 3) return DD_EINVAL;
+  if ((p->inner_dtype == DD_F32) == (p->store_dtype == DD_F64)) return DD_EINVAL;
+  if (p->coarse_restart < 1 || p->fgmres_restart < 1) return DD_EINVAL;
+  const dd_dtype vt = p->inner_dtype == DD_F64 ? DD_F64 : DD_F32;
+  const dd_dtype st = vt == DD_F64 ? DD_F64 : p->store_dtype;
+  const long long n = p->n_vec, nc = 2 * n, nfine = 12 * V * n;
+  const size_t fpair = 108ULL * V;   // links, clover and inverse: 36 complex pairs each per site
+  // gauge: FP64 master, FP32 copy (also the source of half copies), half copy, block tables
+  size_t gauge = 16 * fpair + 40ULL * Vc;
+  if (st != DD_F64) gauge += 8 * fpair;
+  if (st == DD_F16 || st == DD_BF16) gauge += 4 * fpair;
+  // setup: P in FP64 and in the storage type, working vectors, D_c and inverses
+  const size_t blocks = (size_t)nc * nc * (9 * Vc + Vc / 2);
+  size_t setup = 16 * nfine + vector_pair_bytes(vt) * nfine + (st == DD_F64 ? 0 : storage_pair_bytes(st) * nfine) +
+                 (16 + 8) * blocks;
+  if (st == DD_F16 || st == DD_BF16) setup += 4 * blocks;
+  // scratch while a setup runs: the V-cycle workspace for the n vectors, the
+  // build's flag, then the FP32 staging of a half P or the Galerkin chunk
+  const WsShape sh{V, Vc, Vc / 2, (int)nc, p->coarse_restart, p->fgmres_restart, vt};
+  const long long vbytes = 12 * V * (long long)sizeof(double2);
+  long long chunk = std::min<long long>((long long)((4ULL << 30) / (size_t)vbytes), nc);
+  if (chunk >= 16 && chunk < nc) chunk -= chunk % 16;
+  if (chunk < 1) chunk = 1;
+  const size_t stage = (st == DD_F16 || st == DD_BF16) ? sizeof(float2) * (size_t)std::min<long long>(1LL << 27, nfine) : 0;
+  const size_t build = std::max<size_t>(stage, (size_t)chunk * vbytes);
+  const size_t upload = 16 * 36ULL * V;   // dd_gauge_create stages the canonical links
+  out->gauge_bytes = gauge;
+  out->setup_bytes = setup;
+  out->scratch_bytes = std::max<size_t>(upload, ws_bytes(sh, (int)n, false) + sizeof(int) + build);
+  out->workspace_bytes = ws_bytes(sh, nrhs, true);
   return DD_OK;
 }
 
@@ -992,6 +1057,8 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
   if (!b_canon || !x_canon || nrhs < 1 || !(tol > 0.0)) return dd_fail(mg->ctx, DD_EINVAL, "bad solve arguments");
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = (hipStream_t)stream;
+  double mb0, mf0;
+  ktimer_model(&mb0, &mf0);
   dd_status s = ensure_ws(mg, nrhs, true);
   if (s) return s;
   Workspace* w = mg->ws;
@@ -1085,6 +1152,8 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
   launch_unpack_fine(G, DD_F64, nrhs, w->x64, (double2*)x_canon, st);
   DD_HIP(mg->ctx, hipStreamSynchronize(st));
   double tsolve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  double mb1, mf1;
+  ktimer_model(&mb1, &mf1);
   bool all = true;
   for (int r = 0; r < nrhs; ++r) {
     all = all && fin[r];
@@ -1096,8 +1165,8 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
       info[r].true_relres = relres[r];
       info[r].t_setup_s = 0.0;
       info[r].t_solve_s = tsolve;
-      info[r].bytes_model = 0;
-      info[r].flops_model = 0;
+      info[r].bytes_model = (int64_t)(mb1 - mb0);
+      info[r].flops_model = (int64_t)(mf1 - mf0);
     }
   }
   if (!all) return dd_fail(mg->ctx, DD_ENOCONV, "max_outer_iters reached before every right-hand side converged");

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "dd_internal.h"
+#include "ktimer.h"
 
 namespace {
 
@@ -90,6 +91,8 @@ dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, 
     return dd_fail(ctx, DD_EINVAL, "the FP32 inner level takes FP32, FP16 or BF16 operands");
   DD_HIP(ctx, hipSetDevice(ctx->device));
   const auto t0 = std::chrono::steady_clock::now();
+  double mb0, mf0;
+  ktimer_model(&mb0, &mf0);
   hipStream_t st = (hipStream_t)stream;
   dd_status s = ensure_opset(g, od);
   if (s) return s;
@@ -250,6 +253,8 @@ dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, 
   launch_unpack_fine(G, DD_F64, nrhs, x64, (double2*)x_canon, st);
   DD_HIP(ctx, hipStreamSynchronize(st));
   const double tsolve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  double mb1, mf1;
+  ktimer_model(&mb1, &mf1);
   bool all = true;
   for (int q = 0; q < nrhs; ++q) {
     all = all && fin[q];
@@ -261,8 +266,8 @@ dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, 
       info[q].true_relres = relres[q];
       info[q].t_setup_s = 0.0;
       info[q].t_solve_s = tsolve;
-      info[q].bytes_model = 0;
-      info[q].flops_model = 0;
+      info[q].bytes_model = (int64_t)(mb1 - mb0);
+      info[q].flops_model = (int64_t)(mf1 - mf0);
     }
   }
   if (!all)

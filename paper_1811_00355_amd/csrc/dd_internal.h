@@ -307,9 +307,9 @@ struct Tuning {
   int sap_wpe = 2;          // SAP layout: 2 (registers, 2 waves per SIMD) or 3 (lean LDS, 3)
   int dirac_threads = 256;  // D apply workgroup size: 64, 128 or 256
   int coarse_spw = 4;       // FP32 coarse apply: coarse sites (waves) per workgroup, 2, 4 or 8
-  int coarse_half = 0;      // with half-precision storage: 1 = coarse blocks in that type, 0 = FP32 blocks
-  int coarse_basis_half = 0;
-  int coarse_mfma_half = 0;   // half-precision blocks: FP16 / BF16 MFMA with x rounded to that type  // FP32 coarse GMRES: Krylov basis stored in FP16 (1) or FP32 (0)
+  int coarse_half = 0;        // with half-precision storage: 1 = coarse blocks in that type, 0 = FP32 blocks
+  int coarse_basis_half = 0;  // FP32 coarse GMRES: Krylov basis stored in FP16 (1) or FP32 (0)
+  int coarse_mfma_half = 0;   // half-precision blocks: FP16 / BF16 MFMA with x rounded to that type
 };
 
 struct dd_gauge {

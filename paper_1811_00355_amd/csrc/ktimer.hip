@@ -2,6 +2,7 @@
 // every launch of that kernel is bracketed by a pair of HIP events recorded on
 // the launch stream, together with the launch's algorithmic bytes and flops.
 // dd_kernel_timer_read synchronises the recorded events and reports totals.
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -21,6 +22,7 @@ struct Timers {
   std::vector<hipEvent_t> pool;
   bool all = false;
   std::map<std::string, bool> on;
+  std::atomic<bool> any{false};   // some kernel is being timed (read without the lock)
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -40,15 +42,29 @@ Timers& T() {
 
 thread_local hipEvent_t t_start = nullptr;
 thread_local bool t_suspended = false;
+thread_local double t_model_bytes = 0.0, t_model_flops = 0.0;
 
 }  // namespace
 
 void ktimer_suspend(bool on) { t_suspended = on; }
 
+void ktimer_account(double bytes, double flops) {
+  t_model_bytes += bytes;
+  t_model_flops += flops;
+}
+void ktimer_model(double* bytes, double* flops) {
+  *bytes = t_model_bytes;
+  *flops = t_model_flops;
+}
+void ktimer_model_set(double bytes, double flops) {
+  t_model_bytes = bytes;
+  t_model_flops = flops;
+}
+
 bool ktimer_enabled(const char* tag) {
   if (t_suspended) return false;   // launches being captured into a graph are not timed
   Timers& t = T();
-  if (t.on.empty() && !t.all) return false;
+  if (!t.any.load(std::memory_order_acquire)) return false;
   std::lock_guard<std::mutex> g(t.mu);
   return t.all || t.on.count(tag);
 }
@@ -83,10 +99,12 @@ dd_status dd_kernel_timer_enable(const char* name) {
         t.pool.push_back(r.b);
       }
     t.recs.clear();
+    t.any.store(false, std::memory_order_release);
     return DD_OK;
   }
   if (std::strcmp(name, "*") == 0) t.all = true;
   else t.on[name] = true;
+  t.any.store(true, std::memory_order_release);
   return DD_OK;
 }
 

@@ -240,10 +240,12 @@ void run(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const
   int threads = ((g.Bvh + 63) / 64) * 64;
   unsigned nb = xcd_grid(g.Vch, nrhs);
   // per launch (one colour = half the sites): links, clover and odd-site inverse
-  // once, b and x read and x written per RHS
+  // once, b and x read and x written per RHS; useful flops per site and RHS
+  // (k + 2.5) operator applies of 1850 flops: the residual, k MR steps with
+  // their Schur products, and the source projection and odd reconstruction
   const double half = 0.5 * (double)g.V;
   const double bytes = half * (90.0 * sizeof(S) + 36.0 * sizeof(Tv) * nrhs);
-  const double flops = half * nrhs * (1824.0 + (mr + 2) * 1212.0);
+  const double flops = half * nrhs * (mr + 2.5) * 1850.0;
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour)
       DD_TIMED("k_sap_colour", st, bytes, flops,

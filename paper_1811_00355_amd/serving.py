@@ -31,46 +31,15 @@ import numpy as np
 
 
 # ----------------------------------------------------------------------------
-# footprint model (bytes), per site unless stated
+# footprint (bytes): the library reports what it allocates (dd_footprint_bytes)
 # ----------------------------------------------------------------------------
-def gauge_bytes(V, store_bytes=8, Vc=0):
-    """FP64 links, clover and clover inverse (3 x 36 complex pairs), plus their
-    copies in the storage type (same three fields); half-precision copies are
-    rounded from an FP32 copy, which stays resident too.  The block tables take
-    40 B per coarse site (8 neighbour slots, the packed coordinates, the slot of
-    each lexicographic block index)."""
-    return V * 3 * 36 * (16 + 8 + (store_bytes if store_bytes != 8 else 0)) + 40 * Vc
-
-
-def setup_transient_bytes(V, Vc, n, coarse_m=60, inner_bytes=8, store_bytes=8):
-    """Scratch that exists only while a setup runs: the V-cycle workspace for
-    the n test vectors, the coarse-build chunk and, for half storage, the FP32
-    staging of P (at most 1 GiB).  The chunk counted here is the least the
-    library takes (all columns, or 4 GiB of them); with more of the budget free
-    it takes up to half of that free part (at most 32 GiB), so admission on
-    this figure never sends a setup over the budget."""
-    nc = 2 * n
-    stage = min(1 << 30, 8 * 12 * V * n) if store_bytes == 4 else 0
-    return (inner_bytes * 12 * V * n * 2 + inner_bytes * Vc * nc * n * (coarse_m + 8) +
-            min(4 << 30, 16 * 12 * V * nc) + stage)
-
-
-def setup_bytes(V, Vc, n, store_bytes=8, inner_bytes=8):
-    """FP64 P, working vectors (inner type), stored P, coarse operator and
-    odd-site inverses in FP64 and FP32 (and in the storage type when it is a
-    half type)."""
-    nc = 2 * n
-    fine = 12 * V * n
-    half = store_bytes if store_bytes != 8 else 0     # half storage keeps a half copy of D_c too
-    return (16 + inner_bytes + store_bytes) * fine + (16 + 8 + half) * Vc * nc * nc * (9 + 0.5)
-
-
-def workspace_bytes(V, Vc, n, nrhs, m=10, coarse_m=60, inner_bytes=8):
-    """FGMRES(m) in FP64 (m+1 basis, b, x, w, z), preconditioned directions in
-    the inner type, V-cycle and coarse GMRES vectors."""
-    fine = 12 * V * nrhs
-    coarse = Vc * 2 * n * nrhs
-    return 16 * fine * (m + 5) + inner_bytes * fine * (m + 2) + inner_bytes * coarse * (coarse_m + 8)
+def library_footprint(L, block, n_vec, store, nrhs):
+    """Device bytes for one field on the mixed-precision path: the field plus its
+    resident setup, the scratch a setup holds while it runs, and the solve
+    workspace for nrhs right-hand sides, as the library computes them."""
+    from . import binding as B
+    p = B.default_params(block=block, n_vec=n_vec, inner_dtype=B.DD_F32, store_dtype=store)
+    return B.footprint(L, block, p, nrhs)
 
 
 # ----------------------------------------------------------------------------
@@ -263,7 +232,6 @@ class GpuExecutor:
         self.block = tuple(block)
         self.n = n_vec
         self.store = B.DTYPES[store]
-        self.store_bytes = {B.DD_F32: 8, B.DD_F16: 4, B.DD_BF16: 4}[self.store]
         self.c_sw = c_sw
         self.setup_iters = setup_iters
         self.tol = tol
@@ -272,27 +240,34 @@ class GpuExecutor:
         self.keep_x = False           # keep each request's solution (host) in self.results
         self.results = {}
 
-    def _Vc(self, f):
-        return int(np.prod([f.L[m] // self.block[m] for m in range(4)]))
+    def _fp(self, f, nrhs=1):
+        return library_footprint(f.L, self.block, self.n, self.store, nrhs)
 
     def footprint(self, f):
-        return gauge_bytes(f.V, self.store_bytes, self._Vc(f)) + setup_bytes(f.V, self._Vc(f), self.n, self.store_bytes)
+        fp = self._fp(f)
+        return fp["gauge"] + fp["setup"]
 
     def transient(self, f):
-        return setup_transient_bytes(f.V, self._Vc(f), self.n, store_bytes=self.store_bytes)
+        return self._fp(f)["scratch"]
 
     def workspace(self, f, nrhs):
-        return workspace_bytes(f.V, self._Vc(f), self.n, nrhs)
+        return self._fp(f, nrhs)["workspace"]
 
     def load(self, f):
         B = self.B
         g = B.Gauge(self.ctx, f.L, self.block, self.links[f.key], f.m0, self.c_sw)
         p = B.default_params(block=self.block, n_vec=self.n, setup_iters=self.setup_iters, inner_dtype=B.DD_F32,
                              store_dtype=self.store, seed=f.seed)
-        mg = B.MG(g, p)
-        mg.dd_mg_set_graphs(self.graphs)
-        if self.tune_cache:
-            mg.dd_autotune(12, self.tune_cache)
+        try:
+            mg = B.MG(g, p)
+            mg.dd_mg_set_graphs(self.graphs)
+            if self.tune_cache:
+                mg.dd_autotune(12, self.tune_cache)
+        except Exception:
+            if "mg" in locals():
+                mg.destroy()
+            g.destroy()        # a failed setup leaves nothing resident
+            raise
         return (g, mg)
 
     def sources(self, f, r):

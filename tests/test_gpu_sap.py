@@ -66,3 +66,70 @@ def test_sap_parity(ctx, case, dtype):
         print(f"L={L} dtype={dtype} rhs={r}: SAP error {err:.2e}", flush=True)
         assert err < tol
     g.destroy()
+
+
+# The benchmark's smoother: 4^4 domains, N_SAP = 4 sweeps, 4 MR steps per domain
+# solve, 12 right-hand sides in one call, FP32 arithmetic on FP32 / FP16 / BF16
+# stored operands, under every launch layout the autotuner may pick.
+HALF_CASE = ((8, 8, 8, 16), (4, 4, 4, 4), 0.2, -0.1, 1.0, 23)
+SAP_LAYOUTS = [dict(sap_wpe=2), dict(sap_wpe=3)]
+CHECKED_RHS = (0, 7, 11)
+_ref_cache = {}
+
+
+def _stored_oracle(g, U, lat, m0, csw, dtype):
+    """The oracle's operator on exactly the operands the library stores for
+    `dtype`: links rounded to the storage type, clover and clover inverse as
+    exported (FP64) and rounded the way the library rounds them."""
+    import _gpu
+    from oracle.dirac import WilsonClover, chiral_blocks
+    a, ai = g.export_clover()
+    W = WilsonClover(_gpu.round_store(U, dtype), lat, m0, csw, A=_gpu.stored_clover_dense(a, dtype))
+    W.Ainv_blocks = chiral_blocks(_gpu.stored_clover_dense(ai, dtype))
+    return W
+
+
+@pytest.mark.parametrize("layout", SAP_LAYOUTS, ids=lambda t: "-".join(f"{k}{v}" for k, v in t.items()))
+@pytest.mark.parametrize("dtype", [1, 2, 3])
+def test_sap_parity_stored_12rhs(ctx, dtype, layout):
+    """SAP with nu = 4, k = 4 and 12 RHS against the oracle's SAP run on the
+    stored (rounded) operands with the same FP32-rounded inputs; bar 1e-5
+    (FP32 arithmetic).  RHS 0, 7 and 11 are compared (the others share the
+    launch, and batch invariance is tested on whole solves)."""
+    import torch
+    import _gpu
+    from paper_1811_00355_amd import Gauge, default_params
+    from oracle.lattice import Lattice
+    from oracle import amg
+    from workloads import su3_field, gauss_spinor
+    L, blk, eps, m0, csw, seed = HALF_CASE
+    U = su3_field(L, eps, seed)
+    lat = Lattice(L, blk)
+    g = Gauge(ctx, L, blk, U, m0, csw)
+    t = g.dd_gauge_get_tuning()
+    t.update(layout)
+    g.dd_gauge_set_tuning(**t)
+    nrhs, sweeps, mr = 12, 4, 4
+    b = _gpu.round_f32(gauss_spinor(L, nrhs, 91))
+    x0 = _gpu.round_f32(gauss_spinor(L, nrhs, 92) * 0.1)
+    p = default_params(block=blk, sap_sweeps=sweeps, sap_mr_iters=mr)
+    print(f"SAP dtype {dtype} layout {layout}: L={L} nrhs={nrhs} nu={sweeps} k={mr}", flush=True)
+    cb = _gpu.to_dev(b.reshape(nrhs, -1))
+    cx = _gpu.to_dev(x0.reshape(nrhs, -1))
+    pb = g.new_packed(dtype, nrhs)
+    px = g.new_packed(dtype, nrhs)
+    g.pack(dtype, nrhs, cb, pb)
+    g.pack(dtype, nrhs, cx, px)
+    g.dd_sap_smooth(p, dtype, nrhs, pb, px)
+    out = torch.zeros_like(cx)
+    g.unpack(dtype, nrhs, px, out)
+    torch.cuda.synchronize()
+    out = _gpu.to_host(out).reshape(b.shape)
+    if dtype not in _ref_cache:
+        W = _stored_oracle(g, U, lat, m0, csw, dtype)
+        _ref_cache[dtype] = {r: amg.sap(W, b[r], x0[r], sweeps, mr) for r in CHECKED_RHS}
+    for r in CHECKED_RHS:
+        err = _gpu.max_rel(out[r], _ref_cache[dtype][r])
+        print(f"  rhs {r}: SAP error vs oracle on stored operands {err:.2e}", flush=True)
+        assert err < 1e-5
+    g.destroy()

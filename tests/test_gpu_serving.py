@@ -39,3 +39,34 @@ def test_mixed_batches_equal_alone():
     for h, _ in srv.cache.values():
         ex.free(h)
     ctx.close()
+
+
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_reported_footprint_is_what_the_library_allocates(store):
+    """dd_footprint_bytes against the library's allocation counter: a context
+    whose budget is exactly gauge + setup + scratch runs the setup, the field
+    and setup then hold exactly gauge + setup bytes, and a solve adds exactly
+    the workspace figure (so admission on these figures never sees DD_EBUDGET)."""
+    import torch
+    from paper_1811_00355_amd import Context, Gauge, MG, binding as B
+    from paper_1811_00355_amd import serving as S
+    from workloads import su3_field, gauss_spinor
+    L, blk, n, nrhs = (8, 8, 8, 16), (4, 4, 4, 4), 20, 3
+    st = B.DTYPES[store]
+    fp = S.library_footprint(L, blk, n, st, nrhs)
+    print(f"store {store}: footprint {fp}", flush=True)
+    ctx = Context(0, hbm_budget_bytes=fp["gauge"] + fp["setup"] + max(fp["scratch"], fp["workspace"]))
+    g = Gauge(ctx, L, blk, su3_field(L, 0.2, 6201), -0.15, 1.0)
+    p = B.default_params(block=blk, n_vec=n, setup_iters=1, inner_dtype=B.DD_F32, store_dtype=st, seed=7)
+    mg = MG(g, p)
+    assert ctx.bytes_in_use() == fp["gauge"] + fp["setup"]
+    b = torch.from_numpy(gauss_spinor(L, nrhs, 5).reshape(nrhs, -1)).cuda()
+    x = torch.zeros_like(b)
+    info, _ = mg.dd_solve(nrhs, b, x, 1e-10)
+    torch.cuda.synchronize()
+    assert ctx.bytes_in_use() == fp["gauge"] + fp["setup"] + fp["workspace"]
+    assert all(i["converged"] for i in info)
+    mg.destroy()
+    g.destroy()
+    assert ctx.bytes_in_use() == 0
+    ctx.close()

@@ -130,11 +130,28 @@ def test_request_stream_statistics():
     assert all(r.arrival == 0.0 for r in closed)
 
 
-def test_footprint_model_matches_the_workspace_layout():
-    # 32^3x64, n = 20, 12 rhs: the FGMRES(10) + V-cycle workspace is about 100 GB
-    V, Vc = 32 ** 3 * 64, 8 ** 3 * 16
-    ws = S.workspace_bytes(V, Vc, 20, 12)
-    assert 90e9 < ws < 110e9
-    # FP64 + FP32 operator copies: 3 fields x 36 pairs x 24 B per site
-    assert S.gauge_bytes(V, 8) == V * 3 * 36 * 24
-    assert S.gauge_bytes(V, 4) == V * 3 * 36 * 28
+def test_library_footprint_figures():
+    """dd_footprint_bytes (host arithmetic, no device): the large terms of each
+    figure at 32^3x64, n = 20, against the layouts they count."""
+    import os
+    import pytest
+    from paper_1811_00355_amd import binding as B
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libdd.so not built")
+    L, blk, n = (32, 32, 32, 64), (4, 4, 4, 4), 20
+    V, Vc, nc = 32 ** 3 * 64, 8 ** 3 * 16, 40
+    for store, sb in ((B.DD_F32, 8), (B.DD_BF16, 4)):
+        fp = S.library_footprint(L, blk, n, store, 12)
+        # FP64 links/clover/inverse, FP32 copies, half copies, block tables
+        assert fp["gauge"] == V * 108 * (24 + (4 if sb == 4 else 0)) + 40 * Vc
+        # P FP64 + working FP32 + stored P; D_c and inverses (9.5 blocks) in FP64 + FP32 (+ half)
+        assert fp["setup"] == 12 * V * n * (16 + 8 + sb) + nc * nc * (9 * Vc + Vc // 2) * (24 + (4 if sb == 4 else 0))
+        # FGMRES(10) FP64 basis and vectors, FP32 directions, V-cycle and coarse GMRES(60) vectors
+        fine, coarse = 12 * V * 12, Vc * nc * 12
+        core = 16 * fine * 15 + 8 * fine * 12 + 8 * coarse * 68 + 8 * coarse
+        assert core < fp["workspace"] < core * 1.001
+        assert 90e9 < fp["workspace"] < 110e9
+        # while a setup runs: the V-cycle workspace for n vectors plus a 4 GiB Galerkin chunk at least
+        assert fp["scratch"] > 4 * 2 ** 30
+    with pytest.raises(B.DDError):
+        B.footprint((32, 32, 32, 60), blk, B.default_params(block=blk), 1)
