@@ -293,7 +293,8 @@ dd_status dd_prolong(dd_mg* mg, dd_dtype dt, int nrhs, const void* coarse_in, vo
                      void* stream);    /* Eq. 4 */
 dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out,
                           void* stream);   /* Eq. 2 stencil */
-/* approximate D_c^-1: even-odd GMRES to coarse_tol (or coarse_fixed_iters) */
+/* approximate D_c^-1: even-odd GMRES to coarse_tol (or coarse_fixed_iters).
+ * DD_F64 needs an all-FP64 setup (inner_dtype DD_F64); DD_F32 works on either. */
 dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out,
                           int* iters, void* stream);
 /* out = M in (Eq. 5), packed fine vectors of the inner dtype */

@@ -68,6 +68,13 @@ struct Workspace {
   // coarse vectors (inner dtype) and the coarse Krylov basis
   void *cb, *cy, *cr, *cw, *ct1, *ct2, *cres, *CV;
   void* cv32;   // FP32 copy of the current basis vector when the basis is stored in FP16
+  // storage type the coarse basis CV was last written in.  The basis kernels
+  // read every stored vector up to the longest cycle and weight the ones a
+  // masked right-hand side never wrote by zero, so those must hold finite
+  // values: FP32 words read as FP16 pairs need not be, hence CV is cleared
+  // when the basis type changes.
+  dd_dtype cv_type = DD_F32;
+  size_t cv_bytes = 0;
   Arnoldi ca;
   // outer solver
   double2 *b64, *x64, *w64, *zt64, *V64;
@@ -106,15 +113,17 @@ static WsShape ws_shape(const dd_mg* mg) {
   return {G.V, G.Vc, G.Vch, mg->nc, mg->p.coarse_restart, mg->p.fgmres_restart, inner_vt(mg)};
 }
 
-static void carve_ws(Workspace& w, const WsShape& sh, int nrhs, bool outer) {
+// fine = false: the coarse solve's part only (no fine V-cycle vectors, no
+// outer solver), for the allocation-free coarse solve.
+static void carve_ws(Workspace& w, const WsShape& sh, int nrhs, bool outer, bool fine_part = true) {
   Arena& a = w.arena;
   const long long V = sh.V;
   const long long fine = 12LL * V * nrhs;
   const long long coarse = sh.Vc * sh.nc * nrhs;
   const size_t vb = vector_pair_bytes(sh.vt);
   const int mc = sh.mc;
-  w.vin = a.take<char>(fine * vb);
-  w.xs = a.take<char>(fine * vb);
+  w.vin = fine_part ? a.take<char>(fine * vb) : nullptr;
+  w.xs = fine_part ? a.take<char>(fine * vb) : nullptr;
   w.cb = a.take<char>(coarse * vb);
   w.cy = a.take<char>(coarse * vb);
   w.cr = a.take<char>(coarse * vb);
@@ -123,9 +132,10 @@ static void carve_ws(Workspace& w, const WsShape& sh, int nrhs, bool outer) {
   w.ct2 = a.take<char>(coarse * vb);
   w.cres = a.take<char>(coarse * vb);
   w.cv32 = a.take<char>(coarse * sizeof(float2));
-  w.CV = a.take<char>((size_t)(mc + 1) * coarse * vb);
+  w.cv_bytes = (size_t)(mc + 1) * coarse * vb;
+  w.CV = a.take<char>(w.cv_bytes);
   w.ca.carve(a, nrhs, mc);
-  int nblk = dots_blocks(12LL * V, nrhs);
+  int nblk = fine_part ? dots_blocks(12LL * V, nrhs) : 1;
   int nblk_c = dots_blocks(sh.Vc * sh.nc, nrhs);
   if (nblk_c > nblk) nblk = nblk_c;
   size_t np = (size_t)nrhs * 16 * nblk * 2;   // launch_dots: 16 vectors per launch
@@ -322,13 +332,12 @@ static void issue_chunk(const CoarseOps& c, Workspace* w, Arnoldi& a, int passes
 
 // Run a chunk on `st`: directly, or by replaying its graph (captured on first use
 // on the workspace's own stream; capturing launches nothing).
-static dd_status run_chunk(dd_mg* mg, const CoarseOps& c, int nrhs, long long ce, long long ld, long long vs,
-                           int j0, int len, bool ends, hipStream_t st) {
-  Workspace* w = mg->ws;
+static dd_status run_chunk(dd_mg* mg, Workspace* w, bool graphs, const CoarseOps& c, int nrhs, long long ce,
+                           long long ld, long long vs, int j0, int len, bool ends, hipStream_t st) {
   Arnoldi& a = w->ca;
   char* CV = (char*)w->CV;
   const int passes = mg->p.coarse_cgs_passes;
-  if (!mg->use_graphs) {
+  if (!graphs) {
     issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, CV, j0, len, ends, st);
     return DD_OK;
   }
@@ -357,10 +366,30 @@ static dd_status run_chunk(dd_mg* mg, const CoarseOps& c, int nrhs, long long ce
   return DD_OK;
 }
 
-// y ~= D_c^-1 b by GMRES on the even-site Schur complement, then the odd sites.
-static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, void* y, int* iters_out,
-                              hipStream_t st) {
-  Workspace* w = mg->ws;
+// Host copies of per-RHS scalars: on the stack up to kHostRhs right-hand sides
+// (the allocation-free path stays within that), on the heap beyond.
+constexpr int kHostRhs = 64;
+template <typename T>
+struct HostArr {
+  T stack[kHostRhs];
+  std::vector<T> heap;
+  T* p;
+  explicit HostArr(int n, T v = T()) {
+    if (n > kHostRhs) {
+      heap.assign(n, v);
+      p = heap.data();
+    } else {
+      for (int i = 0; i < n; ++i) stack[i] = v;
+      p = stack;
+    }
+  }
+  T& operator[](int i) { return p[i]; }
+};
+
+// y ~= D_c^-1 b by GMRES on the even-site Schur complement, then the odd sites,
+// on workspace w (coarse part), chunks replayed from graphs when `graphs`.
+static dd_status coarse_solve(dd_mg* mg, Workspace* w, bool graphs, dd_dtype vt, int nrhs, const void* b, void* y,
+                              int* iters_out, hipStream_t st) {
   CoarseOps c = coarse_ops(mg, vt);
   const GeomDev& g = *c.g;
   const int nc = c.nc;
@@ -378,18 +407,22 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
   // tolerance: tol * |rhs'|
   norms2(w, vt, nrhs, ce, ld, w->cr, a.nrm2, st);
   {
-    std::vector<double2> n2(nrhs);
-    DD_HIP(mg->ctx, hipMemcpyAsync(n2.data(), a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
+    HostArr<double2> n2(nrhs);
+    HostArr<double> tl(nrhs);
+    HostArr<int> fin(nrhs, 0);
+    DD_HIP(mg->ctx, hipMemcpyAsync(n2.p, a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
     DD_HIP(mg->ctx, hipStreamSynchronize(st));
-    std::vector<double> tl(nrhs);
-    std::vector<int> fin(nrhs, 0);
     for (int r = 0; r < nrhs; ++r) tl[r] = tol * std::sqrt(n2[r].x);
-    DD_HIP(mg->ctx, hipMemcpyAsync(a.tolabs, tl.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(mg->ctx, hipMemcpyAsync(a.tolabs, tl.p, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.p, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
     DD_HIP(mg->ctx, hipStreamSynchronize(st));
   }
   const long long vs = (long long)nrhs * ld;   // basis stride
   char* CV = (char*)w->CV;
+  if (w->cv_type != c.basis) {
+    DD_HIP(mg->ctx, hipMemsetAsync(CV, 0, w->cv_bytes, st));
+    w->cv_type = c.basis;
+  }
   int iters = 0;
   while (iters < cap) {
     // r = rhs' - S y  (first cycle: y = 0)
@@ -410,7 +443,7 @@ static dd_status coarse_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, v
     for (int j = 0; j < mm;) {
       const int len = mm - j < 4 ? mm - j : 4;
       const bool ends = j + len == mm;
-      dd_status cs = run_chunk(mg, c, nrhs, ce, ld, vs, j, len, ends, st);
+      dd_status cs = run_chunk(mg, w, graphs, c, nrhs, ce, ld, vs, j, len, ends, st);
       if (cs) return cs;
       iters += len;
       j += len;
@@ -447,7 +480,7 @@ static dd_status vcycle(dd_mg* mg, int nrhs, const void* v, void* out, int* cite
   dd_dtype vt = inner_vt(mg);
   const GeomDev& g = mg->g->geo;
   launch_restrict(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, v, w->cb, st);
-  dd_status s = coarse_solve(mg, vt, nrhs, w->cb, w->cy, citers, st);
+  dd_status s = coarse_solve(mg, w, mg->use_graphs, vt, nrhs, w->cb, w->cy, citers, st);
   if (s) return s;
   launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, st);
   dd_dtype od = op_dtype(mg);
@@ -1000,8 +1033,10 @@ dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
 dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out, int* iters, void* stream) {
   dd_status s = check_mg_vec(mg, dt, nrhs, in, out);
   if (s) return s;
+  if (dt == DD_F64 && inner_vt(mg) != DD_F64)
+    return dd_fail(mg->ctx, DD_EINVAL, "an FP32 setup's workspace holds no FP64 coarse basis: use DD_F32");
   if ((s = ensure_ws(mg, nrhs, false))) return s;
-  return coarse_solve(mg, dt, nrhs, in, out, iters, (hipStream_t)stream);
+  return coarse_solve(mg, mg->ws, mg->use_graphs, dt, nrhs, in, out, iters, (hipStream_t)stream);
 }
 
 dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void* stream) {

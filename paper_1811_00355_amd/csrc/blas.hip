@@ -694,6 +694,7 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
     else
       dots_typed<float2, double2>(grid, st, nrhs, count, rs, Vi, n, vstride, w, partial, nblk);
     if (timed) ktimer_end("k_dots", st, bytes, flops);
+    ktimer_account(bytes, flops);
     k_reduce<<<nrhs * n, 256, 0, st>>>(n, nblk, partial, out, ldo, off + i0);
   }
 }
@@ -721,6 +722,7 @@ void launch_multi_axpy(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long
     else
       multi_axpy_typed<double2, float2>(grid, st, nrhs, count, rs, Vi, n, vstride, coef, ldc, coff + i0, sign, w);
     if (timed) ktimer_end("k_multi_axpy", st, bytes, flops);
+    ktimer_account(bytes, flops);
   }
 }
 

@@ -541,3 +541,38 @@ def test_restrict_prolong_inner(ctx, store, nrhs):
     print(f"store {store}, {nrhs} rhs: prolongation max error {max(errs):.2e}", flush=True)
     assert max(errs) < 1e-5
     _close(d)
+
+
+def test_switching_coarse_arithmetic_on_one_workspace(ctx):
+    """Regression: the FP16 coarse basis shares its buffer with the FP32 basis.
+    Solving with the FP32 basis and then, on the same setup and workspace, with
+    the FP16 basis and half-precision coarse products must still converge (the
+    basis kernels weight vectors a masked right-hand side never wrote by zero,
+    and FP32 words read as FP16 may be Inf or NaN, so the buffer is cleared when
+    the basis type changes); and back again.  An FP64 coarse solve on an FP32
+    setup is refused (its workspace holds no FP64 basis)."""
+    import torch
+    import _gpu
+    from paper_1811_00355_amd import DDError
+    from workloads import gauss_spinor
+    d = _build(ctx, "b4", inner_dtype=1, store_dtype=3, init_sap_apps=2, setup_iters=1)
+    lat, mg, g = d["lat"], d["mg"], d["g"]
+    nrhs = 12
+    bs = gauss_spinor(lat.L, nrhs, 64)
+    bs[3] *= 1e-3          # sources of different size converge at different coarse steps
+    bd = _gpu.to_dev(bs.reshape(nrhs, -1))
+    for half in (0, 1, 0):
+        g.dd_gauge_set_tuning(2, 256, 4, coarse_half=half, coarse_basis_half=half, coarse_mfma_half=half)
+        xd = torch.zeros_like(bd)
+        info, _ = mg.dd_solve(nrhs, bd, xd, 1e-10)
+        torch.cuda.synchronize()
+        x = _gpu.to_host(xd).reshape(bs.shape)
+        worst = max(np.linalg.norm(bs[r] - d["W"].apply(x[r])) / np.linalg.norm(bs[r]) for r in (0, 3, 11))
+        print(f"coarse half arithmetic {half}: iters {[i['outer_iters'] for i in info]}, "
+              f"oracle residual of rhs 0/3/11 <= {worst:.2e}", flush=True)
+        assert all(i["converged"] for i in info) and worst <= 1e-10
+    c = mg.new_coarse(0, 1)
+    with pytest.raises(DDError) as e:
+        mg.dd_coarse_solve(0, 1, c, mg.new_coarse(0, 1))
+    assert e.value.name == "DD_EINVAL"
+    _close(d)
