@@ -297,6 +297,20 @@ dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
  * DD_F64 needs an all-FP64 setup (inner_dtype DD_F64); DD_F32 works on either. */
 dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out,
                           int* iters, void* stream);
+/* dd_coarse_solve without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernels, same order and the same result as
+ * dd_coarse_solve with graphs off.  Its workspace (coarse vectors, Krylov basis,
+ * Arnoldi state, reduction partials) is carved from a static per-device scratch
+ * array of 128 MiB, held from library load to process exit and not counted
+ * against the context's budget; DD_EBUDGET when the call would need more
+ * (that is (coarse_restart + 9) coarse vectors of nrhs right-hand sides, plus
+ * small state), DD_EINVAL above 64 right-hand sides.  Every call on one GPU
+ * shares that array and clears it first: calls that overlap on one GPU (other
+ * host threads, other streams) race and must not be issued.  Synchronises
+ * `stream` before it returns. */
+dd_status dd_coarse_solve_noalloc(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out,
+                                  int* iters, void* stream);
 /* out = M in (Eq. 5), packed fine vectors of the inner dtype */
 dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void* stream);
 

@@ -109,6 +109,7 @@ SIGNATURES = {
     "dd_prolong": (_I, [_P, _I, _I, _P, _P, _P]),
     "dd_coarse_apply": (_I, [_P, _I, _I, _P, _P, _P]),
     "dd_coarse_solve": (_I, [_P, _I, _I, _P, _P, ctypes.POINTER(_I), _P]),
+    "dd_coarse_solve_noalloc": (_I, [_P, _I, _I, _P, _P, ctypes.POINTER(_I), _P]),
     "dd_precond_apply": (_I, [_P, _I, _P, _P, _P]),
     "dd_solve": (_I, [_P, _I, _P, _P, ctypes.c_double, ctypes.POINTER(dd_solve_info), _P]),
     "dd_export_maps": (_I, [_P, _P, _P, _P, _P]),
@@ -391,6 +392,13 @@ class MG:
         it = _I(0)
         self.ctx.check(self.ctx.lib.dd_coarse_solve(self.h, dtype, nrhs, _ptr(inp), _ptr(out), ctypes.byref(it),
                                                     _stream(stream)))
+        return it.value
+
+    def dd_coarse_solve_noalloc(self, dtype, nrhs, inp, out, stream=None):
+        """dd_coarse_solve on the library's static scratch (no device allocation)."""
+        it = _I(0)
+        self.ctx.check(self.ctx.lib.dd_coarse_solve_noalloc(self.h, dtype, nrhs, _ptr(inp), _ptr(out),
+                                                            ctypes.byref(it), _stream(stream)))
         return it.value
 
     def dd_precond_apply(self, nrhs, inp, out, stream=None):

@@ -2,8 +2,38 @@
 // vectors and the operator apply.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "dd_internal.h"
+
+// Static scratch for the allocation-free coarse solve (dd_coarse_solve_noalloc):
+// every GPU the library runs on holds its own copy of this array until the
+// process ends.  Host code never uses the array's name as a device address: the
+// per-device address comes from hipGetSymbolAddress, taken once per device, with
+// that device current, when the first context on it is created.
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `device`'s scratch array (device current on entry).
+static dd_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return DD_EDEVICE;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return DD_EDEVICE;
+    }
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return DD_OK;
+}
 
 static const char* kStatus[] = {"DD_OK",    "DD_EINVAL", "DD_ESHAPE", "DD_ENOMEM", "DD_EBUDGET",
                                 "DD_ENOCONV", "DD_ENAN", "DD_EDEVICE", "DD_ESTATE"};
@@ -58,10 +88,13 @@ dd_status dd_ctx_create(int device, size_t budget, dd_ctx** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DD_EDEVICE;
   if (hipSetDevice(device) != hipSuccess) return DD_EDEVICE;
+  void* scr = nullptr;
+  if (scratch_address(device, &scr) != DD_OK) scr = nullptr;   // only the allocation-free call needs it
   dd_ctx* c = new dd_ctx();
   c->device = device;
   c->budget = budget;
   c->in_use = 0;
+  c->scratch = scr;
   *out = c;
   return DD_OK;
 }

@@ -1039,6 +1039,53 @@ dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
   return coarse_solve(mg, mg->ws, mg->use_graphs, dt, nrhs, in, out, iters, (hipStream_t)stream);
 }
 
+dd_status dd_coarse_solve_noalloc(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out, int* iters,
+                                  void* stream) {
+  dd_status s = check_mg_vec(mg, dt, nrhs, in, out);
+  if (s) return s;
+  if (dt == DD_F64 && inner_vt(mg) != DD_F64)
+    return dd_fail(mg->ctx, DD_EINVAL, "an FP32 setup's coarse solve runs in DD_F32");
+  if (nrhs > kHostRhs)
+    return dd_fail(mg->ctx, DD_EINVAL, "the allocation-free coarse solve takes at most " + std::to_string(kHostRhs) +
+                                           " right-hand sides");
+  if (!mg->ctx->scratch) return dd_fail(mg->ctx, DD_EDEVICE, "no static scratch address on this device");
+  // the coarse part of the workspace, carved from the static scratch (a
+  // workspace of the call's own dtype, so its basis holds that dtype)
+  WsShape sh = ws_shape(mg);
+  sh.vt = dt;
+  Workspace w;
+  w.nrhs = nrhs;
+  w.arena.sizing = true;
+  carve_ws(w, sh, nrhs, false, false);
+  const size_t bytes = (w.arena.used + 255) & ~size_t(255);
+  if (bytes > kStaticScratchBytes)
+    return dd_fail(mg->ctx, DD_EBUDGET,
+                   "the allocation-free coarse solve needs " + std::to_string(bytes) + " bytes of scratch; the static "
+                   "array holds " + std::to_string(kStaticScratchBytes) + " (use fewer right-hand sides, a shorter "
+                   "coarse restart, or dd_coarse_solve)");
+  w.arena.base = (char*)mg->ctx->scratch;
+  w.arena.cap = kStaticScratchBytes;
+  w.arena.sizing = false;
+  w.arena.used = 0;
+  carve_ws(w, sh, nrhs, false, false);
+  // host mirrors of the per-RHS flags on the stack (no pinned allocation)
+  int hflags[2 * kHostRhs];
+  double hvals[3 * kHostRhs];
+  w.hflags = hflags;
+  w.hvals = hvals;
+  const hipStream_t st = (hipStream_t)stream;
+  // the array keeps the last call's contents: start from zeros (finite basis entries)
+  launch_zero(w.arena.base, bytes, st);
+  w.cv_type = coarse_ops(mg, dt).basis;
+  s = coarse_solve(mg, &w, false, dt, nrhs, in, out, iters, st);
+  const hipError_t e = hipStreamSynchronize(st);   // the host mirrors live in this frame
+  w.hflags = nullptr;
+  w.hvals = nullptr;
+  if (s) return s;
+  if (e != hipSuccess) return dd_hip_check(mg->ctx, e, "allocation-free coarse solve");
+  return DD_OK;
+}
+
 dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void* stream) {
   dd_status s = check_mg_vec(mg, inner_vt(mg), nrhs, in, out);
   if (s) return s;

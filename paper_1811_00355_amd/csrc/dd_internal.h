@@ -291,7 +291,12 @@ struct dd_ctx {
   size_t budget;
   size_t in_use;
   std::string last_error;
+  void* scratch = nullptr;   // device address of this device's static scratch array (allocation-free calls)
 };
+
+// Size of the static per-device scratch array that the allocation-free entry
+// point carves its workspace from (api_core.hip).
+constexpr size_t kStaticScratchBytes = 128ULL << 20;
 
 // Operand copies of one storage type (links, clover, clover inverse).
 struct OpSet {
