@@ -36,24 +36,29 @@ HBM_PEAK_GBS = 8000.0
 # the FP32 ridge (157.3 / 8 = 19.7 flop/byte) are rated against the FP32 peak ("alu").
 FP32_PEAK_TFLOPS = 157.3
 FP32_NONPACKED_TFLOPS = 78.6
-ALU_BOUND = {"k_sap_colour"}
+ALU_BOUND = {"k_sap_colour", "k_sap_dom"}
 TOL = 1e-10
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this workload
 # (scaled by the copy-kernel calibration: FETCH_SIZE x2.000, WRITE_SIZE x1.000; see
-# profiles/k_sap_colour_c3_pmc.md), per SAP layout (the autotuner's sap_wpe).  Reported
-# only while the kernel's sources are unchanged since the measurement.
-_SAP_SOURCES = ["paper_1811_00355_amd/csrc/sap.hip", "paper_1811_00355_amd/csrc/dslash.h",
-                "paper_1811_00355_amd/csrc/dd_internal.h"]
+# profiles/k_sap_dom_c3_pmc.md), per smoother layout.  Reported only while the
+# kernel's sources are unchanged since the measurement.
+_SAP_DOM_SOURCES = ["paper_1811_00355_amd/csrc/sap_dom.hip", "paper_1811_00355_amd/csrc/dslash.h",
+                    "paper_1811_00355_amd/csrc/dd_internal.h"]
 MEASURED_TRAFFIC = {
-    ("k_sap_colour", "C3", "bf16", 3): dict(bytes=16.679e9 + 1.208e9, sha="b0d98d7ad34e41a2", sources=_SAP_SOURCES),
-    ("k_sap_colour", "C3", "bf16", 2): dict(bytes=10.838e9 + 1.208e9, sha="b0d98d7ad34e41a2", sources=_SAP_SOURCES),
+    ("k_sap_dom", "C3", "bf16", "dom2"): dict(bytes=9.7993e9 + 1.2079e9, sha="4ab5373766a0b26b", sources=_SAP_DOM_SOURCES),
+    ("k_sap_dom", "C3", "bf16", "dom4"): dict(bytes=8.0544e9 + 1.2079e9, sha="4ab5373766a0b26b", sources=_SAP_DOM_SOURCES),
 }
 
 
-def measured_traffic(kernel, config, store, sap_wpe):
+def sap_layout(t):
+    """Name of the smoother layout a tuning selects: domD (domain-resident, D RHS per workgroup) or wpeW."""
+    return f"dom{t['sap_dom_rhs']}" if t.get("sap_dom_rhs") else f"wpe{t['sap_wpe']}"
+
+
+def measured_traffic(kernel, config, store, layout):
     import hashlib
-    m = MEASURED_TRAFFIC.get((kernel, config, store, sap_wpe))
+    m = MEASURED_TRAFFIC.get((kernel, config, store, layout))
     if m is None:
         return None
     h = hashlib.sha256()
@@ -67,12 +72,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, lat_shape, n_vec, gpu_outer_iters, gpu_coarse_iters_per_vcycle):
-    """Time the oracle, as it is, on a bounded sample: one outer FGMRES iteration
-    (FP64 operator apply + V-cycle with SAP(4) and the coarse even-odd GMRES) on
-    an 8^3x16 sub-volume with the workload's parameters, extrapolated to the full
-    lattice by the volume ratio and to a whole solve by the GPU's outer iteration
-    count."""
+def _oracle_sample(cfg, n_vec, coarse_iters, coarse_restart, budget_s):
+    """One worker of the CPU baseline: time outer FGMRES iterations (FP64
+    operator apply + V-cycle with SAP and the coarse even-odd GMRES) of the
+    oracle, as it is, on an 8^3x16 sub-volume with the workload's parameters,
+    on one core.  Returns seconds per iteration and the repetitions."""
     from threadpoolctl import threadpool_limits
     from oracle.lattice import Lattice
     from oracle.dirac import WilsonClover
@@ -84,25 +88,50 @@ def cpu_baseline(cfg, lat_shape, n_vec, gpu_outer_iters, gpu_coarse_iters_per_vc
         U = su3_field(L_s, cfg["eps"], cfg["gauge_seed"])
         W = WilsonClover(U, lat, cfg["m0"], cfg["c_sw"])
         tv = gauss_vectors(n_vec, lat.V, cfg["tv_seed"]).reshape(n_vec, lat.V, 4, 3)
-        coarse_iters = max(1, int(round(gpu_coarse_iters_per_vcycle)))
-        p = amg.MGParams(n_vec=n_vec, coarse_fixed_iters=coarse_iters, coarse_restart=min(30, coarse_iters))
+        p = amg.MGParams(n_vec=n_vec, coarse_fixed_iters=coarse_iters, coarse_restart=min(coarse_restart, coarse_iters))
         mg = amg.TwoLevel(W, tv, p)
         v = gauss_spinor(L_s, 1, 5)[0]
         t0 = time.perf_counter()
         reps = 0
         while True:
             z = mg.vcycle(v)
-            w = W.apply(z)
+            W.apply(z)
             reps += 1
-            if time.perf_counter() - t0 > 12.0 or reps >= 10:
+            if time.perf_counter() - t0 > budget_s or reps >= 10:
                 break
-        t_iter = (time.perf_counter() - t0) / reps
+        return (time.perf_counter() - t0) / reps, reps, lat.V
+
+
+def cpu_baseline(cfg, lat_shape, n_vec, gpu_outer_iters, gpu_coarse_iters_per_vcycle, coarse_restart):
+    """The oracle on the host's cores: one worker process per core (at most the
+    16 cores a one-GPU share has), each timing the bounded sample of
+    _oracle_sample; independent solves run side by side, so the host's rate is
+    workers / (time per solve), with time per solve = time per outer iteration
+    x the volume ratio to the full lattice x the GPU's outer iteration count
+    (an extrapolation, labelled as such)."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    coarse_iters = max(1, int(round(gpu_coarse_iters_per_vcycle)))
+    ctx = mp.get_context("spawn")      # fresh interpreters: nothing of this process's GPU state
+    with ctx.Pool(cores) as pool:
+        res = pool.starmap(_oracle_sample, [(cfg, n_vec, coarse_iters, coarse_restart, 12.0)] * cores)
+    t_iter = float(np.mean([r[0] for r in res]))
+    reps = int(sum(r[1] for r in res))
+    V_s = res[0][2]
     V_full = int(np.prod(lat_shape))
-    t_solve = t_iter * (V_full / lat.V) * gpu_outer_iters
-    return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
-                sample=(f"one outer FGMRES iteration (FP64 D + V-cycle: SAP 4x4, coarse GMRES {coarse_iters} its) "
-                        f"of the numpy oracle on an 8^3x16 sub-volume, {reps} reps, {t_iter:.2f} s/iteration; "
-                        f"scaled by volume x{V_full // lat.V} and {gpu_outer_iters:.1f} outer iterations per solve"))
+    t_solve = t_iter * (V_full / V_s) * gpu_outer_iters
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
+    except OSError:
+        pass
+    return dict(value=cores / t_solve, unit="solves/s", cores=cores, cpu_model=model, kind="oracle",
+                sample=(f"{cores} worker processes, one per core, each timing outer FGMRES iterations (FP64 D + "
+                        f"V-cycle: SAP 4x4, coarse GMRES {coarse_iters} its, restart {min(coarse_restart, coarse_iters)}) "
+                        f"of the numpy oracle on an 8^3x16 sub-volume ({reps} iterations in all, "
+                        f"{t_iter:.2f} s each); extrapolated by volume x{V_full // V_s} and {gpu_outer_iters:.1f} "
+                        f"outer iterations per solve"))
 
 
 def dapply_table(B, g, reps=20):
@@ -126,6 +155,43 @@ def dapply_table(B, g, reps=20):
         gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
         rows[name] = dict(ms=round(k["ms"] / k["launches"], 4), GBs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
         del src, dst
+    return rows
+
+
+def sap_table(B, g, cfg, store_name, reps=5, mr=4, layouts=("wpe2", "wpe3", "dom4")):
+    """SAP smoother alone on this lattice (12 RHS, N_SAP = 1 sweep per call, mr
+    MR steps per domain solve) in the given layouts: mean launch time and the
+    roofline figures from the kernel timer."""
+    import torch
+    dt = B.DTYPES[store_name]
+    nrhs = 12
+    p = B.default_params(block=cfg["block"], sap_sweeps=1, sap_mr_iters=mr)
+    b, x = g.new_packed(dt, nrhs), g.new_packed(dt, nrhs)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(77)
+    bf = b.view(torch.float32)            # packed FP32 vectors (the buffer is raw bytes)
+    bf.copy_(torch.randn(bf.shape, generator=gen, device="cuda", dtype=torch.float32))
+    rows = {}
+    t0 = g.dd_gauge_get_tuning()
+    all_layouts = {"wpe2": dict(sap_wpe=2, sap_dom_rhs=0), "wpe3": dict(sap_wpe=3, sap_dom_rhs=0),
+                   "dom4": dict(sap_dom_rhs=4), "dom2": dict(sap_dom_rhs=2)}
+    for name, lay in ((n, all_layouts[n]) for n in layouts):
+        g.dd_gauge_set_tuning(**dict(t0, **lay))
+        x.zero_()
+        g.dd_sap_smooth(p, dt, nrhs, b, x)
+        torch.cuda.synchronize()
+        B.kernel_timer_enable("*")
+        for _ in range(reps):
+            g.dd_sap_smooth(p, dt, nrhs, b, x)
+        torch.cuda.synchronize()
+        k = {n: B.kernel_timer_read(n) for n in B.kernel_timer_names()}
+        B.kernel_timer_enable(None)
+        (kn, ks), = k.items()
+        ms = ks["ms"] / ks["launches"]
+        rows[name] = dict(kernel=kn, ms=round(ms, 4), TFLOPs=round(ks["flops"] / (ks["ms"] * 1e-3) / 1e12, 2),
+                          frac=round(ks["flops"] / (ks["ms"] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4))
+        log(f"[bench] SAP {store_name} k={mr} {name}: {rows[name]}")
+    g.dd_gauge_set_tuning(**t0)
     return rows
 
 
@@ -195,7 +261,7 @@ def fp64_single_rhs(B, g, cfg, b, args):
                 outer_iters_mean=round(float(np.mean(iters)), 2), seconds=round(elapsed, 3))
 
 
-def _roofline(kernel, ks, elapsed_ms_per_launch_set, args, store_name, sap_wpe):
+def _roofline(kernel, ks, elapsed_ms_per_launch_set, args, store_name, layout):
     """Roofline entry of one kernel from its kernel-timer record (algorithmic
     bytes and flops per launch over the mean event-timed launch duration)."""
     avg_ms = ks["ms"] / max(ks["launches"], 1)
@@ -208,7 +274,7 @@ def _roofline(kernel, ks, elapsed_ms_per_launch_set, args, store_name, sap_wpe):
                  algorithmic_flops_per_launch=round(ks["flops"] / max(ks["launches"], 1)))
     else:
         r = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4))
-    r.update(traffic=measured_traffic(kernel, args.config, store_name, sap_wpe), kernel=kernel,
+    r.update(traffic=measured_traffic(kernel, args.config, store_name, layout), kernel=kernel,
              algorithmic_bytes_per_launch=round(ks["bytes"] / max(ks["launches"], 1)),
              hbm_GBs_algorithmic=round(gbs, 1), arithmetic_intensity=round(ai, 2),
              avg_launch_ms=round(avg_ms, 4), launches=ks["launches"])
@@ -294,9 +360,9 @@ def measure(B, g, cfg, args, store_name, b):
     elapsed = time.perf_counter() - t0
     kd = B.kernel_timer_read(dom)
     B.kernel_timer_enable(None)
-    sap_wpe = g.dd_gauge_get_tuning()["sap_wpe"]
+    layout = sap_layout(g.dd_gauge_get_tuning())
     seen = kd["launches"] == kfull[dom]["launches"] * args.steps
-    roofline = _roofline(dom, kd if seen else kfull[dom], None, args, store_name, sap_wpe)
+    roofline = _roofline(dom, kd if seen else kfull[dom], None, args, store_name, layout)
     roofline.update(share_of_step=round((kd["ms"] if seen else kfull[dom]["ms"] * args.steps) / (1e3 * elapsed), 3),
                     timed_in="timed steps" if seen else "the breakdown step (launches inside graphs)")
     outer = float(np.mean([i["outer_iters"] for inf in infos for i in inf]))
@@ -371,6 +437,9 @@ def main():
     ap.add_argument("--no-dapply", action="store_true", help="skip the D-apply bandwidth table")
     ap.add_argument("--dapply-only", action="store_true",
                     help="only prepare the gauge field and print the D-apply bandwidth table (for counter runs)")
+    ap.add_argument("--sap-only", action="store_true",
+                    help="only prepare the gauge field and time the SAP smoother in every layout (for counter runs)")
+    ap.add_argument("--sap-mr", default="4", help="--sap-only: comma list of MR step counts")
     ap.add_argument("--baseline-dd", action="store_true",
                     help="also time the paper's comparison solver (SAP-preconditioned BiCGstab) on the same sources")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -407,6 +476,16 @@ def main():
     ctx = B.Context(0, hbm_budget_bytes=270 << 30)
     g = B.Gauge(ctx, L, blk, U, cfg["m0"], cfg["c_sw"])
     del U
+    if args.sap_only:
+        rows = {}
+        for st_ in args.store.split(","):
+            for mr in (int(v) for v in args.sap_mr.split(",")):
+                lay = ("wpe2", "wpe3", "dom4", "dom2") if mr == 4 else ("dom4", "dom2")
+                rows[f"{st_}_k{mr}"] = sap_table(B, g, cfg, st_, mr=mr, layouts=lay)
+        print(json.dumps({"workload": args.config, "sap": rows}))
+        g.destroy()
+        ctx.close()
+        return
     if args.dapply_only:
         print(json.dumps({"workload": args.config, "dapply": dapply_table(B, g)}))
         g.destroy()
@@ -475,7 +554,8 @@ def main():
         log(f"[bench] FP64 single-RHS: {out['config']['fp64_single_rhs']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(cfg, L, n_vec, float(outer), float(coarse_per_vcycle))
+        out["cpu_baseline"] = cpu_baseline(cfg, L, n_vec, float(outer), float(coarse_per_vcycle),
+                                           args.coarse_restart)
     print(json.dumps(out), flush=True)
     g.destroy()
     ctx.close()

@@ -139,6 +139,12 @@ typedef struct {
                                 FP16 / BF16 matrix cores with x rounded to the same type and FP32
                                 accumulation (1), or convert them to FP32 (0); never changed by
                                 dd_autotune */
+  int32_t sap_dom_rhs;       /* SAP on 4^4 domains with FP16 / BF16 operands: one workgroup per domain,
+                                its operator staged in LDS once and shared by the right-hand sides,
+                                taken 2 at a time (links and inverse in LDS, two workgroups per CU) or
+                                4 at a time (clover in LDS too, one per CU); 0 = one workgroup per
+                                (domain, RHS) in layout sap_wpe.  Same arithmetic, rounding may differ
+                                in the last place. */
 } dd_tuning;
 
 /* ---- gauge field (field preparation) ---------------------------------------
@@ -258,7 +264,7 @@ dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, 
 
 /* ---- autotuner --------------------------------------------------------------------------
  * dd_autotune times every launch-shape candidate of the smoother (waves per
- * SIMD), the FP64 D apply (workgroup size) and the coarse stencil on matrix
+ * SIMD, domain-resident form), the FP64 D apply (workgroup size) and the coarse stencil on matrix
  * cores (sites per workgroup, in the coarse block type the tuning already
  * selects) on this setup's own operators and workspace for nrhs right-hand
  * sides, keeps the fastest in the gauge field (shared by every setup on it)

@@ -368,7 +368,7 @@ dd_status dd_sap_smooth(dd_gauge* g, const dd_mg_params* p, dd_dtype dt, int nrh
   if (p->sap_sweeps < 0 || p->sap_mr_iters < 0) return dd_fail(g->ctx, DD_EINVAL, "negative SAP iteration counts");
   if (b == x) return dd_fail(g->ctx, DD_EINVAL, "b and x must not alias");
   if ((st = ensure_opset(g, dt))) return st;
-  launch_sap(g->geo, dt, g->ops[dt], nrhs, p->sap_sweeps, p->sap_mr_iters, b, x, g->tune.sap_wpe,
+  launch_sap(g->geo, dt, g->ops[dt], nrhs, p->sap_sweeps, p->sap_mr_iters, b, x, g->tune.sap_wpe, g->tune.sap_dom_rhs,
              (hipStream_t)stream);
   DD_HIP(g->ctx, hipGetLastError());
   return DD_OK;

@@ -484,7 +484,8 @@ static dd_status vcycle(dd_mg* mg, int nrhs, const void* v, void* out, int* cite
   if (s) return s;
   launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, st);
   dd_dtype od = op_dtype(mg);
-  launch_sap(g, od, mg->g->ops[od], nrhs, mg->p.sap_sweeps, mg->p.sap_mr_iters, v, out, mg->g->tune.sap_wpe, st);
+  launch_sap(g, od, mg->g->ops[od], nrhs, mg->p.sap_sweeps, mg->p.sap_mr_iters, v, out, mg->g->tune.sap_wpe,
+             mg->g->tune.sap_dom_rhs, st);
   DD_HIP(mg->ctx, hipGetLastError());
   return DD_OK;
 }
@@ -680,7 +681,8 @@ static dd_status setup_common(dd_gauge* g, const dd_mg_params* p, const double* 
   for (int k = 0; k < p->init_sap_apps; ++k) {
     DD_HIP(mg->ctx, hipMemcpyAsync(w->vin, mg->tv, fb, hipMemcpyDeviceToDevice, st));
     DD_HIP(mg->ctx, hipMemsetAsync(mg->tv, 0, fb, st));
-    launch_sap(G, od, g->ops[od], mg->n, p->sap_sweeps, p->sap_mr_iters, w->vin, mg->tv, g->tune.sap_wpe, st);
+    launch_sap(G, od, g->ops[od], mg->n, p->sap_sweeps, p->sap_mr_iters, w->vin, mg->tv, g->tune.sap_wpe,
+               g->tune.sap_dom_rhs, st);
     normalize_vectors(mg, mg->tv, st);
   }
   if ((s = build(mg, st))) return fail(s);
@@ -709,7 +711,8 @@ static dd_status check_mg_vec(dd_mg* mg, dd_dtype dt, int nrhs, const void* a, c
 // ---------------------------------------------------------------------------
 // autotuner cache: a JSON object, one entry per line,
 //   "<device>|L=..|b=..|n=..|nrhs=..|op=..|inner=..|cblk=..":
-//       {"sap_wpe": 2, "dirac_threads": 256, "coarse_spw": 4, "coarse_half": 0}
+//       {"sap_wpe": 2, "sap_dom_rhs": 4, "dirac_threads": 256, "coarse_spw": 4}
+// (launch shapes only; the coarse arithmetic choices are the caller's and part of the key)
 // Lines that do not parse are dropped (the file is rewritten on the next miss).
 // ---------------------------------------------------------------------------
 static bool tune_field(const std::string& obj, const char* name, int& v) {
@@ -730,8 +733,8 @@ static void tune_cache_read(const char* path, std::map<std::string, Tuning>& out
     if (c == std::string::npos) continue;
     std::string obj = l.substr(o, c - o + 1);
     Tuning t;
-    if (tune_field(obj, "sap_wpe", t.sap_wpe) && tune_field(obj, "dirac_threads", t.dirac_threads) &&
-        tune_field(obj, "coarse_spw", t.coarse_spw) && tune_field(obj, "coarse_half", t.coarse_half))
+    if (tune_field(obj, "sap_wpe", t.sap_wpe) && tune_field(obj, "sap_dom_rhs", t.sap_dom_rhs) &&
+        tune_field(obj, "dirac_threads", t.dirac_threads) && tune_field(obj, "coarse_spw", t.coarse_spw))
       out[l.substr(a + 1, b - a - 1)] = t;
   }
   std::fclose(f);
@@ -744,9 +747,9 @@ static bool tune_cache_write(const char* path, const std::map<std::string, Tunin
   std::fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : m)
-    std::fprintf(f, " \"%s\": {\"sap_wpe\": %d, \"dirac_threads\": %d, \"coarse_spw\": %d, \"coarse_half\": %d}%s\n",
-                 kv.first.c_str(), kv.second.sap_wpe, kv.second.dirac_threads, kv.second.coarse_spw,
-                 kv.second.coarse_half, ++i < m.size() ? "," : "");
+    std::fprintf(f, " \"%s\": {\"sap_wpe\": %d, \"sap_dom_rhs\": %d, \"dirac_threads\": %d, \"coarse_spw\": %d}%s\n",
+                 kv.first.c_str(), kv.second.sap_wpe, kv.second.sap_dom_rhs, kv.second.dirac_threads,
+                 kv.second.coarse_spw, ++i < m.size() ? "," : "");
   std::fprintf(f, "}\n");
   bool ok = std::fclose(f) == 0;
   return ok && std::rename(tmp.c_str(), path) == 0;
@@ -774,14 +777,15 @@ dd_status dd_setup_update_mass(dd_mg* mg, double m0) {
 
 dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t) {
   if (!g || !t) return DD_EINVAL;
-  if ((t->sap_wpe != 2 && t->sap_wpe != 3) ||
+  if ((t->sap_wpe != 2 && t->sap_wpe != 3) || (t->sap_dom_rhs != 0 && t->sap_dom_rhs != 2 && t->sap_dom_rhs != 4) ||
       (t->dirac_threads != 64 && t->dirac_threads != 128 && t->dirac_threads != 256) ||
       (t->coarse_spw != 2 && t->coarse_spw != 4 && t->coarse_spw != 8) || (t->coarse_half != 0 && t->coarse_half != 1) ||
       (t->coarse_basis_half != 0 && t->coarse_basis_half != 1) || (t->coarse_mfma_half != 0 && t->coarse_mfma_half != 1))
     return dd_fail(g->ctx, DD_EINVAL,
-                   "tuning: sap_wpe 2|3, dirac_threads 64|128|256, coarse_spw 2|4|8, coarse_half 0|1, "
+                   "tuning: sap_wpe 2|3, sap_dom_rhs 0|2|4, dirac_threads 64|128|256, coarse_spw 2|4|8, coarse_half 0|1, "
                    "coarse_basis_half 0|1, coarse_mfma_half 0|1");
   g->tune.sap_wpe = t->sap_wpe;
+  g->tune.sap_dom_rhs = t->sap_dom_rhs;
   g->tune.dirac_threads = t->dirac_threads;
   g->tune.coarse_spw = t->coarse_spw;
   g->tune.coarse_half = t->coarse_half;
@@ -793,6 +797,7 @@ dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t) {
 dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t) {
   if (!g || !t) return DD_EINVAL;
   t->sap_wpe = g->tune.sap_wpe;
+  t->sap_dom_rhs = g->tune.sap_dom_rhs;
   t->dirac_threads = g->tune.dirac_threads;
   t->coarse_spw = g->tune.coarse_spw;
   t->coarse_half = g->tune.coarse_half;
@@ -857,14 +862,24 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
     char line[160];
     const dd_dtype od = op_dtype(mg), vt = inner_vt(mg);
     Tuning best = g->tune;
-    // SAP: one sweep over scratch vectors of the workspace
+    // SAP: one sweep over scratch vectors of the workspace; the per-RHS layouts,
+    // then (4^4 domains, half-precision operands) the domain-resident form
     if (od != DD_F64) {
       float bt = 1e30f;
+      best.sap_dom_rhs = 0;
       for (int wpe : {2, 3}) {
-        float t = time_ms([&] { launch_sap(G, od, g->ops[od], nrhs, 1, mg->p.sap_mr_iters, w->vin, w->xs, wpe, st); });
+        float t = time_ms([&] { launch_sap(G, od, g->ops[od], nrhs, 1, mg->p.sap_mr_iters, w->vin, w->xs, wpe, 0, st); });
         std::snprintf(line, sizeof(line), "k_sap_colour sap_wpe=%d %.3f ms/sweep\n", wpe, t);
         rep += line;
         if (t < bt) bt = t, best.sap_wpe = wpe;
+      }
+      if (sap_dom_supported(G, od)) {
+        for (int dr : {4, 2}) {
+          float t = time_ms([&] { launch_sap(G, od, g->ops[od], nrhs, 1, mg->p.sap_mr_iters, w->vin, w->xs, 2, dr, st); });
+          std::snprintf(line, sizeof(line), "k_sap_dom sap_dom_rhs=%d %.3f ms/sweep\n", dr, t);
+          rep += line;
+          if (t < bt) bt = t, best.sap_dom_rhs = dr;
+        }
       }
     }
     // FP64 D apply of the outer solver
@@ -904,8 +919,8 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
       rep += std::string("could not write ") + cache_path + "\n";
   }
   char line[128];
-  std::snprintf(line, sizeof(line), "chosen sap_wpe=%d dirac_threads=%d coarse_spw=%d coarse_half=%d\n",
-                g->tune.sap_wpe, g->tune.dirac_threads, g->tune.coarse_spw, g->tune.coarse_half);
+  std::snprintf(line, sizeof(line), "chosen sap_wpe=%d sap_dom_rhs=%d dirac_threads=%d coarse_spw=%d coarse_half=%d\n",
+                g->tune.sap_wpe, g->tune.sap_dom_rhs, g->tune.dirac_threads, g->tune.coarse_spw, g->tune.coarse_half);
   rep += line;
   if (report && report_cap) {
     std::strncpy(report, rep.c_str(), report_cap - 1);

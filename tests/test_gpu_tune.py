@@ -52,7 +52,7 @@ def test_tuning_choices_bit_identical(ctx, tmp_path):
     with pytest.raises(Exception):
         g.dd_gauge_set_tuning(2, 256, 4, coarse_mfma_half=2)
     chosen = g.dd_gauge_get_tuning()
-    numeric = ("coarse_basis_half", "coarse_mfma_half")   # the caller's numerical choices, not launch shapes
+    numeric = ("coarse_half", "coarse_basis_half", "coarse_mfma_half")   # the caller's numerical choices
     assert all(chosen[k] == 0 for k in numeric)
     launch = {k: v for k, v in chosen.items() if k not in numeric}
     data = json.loads(cache.read_text())
@@ -60,7 +60,8 @@ def test_tuning_choices_bit_identical(ctx, tmp_path):
     # the cache holds launch shapes only: the caller's numerical choices survive a hit
     g.dd_gauge_set_tuning(3, 64, 2, coarse_basis_half=1, coarse_mfma_half=1)
     rep2 = mg.dd_autotune(nrhs, str(cache))
-    assert "cache hit" in rep2 and g.dd_gauge_get_tuning() == dict(launch, coarse_basis_half=1, coarse_mfma_half=1)
+    assert "cache hit" in rep2 and g.dd_gauge_get_tuning() == dict(launch, coarse_half=0, coarse_basis_half=1,
+                                                                   coarse_mfma_half=1)
     g.dd_gauge_set_tuning(**launch)
     x = torch.zeros_like(bd)
     mg.dd_solve(nrhs, bd, x, 1e-10)

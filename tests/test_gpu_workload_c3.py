@@ -63,8 +63,8 @@ def _host_rhs(x0, r):
 
 
 def _bench_tuning(g):
-    # the benchmark's autotuned launch choices on this lattice, with its half-precision coarse options
-    g.dd_gauge_set_tuning(3, 256, 2, coarse_half=1, coarse_basis_half=1, coarse_mfma_half=1)
+    # the benchmark's launch choices on this lattice (domain-resident SAP, FP32 coarse blocks, basis and products)
+    g.dd_gauge_set_tuning(3, 256, 4, coarse_half=0, coarse_basis_half=0, coarse_mfma_half=0, sap_dom_rhs=2)
 
 
 @pytest.mark.parametrize("dtype", [0, 3])
