@@ -378,6 +378,22 @@ def measure(B, g, cfg, args, store_name, b):
                       info_flops_model=int(binfo[0]["flops_model"]), info_bytes_model=int(binfo[0]["bytes_model"]))
     log(f"[bench] store {store_name}: {value:.2f} solves/s; dominant kernel {dom}: {roofline}; kernels {kernels}")
     log(f"[bench] step model {step_model}")
+    whole_m = None
+    if args.graphs != 2 and not args.no_whole_m_graph:
+        # the same solves with all of M replayed from one graph per call (graph mode 2: no host
+        # synchronisation inside M, the coarse GMRES stopped on the device): bits and iterations equal
+        mg.dd_mg_set_graphs(2)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infw = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        elw = time.perf_counter() - t0
+        mg.dd_mg_set_graphs(args.graphs)
+        whole_m = dict(value=round(nrhs * args.steps / elw, 3), ms_per_step=round(1e3 * elw / args.steps, 2),
+                       outer_iters_mean=round(float(np.mean([i["outer_iters"] for inf in infw for i in inf])), 2),
+                       coarse_max_iters=args.coarse_max_iters)
+        log(f"[bench] store {store_name}, all of M from one graph: {whole_m}")
     half_coarse = None
     if half_store and not args.no_half_coarse and not (args.coarse_half and args.coarse_mfma_half and args.coarse_basis_half):
         # the same setup with half-precision coarse blocks on half matrix cores and an FP16 coarse basis
@@ -400,7 +416,8 @@ def measure(B, g, cfg, args, store_name, b):
     mg.destroy()
     return dict(value=round(value, 3), ms_per_step=round(1e3 * elapsed / args.steps, 2), elapsed=elapsed,
                 setup_s=round(t_setup, 3), outer=round(outer, 2), coarse_per_vcycle=coarse_per_vcycle,
-                tuning=tuning, roofline=roofline, kernels=kernels, half_coarse=half_coarse, step_model=step_model)
+                tuning=tuning, roofline=roofline, kernels=kernels, half_coarse=half_coarse, step_model=step_model,
+                whole_m=whole_m)
 
 
 def main():
@@ -418,8 +435,8 @@ def main():
     ap.add_argument("--coarse-cgs-passes", type=int, default=1)
     ap.add_argument("--outer-cgs-passes", type=int, default=1, choices=[1, 2],
                     help="classical Gram-Schmidt passes of the FP64 outer FGMRES")
-    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
-                    help="replay the coarse GMRES from captured HIP graphs")
+    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1, 2],
+                    help="0: launches; 1: coarse GMRES chunks replayed from HIP graphs; 2: all of M from one graph")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="time the launch-shape candidates before the timed steps")
     ap.add_argument("--tune-cache", default=None, help="JSON cache of autotuner choices")
@@ -429,6 +446,8 @@ def main():
                     help="store the FP32 coarse GMRES basis in FP16")
     ap.add_argument("--coarse-mfma-half", type=int, default=0, choices=[0, 1],
                     help="half-precision coarse blocks on FP16/BF16 matrix cores (x rounded to that type)")
+    ap.add_argument("--no-whole-m-graph", action="store_true",
+                    help="skip the timing with all of M replayed from one graph (graph mode 2)")
     ap.add_argument("--no-half-coarse", action="store_true",
                     help="skip the second timing with half-precision coarse blocks, products and basis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -519,7 +538,7 @@ def main():
         "config": {"workload": f"{args.config}: {L[0]}^3x{L[3]} Wilson-clover, 12 point-source RHS "
                                f"(solve calls of {args.rhs_batch}), 2-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
                    "lattice": list(L), "rhs": nrhs, "rhs_batch": args.rhs_batch, "m0": cfg["m0"],
-                   "c_sw": cfg["c_sw"], "eps": cfg["eps"], "store_dtype": stores[0], "graphs": bool(args.graphs),
+                   "c_sw": cfg["c_sw"], "eps": cfg["eps"], "store_dtype": stores[0], "graphs": args.graphs,
                    "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
                    "outer_cgs_passes": args.outer_cgs_passes,
                    "coarse_blocks": stores[0] if args.coarse_half and stores[0] in ("f16", "bf16") else "f32",
@@ -531,6 +550,7 @@ def main():
                    "solves_per_s_incl_setup": round(nrhs / (r0["setup_s"] + elapsed / args.steps), 3),
                    "tuning": r0["tuning"],
                    "half_coarse_arithmetic": r0["half_coarse"],
+                   "whole_m_graph": r0["whole_m"],
                    "step_model": r0["step_model"],
                    "other_stores": {st_: {k: r[k] for k in ("value", "ms_per_step", "setup_s", "outer")}
                                     for st_, r in zip(stores[1:], runs[1:])},

@@ -202,14 +202,24 @@ dd_status dd_setup(dd_gauge* g, const dd_mg_params* p, dd_mg** out);
 dd_status dd_setup_from_vectors(dd_gauge* g, const dd_mg_params* p, const double* tv_host,
                                 dd_mg** out);
 dd_status dd_mg_destroy(dd_mg* mg);
-/* Replay the coarse even-odd GMRES from captured HIP graphs (enable != 0) or
- * launch its kernels one by one (0, the default).  Between two host
- * convergence checks the solver runs four Arnoldi steps; each such chunk is
- * captured once per (nrhs, dtype, position in the restart cycle) and then
- * replayed.  Same kernels in the same order, so the results are bit-identical
- * either way.  Graphs hold workspace addresses and are dropped when the
- * workspace is reallocated.  Kernel timers do not see launches inside graphs. */
-dd_status dd_mg_set_graphs(dd_mg* mg, int enable);
+/* Graph mode of the preconditioner M (Eq. 5) inside dd_solve and dd_precond_apply:
+ *   0 (default): kernels launched one by one; the host checks the coarse GMRES
+ *      between chunks of four Arnoldi steps;
+ *   1: the same, each chunk captured once per (nrhs, dtype, position in the
+ *      restart cycle) and replayed;
+ *   2: all of M (restriction, coarse solve, prolongation, SAP) captured as one
+ *      graph per (nrhs, launch and arithmetic choices, input and output buffers)
+ *      and replayed, with no host synchronisation: the coarse GMRES decides on
+ *      the device which right-hand sides are still active, and the launches of
+ *      a step (or cycle) nobody needs return at once.  The graph holds
+ *      coarse_max_iters steps, so its cost grows with that cap even when the
+ *      solve converges early (an empty launch costs about 2 us).
+ * All three give bit-identical results (the masked right-hand sides are never
+ * written; mode 2 counts info.coarse_iters_total as the sum over cycles of the
+ * longest Arnoldi run).  Graphs hold workspace and buffer addresses and are
+ * dropped when the workspace is reallocated.  Kernel timers do not see
+ * launches inside graphs.  DD_EINVAL for another mode. */
+dd_status dd_mg_set_graphs(dd_mg* mg, int mode);
 /* Free the solver workspace of a setup (Krylov bases, scratch vectors and the
  * graphs captured on them); the next solve allocates it again.  For callers
  * that keep many setups resident and solve on one at a time.  Synchronises

@@ -360,8 +360,9 @@ class MG:
     def dd_mg_release_workspace(self):
         self.ctx.check(self.ctx.lib.dd_mg_release_workspace(self.h))
 
-    def dd_mg_set_graphs(self, enable):
-        self.ctx.check(self.ctx.lib.dd_mg_set_graphs(self.h, int(bool(enable))))
+    def dd_mg_set_graphs(self, mode):
+        """0: launches; 1: coarse GMRES chunks from graphs; 2: all of M from one graph (True means 1)."""
+        self.ctx.check(self.ctx.lib.dd_mg_set_graphs(self.h, int(mode)))
 
     def dd_setup_update_mass(self, m0):
         self.ctx.check(self.ctx.lib.dd_setup_update_mass(self.h, m0))

@@ -81,6 +81,7 @@ struct Workspace {
   void* Z;
   Arnoldi fa;
   double* partial;
+  int* citers = nullptr;   // coarse Arnoldi steps of the device-driven solves (whole-M graphs)
   int* hflags = nullptr;   // pinned host mirror: active[nrhs], kcyc[nrhs]
   double* hvals = nullptr; // pinned host mirror: est[nrhs], tolabs[nrhs], nrm[nrhs]
   // captured coarse GMRES chunks, keyed by (nrhs, dtype, basis dtype, block dtype, waves per workgroup,
@@ -92,6 +93,8 @@ struct Workspace {
     double bytes, flops;   // algorithmic work of the captured launches, added at every replay
   };
   std::map<std::array<int, 9>, Captured> graphs;
+  // whole preconditioner M captured per (nrhs, launch and arithmetic choices, input and output buffers)
+  std::map<std::array<long long, 12>, Captured> mgraphs;
 };
 
 static dd_dtype inner_vt(const dd_mg* mg) { return mg->p.inner_dtype == DD_F64 ? DD_F64 : DD_F32; }
@@ -147,6 +150,7 @@ static void carve_ws(Workspace& w, const WsShape& sh, int nrhs, bool outer, bool
   }
   if (np_gs > np) np = np_gs;
   w.partial = a.take<double>(np);
+  w.citers = a.take<int>(1);
   w.b64 = w.x64 = w.w64 = w.zt64 = w.V64 = nullptr;
   w.Z = nullptr;
   if (outer) {
@@ -176,6 +180,7 @@ static void free_ws(dd_mg* mg) {
   if (w->hflags) (void)hipHostFree(w->hflags);
   if (w->hvals) (void)hipHostFree(w->hvals);
   for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  for (auto& kv : w->mgraphs) (void)hipGraphExecDestroy(kv.second.exec);
   if (w->cap) (void)hipStreamDestroy(w->cap);
   delete w;
   mg->ws = nullptr;
@@ -480,7 +485,7 @@ static dd_status vcycle(dd_mg* mg, int nrhs, const void* v, void* out, int* cite
   dd_dtype vt = inner_vt(mg);
   const GeomDev& g = mg->g->geo;
   launch_restrict(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, v, w->cb, st);
-  dd_status s = coarse_solve(mg, w, mg->use_graphs, vt, nrhs, w->cb, w->cy, citers, st);
+  dd_status s = coarse_solve(mg, w, mg->graphs == 1, vt, nrhs, w->cb, w->cy, citers, st);
   if (s) return s;
   launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, st);
   dd_dtype od = op_dtype(mg);
@@ -488,6 +493,129 @@ static dd_status vcycle(dd_mg* mg, int nrhs, const void* v, void* out, int* cite
              mg->g->tune.sap_dom_rhs, st);
   DD_HIP(mg->ctx, hipGetLastError());
   return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// M without host round trips (graph mode 2): the coarse GMRES decides on the
+// device when each right-hand side is done.  The launches are those of
+// coarse_solve, in the same order, for a fixed number of steps (the iteration
+// cap, in cycles of the restart length from steps 0, m, 2m, ...); gates make a
+// step's kernels return at once when no right-hand side is active in it, and a
+// cycle's residual and update kernels when every right-hand side is finished.
+// A masked right-hand side is never written, the basis update runs over the
+// whole cycle with zero coefficients past a right-hand side's own steps, so the
+// result equals the host-checked solve bit for bit (the cycle boundaries differ
+// only after an exact breakdown of the Arnoldi process, h = 0, which the host
+// form would follow by a shorter cycle).
+// ---------------------------------------------------------------------------
+static void coarse_solve_device(dd_mg* mg, Workspace* w, dd_dtype vt, int nrhs, const void* b, void* y,
+                                hipStream_t st) {
+  CoarseOps c = coarse_ops(mg, vt);
+  const GeomDev& g = *c.g;
+  const int nc = c.nc;
+  const long long ld = (long long)g.Vc * nc, ce = (long long)g.Vch * nc;
+  const size_t vb = vector_pair_bytes(vt);
+  Arnoldi& a = w->ca;
+  const int m = a.m;
+  const bool fixed = mg->p.coarse_fixed_iters > 0;
+  const int cap = fixed ? mg->p.coarse_fixed_iters : mg->p.coarse_max_iters;
+  const double tol = fixed ? 0.0 : mg->p.coarse_tol;
+  const int passes = mg->p.coarse_cgs_passes;
+  const long long vs = (long long)nrhs * ld;
+  char* CV = (char*)w->CV;
+  // rhs' = b_e - D_eo D_oo^-1 b_o; y = 0; tolerance from |rhs'| (all on the device)
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st, c.spw, c.bt, c.hm);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st, c.spw, c.bt, c.hm);
+  launch_zero(y, (size_t)nrhs * ld * vb, st);
+  norms2(w, vt, nrhs, ce, ld, w->cr, a.nrm2, st);
+  launch_set_tol(nrhs, tol, a.nrm2, a.tolabs, a.finished, a.active, st);
+  const Gate unfinished{a.finished, nrhs, 0}, active{a.active, nrhs, 1};
+  for (int c0 = 0; c0 < cap; c0 += m) {
+    const int mm = cap - c0 < m ? cap - c0 : m;
+    {
+      GateScope gs(unfinished);
+      if (c0 == 0) {
+        launch_copy(vt, (long long)nrhs * ld, w->cr, w->cres, st);
+      } else {
+        schur_apply(c, nrhs, y, w->cw, w->ct1, w->ct2, st);
+        launch_sub(vt, (long long)nrhs * ld, w->cr, w->cw, w->cres, st);
+      }
+      norms2(w, vt, nrhs, ce, ld, w->cres, a.nrm2, st);
+      launch_cycle_init(nrhs, m, a.nrm2, a.tolabs, a.finished, a.gv, a.beta, a.active, a.kcyc, st);
+    }
+    {
+      GateScope ga(active);
+      launch_normalize(vt, nrhs, ce, ld, w->cres, nullptr, a.beta, a.active, CV, st, c.basis,
+                       c.basis == DD_F16 ? w->cv32 : nullptr);
+      issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, CV, 0, mm, true, st);
+    }
+    {
+      GateScope gs(unfinished);
+      launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
+      launch_multi_axpy(c.basis, vt, nrhs, ce, ld, CV, mm, vs, a.y, m, 0, 1.0, y, st);
+      launch_finish(nrhs, a.est, a.tolabs, a.finished, a.active, a.kcyc, w->citers, st);
+    }
+  }
+  // odd sites: y_o = D_oo^-1 (b_o - D_oe y_e)
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st, c.spw, c.bt, c.hm);
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st, c.spw, c.bt, c.hm);
+}
+
+// M v as one graph: restriction, the device-driven coarse solve, prolongation
+// and SAP, captured on first use per (nrhs, choices, buffers) and replayed.
+static dd_status vcycle_graph(dd_mg* mg, int nrhs, const void* v, void* out, hipStream_t st) {
+  Workspace* w = mg->ws;
+  const dd_dtype vt = inner_vt(mg);
+  const CoarseOps c = coarse_ops(mg, vt);
+  const Tuning& t = mg->g->tune;
+  const std::array<long long, 12> key = {nrhs, (long long)vt, (long long)c.basis, (long long)c.bt, c.spw, c.hm ? 1 : 0,
+                                         t.sap_wpe, t.sap_dom_rhs, (long long)(intptr_t)v, (long long)(intptr_t)out,
+                                         mg->p.coarse_max_iters, mg->p.coarse_fixed_iters};
+  auto it = w->mgraphs.find(key);
+  if (it == w->mgraphs.end()) {
+    if (w->cv_type != c.basis) {   // clear the basis outside the capture (no fill nodes recorded)
+      launch_zero(w->CV, w->cv_bytes, st);
+      w->cv_type = c.basis;
+    }
+    if (w->mgraphs.size() >= 64) {   // callers cycling through many buffers: start over
+      for (auto& kv : w->mgraphs) (void)hipGraphExecDestroy(kv.second.exec);
+      w->mgraphs.clear();
+    }
+    if (!w->cap) DD_HIP(mg->ctx, hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
+    DD_HIP(mg->ctx, hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
+    double b0, f0, b1, f1;
+    ktimer_model(&b0, &f0);
+    ktimer_suspend(true);
+    const GeomDev& g = mg->g->geo;
+    launch_restrict(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, v, w->cb, w->cap);
+    coarse_solve_device(mg, w, vt, nrhs, w->cb, w->cy, w->cap);
+    launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, w->cap);
+    const dd_dtype od = op_dtype(mg);
+    launch_sap(g, od, mg->g->ops[od], nrhs, mg->p.sap_sweeps, mg->p.sap_mr_iters, v, out, t.sap_wpe, t.sap_dom_rhs,
+               w->cap);
+    ktimer_suspend(false);
+    ktimer_model(&b1, &f1);
+    ktimer_model_set(b0, f0);
+    hipGraph_t gr = nullptr;
+    DD_HIP(mg->ctx, hipStreamEndCapture(w->cap, &gr));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return dd_hip_check(mg->ctx, e, "hipGraphInstantiate (preconditioner)");
+    it = w->mgraphs.emplace(key, Workspace::Captured{ex, b1 - b0, f1 - f0}).first;
+  }
+  DD_HIP(mg->ctx, hipGraphLaunch(it->second.exec, st));
+  ktimer_account(it->second.bytes, it->second.flops);
+  return DD_OK;
+}
+
+// M v in the mode the setup is in
+static dd_status apply_M(dd_mg* mg, int nrhs, const void* v, void* out, int* citers, hipStream_t st) {
+  if (mg->graphs == 2) {
+    if (citers) *citers = 0;   // counted on the device (Workspace::citers)
+    return vcycle_graph(mg, nrhs, v, out, st);
+  }
+  return vcycle(mg, nrhs, v, out, citers, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -981,9 +1109,10 @@ dd_status dd_mg_release_workspace(dd_mg* mg) {
   return DD_OK;
 }
 
-dd_status dd_mg_set_graphs(dd_mg* mg, int enable) {
+dd_status dd_mg_set_graphs(dd_mg* mg, int mode) {
   if (!mg) return DD_EINVAL;
-  mg->use_graphs = enable != 0;
+  if (mode < 0 || mode > 2) return dd_fail(mg->ctx, DD_EINVAL, "graph mode must be 0, 1 or 2");
+  mg->graphs = mode;
   return DD_OK;
 }
 
@@ -1051,7 +1180,7 @@ dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
   if (dt == DD_F64 && inner_vt(mg) != DD_F64)
     return dd_fail(mg->ctx, DD_EINVAL, "an FP32 setup's workspace holds no FP64 coarse basis: use DD_F32");
   if ((s = ensure_ws(mg, nrhs, false))) return s;
-  return coarse_solve(mg, mg->ws, mg->use_graphs, dt, nrhs, in, out, iters, (hipStream_t)stream);
+  return coarse_solve(mg, mg->ws, mg->graphs == 1, dt, nrhs, in, out, iters, (hipStream_t)stream);
 }
 
 dd_status dd_coarse_solve_noalloc(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out, int* iters,
@@ -1105,7 +1234,7 @@ dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void*
   dd_status s = check_mg_vec(mg, inner_vt(mg), nrhs, in, out);
   if (s) return s;
   if ((s = ensure_ws(mg, nrhs, false))) return s;
-  return vcycle(mg, nrhs, in, out, nullptr, (hipStream_t)stream);
+  return apply_M(mg, nrhs, in, out, nullptr, (hipStream_t)stream);
 }
 
 dd_status dd_export_coarse(const dd_mg* mg, double* dc_host) {
@@ -1169,6 +1298,7 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
   const long long vs64 = fine, vsz = fine;   // basis strides (entries)
   launch_pack_fine(G, DD_F64, nrhs, (const double2*)b_canon, w->b64, st);
   DD_HIP(mg->ctx, hipMemsetAsync(w->x64, 0, sizeof(double2) * fine, st));
+  if (mg->graphs == 2) launch_zero(w->citers, sizeof(int), st);   // coarse steps counted on the device
   // |b|, tolerance, non-finite check
   norms2(w, DD_F64, nrhs, cnt, cnt, w->b64, a.nrm2, st);
   std::vector<double2> n2(nrhs);
@@ -1220,10 +1350,10 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
       // z_j = M v_j in the inner precision
       int ci = 0;
       if (vt == DD_F64) {
-        if ((s = vcycle(mg, nrhs, Vj, Zj, &ci, st))) return s;
+        if ((s = apply_M(mg, nrhs, Vj, Zj, &ci, st))) return s;
         launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, Zj, w->w64, st, g->tune.dirac_threads);
       } else {
-        if ((s = vcycle(mg, nrhs, w->vin, Zj, &ci, st))) return s;
+        if ((s = apply_M(mg, nrhs, w->vin, Zj, &ci, st))) return s;
         launch_dirac_f32_in(G, g->ops[DD_F64], nrhs, (const float2*)Zj, w->w64, st, g->tune.dirac_threads);
       }
       total_coarse += ci;
@@ -1247,6 +1377,7 @@ dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, 
       }
   }
   launch_unpack_fine(G, DD_F64, nrhs, w->x64, (double2*)x_canon, st);
+  if (mg->graphs == 2) DD_HIP(mg->ctx, hipMemcpyAsync(&total_coarse, w->citers, sizeof(int), hipMemcpyDeviceToHost, st));
   DD_HIP(mg->ctx, hipStreamSynchronize(st));
   double tsolve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   double mb1, mf1;

@@ -31,7 +31,8 @@ constexpr int nv_unroll() { return NV >= 8 ? 1 : 8 / NV; }
 template <int NV, typename Tv, typename Tw>
 __global__ void __launch_bounds__(256) k_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V, int nv,
                                               long long vstride, const Tw* __restrict__ w, double* __restrict__ partial,
-                                              int nblk) {
+                                              int nblk, Gate gt) {
+  if (gate_closed(gt)) return;
   constexpr int U = nv_unroll<NV>();
   __shared__ double red[4][2 * NV];
   const int r = blockIdx.y, blk = blockIdx.x;
@@ -84,7 +85,8 @@ __global__ void __launch_bounds__(256) k_dots(int nrhs, long long count, long lo
 
 // out[r * ldo + off + i] = sum over blocks of partial[r][i][blk]
 __global__ void __launch_bounds__(256) k_reduce(int nv, int nblk, const double* __restrict__ partial,
-                                                double2* __restrict__ out, int ldo, int off) {
+                                                double2* __restrict__ out, int ldo, int off, Gate gt) {
+  if (gate_closed(gt)) return;
   __shared__ double red[2][256];
   const int q = blockIdx.x;   // r * nv + i
   const int r = q / nv, i = q % nv;
@@ -110,7 +112,8 @@ __global__ void __launch_bounds__(256) k_reduce(int nv, int nblk, const double* 
 template <int NV, typename Tv, typename Tw>
 __global__ void __launch_bounds__(256) k_multi_axpy(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
                                                     int nv, long long vstride, const double2* __restrict__ coef, int ldc,
-                                                    int coff, double sign, Tw* __restrict__ w) {
+                                                    int coff, double sign, Tw* __restrict__ w, Gate gt) {
+  if (gate_closed(gt)) return;
   constexpr int U = nv_unroll<NV>();
   __shared__ cx<double> c[NV];
   const int r = blockIdx.y;
@@ -152,7 +155,8 @@ __global__ void __launch_bounds__(256) k_multi_axpy(int nrhs, long long count, l
 template <int NV, typename Tv, typename Tw, bool NORM>
 __global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
                                                    int nv, long long vstride, const double2* __restrict__ coef, int ldc,
-                                                   Tw* __restrict__ w, double* __restrict__ partial, int nblk) {
+                                                   Tw* __restrict__ w, double* __restrict__ partial, int nblk, Gate gt) {
+  if (gate_closed(gt)) return;
   constexpr int U = nv_unroll<NV>();
   __shared__ double red[4][2 * NV];
   __shared__ cx<double> c[NV];
@@ -264,7 +268,8 @@ __device__ __forceinline__ double fold8(double* a, int lane) {
 template <typename Tv, typename Tw>
 __global__ void __launch_bounds__(256) k_gs_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
                                                  int nv, long long vstride, const Tw* __restrict__ w,
-                                                 double* __restrict__ partial, int nblk) {
+                                                 double* __restrict__ partial, int nblk, Gate gt) {
+  if (gate_closed(gt)) return;
   static_assert(kGsGroup == 4, "fold8 folds 2 x 4 values");
   __shared__ double red[4][2 * kGsMaxNv];
   const int r = blockIdx.y, blk = blockIdx.x, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -311,7 +316,8 @@ template <typename Tv, typename Tw>
 __global__ void __launch_bounds__(256) k_gs_axpy_norm(int nrhs, long long count, long long rs,
                                                       const Tv* __restrict__ V, int nv, long long vstride,
                                                       const double2* __restrict__ coef, int ldc, Tw* __restrict__ w,
-                                                      double* __restrict__ partial, int nblk) {
+                                                      double* __restrict__ partial, int nblk, Gate gt) {
+  if (gate_closed(gt)) return;
   __shared__ cx<double> c[kGsMaxNv + kGsGroup];
   __shared__ double red[4];
   const int r = blockIdx.y, blk = blockIdx.x, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -369,7 +375,8 @@ template <typename Ts, typename Td>
 __global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, long long rs, const Ts* __restrict__ src,
                                                    const double2* __restrict__ nrm2, const double* __restrict__ nrm,
                                                    const int* __restrict__ mask, Td* __restrict__ dst,
-                                                   float2* __restrict__ copy32) {
+                                                   float2* __restrict__ copy32, Gate gt) {
+  if (gate_closed(gt)) return;
   const int r = blockIdx.y;
   if (mask && !mask[r]) return;
   double n = nrm ? nrm[r] : sqrt(nrm2[r].x);
@@ -388,7 +395,8 @@ __global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, lo
 
 // out = a - b   (elementwise, same layout)
 template <typename Tv>
-__global__ void k_sub(long long n, const Tv* __restrict__ a, const Tv* __restrict__ b, Tv* __restrict__ out) {
+__global__ void k_sub(long long n, const Tv* __restrict__ a, const Tv* __restrict__ b, Tv* __restrict__ out, Gate gt) {
+  if (gate_closed(gt)) return;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     cx<double> x = ld<double, Tv>(a + i), y = ld<double, Tv>(b + i);
@@ -417,7 +425,8 @@ __global__ void k_add(long long n, const Tv* __restrict__ a, Tv* __restrict__ ou
 // start of a cycle: g = (beta, 0, ...), active if beta > tolabs and not finished
 __global__ void k_cycle_init(int nrhs, int m, const double2* __restrict__ nrm2, const double* __restrict__ tolabs,
                              const int* __restrict__ finished, double2* __restrict__ gv, double* __restrict__ beta,
-                             int* __restrict__ active, int* __restrict__ kcyc) {
+                             int* __restrict__ active, int* __restrict__ kcyc, Gate gt) {
+  if (gate_closed(gt)) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
   double b = sqrt(nrm2[r].x);
@@ -432,7 +441,8 @@ __global__ void k_arnoldi(int nrhs, int m, int j, const double2* __restrict__ h1
                           const double2* __restrict__ nrm2, double2* __restrict__ H, double* __restrict__ cs,
                           double2* __restrict__ sn, double2* __restrict__ gv, const double* __restrict__ tolabs,
                           int* __restrict__ active, int* __restrict__ kcyc, double* __restrict__ est,
-                          double* __restrict__ hnext) {
+                          double* __restrict__ hnext, Gate gt) {
+  if (gate_closed(gt)) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs || !active[r]) return;
   double2* Hc = H + ((long long)r * m + j) * (m + 1);   // column j
@@ -488,7 +498,8 @@ __global__ void k_arnoldi(int nrhs, int m, int j, const double2* __restrict__ h1
 
 // y = R^-1 g over the kcyc[r] leading entries; y beyond kcyc is zero
 __global__ void k_lsq(int nrhs, int m, const double2* __restrict__ H, const double2* __restrict__ gv,
-                      const int* __restrict__ kcyc, double2* __restrict__ y) {
+                      const int* __restrict__ kcyc, double2* __restrict__ y, Gate gt) {
+  if (gate_closed(gt)) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
   int k = kcyc[r];
@@ -522,7 +533,8 @@ __global__ void __launch_bounds__(64) k_arnoldi_w(int m, int j, const double2* _
                                                   double2* __restrict__ sn, double2* __restrict__ gv,
                                                   const double* __restrict__ tolabs, int* __restrict__ active,
                                                   int* __restrict__ kcyc, double* __restrict__ est,
-                                                  double* __restrict__ hnext) {
+                                                  double* __restrict__ hnext, Gate gt) {
+  if (gate_closed(gt)) return;
   const int r = blockIdx.x, lane = threadIdx.x;
   if (!active[r]) return;   // uniform per wave
   double2* Hc = H + ((long long)r * m + j) * (m + 1);   // column j
@@ -586,7 +598,8 @@ __global__ void __launch_bounds__(64) k_arnoldi_w(int m, int j, const double2* _
 
 // y = R^-1 g over the kcyc[r] leading entries (column-oriented back substitution); y beyond kcyc is zero
 __global__ void __launch_bounds__(64) k_lsq_w(int m, const double2* __restrict__ H, const double2* __restrict__ gv,
-                                              const int* __restrict__ kcyc, double2* __restrict__ y) {
+                                              const int* __restrict__ kcyc, double2* __restrict__ y, Gate gt) {
+  if (gate_closed(gt)) return;
   const int r = blockIdx.x, lane = threadIdx.x;
   const int k = kcyc[r];
   cx<double> g = {0.0, 0.0}, yl = {0.0, 0.0};
@@ -604,6 +617,43 @@ __global__ void __launch_bounds__(64) k_lsq_w(int m, const double2* __restrict__
     }
   }
   if (lane < m) y[r * m + lane] = make_double2(yl.re, yl.im);
+}
+
+// Device-side controls of the coarse GMRES when no host round trip is taken:
+// the tolerance from |rhs'|, the finished marks after a cycle, a vector copy.
+__global__ void k_set_tol(int nrhs, double tol, const double2* __restrict__ nrm2, double* __restrict__ tolabs,
+                          int* __restrict__ finished, int* __restrict__ active) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  tolabs[r] = tol * sqrt(nrm2[r].x);
+  finished[r] = 0;
+  active[r] = 1;
+}
+
+// after a cycle: a right-hand side whose residual estimate met its tolerance is
+// finished; the activity flags become "not finished" (the gate of the next
+// cycle's residual kernels); the cycle's longest Arnoldi run is added to iters
+__global__ void k_finish(int nrhs, const double* __restrict__ est, const double* __restrict__ tolabs,
+                         int* __restrict__ finished, int* __restrict__ active, const int* __restrict__ kcyc,
+                         int* __restrict__ iters, Gate gt) {
+  if (gate_closed(gt)) return;
+  __shared__ int kmax;
+  if (threadIdx.x == 0) kmax = 0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+    if (est[r] <= tolabs[r]) finished[r] = 1;
+    active[r] = finished[r] ? 0 : 1;
+    atomicMax(&kmax, kcyc[r]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *iters += kmax;
+}
+
+template <typename Tv>
+__global__ void k_copy(long long n, const Tv* __restrict__ a, Tv* __restrict__ out, Gate gt) {
+  if (gate_closed(gt)) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i];
 }
 
 inline unsigned grid1(long long n) {
@@ -643,7 +693,7 @@ template <typename Tv, typename Tw>
 void dots_typed(dim3 grid, hipStream_t st, int nrhs, long long count, long long rs, const void* V, int n,
                 long long vstride, const void* w, double* partial, int nblk) {
 #define DD_DOTS(NV) \
-  k_dots<NV, Tv, Tw><<<grid, 256, 0, st>>>(nrhs, count, rs, (const Tv*)V, n, vstride, (const Tw*)w, partial, nblk)
+  k_dots<NV, Tv, Tw><<<grid, 256, 0, st>>>(nrhs, count, rs, (const Tv*)V, n, vstride, (const Tw*)w, partial, nblk, current_gate())
   DD_NV_BUCKET(n, DD_DOTS)
 #undef DD_DOTS
 }
@@ -653,7 +703,7 @@ void multi_axpy_typed(dim3 grid, hipStream_t st, int nrhs, long long count, long
                       long long vstride, const double2* coef, int ldc, int coff, double sign, void* w) {
 #define DD_MAXPY(NV)                                                                                          \
   k_multi_axpy<NV, Tv, Tw><<<grid, 256, 0, st>>>(nrhs, count, rs, (const Tv*)V, n, vstride, coef, ldc, coff, sign, \
-                                                  (Tw*)w)
+                                                  (Tw*)w, current_gate())
   DD_NV_BUCKET(n, DD_MAXPY)
 #undef DD_MAXPY
 }
@@ -663,7 +713,7 @@ void axpy_dots_typed(dim3 grid, hipStream_t st, int nrhs, long long count, long 
                      long long vstride, const double2* coef, int ldc, void* w, double* partial, int nblk) {
 #define DD_AXD(NV)                                                                                                \
   k_axpy_dots<NV, Tv, Tw, NORM><<<grid, 256, 0, st>>>(nrhs, count, rs, (const Tv*)V, n, vstride, coef, ldc, (Tw*)w, \
-                                                       partial, nblk)
+                                                       partial, nblk, current_gate())
   DD_NV_BUCKET(n, DD_AXD)
 #undef DD_AXD
 }
@@ -695,7 +745,7 @@ void launch_dots(dd_dtype vt, dd_dtype wt, int nrhs, long long count, long long 
       dots_typed<float2, double2>(grid, st, nrhs, count, rs, Vi, n, vstride, w, partial, nblk);
     if (timed) ktimer_end("k_dots", st, bytes, flops);
     ktimer_account(bytes, flops);
-    k_reduce<<<nrhs * n, 256, 0, st>>>(n, nblk, partial, out, ldo, off + i0);
+    k_reduce<<<nrhs * n, 256, 0, st>>>(n, nblk, partial, out, ldo, off + i0, current_gate());
   }
 }
 
@@ -742,7 +792,7 @@ void launch_axpy_dots(dd_dtype vt, int nrhs, long long count, long long rs, cons
   const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
   const double bytes = (double)nrhs * count * (nv * eb + 2 * es), flops = 16.0 * nrhs * count * nv;
   DD_TIMED("k_axpy_dots", st, bytes, flops, DD_BASIS_DISPATCH(false));
-  k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0);
+  k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0, current_gate());
 }
 
 void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv, long long vstride,
@@ -752,7 +802,7 @@ void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long rs, cons
   const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
   const double bytes = (double)nrhs * count * (nv * eb + 2 * es), flops = 8.0 * nrhs * count * (nv + 1);
   DD_TIMED("k_axpy_norm", st, bytes, flops, DD_BASIS_DISPATCH(true));
-  k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0);
+  k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0, current_gate());
 }
 #undef DD_BASIS_DISPATCH
 
@@ -763,13 +813,13 @@ int gs_blocks(long long count) { return (int)((count + kGsTile - 1) / kGsTile); 
 #define DD_GS_DISPATCH(KERNEL, ...)                                                                  \
   if (vt == DD_F64)                                                                                   \
     KERNEL<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,   \
-                                                   __VA_ARGS__, (double2*)w, partial, nblk);          \
+                                                   __VA_ARGS__, (double2*)w, partial, nblk, current_gate());          \
   else if (bt == DD_F16)                                                                              \
     KERNEL<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride,    \
-                                                  __VA_ARGS__, (float2*)w, partial, nblk);            \
+                                                  __VA_ARGS__, (float2*)w, partial, nblk, current_gate());            \
   else                                                                                                \
     KERNEL<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,      \
-                                                 __VA_ARGS__, (float2*)w, partial, nblk);
+                                                 __VA_ARGS__, (float2*)w, partial, nblk, current_gate());
 
 void launch_gs_dots(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv,
                     long long vstride, const void* w, double* partial, double2* out, int ldo, hipStream_t st) {
@@ -780,16 +830,16 @@ void launch_gs_dots(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long lo
   if (vt == DD_F64)
     DD_TIMED("k_gs_dots", st, bytes, flops,
              (k_gs_dots<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,
-                                                                (const double2*)w, partial, nblk)));
+                                                                (const double2*)w, partial, nblk, current_gate())));
   else if (bt == DD_F16)
     DD_TIMED("k_gs_dots", st, bytes, flops,
              (k_gs_dots<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride,
-                                                               (const float2*)w, partial, nblk)));
+                                                               (const float2*)w, partial, nblk, current_gate())));
   else
     DD_TIMED("k_gs_dots", st, bytes, flops,
              (k_gs_dots<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,
-                                                              (const float2*)w, partial, nblk)));
-  k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0);
+                                                              (const float2*)w, partial, nblk, current_gate())));
+  k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0, current_gate());
 }
 
 void launch_gs_axpy_norm(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv,
@@ -800,7 +850,7 @@ void launch_gs_axpy_norm(dd_dtype bt, dd_dtype vt, int nrhs, long long count, lo
   const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
   const double bytes = (double)nrhs * count * (nv * eb + 2 * es), flops = 8.0 * nrhs * count * (nv + 1);
   DD_TIMED("k_gs_axpy_norm", st, bytes, flops, DD_GS_DISPATCH(k_gs_axpy_norm, coef, ldc));
-  k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0);
+  k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0, current_gate());
 }
 #undef DD_GS_DISPATCH
 
@@ -809,21 +859,37 @@ void launch_normalize(dd_dtype vt, int nrhs, long long count, long long rs, cons
   dim3 grid(grid1(count), nrhs);
   if (vt == DD_F64)
     k_normalize<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)src, nrm2, nrm, mask,
-                                                        (double2*)dst, (float2*)copy32);
+                                                        (double2*)dst, (float2*)copy32, current_gate());
   else if (dt == DD_F16)
     k_normalize<float2, __half2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)src, nrm2, nrm, mask,
-                                                       (__half2*)dst, (float2*)copy32);
+                                                       (__half2*)dst, (float2*)copy32, current_gate());
   else
     k_normalize<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)src, nrm2, nrm, mask,
-                                                      (float2*)dst, (float2*)copy32);
+                                                      (float2*)dst, (float2*)copy32, current_gate());
 }
 
 void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st) {
   unsigned nb = (unsigned)((n + 255) / 256);
   if (vt == DD_F64)
-    k_sub<double2><<<nb, 256, 0, st>>>(n, (const double2*)a, (const double2*)b, (double2*)out);
+    k_sub<double2><<<nb, 256, 0, st>>>(n, (const double2*)a, (const double2*)b, (double2*)out, current_gate());
   else
-    k_sub<float2><<<nb, 256, 0, st>>>(n, (const float2*)a, (const float2*)b, (float2*)out);
+    k_sub<float2><<<nb, 256, 0, st>>>(n, (const float2*)a, (const float2*)b, (float2*)out, current_gate());
+}
+
+void launch_set_tol(int nrhs, double tol, const double2* nrm2, double* tolabs, int* finished, int* active,
+                    hipStream_t st) {
+  k_set_tol<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, tol, nrm2, tolabs, finished, active);
+}
+
+void launch_finish(int nrhs, const double* est, const double* tolabs, int* finished, int* active, const int* kcyc,
+                   int* iters, hipStream_t st) {
+  k_finish<<<1, 64, 0, st>>>(nrhs, est, tolabs, finished, active, kcyc, iters, current_gate());
+}
+
+void launch_copy(dd_dtype vt, long long n, const void* a, void* out, hipStream_t st) {
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (vt == DD_F64) k_copy<double2><<<nb, 256, 0, st>>>(n, (const double2*)a, (double2*)out, current_gate());
+  else k_copy<float2><<<nb, 256, 0, st>>>(n, (const float2*)a, (float2*)out, current_gate());
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t st) {
@@ -842,21 +908,26 @@ void launch_add(dd_dtype vt, long long n, const void* a, void* out, hipStream_t 
 
 void launch_cycle_init(int nrhs, int m, const double2* nrm2, const double* tolabs, const int* finished, double2* gv,
                        double* beta, int* active, int* kcyc, hipStream_t st) {
-  k_cycle_init<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, nrm2, tolabs, finished, gv, beta, active, kcyc);
+  k_cycle_init<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, nrm2, tolabs, finished, gv, beta, active, kcyc, current_gate());
 }
 
 void launch_arnoldi(int nrhs, int m, int j, const double2* h1, const double2* h2, const double2* nrm2, double2* H,
                     double* cs, double2* sn, double2* gv, const double* tolabs, int* active, int* kcyc, double* est,
                     double* hnext, hipStream_t st) {
   if (m <= 64)
-    k_arnoldi_w<<<nrhs, 64, 0, st>>>(m, j, h1, h2, nrm2, H, cs, sn, gv, tolabs, active, kcyc, est, hnext);
+    k_arnoldi_w<<<nrhs, 64, 0, st>>>(m, j, h1, h2, nrm2, H, cs, sn, gv, tolabs, active, kcyc, est, hnext, current_gate());
   else
-    k_arnoldi<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, j, h1, h2, nrm2, H, cs, sn, gv, tolabs, active, kcyc, est, hnext);
+    k_arnoldi<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, j, h1, h2, nrm2, H, cs, sn, gv, tolabs, active, kcyc, est, hnext, current_gate());
 }
 
 void launch_lsq(int nrhs, int m, const double2* H, const double2* gv, const int* kcyc, double2* y, hipStream_t st) {
   if (m <= 64)
-    k_lsq_w<<<nrhs, 64, 0, st>>>(m, H, gv, kcyc, y);
+    k_lsq_w<<<nrhs, 64, 0, st>>>(m, H, gv, kcyc, y, current_gate());
   else
-    k_lsq<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, H, gv, kcyc, y);
+    k_lsq<<<(nrhs + 63) / 64, 64, 0, st>>>(nrhs, m, H, gv, kcyc, y, current_gate());
+}
+
+Gate& current_gate() {
+  static thread_local Gate g;
+  return g;
 }

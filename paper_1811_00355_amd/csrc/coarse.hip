@@ -27,7 +27,9 @@ __global__ void __launch_bounds__(64 * kSitesPerWG) k_coarse_mv(GeomDev g, int n
                                                               int site_begin, int count, R a_self,
                                                               const Tv* __restrict__ xs, R a_hop,
                                                               const Tv* __restrict__ xh, R beta,
-                                                              const Tv* __restrict__ z, Tv* __restrict__ out) {
+                                                              const Tv* __restrict__ z, Tv* __restrict__ out,
+                                                              Gate gt) {
+  if (gate_closed(gt)) return;
   __shared__ cx<R> xsh[kSitesPerWG][64][NR];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int local = blockIdx.x * kSitesPerWG + w;
@@ -152,7 +154,8 @@ template <int NC, int S, typename Sd>
 __global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) k_coarse_mfma(
     GeomDev g, const Sd* __restrict__ Dc, const Sd* __restrict__ Minv, int use_inv, int nrhs, int site_begin,
     int count, float a_self, const float2* __restrict__ xs, float a_hop, const float2* __restrict__ xh, float beta,
-    const float2* __restrict__ z, float2* __restrict__ out) {
+    const float2* __restrict__ z, float2* __restrict__ out, Gate gt) {
+  if (gate_closed(gt)) return;
   constexpr int MT = (NC + 15) / 16, KS = NC / 4, XP = 17;
   constexpr int P = tile_group(NC, (int)sizeof(Sd));
   struct alignas(P * sizeof(Sd)) Pack {
@@ -288,7 +291,8 @@ template <int NC, int S, typename Sd>
 __global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_mfma_h(
     GeomDev g, const Sd* __restrict__ Dc, const Sd* __restrict__ Minv, int use_inv, int nrhs, int site_begin,
     int count, float a_self, const float2* __restrict__ xs, float a_hop, const float2* __restrict__ xh, float beta,
-    const float2* __restrict__ z, float2* __restrict__ out) {
+    const float2* __restrict__ z, float2* __restrict__ out, Gate gt) {
+  if (gate_closed(gt)) return;
   typedef HalfOp<Sd> H;
   typedef typename H::vec vec;
   typedef typename H::elem elem;
@@ -421,7 +425,7 @@ __global__ void __launch_bounds__(64 * S * ((NC + 15) / 16)) __attribute__((amdg
 }
 
 typedef void (*MfmaFn)(GeomDev, const void*, const void*, int, int, int, int, float, const float2*, float,
-                       const float2*, float, const float2*, float2*);
+                       const float2*, float, const float2*, float2*, Gate);
 
 // spw: target waves per workgroup; sites per workgroup S = max(1, spw / MT), at most 4
 template <int NC, typename Sd, bool HM = false>
@@ -472,7 +476,8 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
   DD_TIMED("k_coarse_mv", st, bytes, flops,                                                                        \
            (k_coarse_mv<R, Sd, Tv, NRV><<<nb, blk, 0, st>>>(g, nc, (const Sd*)Dc, (const Sd*)Minv, use_inv, nrhs,   \
                                                              site_begin, count, (R)a_self, (const Tv*)xs, (R)a_hop, \
-                                                             (const Tv*)xh, (R)beta, (const Tv*)z, (Tv*)out)))
+                                                             (const Tv*)xh, (R)beta, (const Tv*)z, (Tv*)out, \
+                                                             current_gate())))
   if (sizeof(R) == 4 && nc <= kMfmaMaxNc) {
     dim3 grid, wg;
     MfmaFn fn = bt == DD_F16    ? (hm ? mfma_pick<__half2, true>(nc, spw, count, grid, wg)
@@ -483,7 +488,8 @@ void mv(const GeomDev& g, int nc, const void* Dc, const void* Minv, int use_inv,
     const double hb = bt == DD_F32 ? 1.0 : 0.5;   // half-precision blocks stream half the bytes
     DD_TIMED("k_coarse_mfma", st, bytes - (1.0 - hb) * (double)count * nblocks_read * nc * nc * sizeof(Sd), flops,
              (fn<<<grid, wg, 0, st>>>(g, Dc, Minv, use_inv, nrhs, site_begin, count, (float)a_self, (const float2*)xs,
-                                      (float)a_hop, (const float2*)xh, (float)beta, (const float2*)z, (float2*)out)));
+                                      (float)a_hop, (const float2*)xh, (float)beta, (const float2*)z, (float2*)out,
+                                      current_gate())));
   } else if (nrhs == 1) DD_MV(1);
   else if (nrhs <= 4) DD_MV(4);
   else DD_MV(12);

@@ -273,6 +273,31 @@ __device__ __forceinline__ bool xcd_slab_tile(const GeomDev& g, int per_blk, int
   return true;
 }
 
+// Device-side gate of a launch: the kernel returns at once unless some entry
+// of `flags` (one per right-hand side) equals `open_on`.  With the Arnoldi
+// activity flags (open_on 1) the steps of a coarse GMRES cycle become no-ops
+// once every right-hand side has converged; with the finished flags
+// (open_on 0) so do the cycle-level kernels once every right-hand side is done.
+// A null gate is always open.  The host sets the gate launches take through
+// GateScope (per host thread), so the launchers keep their signatures.
+struct Gate {
+  const int* flags = nullptr;
+  int n = 0;
+  int open_on = 1;
+};
+__device__ __forceinline__ bool gate_closed(const Gate& g) {
+  if (!g.flags) return false;
+  for (int r = 0; r < g.n; ++r)
+    if (g.flags[r] == g.open_on) return false;
+  return true;
+}
+Gate& current_gate();
+struct GateScope {
+  Gate saved;
+  explicit GateScope(const Gate& g) : saved(current_gate()) { current_gate() = g; }
+  ~GateScope() { current_gate() = saved; }
+};
+
 // lexicographic site index of a packed site
 __host__ __device__ __forceinline__ long long lex_site(const GeomDev& g, const SiteLoc& s) {
   int bc = g.blk_coord[s.slot];
@@ -355,7 +380,7 @@ struct dd_mg {
   float2* Dinv32 = nullptr;
   void* Dinvh = nullptr;
   Workspace* ws = nullptr;
-  bool use_graphs = false;   // coarse GMRES chunks replayed from captured HIP graphs
+  int graphs = 0;   // 0: launches; 1: coarse GMRES chunks replayed from graphs; 2: all of M from one graph
 };
 
 // ---------------------------------------------------------------------------
@@ -459,6 +484,12 @@ void launch_normalize(dd_dtype vt, int nrhs, long long count, long long ld, cons
                       dd_dtype dt = DD_F32, void* copy32 = nullptr);   // dt: dtype of dst (F16 basis)
 void launch_sub(dd_dtype vt, long long n, const void* a, const void* b, void* out, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);   // bytes: multiple of 4
+// device-side controls of the coarse GMRES (no host round trip)
+void launch_set_tol(int nrhs, double tol, const double2* nrm2, double* tolabs, int* finished, int* active,
+                    hipStream_t st);
+void launch_finish(int nrhs, const double* est, const double* tolabs, int* finished, int* active, const int* kcyc,
+                   int* iters, hipStream_t st);
+void launch_copy(dd_dtype vt, long long n, const void* a, void* out, hipStream_t st);
 // FP32 (and, when half is DD_F16 / DD_BF16, half) copies of nblk FP64 coarse
 // blocks in the order the matrix-core apply reads
 void launch_coarse_tile(int nc, const double2* src64, long long nblk, float2* dst32, dd_dtype half, void* dsth,

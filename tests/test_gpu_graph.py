@@ -134,3 +134,67 @@ def test_graphs_follow_tuning_changes(ctx):
     assert not torch.equal(results[0], results[3]) and not torch.equal(results[3], results[4])
     mg.destroy()
     g.destroy()
+
+
+@pytest.mark.parametrize("store,half", [(1, 0), (3, 1)])
+def test_whole_preconditioner_graph(ctx, store, half):
+    """Graph mode 2: all of M (restriction, the device-driven coarse GMRES,
+    prolongation, SAP) replayed from one graph gives the bits of the launched
+    form (mode 0) and of the chunked graphs (mode 1), for the preconditioner
+    alone and for whole solves; right-hand sides of very different size
+    converge at different coarse steps (masking on the device); every replay is
+    checked, with ordinary launches between the replays; FP32 storage and BF16
+    storage with half-precision coarse arithmetic."""
+    import torch
+    import _gpu
+    from paper_1811_00355_amd import Gauge, MG, default_params
+    from oracle.lattice import Lattice
+    from workloads import su3_field, gauss_vectors, gauss_spinor
+    L, blk, n = (8, 8, 8, 16), (4, 4, 4, 4), 20
+    lat = Lattice(L, blk)
+    g = Gauge(ctx, L, blk, su3_field(L, 0.2, 23), -0.1, 1.0)
+    p = default_params(block=blk, n_vec=n, inner_dtype=1, store_dtype=store, init_sap_apps=2, setup_iters=1,
+                       coarse_restart=20, coarse_max_iters=60)
+    mg = MG(g, p, tv_host=gauss_vectors(n, lat.V, 30).reshape(n, lat.V, 4, 3))
+    t = g.dd_gauge_get_tuning()
+    t.update(coarse_half=half, coarse_basis_half=half, coarse_mfma_half=half)
+    g.dd_gauge_set_tuning(**t)
+    nrhs = 5
+    v = gauss_spinor(L, nrhs, 66)
+    v[1] *= 1e-4
+    v[3] *= 30.0
+    vin = g.new_packed(1, nrhs)
+    g.pack(1, nrhs, _gpu.to_dev(v.reshape(nrhs, -1)), vin)
+    out = g.new_packed(1, nrhs)
+    mg.dd_mg_set_graphs(0)
+    mg.dd_precond_apply(nrhs, vin, out)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    scratch_in, scratch_out = g.new_packed(1, 1), g.new_packed(1, 1)
+    for mode in (1, 2, 2, 2):
+        mg.dd_mg_set_graphs(mode)
+        out.zero_()
+        mg.dd_precond_apply(nrhs, vin, out)
+        torch.cuda.synchronize()
+        same = torch.equal(out, ref)
+        print(f"store {store} half {half}: M in graph mode {mode}: bitwise {same}", flush=True)
+        assert same
+        g.dd_dirac_apply(1, 1, scratch_in, scratch_out)      # ordinary work between replays
+        torch.cuda.synchronize()
+    bd = _gpu.to_dev(v.reshape(nrhs, -1))
+    sols = {}
+    for mode in (0, 2, 1, 2):
+        mg.dd_mg_set_graphs(mode)
+        x = torch.zeros_like(bd)
+        info, _ = mg.dd_solve(nrhs, bd, x, 1e-10)
+        torch.cuda.synchronize()
+        its = [i["outer_iters"] for i in info]
+        print(f"solve, graph mode {mode}: outer iterations {its}, coarse steps {info[0]['coarse_iters_total']}",
+              flush=True)
+        assert all(i["converged"] for i in info)
+        if 0 in sols:
+            assert torch.equal(x, sols[0][0]) and its == sols[0][1]
+        else:
+            sols[0] = (x.clone(), its)
+    mg.destroy()
+    g.destroy()
