@@ -27,13 +27,15 @@
  *
  * Ownership: the library owns every handle and its own device workspace, which
  * counts against the context's HBM budget.  Callers own every vector buffer
- * they pass (device pointers).  A dd_ctx is used from one host thread;
- * concurrency comes from the streams passed in.  Apply calls are asynchronous
- * on `stream` (a hipStream_t, NULL = default stream).  dd_setup and dd_solve
- * synchronise `stream` at their convergence checks.
+ * they pass (device pointers).  Threads may share a dd_ctx (its allocation
+ * accounting is locked), each driving its own dd_gauge / dd_mg / dd_solve_state
+ * on its own stream; one handle is used by one thread at a time.  Apply calls
+ * are asynchronous on `stream` (a hipStream_t, NULL = default stream).
+ * dd_setup and the solve calls synchronise `stream` at their convergence checks.
  *
  * Errors: every call returns a dd_status; nothing aborts or throws across the
- * ABI.  dd_last_error() gives the text of the last error on a context.
+ * ABI.  dd_last_error() gives the text of the last error that the calling
+ * thread met on a context ("" if none).
  */
 #ifndef DD_H
 #define DD_H
@@ -337,6 +339,44 @@ dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void*
  * b and x: canonical complex128 device buffers [nrhs][V][4][3]; info: nrhs entries. */
 dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon_dev, double* x_canon_dev,
                    double tol, dd_solve_info* info, void* stream);
+
+/* ---- stepwise solve ----------------------------------------------------------------------
+ * The same FGMRES(m) as dd_solve (which is begin, add every right-hand side,
+ * step until no slot runs, take every slot, end), driven one restart cycle at a
+ * time, for a server that admits right-hand sides into a running batch at the
+ * restart boundaries and hands results back as they finish.
+ *
+ * A state holds `capacity` slots, each free, running or done.  Every launch of
+ * a step covers slots [0, highest running slot]; reductions, masks and
+ * Hessenberg data are per slot, so a right-hand side gets bit-identical results
+ * whether it runs alone or beside others and whenever it joins.  The iteration
+ * cap max_outer_iters is applied per slot at restart boundaries (a cycle is
+ * shortened so the longest-running slot stops at the cap).
+ *
+ * dd_solve_begin: allocate (or reuse) the workspace for `capacity` right-hand
+ *   sides; tol as in dd_solve.  One live state per dd_mg (they share its
+ *   workspace).  DD_EBUDGET/DD_ENOMEM as dd_solve.
+ * dd_solve_add: start slot `slot` (must be free) from x = 0 on the canonical
+ *   complex128 device vector b [V][4][3] (read before the call returns).
+ *   A zero b is done at once (x = 0, converged); non-finite b gives DD_ENAN
+ *   and leaves the slot free.  Synchronises the state's stream.
+ * dd_solve_step: one restart cycle of the running slots, then their
+ *   true-residual check: a slot whose |b - D x| / |b| <= tol (FP64 operator),
+ *   or that reached max_outer_iters, becomes done.  slot_state (capacity
+ *   int32 entries, may be NULL) receives 0 free, 1 running, 2 done.  DD_ENAN
+ *   on breakdown.  A step with no running slot does nothing.  Synchronises
+ *   the state's stream.
+ * dd_solve_take: copy a done slot's solution to the canonical complex128
+ *   device buffer x [V][4][3], fill info (may be NULL; t_solve_s counts from
+ *   dd_solve_begin, coarse_iters_total and the work model cover every slot of
+ *   the state so far) and free the slot.  DD_ESTATE if the slot is not done.
+ * dd_solve_end: release the state (not the workspace, which the dd_mg keeps). */
+typedef struct dd_solve_state dd_solve_state;
+dd_status dd_solve_begin(dd_mg* mg, int capacity, double tol, void* stream, dd_solve_state** out);
+dd_status dd_solve_add(dd_solve_state* s, int slot, const double* b_canon_dev);
+dd_status dd_solve_step(dd_solve_state* s, int32_t* slot_state);
+dd_status dd_solve_take(dd_solve_state* s, int slot, double* x_canon_dev, dd_solve_info* info);
+dd_status dd_solve_end(dd_solve_state* s);
 
 /* ---- exports for parity checks (host buffers) ----------------------------------------- */
 dd_status dd_export_maps(const dd_gauge* g, int32_t* agg_of_site, int32_t* local_of_site,

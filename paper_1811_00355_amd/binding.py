@@ -112,6 +112,11 @@ SIGNATURES = {
     "dd_coarse_solve_noalloc": (_I, [_P, _I, _I, _P, _P, ctypes.POINTER(_I), _P]),
     "dd_precond_apply": (_I, [_P, _I, _P, _P, _P]),
     "dd_solve": (_I, [_P, _I, _P, _P, ctypes.c_double, ctypes.POINTER(dd_solve_info), _P]),
+    "dd_solve_begin": (_I, [_P, _I, ctypes.c_double, _P, ctypes.POINTER(_P)]),
+    "dd_solve_add": (_I, [_P, _I, _P]),
+    "dd_solve_step": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "dd_solve_take": (_I, [_P, _I, _P, ctypes.POINTER(dd_solve_info)]),
+    "dd_solve_end": (_I, [_P]),
     "dd_export_maps": (_I, [_P, _P, _P, _P, _P]),
     "dd_export_clover": (_I, [_P, _P, _P]),
     "dd_export_operands": (_I, [_P, _I, _P, _P]),
@@ -411,10 +416,57 @@ class MG:
         st = self.ctx.lib.dd_solve(self.h, nrhs, _ptr(b_canon), _ptr(x_canon), tol, info, _stream(stream))
         if st and not (st == 5 and not raise_on_noconv):
             self.ctx.check(st)
-        return [dict(outer_iters=i.outer_iters, restarts=i.restarts, coarse_iters_total=i.coarse_iters_total,
-                     converged=bool(i.converged), true_relres=i.true_relres, t_setup_s=i.t_setup_s,
-                     t_solve_s=i.t_solve_s, bytes_model=i.bytes_model, flops_model=i.flops_model)
-                for i in info], st
+        return [_info_dict(i) for i in info], st
+
+    def dd_solve_begin(self, capacity, tol, stream=None):
+        """A stepwise solve with `capacity` slots on this multigrid's workspace."""
+        return SolveState(self, capacity, tol, stream)
+
+
+def _info_dict(i):
+    return dict(outer_iters=i.outer_iters, restarts=i.restarts, coarse_iters_total=i.coarse_iters_total,
+                converged=bool(i.converged), true_relres=i.true_relres, t_setup_s=i.t_setup_s,
+                t_solve_s=i.t_solve_s, bytes_model=i.bytes_model, flops_model=i.flops_model)
+
+
+SLOT_FREE, SLOT_RUNNING, SLOT_DONE = 0, 1, 2
+
+
+class SolveState:
+    """dd_solve_begin / add / step / take / end: FGMRES driven one restart
+    cycle at a time, right-hand sides admitted into free slots between steps."""
+
+    def __init__(self, mg, capacity, tol, stream=None):
+        self.mg, self.ctx, self.capacity = mg, mg.ctx, capacity
+        self.stream = stream
+        self.h = _P()
+        self.ctx.check(self.ctx.lib.dd_solve_begin(mg.h, capacity, tol, _stream(stream), ctypes.byref(self.h)))
+        self.states = (ctypes.c_int32 * capacity)()
+
+    def add(self, slot, b_canon):
+        """Start `slot` from x = 0 on b (canonical complex128 device vector of one right-hand side)."""
+        self.ctx.check(self.ctx.lib.dd_solve_add(self.h, slot, _ptr(b_canon)))
+
+    def step(self):
+        """Residual check, then one restart cycle; returns the slot states (0 free, 1 running, 2 done)."""
+        self.ctx.check(self.ctx.lib.dd_solve_step(self.h, self.states))
+        return list(self.states)
+
+    def take(self, slot, x_canon):
+        info = dd_solve_info()
+        self.ctx.check(self.ctx.lib.dd_solve_take(self.h, slot, _ptr(x_canon), ctypes.byref(info)))
+        return _info_dict(info)
+
+    def end(self):
+        if self.h:
+            self.ctx.check(self.ctx.lib.dd_solve_end(self.h))
+            self.h = _P()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.end()
 
     def export_coarse(self):
         nc = 2 * self.n

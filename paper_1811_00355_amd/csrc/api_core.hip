@@ -38,8 +38,16 @@ static dd_status scratch_address(int device, void** out) {
 static const char* kStatus[] = {"DD_OK",    "DD_EINVAL", "DD_ESHAPE", "DD_ENOMEM", "DD_EBUDGET",
                                 "DD_ENOCONV", "DD_ENAN", "DD_EDEVICE", "DD_ESTATE"};
 
+// the last failure is kept per thread (and per context), so that threads driving
+// different solvers on one context each read their own message
+static thread_local const dd_ctx* t_err_ctx = nullptr;
+static thread_local std::string t_err;
+
 dd_status dd_fail(dd_ctx* ctx, dd_status s, const std::string& msg) {
-  if (ctx) ctx->last_error = std::string(kStatus[s]) + ": " + msg;
+  if (ctx) {
+    t_err_ctx = ctx;
+    t_err = std::string(kStatus[s]) + ": " + msg;
+  }
   return s;
 }
 
@@ -51,24 +59,38 @@ dd_status dd_hip_check(dd_ctx* ctx, hipError_t e, const char* what) {
 dd_status dd_alloc(dd_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) return DD_OK;
-  if (ctx->in_use + bytes > ctx->budget)
-    return dd_fail(ctx, DD_EBUDGET, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
-                                        std::to_string(ctx->in_use) + " of " + std::to_string(ctx->budget) +
-                                        " in use)");
+  {
+    // reserve under the lock, allocate outside it
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->in_use + bytes > ctx->budget)
+      return dd_fail(ctx, DD_EBUDGET, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
+                                          std::to_string(ctx->in_use) + " of " + std::to_string(ctx->budget) +
+                                          " in use)");
+    ctx->in_use += bytes;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->in_use -= bytes;
+    }
     return dd_hip_check(ctx, e, "hipMalloc");
   }
-  ctx->in_use += bytes;
   return DD_OK;
 }
 
 void dd_free(dd_ctx* ctx, void* p, size_t bytes) {
   if (!p) return;
   (void)hipFree(p);
+  std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->in_use -= bytes;
+}
+
+size_t ctx_in_use(dd_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return ctx->in_use;
 }
 
 extern "C" {
@@ -78,9 +100,12 @@ const char* dd_status_str(dd_status s) {
   return kStatus[s];
 }
 
-const char* dd_last_error(const dd_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+const char* dd_last_error(const dd_ctx* ctx) {
+  if (!ctx) return "null context";
+  return t_err_ctx == ctx ? t_err.c_str() : "";
+}
 
-size_t dd_ctx_bytes_in_use(const dd_ctx* ctx) { return ctx ? ctx->in_use : 0; }
+size_t dd_ctx_bytes_in_use(const dd_ctx* ctx) { return ctx ? ctx_in_use(const_cast<dd_ctx*>(ctx)) : 0; }
 
 dd_status dd_ctx_create(int device, size_t budget, dd_ctx** out) {
   if (!out) return DD_EINVAL;

@@ -670,7 +670,7 @@ static dd_status build(dd_mg* mg, hipStream_t st) {
   // rounded down to whole 16-column passes of the restriction.  Every column is
   // computed on its own, so the chunk changes the number of passes, not the result.
   const long long vbytes = 12LL * G.V * (long long)sizeof(double2);
-  const size_t free_b = mg->ctx->budget > mg->ctx->in_use ? mg->ctx->budget - mg->ctx->in_use : 0;
+  const size_t used = ctx_in_use(mg->ctx), free_b = mg->ctx->budget > used ? mg->ctx->budget - used : 0;
   const size_t wcap = std::max<size_t>(4ULL << 30, std::min<size_t>(free_b / 2, 32ULL << 30));
   int chunk = (int)std::min<long long>((long long)(wcap / (size_t)vbytes), mg->nc);
   if (chunk >= 16 && chunk < mg->nc) chunk -= chunk % 16;
@@ -894,6 +894,7 @@ dd_status dd_setup_from_vectors(dd_gauge* g, const dd_mg_params* p, const double
 
 dd_status dd_setup_update_mass(dd_mg* mg, double m0) {
   if (!mg) return DD_EINVAL;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
   if (!std::isfinite(m0)) return dd_fail(mg->ctx, DD_EINVAL, "non-finite mass");
   if (mg->g->refcount != 1)
     return dd_fail(mg->ctx, DD_ESTATE, "another multigrid setup references this gauge field");
@@ -936,6 +937,7 @@ dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t) {
 
 dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report, size_t report_cap) {
   if (!mg || nrhs < 1) return DD_EINVAL;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
   dd_gauge* g = mg->g;
   const GeomDev& G = g->geo;
   std::string key;
@@ -1104,6 +1106,7 @@ dd_status dd_footprint_bytes(const dd_problem* prob, const dd_mg_params* p, int 
 
 dd_status dd_mg_release_workspace(dd_mg* mg) {
   if (!mg) return DD_EINVAL;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
   DD_HIP(mg->ctx, hipDeviceSynchronize());
   free_ws(mg);
   return DD_OK;
@@ -1111,6 +1114,7 @@ dd_status dd_mg_release_workspace(dd_mg* mg) {
 
 dd_status dd_mg_set_graphs(dd_mg* mg, int mode) {
   if (!mg) return DD_EINVAL;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
   if (mode < 0 || mode > 2) return dd_fail(mg->ctx, DD_EINVAL, "graph mode must be 0, 1 or 2");
   mg->graphs = mode;
   return DD_OK;
@@ -1118,6 +1122,7 @@ dd_status dd_mg_set_graphs(dd_mg* mg, int mode) {
 
 dd_status dd_mg_destroy(dd_mg* mg) {
   if (!mg) return DD_EINVAL;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
   (void)hipDeviceSynchronize();
   mg_free(mg);
   return DD_OK;
@@ -1177,6 +1182,7 @@ dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
 dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out, int* iters, void* stream) {
   dd_status s = check_mg_vec(mg, dt, nrhs, in, out);
   if (s) return s;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
   if (dt == DD_F64 && inner_vt(mg) != DD_F64)
     return dd_fail(mg->ctx, DD_EINVAL, "an FP32 setup's workspace holds no FP64 coarse basis: use DD_F32");
   if ((s = ensure_ws(mg, nrhs, false))) return s;
@@ -1233,6 +1239,7 @@ dd_status dd_coarse_solve_noalloc(dd_mg* mg, dd_dtype dt, int nrhs, const void* 
 dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void* stream) {
   dd_status s = check_mg_vec(mg, inner_vt(mg), nrhs, in, out);
   if (s) return s;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
   if ((s = ensure_ws(mg, nrhs, false))) return s;
   return apply_M(mg, nrhs, in, out, nullptr, (hipStream_t)stream);
 }
@@ -1277,126 +1284,249 @@ dd_status dd_export_vectors(const dd_mg* mg, double* tv_host) {
 // ---------------------------------------------------------------------------
 // outer flexible GMRES (FP64), right preconditioned by M
 // ---------------------------------------------------------------------------
-dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, double tol, dd_solve_info* info,
-                   void* stream) {
-  if (!mg) return DD_EINVAL;
-  if (!b_canon || !x_canon || nrhs < 1 || !(tol > 0.0)) return dd_fail(mg->ctx, DD_EINVAL, "bad solve arguments");
-  auto t0 = std::chrono::steady_clock::now();
-  hipStream_t st = (hipStream_t)stream;
-  double mb0, mf0;
-  ktimer_model(&mb0, &mf0);
-  dd_status s = ensure_ws(mg, nrhs, true);
-  if (s) return s;
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// outer flexible GMRES (FP64), right preconditioned by M, as a sequence of
+// restart cycles over slots: a right-hand side occupies a slot from the
+// moment it is added until it is taken.  Adding a slot sets its residual to b
+// (x = 0); one step is one restart cycle of the running slots followed by the
+// true-residual check that decides which of them are done.  Slots are
+// independent (per-RHS reductions and masks), so a right-hand side gets the
+// same bits whether it starts alone, with others, or joins a running batch at
+// a step boundary.
+// ---------------------------------------------------------------------------
+struct dd_solve_state {
+  dd_mg* mg = nullptr;
+  int cap = 0;
+  double tol = 0.0;
+  hipStream_t st = nullptr;
+  std::vector<int> state;    // kSlotFree / kSlotRunning / kSlotDone
+  std::vector<int> conv, iters, restarts;
+  std::vector<double> bnorm, relres;
+  int total_coarse = 0;
+  double mb0 = 0.0, mf0 = 0.0;
+  std::chrono::steady_clock::time_point t0;
+};
+
+enum { kSlotFree = 0, kSlotRunning = 1, kSlotDone = 2 };
+
+// slot <- b: x = 0, r = b (a copy, as the first cycle of a solve from x = 0 takes it), |r|, tolerance
+static dd_status solve_add(dd_solve_state* S, int slot, const double* b_canon) {
+  dd_mg* mg = S->mg;
+  Workspace* w = mg->ws;
+  const GeomDev& G = mg->g->geo;
+  const long long cnt = 12LL * G.V;
+  hipStream_t st = S->st;
+  double2* bs = w->b64 + (size_t)slot * cnt;
+  double2* rs = w->w64 + (size_t)slot * cnt;
+  launch_pack_fine(G, DD_F64, 1, (const double2*)b_canon, bs, st);
+  DD_HIP(mg->ctx, hipMemsetAsync(w->x64 + (size_t)slot * cnt, 0, sizeof(double2) * cnt, st));
+  DD_HIP(mg->ctx, hipMemcpyAsync(rs, bs, sizeof(double2) * cnt, hipMemcpyDeviceToDevice, st));
+  norms2(w, DD_F64, 1, cnt, cnt, rs, w->fa.nrm2 + slot, st);
+  double2 n2;
+  DD_HIP(mg->ctx, hipMemcpyAsync(&n2, w->fa.nrm2 + slot, sizeof(double2), hipMemcpyDeviceToHost, st));
+  DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  const double bn = std::sqrt(n2.x);
+  if (!std::isfinite(bn)) return dd_fail(mg->ctx, DD_ENAN, "non-finite right-hand side in slot " + std::to_string(slot));
+  const double tl = S->tol * bn;
+  DD_HIP(mg->ctx, hipMemcpyAsync(w->fa.tolabs + slot, &tl, sizeof(double), hipMemcpyHostToDevice, st));
+  DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  S->bnorm[slot] = bn;
+  S->relres[slot] = bn == 0.0 ? 0.0 : 1.0;
+  S->iters[slot] = S->restarts[slot] = 0;
+  S->conv[slot] = S->relres[slot] <= S->tol ? 1 : 0;   // zero b: x = 0 is exact
+  S->state[slot] = S->conv[slot] ? kSlotDone : kSlotRunning;
+  return DD_OK;
+}
+
+// one restart cycle of the running slots, then their true-residual check
+static dd_status solve_step(dd_solve_state* S) {
+  dd_mg* mg = S->mg;
   Workspace* w = mg->ws;
   dd_gauge* g = mg->g;
   const GeomDev& G = g->geo;
-  const long long cnt = 12LL * G.V, fine = cnt * nrhs;
+  const long long cnt = 12LL * G.V;
   const dd_dtype vt = inner_vt(mg);
   const size_t vb = vector_pair_bytes(vt);
   Arnoldi& a = w->fa;
   const int m = a.m;
+  hipStream_t st = S->st;
+  dd_status s;
+  int nhi = 0;   // slots [0, nhi) take part in the launches
+  int longest = 0;
+  for (int r = 0; r < S->cap; ++r)
+    if (S->state[r] == kSlotRunning) {
+      nhi = r + 1;
+      longest = std::max(longest, S->iters[r]);
+    }
+  if (nhi == 0) return DD_OK;
+  const long long fine = cnt * nhi;
+  // the residuals r = b - D x of the running slots and their norms are in
+  // w64 / nrm2 (from the last check, or from dd_solve_add)
+  HostArr<int> fin(nhi, 1);
+  for (int r = 0; r < nhi; ++r) fin[r] = S->state[r] == kSlotRunning ? 0 : 1;
+  DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.p, sizeof(int) * nhi, hipMemcpyHostToDevice, st));
+  launch_cycle_init(nhi, m, a.nrm2, a.tolabs, a.finished, a.gv, a.beta, a.active, a.kcyc, st);
+  // with an FP32 preconditioner the normalisation also writes v_j rounded to FP32 (its input)
+  void* vin32 = vt == DD_F64 ? nullptr : w->vin;
   const long long vs64 = fine, vsz = fine;   // basis strides (entries)
-  launch_pack_fine(G, DD_F64, nrhs, (const double2*)b_canon, w->b64, st);
-  DD_HIP(mg->ctx, hipMemsetAsync(w->x64, 0, sizeof(double2) * fine, st));
-  if (mg->graphs == 2) launch_zero(w->citers, sizeof(int), st);   // coarse steps counted on the device
-  // |b|, tolerance, non-finite check
-  norms2(w, DD_F64, nrhs, cnt, cnt, w->b64, a.nrm2, st);
-  std::vector<double2> n2(nrhs);
-  DD_HIP(mg->ctx, hipMemcpyAsync(n2.data(), a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
-  DD_HIP(mg->ctx, hipStreamSynchronize(st));
-  std::vector<double> bnorm(nrhs), tl(nrhs), relres(nrhs, 1.0);
-  std::vector<int> fin(nrhs, 0), iters(nrhs, 0), restarts(nrhs, 0);
-  for (int r = 0; r < nrhs; ++r) {
-    bnorm[r] = std::sqrt(n2[r].x);
-    if (!std::isfinite(bnorm[r])) return dd_fail(mg->ctx, DD_ENAN, "non-finite right-hand side " + std::to_string(r));
-    tl[r] = tol * bnorm[r];
-    if (bnorm[r] == 0.0) {
-      fin[r] = 1;
-      relres[r] = 0.0;
-    }
-  }
-  DD_HIP(mg->ctx, hipMemcpyAsync(a.tolabs, tl.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-  int total_coarse = 0, outer = 0;
-  bool first = true;
-  while (true) {
-    // true residual r = b - D x (FP64 operator); the first cycle starts from x = 0
-    if (first) {
-      DD_HIP(mg->ctx, hipMemcpyAsync(w->w64, w->b64, sizeof(double2) * fine, hipMemcpyDeviceToDevice, st));
+  launch_normalize(DD_F64, nhi, cnt, cnt, w->w64, nullptr, a.beta, a.active, w->V64, st, DD_F64, vin32);
+  // the cycle ends at the restart length or where the longest-running slot reaches the iteration cap
+  const int mm = mg->p.max_outer_iters - longest < m ? mg->p.max_outer_iters - longest : m;
+  for (int j = 0; j < mm; ++j) {
+    double2* Vj = w->V64 + (size_t)j * vs64;
+    char* Zj = (char*)w->Z + (size_t)j * vsz * vb;
+    // z_j = M v_j in the inner precision
+    int ci = 0;
+    if (vt == DD_F64) {
+      if ((s = apply_M(mg, nhi, Vj, Zj, &ci, st))) return s;
+      launch_dirac(G, DD_F64, g->ops[DD_F64], nhi, Zj, w->w64, st, g->tune.dirac_threads);
     } else {
-      launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, w->x64, w->zt64, st, g->tune.dirac_threads);
-      launch_sub(DD_F64, fine, w->b64, w->zt64, w->w64, st);
+      if ((s = apply_M(mg, nhi, w->vin, Zj, &ci, st))) return s;
+      launch_dirac_f32_in(G, g->ops[DD_F64], nhi, (const float2*)Zj, w->w64, st, g->tune.dirac_threads);
     }
-    first = false;
-    norms2(w, DD_F64, nrhs, cnt, cnt, w->w64, a.nrm2, st);
-    DD_HIP(mg->ctx, hipMemcpyAsync(n2.data(), a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
-    DD_HIP(mg->ctx, hipStreamSynchronize(st));
-    int nfin = 0;
-    for (int r = 0; r < nrhs; ++r) {
-      if (bnorm[r] > 0.0) relres[r] = std::sqrt(n2[r].x) / bnorm[r];
-      if (!std::isfinite(relres[r])) return dd_fail(mg->ctx, DD_ENAN, "breakdown: non-finite residual");
-      if (relres[r] <= tol) fin[r] = 1;
-      nfin += fin[r];
-    }
-    if (nfin == nrhs || outer >= mg->p.max_outer_iters) break;
-    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-    launch_cycle_init(nrhs, m, a.nrm2, a.tolabs, a.finished, a.gv, a.beta, a.active, a.kcyc, st);
-    // with an FP32 preconditioner the normalisation also writes v_j rounded to FP32 (its input)
-    void* vin32 = vt == DD_F64 ? nullptr : w->vin;
-    launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.beta, a.active, w->V64, st, DD_F64, vin32);
-    int mm = mg->p.max_outer_iters - outer < m ? mg->p.max_outer_iters - outer : m;
-    for (int j = 0; j < mm; ++j) {
-      double2* Vj = w->V64 + (size_t)j * vs64;
-      char* Zj = (char*)w->Z + (size_t)j * vsz * vb;
-      // z_j = M v_j in the inner precision
-      int ci = 0;
-      if (vt == DD_F64) {
-        if ((s = apply_M(mg, nrhs, Vj, Zj, &ci, st))) return s;
-        launch_dirac(G, DD_F64, g->ops[DD_F64], nrhs, Zj, w->w64, st, g->tune.dirac_threads);
-      } else {
-        if ((s = apply_M(mg, nrhs, w->vin, Zj, &ci, st))) return s;
-        launch_dirac_f32_in(G, g->ops[DD_F64], nrhs, (const float2*)Zj, w->w64, st, g->tune.dirac_threads);
-      }
-      total_coarse += ci;
-      const int op = mg->p.outer_cgs_passes;
-      cgs(w, a, DD_F64, nrhs, cnt, cnt, w->V64, vs64, j + 1, w->w64, op, st, DD_F64);
-      launch_arnoldi(nrhs, m, j, a.h1, op == 2 ? a.h2 : nullptr, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active,
-                     a.kcyc, a.est, a.hnext, st);
-      ++outer;
-      if (j + 1 == mm) break;
-      launch_normalize(DD_F64, nrhs, cnt, cnt, w->w64, nullptr, a.hnext, a.active, w->V64 + (size_t)(j + 1) * vs64, st,
-                       DD_F64, vin32);
-      if (count_active(w, a.active, nrhs, st) == 0) break;
-    }
-    launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
-    int kmax = max_kcyc(w, a, nrhs, st);   // also leaves kcyc in hflags[nrhs..]
-    launch_multi_axpy(vt, DD_F64, nrhs, cnt, cnt, w->Z, kmax, vsz, a.y, m, 0, 1.0, w->x64, st);
-    for (int r = 0; r < nrhs; ++r)
-      if (!fin[r]) {
-        iters[r] += w->hflags[nrhs + r];
-        restarts[r] += 1;
-      }
+    S->total_coarse += ci;
+    const int op = mg->p.outer_cgs_passes;
+    cgs(w, a, DD_F64, nhi, cnt, cnt, w->V64, vs64, j + 1, w->w64, op, st, DD_F64);
+    launch_arnoldi(nhi, m, j, a.h1, op == 2 ? a.h2 : nullptr, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active,
+                   a.kcyc, a.est, a.hnext, st);
+    if (j + 1 == mm) break;
+    launch_normalize(DD_F64, nhi, cnt, cnt, w->w64, nullptr, a.hnext, a.active, w->V64 + (size_t)(j + 1) * vs64, st,
+                     DD_F64, vin32);
+    if (count_active(w, a.active, nhi, st) == 0) break;
   }
-  launch_unpack_fine(G, DD_F64, nrhs, w->x64, (double2*)x_canon, st);
-  if (mg->graphs == 2) DD_HIP(mg->ctx, hipMemcpyAsync(&total_coarse, w->citers, sizeof(int), hipMemcpyDeviceToHost, st));
+  launch_lsq(nhi, m, a.H, a.gv, a.kcyc, a.y, st);
+  const int kmax = max_kcyc(w, a, nhi, st);   // also leaves kcyc in hflags[nhi..]
+  launch_multi_axpy(vt, DD_F64, nhi, cnt, cnt, w->Z, kmax, vsz, a.y, m, 0, 1.0, w->x64, st);
+  for (int r = 0; r < nhi; ++r)
+    if (!fin[r]) {
+      S->iters[r] += w->hflags[nhi + r];
+      S->restarts[r] += 1;
+    }
+  // true residual r = b - D x with the FP64 operator
+  launch_dirac(G, DD_F64, g->ops[DD_F64], nhi, w->x64, w->zt64, st, g->tune.dirac_threads);
+  launch_sub(DD_F64, fine, w->b64, w->zt64, w->w64, st);
+  norms2(w, DD_F64, nhi, cnt, cnt, w->w64, a.nrm2, st);
+  HostArr<double2> n2(nhi);
+  DD_HIP(mg->ctx, hipMemcpyAsync(n2.p, a.nrm2, sizeof(double2) * nhi, hipMemcpyDeviceToHost, st));
   DD_HIP(mg->ctx, hipStreamSynchronize(st));
-  double tsolve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int r = 0; r < nhi; ++r) {
+    if (fin[r]) continue;
+    S->relres[r] = std::sqrt(n2[r].x) / S->bnorm[r];
+    if (!std::isfinite(S->relres[r])) return dd_fail(mg->ctx, DD_ENAN, "breakdown: non-finite residual");
+    if (S->relres[r] <= S->tol) {
+      S->conv[r] = 1;
+      S->state[r] = kSlotDone;
+    } else if (S->iters[r] >= mg->p.max_outer_iters) {
+      S->state[r] = kSlotDone;
+    }
+  }
+  return DD_OK;
+}
+
+static void solve_info(const dd_solve_state* S, int r, dd_solve_info* info) {
+  if (!info) return;
   double mb1, mf1;
   ktimer_model(&mb1, &mf1);
-  bool all = true;
-  for (int r = 0; r < nrhs; ++r) {
-    all = all && fin[r];
-    if (info) {
-      info[r].outer_iters = iters[r];
-      info[r].restarts = restarts[r];
-      info[r].coarse_iters_total = total_coarse;
-      info[r].converged = fin[r];
-      info[r].true_relres = relres[r];
-      info[r].t_setup_s = 0.0;
-      info[r].t_solve_s = tsolve;
-      info[r].bytes_model = (int64_t)(mb1 - mb0);
-      info[r].flops_model = (int64_t)(mf1 - mf0);
-    }
+  info->outer_iters = S->iters[r];
+  info->restarts = S->restarts[r];
+  info->coarse_iters_total = S->total_coarse;
+  info->converged = S->conv[r];
+  info->true_relres = S->relres[r];
+  info->t_setup_s = 0.0;
+  info->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
+  info->bytes_model = (int64_t)(mb1 - S->mb0);
+  info->flops_model = (int64_t)(mf1 - S->mf0);
+}
+
+extern "C" {
+
+dd_status dd_solve_begin(dd_mg* mg, int capacity, double tol, void* stream, dd_solve_state** out) {
+  if (!mg || !out) return DD_EINVAL;
+  *out = nullptr;
+  if (capacity < 1 || !(tol > 0.0)) return dd_fail(mg->ctx, DD_EINVAL, "bad solve arguments");
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
+  dd_status s = ensure_ws(mg, capacity, true);
+  if (s) return s;
+  dd_solve_state* S = new dd_solve_state();
+  S->mg = mg;
+  S->cap = capacity;
+  S->tol = tol;
+  S->st = (hipStream_t)stream;
+  S->state.assign(capacity, kSlotFree);
+  S->conv.assign(capacity, 0);
+  S->iters.assign(capacity, 0);
+  S->restarts.assign(capacity, 0);
+  S->bnorm.assign(capacity, 0.0);
+  S->relres.assign(capacity, 1.0);
+  S->t0 = std::chrono::steady_clock::now();
+  ktimer_model(&S->mb0, &S->mf0);
+  if (mg->graphs == 2) launch_zero(mg->ws->citers, sizeof(int), S->st);   // coarse steps counted on the device
+  mg->live = S;
+  *out = S;
+  return DD_OK;
+}
+
+dd_status dd_solve_add(dd_solve_state* S, int slot, const double* b_canon_dev) {
+  if (!S) return DD_EINVAL;
+  if (slot < 0 || slot >= S->cap || !b_canon_dev) return dd_fail(S->mg->ctx, DD_EINVAL, "bad slot or source");
+  if (S->state[slot] != kSlotFree) return dd_fail(S->mg->ctx, DD_ESTATE, "slot " + std::to_string(slot) + " is in use");
+  return solve_add(S, slot, b_canon_dev);
+}
+
+dd_status dd_solve_step(dd_solve_state* S, int32_t* slot_state) {
+  if (!S) return DD_EINVAL;
+  dd_status s = solve_step(S);
+  if (slot_state)
+    for (int r = 0; r < S->cap; ++r) slot_state[r] = S->state[r];
+  return s;
+}
+
+dd_status dd_solve_take(dd_solve_state* S, int slot, double* x_canon_dev, dd_solve_info* info) {
+  if (!S) return DD_EINVAL;
+  if (slot < 0 || slot >= S->cap || !x_canon_dev) return dd_fail(S->mg->ctx, DD_EINVAL, "bad slot or output");
+  if (S->state[slot] != kSlotDone) return dd_fail(S->mg->ctx, DD_ESTATE, "slot " + std::to_string(slot) + " is not done");
+  dd_mg* mg = S->mg;
+  const long long cnt = 12LL * mg->g->geo.V;
+  launch_unpack_fine(mg->g->geo, DD_F64, 1, mg->ws->x64 + (size_t)slot * cnt, (double2*)x_canon_dev, S->st);
+  if (mg->graphs == 2)
+    DD_HIP(mg->ctx, hipMemcpyAsync(&S->total_coarse, mg->ws->citers, sizeof(int), hipMemcpyDeviceToHost, S->st));
+  DD_HIP(mg->ctx, hipStreamSynchronize(S->st));
+  solve_info(S, slot, info);
+  S->state[slot] = kSlotFree;
+  return DD_OK;
+}
+
+dd_status dd_solve_end(dd_solve_state* S) {
+  if (!S) return DD_EINVAL;
+  if (S->mg->live == S) S->mg->live = nullptr;
+  delete S;
+  return DD_OK;
+}
+
+dd_status dd_solve(dd_mg* mg, int nrhs, const double* b_canon, double* x_canon, double tol, dd_solve_info* info,
+                   void* stream) {
+  if (!mg) return DD_EINVAL;
+  if (!b_canon || !x_canon || nrhs < 1 || !(tol > 0.0)) return dd_fail(mg->ctx, DD_EINVAL, "bad solve arguments");
+  dd_solve_state* S = nullptr;
+  dd_status s = dd_solve_begin(mg, nrhs, tol, stream, &S);
+  if (s) return s;
+  const long long cnt = 12LL * mg->g->geo.V;
+  for (int r = 0; r < nrhs && !s; ++r) s = solve_add(S, r, b_canon + 2 * (size_t)r * cnt);
+  bool running = true;
+  while (!s && running) {
+    s = solve_step(S);
+    running = false;
+    for (int r = 0; r < nrhs; ++r) running = running || S->state[r] == kSlotRunning;
   }
+  bool all = true;
+  for (int r = 0; r < nrhs && !s; ++r) {
+    all = all && S->conv[r];
+    s = dd_solve_take(S, r, x_canon + 2 * (size_t)r * cnt, info ? info + r : nullptr);
+  }
+  dd_solve_end(S);
+  if (s) return s;
   if (!all) return dd_fail(mg->ctx, DD_ENOCONV, "max_outer_iters reached before every right-hand side converged");
   return DD_OK;
 }

@@ -370,7 +370,10 @@ __global__ void __launch_bounds__(256) k_gs_axpy_norm(int nrhs, long long count,
         threadIdx.x == 0 ? red[0] + red[1] + red[2] + red[3] : 0.0;
 }
 
-// dst[r] = src[r] / sqrt(nrm[r].x) where mask[r] != 0 (mask may be null); zero norm gives zero
+// dst[r] = src[r] / sqrt(nrm[r].x) where mask[r] != 0 (mask may be null); zero norm gives zero,
+// and so does a masked-off r: whatever a finished or unused slot held before,
+// the preconditioner then sees zeros there, never stale or uninitialised words
+// (which x += 0 * M(v) would carry into a finished solution as NaN)
 template <typename Ts, typename Td>
 __global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, long long rs, const Ts* __restrict__ src,
                                                    const double2* __restrict__ nrm2, const double* __restrict__ nrm,
@@ -378,13 +381,13 @@ __global__ void __launch_bounds__(256) k_normalize(int nrhs, long long count, lo
                                                    float2* __restrict__ copy32, Gate gt) {
   if (gate_closed(gt)) return;
   const int r = blockIdx.y;
-  if (mask && !mask[r]) return;
+  const bool on = !(mask && !mask[r]);
   double n = nrm ? nrm[r] : sqrt(nrm2[r].x);
   double s = n > 0.0 ? 1.0 / n : 0.0;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (long long)gridDim.x * blockDim.x) {
-    cx<double> v = ld<double, Ts>(src + (long long)r * rs + e);
+    cx<double> v = on ? s * ld<double, Ts>(src + (long long)r * rs + e) : cx<double>{0.0, 0.0};
     Td q;
-    st<Td, double>(&q, s * v);
+    st<Td, double>(&q, v);
     dst[(long long)r * rs + e] = q;
     if (copy32) {   // the stored (rounded) value, widened to FP32
       const cx<float> f = ld<float, Td>(&q);

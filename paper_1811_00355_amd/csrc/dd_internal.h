@@ -7,6 +7,7 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -314,8 +315,8 @@ __host__ __device__ __forceinline__ long long lex_site(const GeomDev& g, const S
 struct dd_ctx {
   int device;
   size_t budget;
-  size_t in_use;
-  std::string last_error;
+  size_t in_use;             // guarded by mu: threads that drive different solvers share one context
+  std::mutex mu;
   void* scratch = nullptr;   // device address of this device's static scratch array (allocation-free calls)
 };
 
@@ -381,12 +382,14 @@ struct dd_mg {
   void* Dinvh = nullptr;
   Workspace* ws = nullptr;
   int graphs = 0;   // 0: launches; 1: coarse GMRES chunks replayed from graphs; 2: all of M from one graph
+  dd_solve_state* live = nullptr;   // the stepwise solve that holds the workspace, if any
 };
 
 // ---------------------------------------------------------------------------
 // error handling
 // ---------------------------------------------------------------------------
 dd_status dd_fail(dd_ctx* ctx, dd_status s, const std::string& msg);
+size_t ctx_in_use(dd_ctx* ctx);   // bytes reserved against the budget (locked read)
 dd_status dd_hip_check(dd_ctx* ctx, hipError_t e, const char* what);
 #define DD_HIP(ctx, call)                                            \
   do {                                                               \

@@ -1,4 +1,4 @@
-"""Serving loop for batches of Wilson-clover solves (one GPU).
+"""Serving loop for Wilson-clover solves on one GPU, with continuous batching.
 
 Requests arrive as a Poisson stream.  Each asks for `nrhs` solves D x = b on one
 gauge field (lattice shape, link roughness, bare mass).  The paper's accounting
@@ -6,24 +6,31 @@ gauge field (lattice shape, link roughness, bare mass).  The paper's accounting
 per-field setup cache pay: the first request on a field pays for the upload
 and the setup, later ones reuse them.
 
+* Lanes: a field being solved has one lane, a solve state of `capacity` slots
+  (right-hand sides) on its own HIP stream and host thread.  A lane advances
+  one FGMRES restart cycle per step; lanes on different fields run at the same
+  time, so their kernels overlap on the device.
+* Joining: a request on a field whose lane runs and has free slots joins it at
+  the lane's next restart boundary; slots freed by finished right-hand sides
+  are reused.  Every reduction and mask of the solver is per slot, so a result
+  has the same bits alone, in a batch, or joined mid-run.
 * Setup cache: gauge field + multigrid setup stay resident on the device, keyed
-  by field, least recently used first out.
-* Admission: a request is started only when the HBM footprint of its field
-  (cached or not) plus the solver workspace of its batch fits the budget; idle
-  cached fields are evicted to make room; a request that cannot fit even on an
-  empty device is rejected.
-* Continuous batching: whenever the device is free, the oldest waiting request
-  is taken together with every other waiting request on the same field, up to
-  `max_rhs` right-hand sides, as one batched solve.  The solver reduces each
-  right-hand side in an order independent of the batch and masks converged
-  ones, so every request gets the same bits alone or in any batch.
+  by field, least recently used idle field evicted first.
+* Admission: a lane opens only when its field's footprint (if not cached), the
+  scratch of its setup and the workspace of its slots fit the HBM budget beside
+  the resident fields and the other lanes; the oldest request that is blocked
+  for memory holds a reservation that later requests may not eat into.  A
+  request that cannot fit on an empty device is rejected.
 * Latency runs from arrival to the solution being back in host memory.
 
 The scheduler is plain host logic driven through an executor object; the GPU
-executor calls the library, and tests drive the same scheduler with a CPU fake.
+executor calls the library (dd_solve_begin/add/step/take/end), and tests drive
+the same scheduler with a CPU fake on a virtual clock.
 """
 import dataclasses
 import math
+import queue as _queue
+import threading
 import time
 from collections import OrderedDict
 
@@ -75,9 +82,11 @@ class Done:
     arrival: float
     start: float
     finish: float
-    batch_rhs: int
+    batch_rhs: int          # most slots of its lane running at once while it ran
     setup_miss: bool
     relres: list
+    lane: int = -1
+    joined: bool = False    # added to a lane that was already running
 
     @property
     def latency(self):
@@ -116,91 +125,227 @@ def make_requests(n, rate, shapes, field_pool, rng_seed=5001, reuse_prob=0.3, ma
 # ----------------------------------------------------------------------------
 # scheduler
 # ----------------------------------------------------------------------------
+class Lane:
+    """One field being solved: `capacity` slots, at most one job in flight."""
+
+    def __init__(self, lid, field, capacity, mem, miss):
+        self.lid, self.field, self.capacity = lid, field, capacity
+        self.mem = mem                   # bytes charged to the lane (workspace; setup scratch while opening)
+        self.miss = miss
+        self.slots = [None] * capacity   # (rid, j) of the right-hand side in each slot
+        self.waiting = []                # requests assigned, added at the next step
+        self.state = "opening"           # opening -> running -> closing
+        self.peak = 0
+
+    def free_slots(self):
+        return sum(s is None for s in self.slots) - sum(r.nrhs for r in self.waiting)
+
+    def running(self):
+        return sum(s is not None for s in self.slots)
+
+
 class Server:
     """Runs a request list through an executor.
 
     The executor provides:
-      footprint(field)            -> bytes of the field's gauge + setup (resident)
-      transient(field)            -> bytes needed only while its setup runs
-      workspace(field, nrhs)      -> bytes of a batch's solver workspace (freed after the batch)
-      load(field)                 -> handle          (upload + setup)
-      solve(handle, field, reqs)  -> [relres list per request]  (results on the host)
-      free(handle)
-      now()                       -> seconds (monotonic)
-      sleep_until(t)              -> wait for the clock (the fake advances it)
+      footprint(field)             -> bytes of the field's gauge + setup (resident while cached)
+      transient(field)             -> bytes needed only while its setup runs
+      workspace(field, capacity)   -> bytes of a lane's solver workspace (freed when the lane closes)
+      open(lid, field, handle, capacity)  async: load the field if handle is None, start a solve state
+      step(lid, adds)              async: add [(slot, request, j)], one restart cycle, take finished slots
+      close(lid)                   async: end the solve state, free the workspace
+      free(handle)                 drop an idle cached field
+      now()                        -> seconds (monotonic)
+      wait_event(deadline)         -> the next finished job (kind, lid, payload, error, t) or None
+                                      once the clock reaches `deadline` (None: wait for a job)
+    Job payloads: open -> handle; step -> {slot: true relative residual} of the slots it finished.
     """
 
-    def __init__(self, executor, hbm_budget, max_rhs=12, log=None):
+    def __init__(self, executor, hbm_budget, max_rhs=12, max_lanes=4, log=None):
         self.ex = executor
         self.budget = hbm_budget
         self.max_rhs = max_rhs
-        self.cache = OrderedDict()     # field key -> (handle, bytes)
-        self.resident = 0
+        self.max_lanes = max_lanes
+        self.cache = OrderedDict()     # field key -> [handle, bytes, lanes using it]
+        self.resident = 0              # bytes of cached fields (reserved from the moment a load starts)
+        self.inuse = 0                 # bytes charged to open lanes
+        self.peak_bytes = 0
         self.log = log or (lambda *a: None)
         self.rejected = []
+        self.failed = []
         self.evictions = 0
+        self.lanes = {}                # field key -> Lane
+        self._lid = 0
+
+    # -- memory ------------------------------------------------------------------
+    def _idle_bytes(self, keep):
+        return sum(b for k, (h, b, u) in self.cache.items() if u == 0 and k != keep)
 
     def _evict_for(self, need, keep):
-        while self.resident + need > self.budget:
-            victim = next((k for k in self.cache if k != keep), None)
+        while self.resident + self.inuse + need > self.budget:
+            victim = next((k for k, (h, b, u) in self.cache.items() if u == 0 and k != keep), None)
             if victim is None:
                 return False
-            h, b = self.cache.pop(victim)
+            h, b, _ = self.cache.pop(victim)
             self.ex.free(h)
             self.resident -= b
             self.evictions += 1
         return True
 
-    def _form_batch(self, queue):
-        """Oldest request first, then every waiting request on its field, in
-        arrival order, while the right-hand sides fit."""
-        head = queue[0]
-        batch, total = [], 0
-        for r in queue:
-            if r.field.key == head.field.key and total + r.nrhs <= self.max_rhs:
-                batch.append(r)
-                total += r.nrhs
-        return batch
+    # -- admission ---------------------------------------------------------------
+    def _schedule(self, queue, now):
+        reserved = 0
+        for r in list(queue):
+            if r not in queue:
+                continue
+            f = r.field
+            lane = self.lanes.get(f.key)
+            if lane is not None:
+                if lane.state != "closing" and lane.free_slots() >= r.nrhs:
+                    lane.waiting.append(r)
+                    queue.remove(r)
+                    self._start[r.rid] = [None, lane.lid, lane.state == "running"]
+                continue
+            if len(self.lanes) >= self.max_lanes:
+                continue
+            cached = f.key in self.cache
+            fb = 0 if cached else self.ex.footprint(f)
+            tr = 0 if cached else self.ex.transient(f)
+
+            def need(c):
+                return fb + max(self.ex.workspace(f, c), tr)
+
+            held = 0 if not cached else self.cache[f.key][1]
+            if held + need(r.nrhs) > self.budget:
+                queue.remove(r)
+                self.rejected.append(r.rid)
+                self.log(f"[serve] rejected {r.rid}: {need(r.nrhs):.3e} B over budget")
+                continue
+            avail = self.budget - self.resident - self.inuse + self._idle_bytes(f.key) - reserved
+            batch, nb = [], 0
+            for q in queue:
+                if q.field.key == f.key and nb + q.nrhs <= self.max_rhs:
+                    batch.append(q)
+                    nb += q.nrhs
+            cap = next((c for c in (self.max_rhs, nb, r.nrhs) if need(c) <= avail), None)
+            if cap is None:
+                if reserved == 0:
+                    reserved = need(r.nrhs)   # the oldest blocked request keeps its place
+                continue
+            self._evict_for(need(cap), f.key)
+            lane = Lane(self._lid, f, cap, max(self.ex.workspace(f, cap), tr), not cached)
+            self._lid += 1
+            if cached:
+                self.cache[f.key][2] += 1
+                self.cache.move_to_end(f.key)
+            else:
+                self.cache[f.key] = [None, fb, 1]
+                self.resident += fb
+            self.inuse += lane.mem
+            self.peak_bytes = max(self.peak_bytes, self.resident + self.inuse)
+            nb = 0
+            for q in batch:
+                if nb + q.nrhs <= cap:
+                    lane.waiting.append(q)
+                    queue.remove(q)
+                    self._start[q.rid] = [now, lane.lid, False]   # the lane's setup is part of its service
+                    nb += q.nrhs
+            self.lanes[f.key] = lane
+            self.ex.open(lane.lid, f, self.cache[f.key][0], cap)
+            self.log(f"[serve] t={now:7.2f}s lane {lane.lid} opens on {f.key} L={f.L} capacity {cap} "
+                     f"({'setup' if lane.miss else 'cached'}), {nb} rhs")
+
+    def _step(self, lane, now):
+        adds = []
+        free = [i for i, s in enumerate(lane.slots) if s is None]
+        for r in lane.waiting:
+            for j in range(r.nrhs):
+                k = free.pop(0)
+                lane.slots[k] = (r.rid, j)
+                adds.append((k, r, j))
+            if self._start[r.rid][0] is None:
+                self._start[r.rid][0] = now  # a join is on the device from this restart boundary on
+        lane.waiting = []
+        lane.peak = max(lane.peak, lane.running())
+        for rid in {s[0] for s in lane.slots if s is not None}:
+            self._peak[rid] = max(self._peak.get(rid, 0), lane.running())
+        self.ex.step(lane.lid, adds)
+
+    def _finish_lane(self, lane, key):
+        self.inuse -= lane.mem
+        del self.lanes[key]
+        if key in self.cache:
+            self.cache[key][2] -= 1
+
+    # -- events ------------------------------------------------------------------
+    def _handle(self, ev, queue, done, t0):
+        kind, lid, payload, err, t = ev
+        now = t - t0
+        lane = next(ln for ln in self.lanes.values() if ln.lid == lid)
+        key = lane.field.key
+        if err is not None:
+            rids = {s[0] for s in lane.slots if s is not None} | {r.rid for r in lane.waiting}
+            self.failed.extend(sorted(rids))
+            for rid in rids:
+                self._res.pop(rid, None)
+            self.log(f"[serve] lane {lid} ({key}) failed in {kind}: {err}")
+            if kind == "open" and lane.miss:
+                _, b, _ = self.cache.pop(key)
+                self.resident -= b
+                self.inuse -= lane.mem
+                del self.lanes[key]
+            else:
+                self._finish_lane(lane, key)
+            return
+        if kind == "open":
+            self.cache[key][0] = payload
+            ws = self.ex.workspace(lane.field, lane.capacity)
+            self.inuse -= lane.mem - ws      # the setup's scratch is gone
+            lane.mem = ws
+            lane.state = "running"
+            self._step(lane, now)
+        elif kind == "step":
+            for slot, rr in payload.items():
+                rid, j = lane.slots[slot]
+                lane.slots[slot] = None
+                self._res[rid][j] = rr
+                if all(v is not None for v in self._res[rid]):
+                    r = self._req[rid]
+                    st, _, joined = self._start[rid]
+                    done.append(Done(rid, key, r.nrhs, r.arrival, st, now, self._peak.get(rid, r.nrhs),
+                                     lane.miss and not joined, self._res.pop(rid), lid, joined))
+            self._schedule(queue, now)       # same-field arrivals join at this restart boundary
+            if lane.running() or lane.waiting:
+                self._step(lane, now)
+            else:
+                lane.state = "closing"
+                self.ex.close(lid)
+        elif kind == "close":
+            self._finish_lane(lane, key)
+            self.log(f"[serve] t={now:7.2f}s lane {lid} on {key} closes (peak {lane.peak} rhs) queue {len(queue)}")
 
     def run(self, requests):
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        self._req = {r.rid: r for r in pending}
+        self._res = {r.rid: [None] * r.nrhs for r in pending}
+        self._start, self._peak = {}, {}
         queue, done = [], []
         t0 = self.ex.now()
         i = 0
-        while i < len(pending) or queue:
+        while i < len(pending) or queue or self.lanes:
             now = self.ex.now() - t0
             while i < len(pending) and pending[i].arrival <= now:
                 queue.append(pending[i])
                 i += 1
-            if not queue:
-                self.ex.sleep_until(t0 + pending[i].arrival)
-                continue
-            batch = self._form_batch(queue)
-            f = batch[0].field
-            nrhs = sum(r.nrhs for r in batch)
-            ws = self.ex.workspace(f, nrhs)
-            miss = f.key not in self.cache
-            fb = self.ex.footprint(f) if miss else 0
-            tr = self.ex.transient(f) if miss else 0
-            need = fb + max(ws, tr)
-            if need > self.budget or not self._evict_for(need, f.key):
-                for r in batch:
-                    queue.remove(r)
-                    self.rejected.append(r.rid)
-                self.log(f"[serve] rejected {[r.rid for r in batch]}: {need:.3e} B over budget")
-                continue
-            start = self.ex.now() - t0
-            if miss:
-                self.cache[f.key] = (self.ex.load(f), fb)
-                self.resident += fb
-            self.cache.move_to_end(f.key)
-            relres = self.ex.solve(self.cache[f.key][0], f, batch)
-            finish = self.ex.now() - t0
-            for r, rr in zip(batch, relres):
-                queue.remove(r)
-                done.append(Done(r.rid, f.key, r.nrhs, r.arrival, start, finish, nrhs, miss, rr))
-            self.log(f"[serve] t={finish:7.2f}s field {f.key} L={f.L} batch {len(batch)} req / {nrhs} rhs "
-                     f"{'setup+' if miss else ''}solve {finish - start:.3f}s queue {len(queue)}")
+            self._schedule(queue, now)
+            if not self.lanes and queue:
+                continue                      # an empty device admits or rejects the head at once
+            deadline = t0 + pending[i].arrival if i < len(pending) else None
+            if deadline is None and not self.lanes:
+                break
+            ev = self.ex.wait_event(deadline)
+            if ev is not None:
+                self._handle(ev, queue, done, t0)
         return done
 
 
@@ -211,21 +356,119 @@ def summarize(done, wall):
                 mean_s=round(float(lat.mean()), 4),
                 solves_per_s=round(sum(d.nrhs for d in done) / max(wall, 1e-9), 3),
                 setup_misses=int(sum(d.setup_miss for d in done)),
+                joined=int(sum(d.joined for d in done)),
                 mean_batch_rhs=round(float(np.mean([d.batch_rhs for d in done])) if done else 0.0, 2),
                 max_relres=float(max((max(d.relres) for d in done), default=0.0)))
+
+
+def overlap_seconds(intervals):
+    """Time covered by at least two lanes' intervals at once, from (lane, start, end) triples."""
+    pts = sorted([(s, 1, ln) for ln, s, e in intervals] + [(e, -1, ln) for ln, s, e in intervals])
+    active, total, last = {}, 0.0, None
+    for t, d, ln in pts:
+        if last is not None and sum(1 for v in active.values() if v > 0) >= 2:
+            total += t - last
+        active[ln] = active.get(ln, 0) + d
+        last = t
+    return total
 
 
 # ----------------------------------------------------------------------------
 # GPU executor
 # ----------------------------------------------------------------------------
+class _LaneWorker(threading.Thread):
+    """Host thread of one lane: its jobs run in order on its own HIP stream."""
+
+    def __init__(self, ex, lid):
+        super().__init__(daemon=True)
+        import torch
+        self.ex, self.lid = ex, lid
+        self.jobs = _queue.Queue()
+        self.stream = torch.cuda.Stream()
+        self.field = self.handle = self.state = None
+        self.slot_req = {}
+
+    def run(self):
+        while True:
+            kind, args = self.jobs.get()
+            try:
+                payload, err = getattr(self, "_" + kind)(*args), None
+            except Exception as e:   # reported to the scheduler; the lane cleans up and stops
+                payload, err = None, e
+                self._cleanup(kind)
+            self.ex.events.put((kind, self.lid, payload, err, time.perf_counter()))
+            if kind == "close" or err is not None:
+                return
+
+    def _cleanup(self, kind):
+        try:
+            if self.state is not None:
+                self.state.end()
+                self.state = None
+            if self.handle is not None and kind != "open":
+                self.handle[1].dd_mg_release_workspace()
+        except Exception:
+            pass
+
+    def _open(self, f, handle, capacity):
+        self.field = f
+        fresh = handle is None
+        if fresh:
+            handle = self.ex.load(f)
+        try:
+            self.state = handle[1].dd_solve_begin(capacity, self.ex.tol, self.stream)
+        except Exception:
+            if fresh:                  # the scheduler drops a field whose lane failed to open
+                self.ex.free(handle)
+            raise
+        self.handle = handle
+        return handle
+
+    def _step(self, adds):
+        import torch
+        from . import binding as B
+        ex, f = self.ex, self.field
+        with torch.cuda.stream(self.stream):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(self.stream)
+            src = {}
+            for slot, r, j in adds:
+                if r.rid not in src:
+                    src[r.rid] = ex.sources(f, r)
+                self.state.add(slot, src[r.rid][j])
+                self.slot_req[slot] = (r.rid, j, r.nrhs)
+            states = self.state.step()
+            out = {}
+            for slot, s in enumerate(states):
+                if s != B.SLOT_DONE:
+                    continue
+                x = torch.empty(f.V * 12, dtype=torch.complex128, device="cuda")
+                info = self.state.take(slot, x)
+                out[slot] = info["true_relres"]
+                rid, j, nrhs = self.slot_req.pop(slot)
+                if ex.keep_x:
+                    xs = ex.results.setdefault(rid, torch.zeros((nrhs, f.V * 12), dtype=torch.complex128))
+                    xs[j] = x.cpu()
+            e1.record(self.stream)
+        ex.intervals.append((self.lid, e0, e1))
+        return out
+
+    def _close(self):
+        self.state.end()
+        self.state = None
+        self.handle[1].dd_mg_release_workspace()
+
+
 class GpuExecutor:
-    """Runs batches through the library on cuda:0.  Links are generated on the
-    host before the run (excluded from latency); sources are drawn on the
-    device from a per-request seed."""
+    """Runs lanes through the library on cuda:0, one host thread and HIP stream
+    per lane.  Links are generated on the host before the run (excluded from
+    latency); sources are drawn on the device from a per-request seed."""
 
     def __init__(self, ctx, links, block=(4, 4, 4, 4), n_vec=20, store="f32", c_sw=1.0, setup_iters=4,
                  tol=1e-10, graphs=True, tune_cache=None):
         from . import binding as B
+        import torch
         self.B = B
         self.ctx = ctx
         self.links = links            # field key -> host links [V][4][3][3]
@@ -239,6 +482,11 @@ class GpuExecutor:
         self.tune_cache = tune_cache
         self.keep_x = False           # keep each request's solution (host) in self.results
         self.results = {}
+        self.events = _queue.Queue()
+        self.workers = {}
+        self.intervals = []           # (lane, start event, end event) of every step, on the lane's stream
+        self.t_origin = torch.cuda.Event(enable_timing=True)
+        self.t_origin.record()
 
     def _fp(self, f, nrhs=1):
         return library_footprint(f.L, self.block, self.n, self.store, nrhs)
@@ -278,21 +526,17 @@ class GpuExecutor:
         im = torch.randn((r.nrhs, f.V * 12), generator=gen, device="cuda", dtype=torch.float64)
         return torch.complex(re, im)
 
-    def solve(self, h, f, reqs):
-        import torch
-        g, mg = h
-        b = torch.cat([self.sources(f, r) for r in reqs], 0)
-        x = torch.zeros_like(b)
-        info, st = mg.dd_solve(b.shape[0], b, x, self.tol, raise_on_noconv=False)
-        xh = x.cpu()                  # the results are back on the host
-        mg.dd_mg_release_workspace()
-        out, k = [], 0
-        for r in reqs:
-            out.append([info[k + j]["true_relres"] for j in range(r.nrhs)])
-            if self.keep_x:
-                self.results[r.rid] = xh[k:k + r.nrhs]
-            k += r.nrhs
-        return out
+    def open(self, lid, f, handle, capacity):
+        w = _LaneWorker(self, lid)
+        self.workers[lid] = w
+        w.start()
+        w.jobs.put(("open", (f, handle, capacity)))
+
+    def step(self, lid, adds):
+        self.workers[lid].jobs.put(("step", (adds,)))
+
+    def close(self, lid):
+        self.workers[lid].jobs.put(("close", ()))
 
     def free(self, h):
         g, mg = h
@@ -302,10 +546,24 @@ class GpuExecutor:
     def now(self):
         return time.perf_counter()
 
-    def sleep_until(self, t):
-        d = t - time.perf_counter()
-        if d > 0:
-            time.sleep(d)
+    def wait_event(self, deadline):
+        try:
+            if deadline is None:
+                ev = self.events.get()
+            else:
+                ev = self.events.get(timeout=max(0.0, deadline - time.perf_counter()))
+        except _queue.Empty:
+            return None
+        if ev[0] == "close" or ev[3] is not None:
+            self.workers.pop(ev[1]).join()
+        return ev
+
+    def device_intervals(self):
+        """(lane, start s, end s) of every step on the device, from the HIP events."""
+        import torch
+        torch.cuda.synchronize()
+        return [(ln, self.t_origin.elapsed_time(a) * 1e-3, self.t_origin.elapsed_time(b) * 1e-3)
+                for ln, a, b in self.intervals]
 
 
 # ----------------------------------------------------------------------------
@@ -314,20 +572,42 @@ class GpuExecutor:
 SHAPES = [(8, 8, 8, 8), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
 
 
-def field_pool(per_shape, seed0=6000):
-    """Fields per shape: seed 6000 + k, link roughness drawn from the tuned set
-    {0.15, 0.2, 0.25}, with the bare mass tuned for that roughness."""
+def m0_for_eps(eps):
+    """Bare mass for a link roughness: piecewise linear through the tuned
+    (roughness, mass) pairs of the 16^3x32, 32^3x64 and 48^3x96 workloads,
+    extended linearly past the ends."""
     from workloads import get_config
-    tuned = {get_config(c)["eps"]: get_config(c)["m0"] for c in ("C2", "C3", "C4")}
-    epss = sorted(tuned)
+    pts = sorted((get_config(c)["eps"], get_config(c)["m0"]) for c in ("C2", "C3", "C4"))
+    xs, ys = [p[0] for p in pts], [p[1] for p in pts]
+    k = 0 if eps <= xs[1] else 1
+    return ys[k] + (ys[k + 1] - ys[k]) * (eps - xs[k]) / (xs[k + 1] - xs[k])
+
+
+def field_pool(per_shape, seed0=6000, eps_range=(0.15, 0.3)):
+    """Fields per shape: seed 6000 + k, link roughness uniform on eps_range
+    (drawn from the same seed), bare mass from m0_for_eps."""
     pool, k = {}, 0
     for L in SHAPES:
         pool[L] = []
         for j in range(per_shape):
-            eps = epss[(k * 7 + j) % len(epss)]
-            pool[L].append(FieldSpec(f"{'x'.join(map(str, L))}#{j}", L, eps, tuned[eps], seed0 + k))
+            eps = float(np.random.default_rng(seed0 + k).uniform(*eps_range))
+            pool[L].append(FieldSpec(f"{'x'.join(map(str, L))}#{j}", L, round(eps, 4),
+                                     round(m0_for_eps(round(eps, 4)), 6), seed0 + k))
             k += 1
     return pool
+
+
+def _run_report(ex, srv, reqs, log):
+    n0 = len(ex.intervals)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    res = summarize(done, time.perf_counter() - t0)
+    ivs = ex.device_intervals()[n0:]
+    busy = overlap_seconds([(0, a, b) for _, a, b in ivs] + [(1, a, b) for _, a, b in ivs]) if ivs else 0.0
+    res.update(rejected=len(srv.rejected), failed=len(srv.failed), evictions=srv.evictions,
+               device_busy_s=round(busy, 3), device_overlap_s=round(overlap_seconds(ivs), 3),
+               peak_hbm_gib=round(srv.peak_bytes / 2 ** 30, 2))
+    return done, res
 
 
 def main(argv=None):
@@ -340,7 +620,8 @@ def main(argv=None):
     ap.add_argument("--per-shape", type=int, default=2)
     ap.add_argument("--load", type=float, default=0.7, help="arrival rate as a fraction of measured capacity")
     ap.add_argument("--hbm-gib", type=float, default=230.0)
-    ap.add_argument("--store", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--store", default="bf16", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--max-lanes", type=int, default=4, help="fields solved at once (1: one batch at a time)")
     ap.add_argument("--shapes", default="all", help="'all' or a count of the smallest shapes to use")
     args = ap.parse_args(argv)
     from . import binding as B
@@ -353,30 +634,33 @@ def main(argv=None):
     for L in shapes:
         for f in pool[L]:
             links[f.key] = su3_field(f.L, f.eps, f.seed)
+            log(f"[serve] field {f.key}: eps {f.eps} m0 {f.m0} seed {f.seed}")
     log(f"[serve] {sum(len(v) for v in pool.values())} fields generated on the host in {time.perf_counter() - t0:.1f} s")
-    ctx = B.Context(0, hbm_budget_bytes=int(args.hbm_gib * (1 << 30)))
-    ex = GpuExecutor(ctx, links, store=args.store)
     budget = int(args.hbm_gib * (1 << 30))
+    ctx = B.Context(0, hbm_budget_bytes=budget)
+    ex = GpuExecutor(ctx, links, store=args.store)
     # closed loop: everything queued at t = 0 gives the capacity
     reqs = make_requests(args.capacity_requests, math.inf, shapes, pool, rng_seed=5002)
-    srv = Server(ex, budget, log=log)
-    t0 = time.perf_counter()
-    done = srv.run(reqs)
-    cap = summarize(done, time.perf_counter() - t0)
+    srv = Server(ex, budget, max_lanes=args.max_lanes, log=log)
+    _, cap = _run_report(ex, srv, reqs, log)
     mu = cap["requests"] / cap["wall_s"]
-    log(f"[serve] closed-loop capacity {mu:.3f} requests/s: {cap}")
-    for h, _ in srv.cache.values():
+    log(f"[serve] closed-loop capacity {mu:.3f} requests/s: {json.dumps(cap)}")
+    for h, _, _ in srv.cache.values():
         ex.free(h)
     # open loop at load * capacity
     reqs = make_requests(args.requests, args.load * mu, shapes, pool, rng_seed=5001)
-    srv = Server(ex, budget, log=log)
-    t0 = time.perf_counter()
-    done = srv.run(reqs)
-    res = summarize(done, time.perf_counter() - t0)
+    srv = Server(ex, budget, max_lanes=args.max_lanes, log=log)
+    done, res = _run_report(ex, srv, reqs, log)
+    by_shape = {}
+    for d in done:
+        L = "x".join(map(str, next(f.L for v in pool.values() for f in v if f.key == d.field)))
+        by_shape.setdefault(L, []).append(d.latency)
     res.update(capacity_requests_per_s=round(mu, 4), arrival_rate_per_s=round(args.load * mu, 4),
-               rejected=len(srv.rejected), evictions=srv.evictions, store=args.store,
-               shapes=["x".join(map(str, L)) for L in shapes], fields_per_shape=args.per_shape)
-    for h, _ in srv.cache.values():
+               store=args.store, max_lanes=args.max_lanes, closed_loop=cap,
+               shapes=["x".join(map(str, L)) for L in shapes], fields_per_shape=args.per_shape,
+               p50_by_shape={k: round(float(np.percentile(v, 50)), 3) for k, v in by_shape.items()},
+               p99_by_shape={k: round(float(np.percentile(v, 99)), 3) for k, v in by_shape.items()})
+    for h, _, _ in srv.cache.values():
         ex.free(h)
     ctx.close()
     print(json.dumps(res), flush=True)

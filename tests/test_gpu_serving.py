@@ -1,43 +1,65 @@
-"""Serving on the GPU: requests merged into shared batches get the same bits as
-the same requests solved one by one; every solve meets the residual bar; the
-footprint model bounds what a cached field really holds."""
+"""Serving on the GPU: concurrent lanes overlap on the device and give every
+request the same bits as solving it alone; every solve meets the residual bar;
+the footprint figures are what the library allocates."""
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
-def test_mixed_batches_equal_alone():
+def test_lanes_overlap_on_the_device_and_results_match_alone():
+    """Two fields solved by concurrent lanes (own stream and host thread each):
+    their steps overlap on the device (HIP event intervals), a request that
+    arrives while its field's lane runs joins it at a restart boundary, and
+    every request gets the same bits as when it is served alone."""
+    import time
     import torch
     from paper_1811_00355_amd import Context
     from paper_1811_00355_amd import serving as S
     from workloads import su3_field
-    fields = [S.FieldSpec("8^4#0", (8, 8, 8, 8), 0.25, -0.2, 6101),
-              S.FieldSpec("8^3x16#0", (8, 8, 8, 16), 0.2, -0.15, 6102)]
+    fields = [S.FieldSpec("8^3x16#0", (8, 8, 8, 16), 0.25, -0.25, 6101),
+              S.FieldSpec("8^3x16#1", (8, 8, 8, 16), 0.2, -0.2, 6102)]
     links = {f.key: su3_field(f.L, f.eps, f.seed) for f in fields}
     ctx = Context(0)
-    ex = S.GpuExecutor(ctx, links, n_vec=20, setup_iters=2)
+    ex = S.GpuExecutor(ctx, links, n_vec=20, setup_iters=2, store="bf16")
     ex.keep_x = True
     a, b = fields
-    reqs = [S.Request(0, 0.0, a, 3, 11), S.Request(1, 0.0, b, 5, 12), S.Request(2, 0.0, a, 4, 13),
-            S.Request(3, 0.0, b, 7, 14), S.Request(4, 0.0, a, 5, 15), S.Request(5, 0.0, b, 2, 16)]
+    # warm both fields into the cache so that the timed part is solves only
+    warm = S.Server(ex, 64 << 30, log=print)
+    warm.run([S.Request(100, 0.0, a, 1, 1), S.Request(101, 0.0, b, 1, 2)])
+    # a's first lane is full (3 + 9 slots): request 3 waits and joins when slots free up
+    reqs = [S.Request(0, 0.0, a, 3, 11), S.Request(1, 0.0, b, 5, 12), S.Request(2, 0.0, a, 9, 13),
+            S.Request(3, 0.0, a, 2, 14), S.Request(4, 0.0, b, 4, 15)]
     srv = S.Server(ex, 64 << 30, log=print)
-    before = ctx.bytes_in_use()
-    done = srv.run(reqs)
-    resident = ctx.bytes_in_use() - before
-    model = sum(ex.footprint(f) for f in fields)
-    print(f"resident after the run {resident / 2**20:.1f} MiB, footprint model {model / 2**20:.1f} MiB", flush=True)
-    assert resident == model                       # the model counts every resident byte
-    assert max(max(d.relres) for d in done) <= 1e-10
-    assert any(d.batch_rhs > d.nrhs for d in done), "no request shared a batch"
-    batched = dict(ex.results)
+    srv.cache = warm.cache
+    srv.resident = warm.resident
+    n0 = len(ex.intervals)
+    t0 = time.perf_counter()
+    done = {d.rid: d for d in srv.run(reqs)}
+    wall = time.perf_counter() - t0
+    ivs = ex.device_intervals()[n0:]
+    ov = S.overlap_seconds(ivs)
+    lanes = sorted({ln for ln, _, _ in ivs})
+    print(f"{len(ivs)} steps on lanes {lanes} in {wall:.3f} s; two lanes on the device together for {ov:.3f} s",
+          flush=True)
+    for d in sorted(done.values(), key=lambda d: d.rid):
+        print(f"request {d.rid} lane {d.lane} joined {d.joined} peak {d.batch_rhs} rhs "
+              f"latency {d.latency:.3f} s relres {max(d.relres):.2e}", flush=True)
+    assert sorted(done) == [0, 1, 2, 3, 4] and not srv.rejected and not srv.failed
+    assert len(lanes) >= 2 and ov > 0.0, "lanes did not overlap on the device"
+    assert max(max(d.relres) for d in done.values()) <= 1e-10
+    assert any(d.joined for d in done.values()), "no request joined a running lane"
+    mixed = {rid: ex.results[rid].clone() for rid in done}
     for r in reqs:
-        ex.results.clear()
-        srv.run([S.Request(r.rid, 0.0, r.field, r.nrhs, r.src_seed)])
-        same = torch.equal(ex.results[r.rid], batched[r.rid])
-        print(f"request {r.rid} ({r.field.key}, {r.nrhs} rhs): alone == in batch: {same}", flush=True)
+        ex.results.pop(r.rid, None)
+        solo = S.Server(ex, 64 << 30)
+        solo.cache, solo.resident = srv.cache, srv.resident
+        solo.run([S.Request(r.rid, 0.0, r.field, r.nrhs, r.src_seed)])
+        same = torch.equal(ex.results[r.rid], mixed[r.rid])
+        print(f"request {r.rid} ({r.field.key}, {r.nrhs} rhs): alone == in the mix: {same}", flush=True)
         assert same
-    for h, _ in srv.cache.values():
+    for h, _, _ in srv.cache.values():
         ex.free(h)
+    assert ctx.bytes_in_use() == 0
     ctx.close()
 
 

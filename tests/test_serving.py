@@ -1,5 +1,7 @@
 """Serving scheduler on the host with a fake executor and a virtual clock:
-batching, admission, eviction, latency accounting and the request stream."""
+lanes that overlap, joins at restart boundaries, slot reuse, admission with
+reservations, eviction, failure handling, latency accounting and the request
+stream."""
 import math
 
 import numpy as np
@@ -9,33 +11,66 @@ from paper_1811_00355_amd import serving as S
 
 
 class FakeExecutor:
-    """Virtual clock; setup costs V * 1e-6 s, a solve 1e-3 + V * nrhs * 1e-8 s.
-    Results are a pure function of (request seed, rhs index)."""
+    """Virtual clock; lanes run concurrently.  A setup costs V * 1e-6 s, a step
+    1e-3 + V * 1e-8 s per running slot.  Right-hand side j of a request finishes
+    after 1 + (seed + j) % 3 steps with residual ((seed * 31 + j) % 97) * 1e-13,
+    a pure function of the request."""
 
-    def __init__(self, per_field_bytes=10, ws_per_rhs=1):
+    def __init__(self, footprints=None, ws_per_rhs=1, transient=0, fail_open=()):
         self.t = 0.0
-        self.loads, self.frees, self.batches = [], [], []
-        self.pfb, self.wpr = per_field_bytes, ws_per_rhs
+        self.pending = []                # (t_end, seq, kind, lid, payload, error)
+        self.seq = 0
+        self.fp = footprints or {}
+        self.wpr, self.tr = ws_per_rhs, transient
+        self.fail_open = set(fail_open)
+        self.loads, self.frees, self.steps, self.opens = [], [], [], []
+        self.lanes = {}                  # lid -> (field, {slot: [steps left, relres]})
+        self.busy_until = {}
 
     def footprint(self, f):
-        return self.pfb
+        return self.fp.get(f.key, 10)
 
     def transient(self, f):
-        return 0
+        return self.tr
 
     def workspace(self, f, nrhs):
         return self.wpr * nrhs
 
-    def load(self, f):
-        self.loads.append(f.key)
-        self.t += f.V * 1e-6
-        return f.key
+    def _push(self, lid, dur, kind, payload, error=None):
+        t0 = max(self.t, self.busy_until.get(lid, 0.0))
+        self.busy_until[lid] = t0 + dur
+        self.pending.append((t0 + dur, self.seq, kind, lid, payload, error))
+        self.seq += 1
+        return t0
 
-    def solve(self, h, f, reqs):
-        nrhs = sum(r.nrhs for r in reqs)
-        self.batches.append((f.key, [r.rid for r in reqs], nrhs))
-        self.t += 1e-3 + f.V * nrhs * 1e-8
-        return [[(r.src_seed * 31 + j) % 97 * 1e-13 for j in range(r.nrhs)] for r in reqs]
+    def open(self, lid, f, handle, capacity):
+        self.opens.append((lid, f.key, capacity, handle is None))
+        self.lanes[lid] = (f, {})
+        if f.key in self.fail_open:
+            self._push(lid, 0.0, "open", None, RuntimeError("setup failed"))
+            return
+        dur = 0.0
+        if handle is None:
+            self.loads.append(f.key)
+            handle, dur = f.key, f.V * 1e-6
+        self._push(lid, dur, "open", handle)
+
+    def step(self, lid, adds):
+        f, slots = self.lanes[lid]
+        for slot, r, j in adds:
+            assert slot not in slots
+            slots[slot] = [1 + (r.src_seed + j) % 3, ((r.src_seed * 31 + j) % 97) * 1e-13]
+        dur = 1e-3 + f.V * 1e-8 * len(slots)
+        out = {}
+        for slot in list(slots):
+            slots[slot][0] -= 1
+            if slots[slot][0] == 0:
+                out[slot] = slots.pop(slot)[1]
+        t0 = self._push(lid, dur, "step", out)
+        self.steps.append((lid, t0, t0 + dur, [a[1].rid for a in adds]))
+
+    def close(self, lid):
+        self._push(lid, 0.0, "close", None)
 
     def free(self, h):
         self.frees.append(h)
@@ -43,70 +78,133 @@ class FakeExecutor:
     def now(self):
         return self.t
 
-    def sleep_until(self, t):
-        self.t = max(self.t, t)
+    def wait_event(self, deadline):
+        if self.pending:
+            ev = min(self.pending)
+            if deadline is None or ev[0] <= deadline:
+                self.pending.remove(ev)
+                self.t = max(self.t, ev[0])
+                return (ev[2], ev[3], ev[4], ev[5], self.t)
+        assert deadline is not None, "scheduler waits with nothing in flight"
+        self.t = max(self.t, deadline)
+        return None
 
 
 def F(key, L=(8, 8, 8, 8)):
     return S.FieldSpec(key, L, 0.2, -0.2, 1)
 
 
-def R(rid, t, f, nrhs):
-    return S.Request(rid, t, f, nrhs, 1000 + rid)
+def R(rid, t, f, nrhs, seed=None):
+    return S.Request(rid, t, f, nrhs, 1000 + rid if seed is None else seed)
 
 
-def test_continuous_batching_groups_waiting_requests_of_one_field():
+def expected_relres(r):
+    return [((r.src_seed * 31 + j) % 97) * 1e-13 for j in range(r.nrhs)]
+
+
+def test_lanes_on_different_fields_overlap_and_same_field_arrivals_join():
     a, b = F("a"), F("b")
-    # all waiting at t = 0: a-requests are merged in arrival order up to 12 rhs
-    reqs = [R(0, 0.0, a, 5), R(1, 0.0, b, 3), R(2, 0.0, a, 6), R(3, 0.0, a, 4), R(4, 0.0, b, 2)]
+    # r2 arrives while lane a runs its first restart cycle and joins at the next boundary
+    reqs = [R(0, 0.0, a, 3), R(1, 0.0, b, 2), R(2, 0.005, a, 2)]
     ex = FakeExecutor()
-    done = S.Server(ex, 1000).run(reqs)
-    assert ex.batches[0] == ("a", [0, 2], 11)        # 5 + 6; the next a-request (4) would exceed 12
-    assert ex.batches[1] == ("b", [1, 4], 5)
-    assert ex.batches[2] == ("a", [3], 4)
-    assert sorted(d.rid for d in done) == [0, 1, 2, 3, 4]
-    # results do not depend on the batch a request ran in
-    alone = {}
+    srv = S.Server(ex, 1000)
+    done = {d.rid: d for d in srv.run(reqs)}
+    assert sorted(done) == [0, 1, 2]
+    assert ex.loads == ["a", "b"]                      # one setup per field
+    assert [o[1] for o in ex.opens] == ["a", "b"]      # no second lane for a
+    assert done[2].lane == done[0].lane and done[2].joined and not done[0].joined
+    assert done[2].start == pytest.approx(4096e-6 + 1e-3 + 4096e-8 * 3)   # the end of a's first step
+    assert not done[2].setup_miss and done[0].setup_miss
+    # the two lanes' steps overlap in time
+    ivs = [(lid, t0, t1) for lid, t0, t1, _ in ex.steps]
+    assert S.overlap_seconds(ivs) > 0
+    for d in done.values():
+        assert d.relres == expected_relres(next(r for r in reqs if r.rid == d.rid))
+    assert srv.inuse == 0 and not srv.lanes
+
+
+def test_slots_are_reused_by_waiting_requests():
+    a = F("a")
+    reqs = [R(0, 0.0, a, 3, seed=0), R(1, 0.0, a, 3, seed=1), R(2, 0.0, a, 1, seed=2)]
+    ex = FakeExecutor()
+    srv = S.Server(ex, 1000, max_rhs=4)
+    done = {d.rid: d for d in srv.run(reqs)}
+    assert len(ex.opens) == 1 and ex.opens[0][2] == 4  # one lane of 4 slots
+    # r0 (3) and r2 (1) fill it; r1 (3) joins once three slots are free again
+    assert ex.steps[0][3] == [0, 0, 0, 2]
+    assert done[1].joined and done[1].start > 0
+    assert any(st[3] == [1, 1, 1] for st in ex.steps)
     for r in reqs:
-        ex1 = FakeExecutor()
-        alone[r.rid] = S.Server(ex1, 1000).run([S.Request(r.rid, 0.0, r.field, r.nrhs, r.src_seed)])[0].relres
-    assert all(d.relres == alone[d.rid] for d in done)
+        assert done[r.rid].relres == expected_relres(r)
+    assert max(d.batch_rhs for d in done.values()) <= 4
+
+
+def test_admission_waits_for_memory_and_honours_the_reservation():
+    a, b, c = F("a"), F("b"), F("c")
+    ex = FakeExecutor(footprints={"a": 10, "b": 10, "c": 1}, ws_per_rhs=5)
+    srv = S.Server(ex, 40, max_rhs=4)
+    # lane a takes 10 + 4 * 5 = 30; b needs 10 + 2 * 5 = 20 and waits, holding a
+    # reservation; c (1 + 5) would fit in the 10 left but must not pass b
+    done = {d.rid: d for d in srv.run([R(0, 0.0, a, 2), R(1, 0.0, b, 2), R(2, 0.0, c, 1)])}
+    assert sorted(done) == [0, 1, 2] and not srv.rejected
+    assert done[1].start >= done[0].finish - 1e-12
+    assert done[2].start >= done[1].start
+    assert srv.peak_bytes <= 40
 
 
 def test_setup_cache_and_lru_eviction():
     fa, fb, fc = F("a"), F("b"), F("c")
-    # budget holds two fields (10 B each) plus a 3-rhs workspace
+    # budget holds two fields (10 B each) plus a 3-slot workspace; requests are spaced so lanes close in between
     reqs = [R(0, 0.0, fa, 1), R(1, 1.0, fb, 1), R(2, 2.0, fa, 1), R(3, 3.0, fc, 1), R(4, 4.0, fa, 1),
             R(5, 5.0, fb, 1)]
     ex = FakeExecutor()
-    srv = S.Server(ex, 23)
+    srv = S.Server(ex, 23, max_rhs=3)
     done = srv.run(reqs)
     assert ex.loads == ["a", "b", "c", "b"]         # c evicts b (least recently used); b is loaded again
     assert ex.frees == ["b", "c"]
     assert srv.evictions == 2
     miss = {d.rid: d.setup_miss for d in done}
     assert miss == {0: True, 1: True, 2: False, 3: True, 4: False, 5: True}
+    assert srv.peak_bytes <= 23
 
 
 def test_admission_rejects_what_cannot_fit():
-    ex = FakeExecutor(per_field_bytes=10, ws_per_rhs=5)
+    ex = FakeExecutor(ws_per_rhs=5)
     srv = S.Server(ex, 30)
     done = srv.run([R(0, 0.0, F("a"), 2), R(1, 0.0, F("b"), 5), R(2, 0.0, F("c"), 4)])
     assert srv.rejected == [1]                       # 10 + 25 > 30
     assert sorted(d.rid for d in done) == [0, 2]
 
 
+def test_a_failed_setup_releases_its_reservation():
+    ex = FakeExecutor(fail_open=["b"])
+    srv = S.Server(ex, 1000)
+    done = srv.run([R(0, 0.0, F("a"), 2), R(1, 0.0, F("b"), 3), R(2, 0.01, F("b"), 1)])
+    assert srv.failed == [1, 2]                      # each lane on b fails to open; nothing else is lost
+    assert [o[1] for o in ex.opens].count("b") == 2
+    assert [d.rid for d in done] == [0]
+    assert "b" not in srv.cache and srv.resident == 10 and srv.inuse == 0
+
+
 def test_latency_is_arrival_to_finish_with_idle_gaps():
     f = F("a", (4, 4, 4, 4))
-    reqs = [R(0, 0.5, f, 2), R(1, 10.0, f, 1)]
+    # seeds chosen so every right-hand side finishes in its first step
+    reqs = [R(0, 0.5, f, 1, seed=0), R(1, 10.0, f, 1, seed=3)]
     ex = FakeExecutor()
     done = {d.rid: d for d in S.Server(ex, 100).run(reqs)}
-    setup, solve2, solve1 = 256e-6, 1e-3 + 256 * 2e-8, 1e-3 + 256e-8
+    setup, step = 256e-6, 1e-3 + 256e-8
     assert done[0].start == pytest.approx(0.5)
-    assert done[0].latency == pytest.approx(setup + solve2)
-    assert done[1].latency == pytest.approx(solve1)   # cached field, idle device
-    s = S.summarize(list(done.values()), 10.0 + solve1)
-    assert s["requests"] == 2 and s["rhs"] == 3 and s["setup_misses"] == 1
+    assert done[0].latency == pytest.approx(setup + step)
+    assert done[1].latency == pytest.approx(step)    # cached field, idle device
+    s = S.summarize(list(done.values()), 10.0 + step)
+    assert s["requests"] == 2 and s["rhs"] == 2 and s["setup_misses"] == 1
+
+
+def test_overlap_seconds():
+    assert S.overlap_seconds([(0, 0.0, 1.0), (1, 0.5, 2.0)]) == pytest.approx(0.5)
+    assert S.overlap_seconds([(0, 0.0, 1.0), (0, 0.5, 2.0)]) == 0.0    # one lane with itself
+    assert S.overlap_seconds([(0, 0.0, 1.0), (1, 1.0, 2.0)]) == 0.0
+    assert S.overlap_seconds([(0, 0.0, 3.0), (1, 1.0, 2.0), (2, 1.5, 4.0)]) == pytest.approx(2.0)
 
 
 def test_request_stream_statistics():
@@ -134,7 +232,6 @@ def test_library_footprint_figures():
     """dd_footprint_bytes (host arithmetic, no device): the large terms of each
     figure at 32^3x64, n = 20, against the layouts they count."""
     import os
-    import pytest
     from paper_1811_00355_amd import binding as B
     if not os.path.exists(B.LIB_PATH):
         pytest.skip("libdd.so not built")
