@@ -422,6 +422,17 @@ class MG:
         """A stepwise solve with `capacity` slots on this multigrid's workspace."""
         return SolveState(self, capacity, tol, stream)
 
+    def export_coarse(self):
+        nc = 2 * self.n
+        dc = np.zeros((self.g.Vc, 9, nc, nc), dtype=np.complex128)
+        self.ctx.check(self.ctx.lib.dd_export_coarse(self.h, dc.ctypes.data_as(_P)))
+        return dc
+
+    def export_vectors(self):
+        tv = np.zeros((self.n, self.g.V, 4, 3), dtype=np.complex128)
+        self.ctx.check(self.ctx.lib.dd_export_vectors(self.h, tv.ctypes.data_as(_P)))
+        return tv
+
 
 def _info_dict(i):
     return dict(outer_iters=i.outer_iters, restarts=i.restarts, coarse_iters_total=i.coarse_iters_total,
@@ -448,7 +459,7 @@ class SolveState:
         self.ctx.check(self.ctx.lib.dd_solve_add(self.h, slot, _ptr(b_canon)))
 
     def step(self):
-        """Residual check, then one restart cycle; returns the slot states (0 free, 1 running, 2 done)."""
+        """One restart cycle, then the residual check; returns the slot states (0 free, 1 running, 2 done)."""
         self.ctx.check(self.ctx.lib.dd_solve_step(self.h, self.states))
         return list(self.states)
 
@@ -467,17 +478,6 @@ class SolveState:
 
     def __exit__(self, *exc):
         self.end()
-
-    def export_coarse(self):
-        nc = 2 * self.n
-        dc = np.zeros((self.g.Vc, 9, nc, nc), dtype=np.complex128)
-        self.ctx.check(self.ctx.lib.dd_export_coarse(self.h, dc.ctypes.data_as(_P)))
-        return dc
-
-    def export_vectors(self):
-        tv = np.zeros((self.n, self.g.V, 4, 3), dtype=np.complex128)
-        self.ctx.check(self.ctx.lib.dd_export_vectors(self.h, tv.ctypes.data_as(_P)))
-        return tv
 
 
 def kernel_timer_enable(name="*"):

@@ -161,11 +161,15 @@ class Server:
     Job payloads: open -> handle; step -> {slot: true relative residual} of the slots it finished.
     """
 
-    def __init__(self, executor, hbm_budget, max_rhs=12, max_lanes=4, log=None):
+    def __init__(self, executor, hbm_budget, max_rhs=12, max_lanes=6, backfill_bytes=None, log=None):
         self.ex = executor
         self.budget = hbm_budget
         self.max_rhs = max_rhs
         self.max_lanes = max_lanes
+        # a lane this small may open inside the oldest blocked request's
+        # reservation: it holds little memory and closes soon
+        self.backfill = hbm_budget // 32 if backfill_bytes is None else backfill_bytes
+        self._hold = False             # the device ran out of memory: open no lane until one closes
         self.cache = OrderedDict()     # field key -> [handle, bytes, lanes using it]
         self.resident = 0              # bytes of cached fields (reserved from the moment a load starts)
         self.inuse = 0                 # bytes charged to open lanes
@@ -173,6 +177,7 @@ class Server:
         self.log = log or (lambda *a: None)
         self.rejected = []
         self.failed = []
+        self.retries = 0
         self.evictions = 0
         self.lanes = {}                # field key -> Lane
         self._lid = 0
@@ -206,7 +211,7 @@ class Server:
                     queue.remove(r)
                     self._start[r.rid] = [None, lane.lid, lane.state == "running"]
                 continue
-            if len(self.lanes) >= self.max_lanes:
+            if len(self.lanes) >= self.max_lanes or self._hold:
                 continue
             cached = f.key in self.cache
             fb = 0 if cached else self.ex.footprint(f)
@@ -221,13 +226,22 @@ class Server:
                 self.rejected.append(r.rid)
                 self.log(f"[serve] rejected {r.rid}: {need(r.nrhs):.3e} B over budget")
                 continue
-            avail = self.budget - self.resident - self.inuse + self._idle_bytes(f.key) - reserved
+            free = self.budget - self.resident - self.inuse + self._idle_bytes(f.key)
             batch, nb = [], 0
             for q in queue:
                 if q.field.key == f.key and nb + q.nrhs <= self.max_rhs:
                     batch.append(q)
                     nb += q.nrhs
-            cap = next((c for c in (self.max_rhs, nb, r.nrhs) if need(c) <= avail), None)
+            idle = self._idle_bytes(f.key)
+
+            def fits(c, room):
+                return need(c) <= room - reserved or need(c) <= min(room, self.backfill)
+
+            # room for joins (all slots) only where no cached field has to go: a
+            # setup costs more than a later lane; evict for the batch at hand
+            cap = next((c for c in (self.max_rhs, nb) if fits(c, free - idle)), None)
+            if cap is None:
+                cap = next((c for c in (nb, r.nrhs) if fits(c, free)), None)
             if cap is None:
                 if reserved == 0:
                     reserved = need(r.nrhs)   # the oldest blocked request keeps its place
@@ -284,11 +298,22 @@ class Server:
         lane = next(ln for ln in self.lanes.values() if ln.lid == lid)
         key = lane.field.key
         if err is not None:
-            rids = {s[0] for s in lane.slots if s is not None} | {r.rid for r in lane.waiting}
-            self.failed.extend(sorted(rids))
-            for rid in rids:
-                self._res.pop(rid, None)
-            self.log(f"[serve] lane {lid} ({key}) failed in {kind}: {err}")
+            retry = kind == "open" and isinstance(err, MemoryError) and len(self.lanes) > 1
+            if retry:
+                # the device is fuller than the budget says (memory outside the
+                # library): requeue, and open nothing new until a lane closes
+                for r in lane.waiting:
+                    del self._start[r.rid]
+                queue.extend(lane.waiting)
+                queue.sort(key=lambda q: (q.arrival, q.rid))
+                self._hold = True
+                self.retries += 1
+            else:
+                rids = {s[0] for s in lane.slots if s is not None} | {r.rid for r in lane.waiting}
+                self.failed.extend(sorted(rids))
+                for rid in rids:
+                    self._res.pop(rid, None)
+            self.log(f"[serve] lane {lid} ({key}) failed in {kind}{' (requeued)' if retry else ''}: {err}")
             if kind == "open" and lane.miss:
                 _, b, _ = self.cache.pop(key)
                 self.resident -= b
@@ -322,6 +347,7 @@ class Server:
                 self.ex.close(lid)
         elif kind == "close":
             self._finish_lane(lane, key)
+            self._hold = False
             self.log(f"[serve] t={now:7.2f}s lane {lid} on {key} closes (peak {lane.peak} rhs) queue {len(queue)}")
 
     def run(self, requests):
@@ -351,9 +377,11 @@ class Server:
 
 def summarize(done, wall):
     lat = np.array([d.latency for d in done]) if done else np.zeros(1)
+    wait = np.array([d.start - d.arrival for d in done]) if done else np.zeros(1)
     return dict(requests=len(done), rhs=int(sum(d.nrhs for d in done)), wall_s=round(wall, 3),
                 p50_s=round(float(np.percentile(lat, 50)), 4), p99_s=round(float(np.percentile(lat, 99)), 4),
                 mean_s=round(float(lat.mean()), 4),
+                wait_p50_s=round(float(np.percentile(wait, 50)), 4), wait_p99_s=round(float(np.percentile(wait, 99)), 4),
                 solves_per_s=round(sum(d.nrhs for d in done) / max(wall, 1e-9), 3),
                 setup_misses=int(sum(d.setup_miss for d in done)),
                 joined=int(sum(d.joined for d in done)),
@@ -411,15 +439,21 @@ class _LaneWorker(threading.Thread):
             pass
 
     def _open(self, f, handle, capacity):
+        from . import binding as B
         self.field = f
         fresh = handle is None
-        if fresh:
-            handle = self.ex.load(f)
         try:
-            self.state = handle[1].dd_solve_begin(capacity, self.ex.tol, self.stream)
-        except Exception:
-            if fresh:                  # the scheduler drops a field whose lane failed to open
-                self.ex.free(handle)
+            if fresh:
+                handle = self.ex.load(f)
+            try:
+                self.state = handle[1].dd_solve_begin(capacity, self.ex.tol, self.stream)
+            except Exception:
+                if fresh:              # the scheduler drops a field whose lane failed to open
+                    self.ex.free(handle)
+                raise
+        except B.DDError as e:
+            if e.name in ("DD_ENOMEM", "DD_EBUDGET"):
+                raise MemoryError(str(e)) from e
             raise
         self.handle = handle
         return handle
@@ -432,11 +466,8 @@ class _LaneWorker(threading.Thread):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(self.stream)
-            src = {}
             for slot, r, j in adds:
-                if r.rid not in src:
-                    src[r.rid] = ex.sources(f, r)
-                self.state.add(slot, src[r.rid][j])
+                self.state.add(slot, ex.source(f, r, j))   # read before the call returns
                 self.slot_req[slot] = (r.rid, j, r.nrhs)
             states = self.state.step()
             out = {}
@@ -455,9 +486,11 @@ class _LaneWorker(threading.Thread):
         return out
 
     def _close(self):
+        import torch
         self.state.end()
         self.state = None
         self.handle[1].dd_mg_release_workspace()
+        torch.cuda.empty_cache()       # the lane's sources and solutions leave torch's cache too
 
 
 class GpuExecutor:
@@ -518,12 +551,14 @@ class GpuExecutor:
             raise
         return (g, mg)
 
-    def sources(self, f, r):
+    def source(self, f, r, j):
+        """Right-hand side j of request r: Gaussian complex entries drawn on the
+        device from the seed (request seed, j), one vector at a time."""
         import torch
         gen = torch.Generator(device="cuda")
-        gen.manual_seed(r.src_seed)
-        re = torch.randn((r.nrhs, f.V * 12), generator=gen, device="cuda", dtype=torch.float64)
-        im = torch.randn((r.nrhs, f.V * 12), generator=gen, device="cuda", dtype=torch.float64)
+        gen.manual_seed(r.src_seed * 16 + j)
+        re = torch.randn(f.V * 12, generator=gen, device="cuda", dtype=torch.float64)
+        im = torch.randn(f.V * 12, generator=gen, device="cuda", dtype=torch.float64)
         return torch.complex(re, im)
 
     def open(self, lid, f, handle, capacity):
@@ -604,7 +639,7 @@ def _run_report(ex, srv, reqs, log):
     res = summarize(done, time.perf_counter() - t0)
     ivs = ex.device_intervals()[n0:]
     busy = overlap_seconds([(0, a, b) for _, a, b in ivs] + [(1, a, b) for _, a, b in ivs]) if ivs else 0.0
-    res.update(rejected=len(srv.rejected), failed=len(srv.failed), evictions=srv.evictions,
+    res.update(rejected=len(srv.rejected), failed=len(srv.failed), retries=srv.retries, evictions=srv.evictions,
                device_busy_s=round(busy, 3), device_overlap_s=round(overlap_seconds(ivs), 3),
                peak_hbm_gib=round(srv.peak_bytes / 2 ** 30, 2))
     return done, res
@@ -619,9 +654,11 @@ def main(argv=None):
     ap.add_argument("--capacity-requests", type=int, default=60)
     ap.add_argument("--per-shape", type=int, default=2)
     ap.add_argument("--load", type=float, default=0.7, help="arrival rate as a fraction of measured capacity")
+    ap.add_argument("--rate", type=float, default=None, help="arrival rate (requests/s); overrides --load")
+    ap.add_argument("--skip-capacity", action="store_true", help="with --rate: no closed-loop run")
     ap.add_argument("--hbm-gib", type=float, default=230.0)
     ap.add_argument("--store", default="bf16", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--max-lanes", type=int, default=4, help="fields solved at once (1: one batch at a time)")
+    ap.add_argument("--max-lanes", type=int, default=6, help="fields solved at once (1: one batch at a time)")
     ap.add_argument("--shapes", default="all", help="'all' or a count of the smallest shapes to use")
     args = ap.parse_args(argv)
     from . import binding as B
@@ -639,23 +676,26 @@ def main(argv=None):
     budget = int(args.hbm_gib * (1 << 30))
     ctx = B.Context(0, hbm_budget_bytes=budget)
     ex = GpuExecutor(ctx, links, store=args.store)
-    # closed loop: everything queued at t = 0 gives the capacity
-    reqs = make_requests(args.capacity_requests, math.inf, shapes, pool, rng_seed=5002)
-    srv = Server(ex, budget, max_lanes=args.max_lanes, log=log)
-    _, cap = _run_report(ex, srv, reqs, log)
-    mu = cap["requests"] / cap["wall_s"]
-    log(f"[serve] closed-loop capacity {mu:.3f} requests/s: {json.dumps(cap)}")
-    for h, _, _ in srv.cache.values():
-        ex.free(h)
-    # open loop at load * capacity
-    reqs = make_requests(args.requests, args.load * mu, shapes, pool, rng_seed=5001)
+    cap, mu = None, None
+    if not (args.skip_capacity and args.rate):
+        # closed loop: everything queued at t = 0 gives the capacity
+        reqs = make_requests(args.capacity_requests, math.inf, shapes, pool, rng_seed=5002)
+        srv = Server(ex, budget, max_lanes=args.max_lanes, log=log)
+        _, cap = _run_report(ex, srv, reqs, log)
+        mu = cap["requests"] / cap["wall_s"]
+        log(f"[serve] closed-loop capacity {mu:.3f} requests/s: {json.dumps(cap)}")
+        for h, _, _ in srv.cache.values():
+            ex.free(h)
+    # open loop at load * capacity, or at the given rate
+    rate = args.rate if args.rate else args.load * mu
+    reqs = make_requests(args.requests, rate, shapes, pool, rng_seed=5001)
     srv = Server(ex, budget, max_lanes=args.max_lanes, log=log)
     done, res = _run_report(ex, srv, reqs, log)
     by_shape = {}
     for d in done:
         L = "x".join(map(str, next(f.L for v in pool.values() for f in v if f.key == d.field)))
         by_shape.setdefault(L, []).append(d.latency)
-    res.update(capacity_requests_per_s=round(mu, 4), arrival_rate_per_s=round(args.load * mu, 4),
+    res.update(capacity_requests_per_s=None if mu is None else round(mu, 4), arrival_rate_per_s=round(rate, 4),
                store=args.store, max_lanes=args.max_lanes, closed_loop=cap,
                shapes=["x".join(map(str, L)) for L in shapes], fields_per_shape=args.per_shape,
                p50_by_shape={k: round(float(np.percentile(v, 50)), 3) for k, v in by_shape.items()},

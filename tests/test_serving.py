@@ -16,13 +16,14 @@ class FakeExecutor:
     after 1 + (seed + j) % 3 steps with residual ((seed * 31 + j) % 97) * 1e-13,
     a pure function of the request."""
 
-    def __init__(self, footprints=None, ws_per_rhs=1, transient=0, fail_open=()):
+    def __init__(self, footprints=None, ws_per_rhs=1, transient=0, fail_open=(), oom_once=()):
         self.t = 0.0
         self.pending = []                # (t_end, seq, kind, lid, payload, error)
         self.seq = 0
         self.fp = footprints or {}
         self.wpr, self.tr = ws_per_rhs, transient
         self.fail_open = set(fail_open)
+        self.oom_once = set(oom_once)     # the first open on these fields meets a full device
         self.loads, self.frees, self.steps, self.opens = [], [], [], []
         self.lanes = {}                  # lid -> (field, {slot: [steps left, relres]})
         self.busy_until = {}
@@ -48,6 +49,10 @@ class FakeExecutor:
         self.lanes[lid] = (f, {})
         if f.key in self.fail_open:
             self._push(lid, 0.0, "open", None, RuntimeError("setup failed"))
+            return
+        if f.key in self.oom_once:
+            self.oom_once.discard(f.key)
+            self._push(lid, 0.0, "open", None, MemoryError("out of device memory"))
             return
         dur = 0.0
         if handle is None:
@@ -142,7 +147,7 @@ def test_slots_are_reused_by_waiting_requests():
 def test_admission_waits_for_memory_and_honours_the_reservation():
     a, b, c = F("a"), F("b"), F("c")
     ex = FakeExecutor(footprints={"a": 10, "b": 10, "c": 1}, ws_per_rhs=5)
-    srv = S.Server(ex, 40, max_rhs=4)
+    srv = S.Server(ex, 40, max_rhs=4, backfill_bytes=0)
     # lane a takes 10 + 4 * 5 = 30; b needs 10 + 2 * 5 = 20 and waits, holding a
     # reservation; c (1 + 5) would fit in the 10 left but must not pass b
     done = {d.rid: d for d in srv.run([R(0, 0.0, a, 2), R(1, 0.0, b, 2), R(2, 0.0, c, 1)])}
@@ -168,6 +173,17 @@ def test_setup_cache_and_lru_eviction():
     assert srv.peak_bytes <= 23
 
 
+def test_lane_capacity_shrinks_before_a_cached_field_is_evicted():
+    a, b = F("a"), F("b")
+    ex = FakeExecutor(ws_per_rhs=5)
+    srv = S.Server(ex, 35, max_rhs=4)
+    # after a's lane closes, a full lane on b (10 + 4 * 5) would need a's 10 B;
+    # a lane sized for the waiting batch (10 + 5) fits beside it
+    done = srv.run([R(0, 0.0, a, 1), R(1, 1.0, b, 1)])
+    assert len(done) == 2 and ex.frees == [] and srv.evictions == 0
+    assert [o[2] for o in ex.opens] == [4, 1]
+
+
 def test_admission_rejects_what_cannot_fit():
     ex = FakeExecutor(ws_per_rhs=5)
     srv = S.Server(ex, 30)
@@ -184,6 +200,27 @@ def test_a_failed_setup_releases_its_reservation():
     assert [o[1] for o in ex.opens].count("b") == 2
     assert [d.rid for d in done] == [0]
     assert "b" not in srv.cache and srv.resident == 10 and srv.inuse == 0
+
+
+def test_a_full_device_requeues_and_waits_for_a_lane_to_close():
+    a, b = F("a", (8, 8, 8, 16)), F("b")
+    ex = FakeExecutor(oom_once=["b"])
+    srv = S.Server(ex, 1000)
+    done = {d.rid: d for d in srv.run([R(0, 0.0, a, 2), R(1, 0.0, b, 3)])}
+    assert sorted(done) == [0, 1] and not srv.failed and srv.retries == 1
+    assert [o[1] for o in ex.opens] == ["a", "b", "b"]
+    assert done[1].start >= done[0].finish - 1e-12   # retried once a's lane had closed
+    assert srv.resident == 20 and srv.inuse == 0
+
+
+def test_small_lanes_backfill_inside_a_reservation():
+    a, b, c = F("a"), F("b"), F("c")
+    ex = FakeExecutor(footprints={"a": 10, "b": 10, "c": 1}, ws_per_rhs=5)
+    # as in the reservation test, but c's lane (1 + 5 B) is small enough to backfill
+    srv = S.Server(ex, 40, max_rhs=4, backfill_bytes=6)
+    done = {d.rid: d for d in srv.run([R(0, 0.0, a, 2), R(1, 0.0, b, 2), R(2, 0.0, c, 1)])}
+    assert done[2].start == 0.0 and done[1].start >= done[0].finish - 1e-12
+    assert srv.peak_bytes <= 40
 
 
 def test_latency_is_arrival_to_finish_with_idle_gaps():
