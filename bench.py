@@ -20,6 +20,7 @@ throughput on a bounded sample.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -46,8 +47,8 @@ TOL = 1e-10
 _SAP_DOM_SOURCES = ["paper_1811_00355_amd/csrc/sap_dom.hip", "paper_1811_00355_amd/csrc/dslash.h",
                     "paper_1811_00355_amd/csrc/dd_internal.h"]
 MEASURED_TRAFFIC = {
-    ("k_sap_dom", "C3", "bf16", "dom2"): dict(bytes=9.7993e9 + 1.2079e9, sha="4ab5373766a0b26b", sources=_SAP_DOM_SOURCES),
-    ("k_sap_dom", "C3", "bf16", "dom4"): dict(bytes=8.0544e9 + 1.2079e9, sha="4ab5373766a0b26b", sources=_SAP_DOM_SOURCES),
+    ("k_sap_dom", "C3", "bf16", "dom2"): dict(bytes=9.7798e9 + 1.2079e9, sha="bb526f3e9e343fab", sources=_SAP_DOM_SOURCES),
+    ("k_sap_dom", "C3", "bf16", "dom4"): dict(bytes=8.0607e9 + 1.2079e9, sha="bb526f3e9e343fab", sources=_SAP_DOM_SOURCES),
 }
 
 
@@ -261,6 +262,57 @@ def fp64_single_rhs(B, g, cfg, b, args):
                 outer_iters_mean=round(float(np.mean(iters)), 2), seconds=round(elapsed, 3))
 
 
+def _mixed_mg(B, g, cfg, args, store_name):
+    p = B.default_params(block=cfg["block"], n_vec=cfg["n_vec"], setup_iters=cfg["setup_iters"],
+                         inner_dtype=B.DD_F32, store_dtype=B.DTYPES[store_name], seed=cfg["tv_seed"],
+                         coarse_restart=args.coarse_restart, coarse_max_iters=args.coarse_max_iters,
+                         coarse_cgs_passes=args.coarse_cgs_passes, outer_cgs_passes=args.outer_cgs_passes)
+    mg = B.MG(g, p)
+    mg.dd_mg_set_graphs(args.graphs)
+    return mg
+
+
+def sigma_leg(B, g, cfg, args, store_name, b, light):
+    """sigma_min(D) at the benchmark's mass by block inverse iteration through
+    the solver (an upper bound that tightens with the iterations), and, where
+    the mass search recorded one, the 12-RHS solve rate at the mass of the
+    smallest sigma_min found on this field."""
+    import torch
+    from paper_1811_00355_amd.spectrum import sigma_min
+    t0 = time.perf_counter()
+    mg = _mixed_mg(B, g, cfg, args, store_name)
+    sig, hist, its = sigma_min(mg, g.V, nvec=4, iters=args.sigma_iters, tol=1e-8, rtol=0.01,
+                               log=lambda m: log("[bench] " + m))
+    mg.destroy()
+    out = dict(value=round(sig, 5), history=[round(h, 5) for h in hist], m0=cfg["m0"], nvec=4, solve_tol=1e-8,
+               bound="upper (Rayleigh-Ritz on (D^dag D)^-1)", seconds=round(time.perf_counter() - t0, 1),
+               free_field_floor=round(math.sin(math.pi / cfg["L"][3]), 5))
+    if light:
+        out["search"] = {k: light[k] for k in ("target", "reached", "m0", "sigma_min")}
+        out["search"]["trials"] = len(light["trials"])
+        g.dd_gauge_set_mass(light["m0"])
+        mg = _mixed_mg(B, g, cfg, args, store_name)
+        t = g.dd_gauge_get_tuning()
+        t.update(coarse_half=0, coarse_basis_half=0, coarse_mfma_half=0)
+        g.dd_gauge_set_tuning(**t)
+        x = torch.zeros_like(b)
+        mg.dd_solve(b.shape[0], b, x, TOL)               # workspace and graphs, untimed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            x = torch.zeros_like(b)
+            info, _ = mg.dd_solve(b.shape[0], b, x, TOL)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        mg.destroy()
+        g.dd_gauge_set_mass(cfg["m0"])
+        out["at_search_mass"] = dict(m0=light["m0"], solves_per_s=round(b.shape[0] / dt, 3),
+                                     outer_iters=max(i["outer_iters"] for i in info),
+                                     max_true_relres=max(i["true_relres"] for i in info))
+    return out
+
+
 def _roofline(kernel, ks, elapsed_ms_per_launch_set, args, store_name, layout):
     """Roofline entry of one kernel from its kernel-timer record (algorithmic
     bytes and flops per launch over the mean event-timed launch duration)."""
@@ -461,6 +513,8 @@ def main():
     ap.add_argument("--sap-mr", default="4", help="--sap-only: comma list of MR step counts")
     ap.add_argument("--baseline-dd", action="store_true",
                     help="also time the paper's comparison solver (SAP-preconditioned BiCGstab) on the same sources")
+    ap.add_argument("--sigma-iters", type=int, default=8,
+                    help="inverse-iteration steps of the sigma_min leg (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -558,6 +612,17 @@ def main():
         "roofline": r0["roofline"],
         "kernels": r0["kernels"],
     }
+    if args.sigma_iters:
+        log("[bench] sigma_min of the benchmark's operator")
+        light = None
+        lpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads", "m0_light.json")
+        if os.path.exists(lpath):
+            with open(lpath) as f:
+                light = json.load(f).get(args.config)
+        sg = sigma_leg(B, g, cfg, args, stores[0], b, light)
+        out["sigma_min_measured"] = sg["value"]
+        out["config"]["sigma_min"] = sg
+        log(f"[bench] sigma_min: {sg}")
     if not args.no_dapply:
         log("[bench] D-apply bandwidth table")
         out["dapply"] = dapply_table(B, g)
