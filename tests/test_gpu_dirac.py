@@ -83,7 +83,7 @@ def test_operand_storage_bit_exact(ctx, case):
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("nrhs", [1, 3, 6])
 def test_dirac_f64(ctx, case, nrhs):
     import _gpu
     from workloads import gauss_spinor
@@ -95,9 +95,10 @@ def test_dirac_f64(ctx, case, nrhs):
     g.destroy()
 
 
-@pytest.mark.parametrize("case", CASES[:2])
+@pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("dtype", [1, 2, 3])
-def test_dirac_mixed(ctx, case, dtype):
+@pytest.mark.parametrize("nrhs", [2, 5])
+def test_dirac_mixed(ctx, case, dtype, nrhs):
     """FP32 vectors with FP32 / FP16 / BF16 operands, against the oracle run on
     the same (rounded) operands and inputs; the quantisation error against the
     FP64 operator is only reported."""
@@ -105,7 +106,6 @@ def test_dirac_mixed(ctx, case, dtype):
     from oracle.dirac import WilsonClover
     from workloads import gauss_spinor
     U, lat, W, g = _setup(ctx, case)
-    nrhs = 2
     psi = _gpu.round_f32(gauss_spinor(lat.L, nrhs, 8))
     out = _gpu.fine_apply(g, dtype, nrhs, psi, lambda i, o: g.dd_dirac_apply(dtype, nrhs, i, o))
     a, _ = g.export_clover()
