@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # the FP32 ridge (157.3 / 8 = 19.7 flop/byte) are rated against the FP32 peak ("alu").
 FP32_PEAK_TFLOPS = 157.3
 FP32_NONPACKED_TFLOPS = 78.6
-ALU_BOUND = {"k_sap_colour", "k_sap_dom"}
+ALU_BOUND = {"k_sap_colour", "k_sap_dom", "k_sap_dom_persist"}
 TOL = 1e-10
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this workload

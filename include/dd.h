@@ -147,6 +147,10 @@ typedef struct {
                                 4 at a time (clover in LDS too, one per CU); 0 = one workgroup per
                                 (domain, RHS) in layout sap_wpe.  Same arithmetic, rounding may differ
                                 in the last place. */
+  int32_t sap_persist;       /* with sap_dom_rhs > 0: every sweep and colour of a smoother application in
+                                one cooperative launch whose workgroups (as many as the CUs hold) meet
+                                at a grid barrier between colours (1), or one launch per colour (0).
+                                Same bits.  Work captured into a graph always takes the launch form. */
 } dd_tuning;
 
 /* ---- gauge field (field preparation) ---------------------------------------

@@ -46,7 +46,8 @@ class dd_mg_params(ctypes.Structure):
 class dd_tuning(ctypes.Structure):
     _fields_ = [("sap_wpe", ctypes.c_int32), ("dirac_threads", ctypes.c_int32), ("coarse_spw", ctypes.c_int32),
                 ("coarse_half", ctypes.c_int32), ("coarse_basis_half", ctypes.c_int32),
-                ("coarse_mfma_half", ctypes.c_int32), ("sap_dom_rhs", ctypes.c_int32)]
+                ("coarse_mfma_half", ctypes.c_int32), ("sap_dom_rhs", ctypes.c_int32),
+                ("sap_persist", ctypes.c_int32)]
 
 
 class dd_bicgstab_params(ctypes.Structure):
@@ -260,9 +261,9 @@ class Gauge:
             self.h = _P()
 
     def dd_gauge_set_tuning(self, sap_wpe, dirac_threads, coarse_spw, coarse_half=0, coarse_basis_half=0,
-                            coarse_mfma_half=0, sap_dom_rhs=2):
+                            coarse_mfma_half=0, sap_dom_rhs=2, sap_persist=0):
         t = dd_tuning(sap_wpe, dirac_threads, coarse_spw, coarse_half, coarse_basis_half, coarse_mfma_half,
-                      sap_dom_rhs)
+                      sap_dom_rhs, sap_persist)
         self.ctx.check(self.ctx.lib.dd_gauge_set_tuning(self.h, ctypes.byref(t)))
 
     def dd_gauge_get_tuning(self):
@@ -270,7 +271,7 @@ class Gauge:
         self.ctx.check(self.ctx.lib.dd_gauge_get_tuning(self.h, ctypes.byref(t)))
         return dict(sap_wpe=t.sap_wpe, dirac_threads=t.dirac_threads, coarse_spw=t.coarse_spw,
                     coarse_half=t.coarse_half, coarse_basis_half=t.coarse_basis_half,
-                    coarse_mfma_half=t.coarse_mfma_half, sap_dom_rhs=t.sap_dom_rhs)
+                    coarse_mfma_half=t.coarse_mfma_half, sap_dom_rhs=t.sap_dom_rhs, sap_persist=t.sap_persist)
 
     def dd_solve_bicgstab(self, params, nrhs, b_canon, x_canon, tol, stream=None, raise_on_noconv=True):
         """The paper's comparison solver (SAP-preconditioned FP32 BiCGstab in an FP64 defect correction)."""

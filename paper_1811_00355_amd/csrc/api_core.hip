@@ -394,7 +394,7 @@ dd_status dd_sap_smooth(dd_gauge* g, const dd_mg_params* p, dd_dtype dt, int nrh
   if (b == x) return dd_fail(g->ctx, DD_EINVAL, "b and x must not alias");
   if ((st = ensure_opset(g, dt))) return st;
   launch_sap(g->geo, dt, g->ops[dt], nrhs, p->sap_sweeps, p->sap_mr_iters, b, x, g->tune.sap_wpe, g->tune.sap_dom_rhs,
-             (hipStream_t)stream);
+             g->tune.sap_persist, (hipStream_t)stream);
   DD_HIP(g->ctx, hipGetLastError());
   return DD_OK;
 }

@@ -490,7 +490,7 @@ static dd_status vcycle(dd_mg* mg, int nrhs, const void* v, void* out, int* cite
   launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, st);
   dd_dtype od = op_dtype(mg);
   launch_sap(g, od, mg->g->ops[od], nrhs, mg->p.sap_sweeps, mg->p.sap_mr_iters, v, out, mg->g->tune.sap_wpe,
-             mg->g->tune.sap_dom_rhs, st);
+             mg->g->tune.sap_dom_rhs, mg->g->tune.sap_persist, st);
   DD_HIP(mg->ctx, hipGetLastError());
   return DD_OK;
 }
@@ -592,7 +592,7 @@ static dd_status vcycle_graph(dd_mg* mg, int nrhs, const void* v, void* out, hip
     launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, w->cap);
     const dd_dtype od = op_dtype(mg);
     launch_sap(g, od, mg->g->ops[od], nrhs, mg->p.sap_sweeps, mg->p.sap_mr_iters, v, out, t.sap_wpe, t.sap_dom_rhs,
-               w->cap);
+               0, w->cap);   // captured: the launch form
     ktimer_suspend(false);
     ktimer_model(&b1, &f1);
     ktimer_model_set(b0, f0);
@@ -810,7 +810,7 @@ static dd_status setup_common(dd_gauge* g, const dd_mg_params* p, const double* 
     DD_HIP(mg->ctx, hipMemcpyAsync(w->vin, mg->tv, fb, hipMemcpyDeviceToDevice, st));
     DD_HIP(mg->ctx, hipMemsetAsync(mg->tv, 0, fb, st));
     launch_sap(G, od, g->ops[od], mg->n, p->sap_sweeps, p->sap_mr_iters, w->vin, mg->tv, g->tune.sap_wpe,
-               g->tune.sap_dom_rhs, st);
+               g->tune.sap_dom_rhs, g->tune.sap_persist, st);
     normalize_vectors(mg, mg->tv, st);
   }
   if ((s = build(mg, st))) return fail(s);
@@ -839,7 +839,7 @@ static dd_status check_mg_vec(dd_mg* mg, dd_dtype dt, int nrhs, const void* a, c
 // ---------------------------------------------------------------------------
 // autotuner cache: a JSON object, one entry per line,
 //   "<device>|L=..|b=..|n=..|nrhs=..|op=..|inner=..|cblk=..":
-//       {"sap_wpe": 2, "sap_dom_rhs": 4, "dirac_threads": 256, "coarse_spw": 4}
+//       {"sap_wpe": 2, "sap_dom_rhs": 4, "sap_persist": 0, "dirac_threads": 256, "coarse_spw": 4}
 // (launch shapes only; the coarse arithmetic choices are the caller's and part of the key)
 // Lines that do not parse are dropped (the file is rewritten on the next miss).
 // ---------------------------------------------------------------------------
@@ -862,7 +862,8 @@ static void tune_cache_read(const char* path, std::map<std::string, Tuning>& out
     std::string obj = l.substr(o, c - o + 1);
     Tuning t;
     if (tune_field(obj, "sap_wpe", t.sap_wpe) && tune_field(obj, "sap_dom_rhs", t.sap_dom_rhs) &&
-        tune_field(obj, "dirac_threads", t.dirac_threads) && tune_field(obj, "coarse_spw", t.coarse_spw))
+        tune_field(obj, "sap_persist", t.sap_persist) && tune_field(obj, "dirac_threads", t.dirac_threads) &&
+        tune_field(obj, "coarse_spw", t.coarse_spw))
       out[l.substr(a + 1, b - a - 1)] = t;
   }
   std::fclose(f);
@@ -875,9 +876,11 @@ static bool tune_cache_write(const char* path, const std::map<std::string, Tunin
   std::fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : m)
-    std::fprintf(f, " \"%s\": {\"sap_wpe\": %d, \"sap_dom_rhs\": %d, \"dirac_threads\": %d, \"coarse_spw\": %d}%s\n",
-                 kv.first.c_str(), kv.second.sap_wpe, kv.second.sap_dom_rhs, kv.second.dirac_threads,
-                 kv.second.coarse_spw, ++i < m.size() ? "," : "");
+    std::fprintf(f,
+                 " \"%s\": {\"sap_wpe\": %d, \"sap_dom_rhs\": %d, \"sap_persist\": %d, \"dirac_threads\": %d, "
+                 "\"coarse_spw\": %d}%s\n",
+                 kv.first.c_str(), kv.second.sap_wpe, kv.second.sap_dom_rhs, kv.second.sap_persist,
+                 kv.second.dirac_threads, kv.second.coarse_spw, ++i < m.size() ? "," : "");
   std::fprintf(f, "}\n");
   bool ok = std::fclose(f) == 0;
   return ok && std::rename(tmp.c_str(), path) == 0;
@@ -907,14 +910,17 @@ dd_status dd_setup_update_mass(dd_mg* mg, double m0) {
 dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t) {
   if (!g || !t) return DD_EINVAL;
   if ((t->sap_wpe != 2 && t->sap_wpe != 3) || (t->sap_dom_rhs != 0 && t->sap_dom_rhs != 2 && t->sap_dom_rhs != 4) ||
+      (t->sap_persist != 0 && t->sap_persist != 1) ||
       (t->dirac_threads != 64 && t->dirac_threads != 128 && t->dirac_threads != 256) ||
       (t->coarse_spw != 2 && t->coarse_spw != 4 && t->coarse_spw != 8) || (t->coarse_half != 0 && t->coarse_half != 1) ||
       (t->coarse_basis_half != 0 && t->coarse_basis_half != 1) || (t->coarse_mfma_half != 0 && t->coarse_mfma_half != 1))
     return dd_fail(g->ctx, DD_EINVAL,
-                   "tuning: sap_wpe 2|3, sap_dom_rhs 0|2|4, dirac_threads 64|128|256, coarse_spw 2|4|8, coarse_half 0|1, "
+                   "tuning: sap_wpe 2|3, sap_dom_rhs 0|2|4, sap_persist 0|1, dirac_threads 64|128|256, coarse_spw 2|4|8, "
+                   "coarse_half 0|1, "
                    "coarse_basis_half 0|1, coarse_mfma_half 0|1");
   g->tune.sap_wpe = t->sap_wpe;
   g->tune.sap_dom_rhs = t->sap_dom_rhs;
+  g->tune.sap_persist = t->sap_persist;
   g->tune.dirac_threads = t->dirac_threads;
   g->tune.coarse_spw = t->coarse_spw;
   g->tune.coarse_half = t->coarse_half;
@@ -927,6 +933,7 @@ dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t) {
   if (!g || !t) return DD_EINVAL;
   t->sap_wpe = g->tune.sap_wpe;
   t->sap_dom_rhs = g->tune.sap_dom_rhs;
+  t->sap_persist = g->tune.sap_persist;
   t->dirac_threads = g->tune.dirac_threads;
   t->coarse_spw = g->tune.coarse_spw;
   t->coarse_half = g->tune.coarse_half;
@@ -998,17 +1005,30 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
       float bt = 1e30f;
       best.sap_dom_rhs = 0;
       for (int wpe : {2, 3}) {
-        float t = time_ms([&] { launch_sap(G, od, g->ops[od], nrhs, 1, mg->p.sap_mr_iters, w->vin, w->xs, wpe, 0, st); });
+        float t =
+            time_ms([&] { launch_sap(G, od, g->ops[od], nrhs, 1, mg->p.sap_mr_iters, w->vin, w->xs, wpe, 0, 0, st); });
         std::snprintf(line, sizeof(line), "k_sap_colour sap_wpe=%d %.3f ms/sweep\n", wpe, t);
         rep += line;
         if (t < bt) bt = t, best.sap_wpe = wpe;
       }
       if (sap_dom_supported(G, od)) {
         for (int dr : {4, 2}) {
-          float t = time_ms([&] { launch_sap(G, od, g->ops[od], nrhs, 1, mg->p.sap_mr_iters, w->vin, w->xs, 2, dr, st); });
+          float t =
+              time_ms([&] { launch_sap(G, od, g->ops[od], nrhs, 1, mg->p.sap_mr_iters, w->vin, w->xs, 2, dr, 0, st); });
           std::snprintf(line, sizeof(line), "k_sap_dom sap_dom_rhs=%d %.3f ms/sweep\n", dr, t);
           rep += line;
           if (t < bt) bt = t, best.sap_dom_rhs = dr;
+        }
+        // the chosen domain form as one cooperative launch of all the smoother's sweeps
+        best.sap_persist = 0;
+        if (best.sap_dom_rhs) {
+          const int sw = mg->p.sap_sweeps > 0 ? mg->p.sap_sweeps : 1;
+          float t = time_ms([&] {
+            launch_sap(G, od, g->ops[od], nrhs, sw, mg->p.sap_mr_iters, w->vin, w->xs, 2, best.sap_dom_rhs, 1, st);
+          }) / sw;
+          std::snprintf(line, sizeof(line), "k_sap_dom_persist sap_dom_rhs=%d %.3f ms/sweep\n", best.sap_dom_rhs, t);
+          rep += line;
+          if (t < bt) bt = t, best.sap_persist = 1;
         }
       }
     }
@@ -1049,8 +1069,10 @@ dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report,
       rep += std::string("could not write ") + cache_path + "\n";
   }
   char line[128];
-  std::snprintf(line, sizeof(line), "chosen sap_wpe=%d sap_dom_rhs=%d dirac_threads=%d coarse_spw=%d coarse_half=%d\n",
-                g->tune.sap_wpe, g->tune.sap_dom_rhs, g->tune.dirac_threads, g->tune.coarse_spw, g->tune.coarse_half);
+  std::snprintf(line, sizeof(line),
+                "chosen sap_wpe=%d sap_dom_rhs=%d sap_persist=%d dirac_threads=%d coarse_spw=%d coarse_half=%d\n",
+                g->tune.sap_wpe, g->tune.sap_dom_rhs, g->tune.sap_persist, g->tune.dirac_threads, g->tune.coarse_spw,
+                g->tune.coarse_half);
   rep += line;
   if (report && report_cap) {
     std::strncpy(report, rep.c_str(), report_cap - 1);

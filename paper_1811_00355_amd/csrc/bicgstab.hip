@@ -136,7 +136,8 @@ dd_status dd_solve_bicgstab(dd_gauge* g, const dd_bicgstab_params* p, int nrhs, 
   // M applied from zero: out = SAP(in)
   auto precond = [&](const float2* in, float2* out) {
     launch_zero(out, sizeof(float2) * fine, st);
-    launch_sap(G, od, g->ops[od], nrhs, p->sap_sweeps, p->sap_mr_iters, in, out, g->tune.sap_wpe, g->tune.sap_dom_rhs, st);
+    launch_sap(G, od, g->ops[od], nrhs, p->sap_sweeps, p->sap_mr_iters, in, out, g->tune.sap_wpe, g->tune.sap_dom_rhs,
+               g->tune.sap_persist, st);
   };
   auto apply_D = [&](const float2* in, float2* out) {
     launch_dirac(G, od, g->ops[od], nrhs, in, out, st, g->tune.dirac_threads);

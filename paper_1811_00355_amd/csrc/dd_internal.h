@@ -336,6 +336,7 @@ struct OpSet {
 // choice gives bit-identical results.
 struct Tuning {
   int sap_wpe = 2;          // SAP layout: 2 (registers, 2 waves per SIMD) or 3 (lean LDS, 3)
+  int sap_persist = 0;      // domain-resident SAP: all sweeps in one cooperative launch (same bits)
   int sap_dom_rhs = 2;      // 4^4 domains, FP16/BF16 operands: RHS per workgroup of the domain-resident
                             // SAP (operator staged in LDS once per domain), 2 or 4; 0 = one workgroup per
                             // (domain, RHS)
@@ -435,10 +436,10 @@ void launch_dirac_f32_in(const GeomDev& g, const OpSet& ops64, int nrhs, const f
                          hipStream_t st, int threads = 256);
 // SAP smoother
 void launch_sap(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters,
-                const void* b, void* x, int wpe, int dom_rhs, hipStream_t st);
+                const void* b, void* x, int wpe, int dom_rhs, int persist, hipStream_t st);
 bool sap_dom_supported(const GeomDev& g, dd_dtype dt);
 void launch_sap_dom(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters,
-                    const void* b, void* x, int rhs_group, hipStream_t st);
+                    const void* b, void* x, int rhs_group, bool persist, hipStream_t st);
 // transfer and coarse construction
 bool supported_nvec(int n);
 void launch_restrict(const GeomDev& g, dd_dtype vt, dd_dtype pst, int n, const void* P, int nrhs,

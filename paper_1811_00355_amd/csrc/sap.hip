@@ -257,9 +257,9 @@ void run(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const
 }  // namespace
 
 void launch_sap(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters, const void* b,
-                void* x, int wpe, int dom_rhs, hipStream_t st) {
+                void* x, int wpe, int dom_rhs, int persist, hipStream_t st) {
   if (dom_rhs > 0 && sap_dom_supported(g, dt)) {   // domain-resident form (sap_dom.hip)
-    launch_sap_dom(g, dt, ops, nrhs, sweeps, mr_iters, b, x, dom_rhs, st);
+    launch_sap_dom(g, dt, ops, nrhs, sweeps, mr_iters, b, x, dom_rhs, persist != 0, st);
     return;
   }
 #define DD_SAP_WPE(R, S, Tv)                                                   \

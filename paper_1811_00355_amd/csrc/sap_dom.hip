@@ -16,6 +16,8 @@
 // Hops inside the domain read their link and neighbour from LDS at a per-thread
 // neighbour table (eight 8-bit half-domain indices, 0xff outside) computed once;
 // only the residual's hops across the domain faces read global memory.
+#include <hip/hip_cooperative_groups.h>
+
 #include "dslash.h"
 #include "ktimer.h"
 
@@ -212,27 +214,30 @@ __device__ __forceinline__ void pair_sum3(float& a, float& b, float& c, float (*
   c = red[q][0][2] + red[q][1][2];
 }
 
-template <typename S, int G, bool CG>
+// PERSIST: one cooperative launch runs every sweep and both colours; its
+// workgroups (as many as the CUs hold at once) take the domains of a colour in
+// turn, contiguous ranges per XCD, and meet at a grid barrier after each
+// colour.  Each domain is computed exactly as in the launch-per-colour form
+// (domains of one colour are independent), so the results are the same bits.
+template <typename S, int G, bool CG, bool PERSIST>
 __global__ void __launch_bounds__(kBvh * G) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_sap_dom(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov, const S* __restrict__ cinv, int nrhs,
-          int colour, int mr_iters, const float2* __restrict__ bvec, float2* __restrict__ xvec) {
+          int colour0, int sweeps, int mr_iters, const float2* __restrict__ bvec, float2* __restrict__ xvec) {
   __shared__ S sL[36 * kBv];        // links [mu][9][site]
   __shared__ S sC[CG ? 1 : 36 * kBv];   // clover [36][site] (CG: read from memory instead)
   __shared__ S sI[36 * kBvh];       // inverse of the odd sites [36][half index]
   __shared__ cx<float> sX[G][12 * kBvh];   // per right-hand side: one half-domain spinor field
   __shared__ float red[G][2][4];
 
-  // domains of one colour in lexicographic block order, contiguous ranges per XCD
-  int tile, unused;
-  xcd_range_tile(g.Vch, 1, tile, unused);
-  if (tile >= g.Vch) return;   // uniform per workgroup
-  const int slot = colour * g.Vch + tile;
   const long long V = g.V;
-  const long long base = (long long)slot * kBv;
   // q (the right-hand side slot) is uniform over a wave: keep it, and the
   // buffer descriptors derived from it, in scalar registers
   const int t = threadIdx.x, q = __builtin_amdgcn_readfirstlane(t / kBvh), j = t % kBvh, w = (t / 64) & 1,
             lane = t & 63;
+
+  auto domain = [&](int tile, int colour) {
+  const int slot = colour * g.Vch + tile;
+  const long long base = (long long)slot * kBv;
 
   // stage the domain's operator: 36 rows of 256 pairs (links; clover unless CG),
   // 36 rows of 128 (odd inverse), in 16-byte pieces, all loads issued before the
@@ -390,21 +395,83 @@ k_sap_dom(GeomDev g, const S* __restrict__ links, const S* __restrict__ clov, co
       store_spinor<float, float2>(x, V, Io, rho);
     }
   }
+  };
+
+  if constexpr (!PERSIST) {
+    // domains of one colour in lexicographic block order, contiguous ranges per XCD
+    int tile, unused;
+    xcd_range_tile(g.Vch, 1, tile, unused);
+    if (tile >= g.Vch) return;   // uniform per workgroup
+    domain(tile, colour0);
+  } else {
+    // gridDim.x is a multiple of 8 and at most Vch; workgroup k of XCD x takes
+    // domains k, k + gridDim.x / 8, ... of that XCD's eighth
+    const int per_x = g.Vch / 8, nwx = gridDim.x / 8, x8 = blockIdx.x & 7, k0 = blockIdx.x >> 3;
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+#pragma unroll 1
+    for (int sw = 0; sw < sweeps; ++sw)
+#pragma unroll 1
+      for (int colour = 0; colour < 2; ++colour) {
+#pragma unroll 1
+        for (int k = k0; k < per_x; k += nwx) {
+          __syncthreads();   // the previous domain's LDS reads are done before the staging overwrites them
+          domain(x8 * per_x + k, colour);
+        }
+        grid.sync();         // the colour's updates of x are visible to the other colour
+      }
+  }
+}
+
+// workgroups of the persistent form: as many as the CUs hold at once (a
+// multiple of 8, at most one per domain of a colour); 0 if it cannot be launched
+template <typename S, int G, bool CG>
+int persist_grid(const GeomDev& g) {
+  static thread_local int cached = -1;
+  static thread_local long long cached_vch = -1;
+  if (cached >= 0 && cached_vch == g.Vch) return cached;
+  int dev = 0, ncu = 0, per_cu = 0, coop = 0;
+  int n = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop &&
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sap_dom<S, G, CG, true>, kBvh * G, 0) == hipSuccess) {
+    const long long cap = (long long)ncu * per_cu;
+    n = (int)((cap < g.Vch ? cap : g.Vch) / 8 * 8);
+  }
+  (void)hipGetLastError();
+  cached = n;
+  cached_vch = g.Vch;
+  return n;
 }
 
 template <typename S, int G, bool CG>
-void run_dom(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const void* b, void* x,
+void run_dom(const GeomDev& g, const OpSet& ops, int nrhs, int sweeps, int mr, const void* b, void* x, bool persist,
              hipStream_t st) {
-  const unsigned nb = xcd_grid(g.Vch, 1);
   const double half = 0.5 * (double)g.V;
   const double bytes = half * (90.0 * sizeof(S) + 36.0 * sizeof(float2) * nrhs);
   const double flops = half * nrhs * (mr + 2.5) * 1850.0;
+  const S* L = (const S*)ops.links;
+  const S* C = (const S*)ops.clover;
+  const S* I = (const S*)ops.cinv;
+  const float2* bb = (const float2*)b;
+  float2* xx = (float2*)x;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(st, &cs);
+  const int pg = persist && cs == hipStreamCaptureStatusNone ? persist_grid<S, G, CG>(g) : 0;
+  if (pg > 0) {
+    GeomDev gg = g;
+    int nr = nrhs, c0 = 0, sw = sweeps, mr_ = mr;
+    void* args[] = {&gg, &L, &C, &I, &nr, &c0, &sw, &mr_, &bb, &xx};
+    DD_TIMED("k_sap_dom_persist", st, bytes * 2 * sweeps, flops * 2 * sweeps,
+             (void)hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sap_dom<S, G, CG, true>), dim3(pg),
+                                              dim3(kBvh * G), args, 0, st));
+    return;
+  }
+  const unsigned nb = xcd_grid(g.Vch, 1);
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour)
       DD_TIMED("k_sap_dom", st, bytes, flops,
-               (k_sap_dom<S, G, CG><<<nb, kBvh * G, 0, st>>>(g, (const S*)ops.links, (const S*)ops.clover,
-                                                         (const S*)ops.cinv, nrhs, colour, mr, (const float2*)b,
-                                                         (float2*)x)));
+               (k_sap_dom<S, G, CG, false><<<nb, kBvh * G, 0, st>>>(g, L, C, I, nrhs, colour, 1, mr, bb, xx)));
 }
 
 }  // namespace
@@ -415,12 +482,12 @@ bool sap_dom_supported(const GeomDev& g, dd_dtype dt) {
 }
 
 void launch_sap_dom(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, int sweeps, int mr_iters,
-                    const void* b, void* x, int rhs_group, hipStream_t st) {
+                    const void* b, void* x, int rhs_group, bool persist, hipStream_t st) {
   if (rhs_group == 2) {
-    if (dt == DD_F16) run_dom<__half2, 2, true>(g, ops, nrhs, sweeps, mr_iters, b, x, st);
-    else run_dom<bf16x2, 2, true>(g, ops, nrhs, sweeps, mr_iters, b, x, st);
+    if (dt == DD_F16) run_dom<__half2, 2, true>(g, ops, nrhs, sweeps, mr_iters, b, x, persist, st);
+    else run_dom<bf16x2, 2, true>(g, ops, nrhs, sweeps, mr_iters, b, x, persist, st);
   } else {
-    if (dt == DD_F16) run_dom<__half2, 4, false>(g, ops, nrhs, sweeps, mr_iters, b, x, st);
-    else run_dom<bf16x2, 4, false>(g, ops, nrhs, sweeps, mr_iters, b, x, st);
+    if (dt == DD_F16) run_dom<__half2, 4, false>(g, ops, nrhs, sweeps, mr_iters, b, x, persist, st);
+    else run_dom<bf16x2, 4, false>(g, ops, nrhs, sweeps, mr_iters, b, x, persist, st);
   }
 }

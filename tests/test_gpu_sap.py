@@ -73,7 +73,7 @@ def test_sap_parity(ctx, case, dtype):
 # stored operands, under every launch layout the autotuner may pick.
 HALF_CASE = ((8, 8, 8, 16), (4, 4, 4, 4), 0.2, -0.1, 1.0, 23)
 SAP_LAYOUTS = [dict(sap_wpe=2, sap_dom_rhs=0), dict(sap_wpe=3, sap_dom_rhs=0), dict(sap_dom_rhs=4),
-               dict(sap_dom_rhs=2)]
+               dict(sap_dom_rhs=2), dict(sap_dom_rhs=2, sap_persist=1), dict(sap_dom_rhs=4, sap_persist=1)]
 CHECKED_RHS = (0, 7, 11)
 _ref_cache = {}
 
@@ -140,4 +140,35 @@ def test_sap_parity_stored(ctx, dtype, layout, nrhs):
         err = _gpu.max_rel(out[r], refs[r])
         print(f"  rhs {r}: SAP error vs oracle on stored operands {err:.2e}", flush=True)
         assert err < 1e-5
+    g.destroy()
+
+
+@pytest.mark.parametrize("dom", [2, 4])
+@pytest.mark.parametrize("nrhs", [12, 3])
+def test_sap_persistent_form_same_bits(ctx, dom, nrhs):
+    """All sweeps and both colours in one cooperative launch (grid barrier
+    between colours) against one launch per colour: identical bits (BF16
+    operands, nu = 4, k = 4)."""
+    import torch
+    import _gpu
+    from paper_1811_00355_amd import Gauge, default_params
+    from workloads import su3_field, gauss_spinor
+    L, blk, eps, m0, csw, seed = HALF_CASE
+    g = Gauge(ctx, L, blk, su3_field(L, eps, seed), m0, csw)
+    p = default_params(block=blk, sap_sweeps=4, sap_mr_iters=4)
+    b = _gpu.to_dev(_gpu.round_f32(gauss_spinor(L, nrhs, 95)).reshape(nrhs, -1))
+    outs = []
+    for persist in (0, 1):
+        t = g.dd_gauge_get_tuning()
+        t.update(sap_dom_rhs=dom, sap_persist=persist)
+        g.dd_gauge_set_tuning(**t)
+        pb = g.new_packed(3, nrhs)
+        px = g.new_packed(3, nrhs)
+        g.pack(3, nrhs, b, pb)
+        g.dd_sap_smooth(p, 3, nrhs, pb, px)
+        torch.cuda.synchronize()
+        outs.append(px.clone())
+    same = torch.equal(outs[0], outs[1])
+    print(f"dom {dom} nrhs {nrhs}: persistent == per-colour launches: {same}", flush=True)
+    assert same
     g.destroy()
