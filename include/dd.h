@@ -223,8 +223,13 @@ dd_status dd_mg_destroy(dd_mg* mg);
  * All three give bit-identical results (the masked right-hand sides are never
  * written; mode 2 counts info.coarse_iters_total as the sum over cycles of the
  * longest Arnoldi run).  Graphs hold workspace and buffer addresses and are
- * dropped when the workspace is reallocated.  Kernel timers do not see
- * launches inside graphs.  DD_EINVAL for another mode. */
+ * dropped when the workspace is reallocated.  Kernel timers do not time
+ * launches inside graphs (the bytes and flops model of info counts every
+ * replay).  Modes 1 and 2 capture on an internal stream on first use; while a
+ * capture runs, HIP refuses legacy-stream work and device-wide synchronisation
+ * from other threads of the process (dd_gauge_create, dd_setup,
+ * dd_mg_release_workspace use them), so threads that overlap such calls with
+ * solves should use mode 0.  DD_EINVAL for another mode. */
 dd_status dd_mg_set_graphs(dd_mg* mg, int mode);
 /* Free the solver workspace of a setup (Krylov bases, scratch vectors and the
  * graphs captured on them); the next solve allocates it again.  For callers

@@ -499,7 +499,7 @@ class GpuExecutor:
     latency); sources are drawn on the device from a per-request seed."""
 
     def __init__(self, ctx, links, block=(4, 4, 4, 4), n_vec=20, store="f32", c_sw=1.0, setup_iters=4,
-                 tol=1e-10, graphs=True, tune_cache=None):
+                 tol=1e-10, graphs=False, tune_cache=None):
         from . import binding as B
         import torch
         self.B = B
@@ -511,6 +511,9 @@ class GpuExecutor:
         self.c_sw = c_sw
         self.setup_iters = setup_iters
         self.tol = tol
+        # graph capture (modes 1 and 2 capture on first use) does not mix with other
+        # threads' legacy-stream work (a setup's uploads, synchronous copies,
+        # device-wide synchronisation): lanes launch directly
         self.graphs = graphs
         self.tune_cache = tune_cache
         self.keep_x = False           # keep each request's solution (host) in self.results
