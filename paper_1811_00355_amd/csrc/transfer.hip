@@ -82,6 +82,10 @@ __global__ void __launch_bounds__(256) k_restrict(GeomDev g, const Sp* __restric
 // 16 k-steps of v_mfma_f32_16x16x4f32 over the sites, three real products per
 // complex one (Gauss: with conj(lambda) = a + ib, v = c + id: a (c + d),
 // (a + b)(-d), (b - a) c).  The four waves' partial sums are added in wave order.
+// Each wave stages into LDS of its own and synchronises with itself only, so the
+// four waves' load and product phases interleave; the FP64 form (Galerkin
+// build) stages 32 sites per step, the two lane halves taking half of the
+// right-hand sides and of the test vectors each.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -101,9 +105,18 @@ template <> struct Mfma4<double> {
   __device__ static int row(int lk, int v) { return lk + 4 * v; }
 };
 
+// order LDS accesses of one wave: its writes are visible to its later reads, and
+// its reads are done before its later writes (a wave's LDS instructions
+// complete in order; this keeps the compiler from moving them across)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // R: FP32 (inner solve) or FP64 (Galerkin build); SW: sites per staging step of a wave
 template <int N, typename Sp, typename R, int SW>
-__global__ void __launch_bounds__(256) k_restrict_mfma(GeomDev g, const Sp* __restrict__ P, int nrhs,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_restrict_mfma(GeomDev g, const Sp* __restrict__ P, int nrhs,
                                                        const typename Mfma4<R>::vec* __restrict__ fine,
                                                        typename Mfma4<R>::vec* __restrict__ out, long long rstride,
                                                        long long sstride) {
@@ -111,6 +124,7 @@ __global__ void __launch_bounds__(256) k_restrict_mfma(GeomDev g, const Sp* __re
   typedef typename M::acc acc_t;
   typedef typename M::vec Tv;
   constexpr int MT = (N + 15) / 16, SP = SW + 1;   // row tiles of the n test vectors; padded site stride
+  constexpr int KU = SW == 32 ? 2 : 4;             // k-steps unrolled (FP64: fewer LDS values in flight)
   // staging of v and lambda; after each chirality the same bytes hold the waves' partial sums [w][row][rhs]
   constexpr size_t kVs = sizeof(Tv) * 4 * 16 * SP, kPs = sizeof(Sp) * 4 * N * SP, kRed = sizeof(Tv) * 4 * N * 16;
   __shared__ __align__(16) char smem[kVs + kPs > kRed ? kVs + kPs : kRed];
@@ -130,21 +144,42 @@ __global__ void __launch_bounds__(256) k_restrict_mfma(GeomDev g, const Sp* __re
       for (int cc = 0; cc < 6; ++cc) {
         const int c = 6 * s + cc;
         for (int h = 0; h < 64 / SW; ++h) {
-          const long long site = base + h * SW + (lane < SW ? lane : 0);
-          Tv xv[16];
-          Sp pv[N];
+          if constexpr (SW == 32) {
+            // 32 sites per step: lane half hf stages right-hand sides 8 hf .. 8 hf + 7 and
+            // test vectors hf N/2 .. (hf + 1) N/2 - 1 of site lane % 32
+            const int hf = lane >> 5, sl = lane & 31;
+            const long long site = base + h * SW + sl;
+            Tv xv[8];
+            Sp pv[N / 2];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) xv[r] = fine[(long long)(r0 + (r < nr ? r : 0)) * 12 * V + (long long)c * V + site];
+            for (int q = 0; q < 8; ++q) {
+              const int r = 8 * hf + q;
+              xv[q] = fine[(long long)(r0 + (r < nr ? r : 0)) * 12 * V + (long long)c * V + site];
+            }
 #pragma unroll
-          for (int i = 0; i < N; ++i) pv[i] = P[((long long)i * 12 + c) * V + site];
-          if (lane < SW) {
+            for (int q = 0; q < N / 2; ++q) pv[q] = P[((long long)(hf * (N / 2) + q) * 12 + c) * V + site];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) vs[w][r][lane] = xv[r];
+            for (int q = 0; q < 8; ++q) vs[w][8 * hf + q][sl] = xv[q];
 #pragma unroll
-            for (int i = 0; i < N; ++i) ps[w][i][lane] = pv[i];
+            for (int q = 0; q < N / 2; ++q) ps[w][hf * (N / 2) + q][sl] = pv[q];
+          } else {
+            const long long site = base + h * SW + (lane < SW ? lane : 0);
+            Tv xv[16];
+            Sp pv[N];
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              xv[r] = fine[(long long)(r0 + (r < nr ? r : 0)) * 12 * V + (long long)c * V + site];
+#pragma unroll
+            for (int i = 0; i < N; ++i) pv[i] = P[((long long)i * 12 + c) * V + site];
+            if (lane < SW) {
+#pragma unroll
+              for (int r = 0; r < 16; ++r) vs[w][r][lane] = xv[r];
+#pragma unroll
+              for (int i = 0; i < N; ++i) ps[w][i][lane] = pv[i];
+            }
           }
-          __syncthreads();
-#pragma unroll 4
+          wave_sync();   // the staging is this wave's own: the other waves go at their own pace
+#pragma unroll(KU)
           for (int ks = 0; ks < SW / 4; ++ks) {
             const Tv xb = vs[w][li][4 * ks + lk];
             const R xc = rhs_ok ? xb.x : (R)0, xd = rhs_ok ? xb.y : (R)0;
@@ -158,9 +193,10 @@ __global__ void __launch_bounds__(256) k_restrict_mfma(GeomDev g, const Sp* __re
               k3[t] = M::op(b - a, xc, k3[t]);
             }
           }
-          __syncthreads();   // every read of the staging is done before it is refilled (or reused below)
+          wave_sync();   // every read of this wave's staging is done before it is refilled
         }
       }
+      __syncthreads();   // the partial sums below reuse every wave's staging bytes
       // this wave's partial result: lane holds rows 16t + M::row(lk, v) of right-hand side li
 #pragma unroll
       for (int t = 0; t < MT; ++t)
