@@ -66,6 +66,111 @@ __global__ void __launch_bounds__(256) k_dirac_blk(GeomDev g, const S* __restric
   store_spinor<R, To>(out + (long long)r * 12 * g.V, g.V, I, acc);
 }
 
+// Half-precision operands, several right-hand sides (4^4 blocks): one workgroup
+// per block takes every right-hand side in turn.  A site's 8 links (4 forward,
+// the 4 backward U_mu(x - mu)) stay in registers in their storage type (72
+// 32-bit registers) and the block's packed clover in LDS, both loaded once, so
+// links and clover are read once per launch instead of once per right-hand
+// side.  Each right-hand side's block spinors are staged in LDS; hops across the
+// block faces read memory.  Same arithmetic, in the same order, as k_dirac_blk.
+template <typename S, int STRIDE>
+__device__ __forceinline__ void clover_rows(const S* C, const cx<float>* in, cx<float>* out) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const S* B = C + 18 * c * STRIDE;
+    cx<float> v[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) v[r] = in[6 * c + r];
+    cx<float> o[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const cx<float> d = ld<float, S>(B + k * STRIDE);
+      o[2 * k] = d.re * v[2 * k];
+      o[2 * k + 1] = d.im * v[2 * k + 1];
+    }
+    int k = 3;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int q = r + 1; q < 6; ++q) {
+        const cx<float> u = ld<float, S>(B + (k++) * STRIDE);
+        cfma4(o[r], u, v[q]);
+        cfma4_conj(o[q], u, v[r]);
+      }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) out[6 * c + r] = o[r];
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_dirac_hl(
+    GeomDev g, const S* __restrict__ links, const S* __restrict__ clov, int nrhs, const float2* __restrict__ in,
+    float2* __restrict__ out) {
+  __shared__ cx<float> sp[12][256];
+  __shared__ S sc[36][256];
+  int tile, unused;
+  if (!xcd_slab_tile(g, 1, 1, tile, unused)) return;   // uniform per workgroup
+  const long long V = g.V, base = (long long)tile * 256, I = base + threadIdx.x;
+  const SiteLoc s = decode_site(g, I);
+  unsigned J[8];   // packed neighbour indices (V < 2^32)
+  unsigned inside = 0, wrap = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    bool w, in_;
+    J[k] = (unsigned)neighbor(g, s, k >> 1, (k & 1) ? -1 : +1, w, in_);
+    inside |= (unsigned)in_ << k;
+    wrap |= (unsigned)w << k;
+  }
+  S u[8][9];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+      u[k][e] = links[(long long)((k >> 1) * 9 + e) * V + ((k & 1) ? (long long)J[k] : I)];
+#pragma unroll
+  for (int e = 0; e < 36; ++e) sc[e][threadIdx.x] = clov[(long long)e * V + I];
+#pragma unroll 1
+  for (int r = 0; r < nrhs; ++r) {
+    const float2* x = in + (long long)r * 12 * V;
+    cx<float> psi[12], acc[12];
+    load_spinor<float, float2>(x, V, I, psi);
+    __syncthreads();   // the previous right-hand side's reads of sp are done
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sp[c][threadIdx.x] = psi[c];
+    __syncthreads();
+    clover_rows<S, 256>(&sc[0][threadIdx.x], psi, acc);
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+      cx<float> nb[12], uk[9];
+      if ((inside >> k) & 1) {
+        const int jl = (int)(J[k] - (unsigned)base);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) nb[c] = sp[c][jl];
+      } else {
+        load_spinor<float, float2>(x, V, (long long)J[k], nb);
+      }
+      const float coef = -0.5f * (((wrap >> k) & 1) ? (float)g.bc_t : 1.f);
+      switch (k) {
+#define DD_HOP(K, MU, SG, DG)                                                      \
+  case K:                                                                         \
+    _Pragma("unroll") for (int e = 0; e < 9; ++e) uk[e] = ld<float, S>(&u[K][e]); \
+    hop_t<MU, SG, DG, float>(uk, nb, coef, acc);                                  \
+    break;
+        DD_HOP(0, 0, -1, false)
+        DD_HOP(1, 0, +1, true)
+        DD_HOP(2, 1, -1, false)
+        DD_HOP(3, 1, +1, true)
+        DD_HOP(4, 2, -1, false)
+        DD_HOP(5, 2, +1, true)
+        DD_HOP(6, 3, -1, false)
+        default: DD_HOP(7, 3, +1, true)
+#undef DD_HOP
+      }
+    }
+    store_spinor<float, float2>(out + (long long)r * 12 * V, V, I, acc);
+  }
+}
+
 // useful flops of one site's D apply: eight hops (project, SU(3) times a half
 // spinor, reconstruct and accumulate: 1320), the two packed 6x6 clover blocks
 // (504) and the final sum (24)
@@ -75,6 +180,17 @@ constexpr double kDiracFlopsPerSite = 1320.0 + 504.0 + 24.0;
 
 static void dirac_dispatch(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
                            int threads, hipStream_t st) {
+  if (g.Bv == 256 && g.Vc % 16 == 0 && nrhs >= 2 && (dt == DD_F16 || dt == DD_BF16)) {
+    // operator in registers across the right-hand sides
+    const unsigned nb = xcd_grid(g.Vc, 1);
+    if (dt == DD_F16)
+      k_dirac_hl<__half2><<<nb, 256, 0, st>>>(g, (const __half2*)ops.links, (const __half2*)ops.clover, nrhs,
+                                               (const float2*)in, (float2*)out);
+    else
+      k_dirac_hl<bf16x2><<<nb, 256, 0, st>>>(g, (const bf16x2*)ops.links, (const bf16x2*)ops.clover, nrhs,
+                                              (const float2*)in, (float2*)out);
+    return;
+  }
   if (g.Bv == 256 && g.Vc % 16 == 0) {   // block form, slab order over the blocks
     const unsigned nb = xcd_grid(g.Vc, nrhs);
     switch (dt) {
