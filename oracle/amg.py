@@ -79,6 +79,12 @@ def gram_schmidt(lat, tv, passes=2, rank_tol=1e-12):
     times its norm before the projections marks the set as rank deficient."""
     g = to_aggregates(lat, tv)                  # [n][Vc][2][K]
     g = np.moveaxis(g, 0, 2).copy()             # [Vc][2][n][K]
+    return mgs_sets(g, passes, rank_tol)
+
+
+def mgs_sets(g, passes=2, rank_tol=1e-12):
+    """Modified Gram-Schmidt of every set g[X, s, :, :] (n vectors of length K),
+    in place: vectors in order, `passes` projection sweeps, real positive norms."""
     n = g.shape[2]
     for i in range(n):
         v = g[:, :, i]
