@@ -341,6 +341,74 @@ dd_status dd_coarse_solve_noalloc(dd_mg* mg, dd_dtype dt, int nrhs, const void* 
 /* out = M in (Eq. 5), packed fine vectors of the inner dtype */
 dd_status dd_precond_apply(dd_mg* mg, int nrhs, const void* in, void* out, void* stream);
 
+/* ---- third level ---------------------------------------------------------------------------
+ * The paper runs two levels and notes that the coarse solver may itself be a
+ * multigrid method (Sec. 1, Sec. 2).  dd_mg_add_level applies the construction
+ * of Eqs. (1)-(4) once more, to D_c:
+ *   - level-2 aggregates are blocks of 2^4 coarse sites; a coarse vector's
+ *     chirality s is its components s*n .. s*n + n - 1 (the coarse gamma5 is +1
+ *     on the first n components of a site, -1 on the last n);
+ *   - P2 holds the n_vec2 level-2 test vectors restricted to each (aggregate,
+ *     chirality), orthonormalised there by modified Gram-Schmidt (two sweeps,
+ *     vectors in order), so a level-3 site carries 2 n_vec2 components;
+ *   - D3 = P2^dag D_c P2 as 9 blocks per level-3 site: block d collects the
+ *     coarse hops (x, dd) with x + dd inside the same 2^4 block (d = self) or
+ *     crossing its face in direction dd (d = dd), with +mu and -mu kept apart.
+ * The coarse correction of M (and dd_coarse_solve) then solves D_c y = b by one
+ * cycle of flexible GMRES on D_c (one classical Gram-Schmidt pass per step,
+ * at most kcycle_max_iters steps, stopped per right-hand side when its residual
+ * estimate reaches kcycle_tol |b|, or exactly kcycle_max_iters steps when
+ * kcycle_fixed), right preconditioned by
+ *   M2 v = MR_k(D_c; v, x0 = P2 D3^-1 R2 v),
+ * k = mr_steps minimal-residual steps on D_c started from the level-3
+ * correction, D3^-1 being the even-odd GMRES of the coarse level run on the
+ * level-3 lattice (l3_tol / l3_restart / l3_max_iters / l3_fixed_iters; the
+ * Gram-Schmidt passes are the setup's coarse_cgs_passes).  Arithmetic is the
+ * setup's inner dtype; the level-3 blocks are FP32 (FP64 for an all-FP64 setup).
+ * Requires every coarse-lattice extent L[mu] / block[mu] to be a multiple of 4
+ * (even level-3 extents, for the even-odd split) and n_vec2 in {6, 8, 12, 16,
+ * 20, 24}.  With a third level, graph mode 2 runs as mode 1 (the level-3 GMRES
+ * checks convergence on the host), dd_autotune and dd_coarse_solve_noalloc
+ * return DD_ESTATE (tune before adding the level), and dd_setup_update_mass
+ * rebuilds D3 from the kept P2.  The level's memory is not part of
+ * dd_footprint_bytes. */
+typedef struct {
+  int32_t n_vec2;            /* level-2 test vectors (6, 8, 12, 16, 20 or 24) */
+  int32_t setup_iters;       /* test vectors without tv2_host: Gaussian vectors (seed) improved by this many
+                                inverse-iteration passes y <- (two-level coarse solve of D_c) y, normalised */
+  int32_t mr_steps;          /* minimal-residual steps on D_c after the level-3 correction */
+  int32_t kcycle_max_iters;  /* steps of the level-2 FGMRES cycle, 1 .. 64 */
+  int32_t kcycle_fixed;      /* 1: exactly kcycle_max_iters steps (no tolerance stop) */
+  int32_t l3_restart;        /* level-3 GMRES restart, 1 .. 256 */
+  int32_t l3_max_iters;      /* level-3 GMRES iteration cap */
+  int32_t l3_fixed_iters;    /* > 0: exactly this many level-3 GMRES steps */
+  double kcycle_tol;         /* level-2 relative residual estimate */
+  double l3_tol;             /* level-3 relative residual */
+  uint64_t seed;             /* Gaussian level-2 test vectors */
+} dd_level3_params;
+void dd_level3_params_default(dd_level3_params* p);
+/* Attach the third level to a setup.  tv2_host: NULL (vectors from the seed and
+ * setup_iters) or [n_vec2][Vc][2n] complex128 level-2 test vectors, coarse sites
+ * in lexicographic block order (the order of dd_pack_coarse's canonical form),
+ * copied.  DD_ESTATE when a level is attached or a stepwise solve holds the
+ * workspace, DD_ESHAPE / DD_EINVAL for the limits above, DD_EINVAL when the
+ * vectors are rank deficient on some (aggregate, chirality). */
+dd_status dd_mg_add_level(dd_mg* mg, const dd_level3_params* p, const double* tv2_host);
+dd_status dd_mg_remove_level(dd_mg* mg);   /* back to the two-level coarse solve */
+/* Vc3 level-3 sites and 2 n_vec2 components per site (0, 0 without a third level) */
+dd_status dd_level3_shape(const dd_mg* mg, int32_t* vc3, int32_t* nc3);
+/* Host copies (each pointer may be NULL), level-3 sites X in lexicographic order
+ * of the level-3 lattice (x fastest), l = lx + 2 (ly + 2 (lz + 2 lt)) the
+ * position of a coarse site inside its block:
+ *   tv2 [n_vec2][Vc][2n]        the level-2 test vectors (coarse sites lexicographic)
+ *   p2  [Vc3][2][n_vec2][16 n]  P2: entry l*n + c of vector i of chirality s of X
+ *   d3  [Vc3][9][nc3][nc3]      D3 blocks, row-major
+ * all complex128. */
+dd_status dd_export_level3(const dd_mg* mg, double* tv2_host, double* p2_host, double* d3_host);
+/* Steps of the last level-2 FGMRES cycle (longest over its right-hand sides) and
+ * the level-3 GMRES steps it ran, summed over its preconditioner applications. */
+dd_status dd_level3_last(const dd_mg* mg, int32_t* kcycle_steps, int32_t* l3_steps);
+
 /* ---- solve -------------------------------------------------------------------------------
  * FGMRES(m) right-preconditioned by M; the outer residual, orthogonalisation
  * and Hessenberg least squares are FP64 on the device; stops when every

@@ -64,6 +64,13 @@ class dd_solve_info(ctypes.Structure):
                 ("flops_model", ctypes.c_int64)]
 
 
+class dd_level3_params(ctypes.Structure):
+    _fields_ = [("n_vec2", ctypes.c_int32), ("setup_iters", ctypes.c_int32), ("mr_steps", ctypes.c_int32),
+                ("kcycle_max_iters", ctypes.c_int32), ("kcycle_fixed", ctypes.c_int32),
+                ("l3_restart", ctypes.c_int32), ("l3_max_iters", ctypes.c_int32), ("l3_fixed_iters", ctypes.c_int32),
+                ("kcycle_tol", ctypes.c_double), ("l3_tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
 class dd_footprint(ctypes.Structure):
     _fields_ = [("gauge_bytes", ctypes.c_size_t), ("setup_bytes", ctypes.c_size_t),
                 ("scratch_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
@@ -122,6 +129,12 @@ SIGNATURES = {
     "dd_export_clover": (_I, [_P, _P, _P]),
     "dd_export_operands": (_I, [_P, _I, _P, _P]),
     "dd_export_coarse": (_I, [_P, _P]),
+    "dd_level3_params_default": (None, [ctypes.POINTER(dd_level3_params)]),
+    "dd_mg_add_level": (_I, [_P, ctypes.POINTER(dd_level3_params), _P]),
+    "dd_mg_remove_level": (_I, [_P]),
+    "dd_level3_shape": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "dd_level3_last": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "dd_export_level3": (_I, [_P, _P, _P, _P]),
     "dd_export_vectors": (_I, [_P, _P]),
     "dd_kernel_timer_enable": (_I, [ctypes.c_char_p]),
     "dd_kernel_timer_read": (_I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -234,6 +247,14 @@ def default_params(**kw):
                     p.sap_block[m] = v[m]
         else:
             setattr(p, k, v)
+    return p
+
+
+def level3_params(**kw):
+    p = dd_level3_params()
+    lib().dd_level3_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
     return p
 
 
@@ -433,6 +454,41 @@ class MG:
         tv = np.zeros((self.n, self.g.V, 4, 3), dtype=np.complex128)
         self.ctx.check(self.ctx.lib.dd_export_vectors(self.h, tv.ctypes.data_as(_P)))
         return tv
+
+    def add_level(self, params, tv2_host=None):
+        """Attach the third level; tv2_host: None or [n_vec2][Vc][2n] complex128 (coarse sites lexicographic)."""
+        if tv2_host is None:
+            self.ctx.check(self.ctx.lib.dd_mg_add_level(self.h, ctypes.byref(params), None))
+        else:
+            tv = np.ascontiguousarray(tv2_host, dtype=np.complex128)
+            assert tv.shape == (params.n_vec2, self.g.Vc, 2 * self.n)
+            self.ctx.check(self.ctx.lib.dd_mg_add_level(self.h, ctypes.byref(params), tv.ctypes.data_as(_P)))
+
+    def remove_level(self):
+        self.ctx.check(self.ctx.lib.dd_mg_remove_level(self.h))
+
+    def level3_shape(self):
+        """(Vc3, nc3): level-3 sites and components per site; (0, 0) without a third level."""
+        a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        self.ctx.check(self.ctx.lib.dd_level3_shape(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def level3_last(self):
+        """(level-2 FGMRES steps, level-3 GMRES steps) of the last coarse solve."""
+        a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        self.ctx.check(self.ctx.lib.dd_level3_last(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def export_level3(self):
+        """(tv2 [n2][Vc][2n], P2 [Vc3][2][n2][16 n], D3 [Vc3][9][nc3][nc3]), complex128, lexicographic sites."""
+        vc3, nc3 = self.level3_shape()
+        n2 = nc3 // 2
+        tv2 = np.zeros((n2, self.g.Vc, 2 * self.n), dtype=np.complex128)
+        p2 = np.zeros((vc3, 2, n2, 16 * self.n), dtype=np.complex128)
+        d3 = np.zeros((vc3, 9, nc3, nc3), dtype=np.complex128)
+        self.ctx.check(self.ctx.lib.dd_export_level3(self.h, tv2.ctypes.data_as(_P), p2.ctypes.data_as(_P),
+                                                     d3.ctypes.data_as(_P)))
+        return tv2, p2, d3
 
 
 def _info_dict(i):

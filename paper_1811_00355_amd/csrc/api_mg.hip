@@ -82,6 +82,7 @@ struct Workspace {
   Arnoldi fa;
   double* partial;
   int* citers = nullptr;   // coarse Arnoldi steps of the device-driven solves (whole-M graphs)
+  double2* mr = nullptr;   // minimal-residual smoother of a third level: <Ar, r>, <Ar, Ar>, alpha per RHS
   int* hflags = nullptr;   // pinned host mirror: active[nrhs], kcyc[nrhs]
   double* hvals = nullptr; // pinned host mirror: est[nrhs], tolabs[nrhs], nrm[nrhs]
   // captured coarse GMRES chunks, keyed by (nrhs, dtype, basis dtype, block dtype, waves per workgroup,
@@ -173,17 +174,50 @@ static size_t ws_bytes(const WsShape& sh, int nrhs, bool outer) {
   return w.arena.used + 256;
 }
 
-static void free_ws(dd_mg* mg) {
-  Workspace* w = mg->ws;
+static void destroy_ws(dd_ctx* ctx, Workspace* w) {
   if (!w) return;
-  dd_free(mg->ctx, w->arena.base, w->arena.cap);
+  dd_free(ctx, w->arena.base, w->arena.cap);
   if (w->hflags) (void)hipHostFree(w->hflags);
   if (w->hvals) (void)hipHostFree(w->hvals);
   for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   for (auto& kv : w->mgraphs) (void)hipGraphExecDestroy(kv.second.exec);
   if (w->cap) (void)hipStreamDestroy(w->cap);
   delete w;
+}
+
+static void free_ws(dd_mg* mg) {
+  destroy_ws(mg->ctx, mg->ws);
   mg->ws = nullptr;
+}
+
+// A workspace for nrhs right-hand sides laid out by carve(w) (called once to
+// size the arena, once to place it), zero-filled, with its pinned host mirrors.
+template <typename Carve>
+static dd_status alloc_ws(dd_ctx* ctx, int nrhs, Carve carve, Workspace** out) {
+  Workspace* w = new Workspace();
+  w->nrhs = nrhs;
+  w->arena.ctx = ctx;
+  w->arena.sizing = true;
+  carve(*w);
+  const size_t bytes = w->arena.used + 256;
+  dd_status st = dd_alloc(ctx, (void**)&w->arena.base, bytes);
+  if (st) {
+    delete w;
+    return st;
+  }
+  w->arena.cap = bytes;
+  w->arena.sizing = false;
+  // start from finite values everywhere (Krylov bases are read up to the longest cycle)
+  (void)hipMemset(w->arena.base, 0, bytes);
+  w->arena.used = 0;
+  carve(*w);
+  if (hipHostMalloc((void**)&w->hflags, sizeof(int) * 2 * nrhs) != hipSuccess ||
+      hipHostMalloc((void**)&w->hvals, sizeof(double) * 3 * nrhs) != hipSuccess) {
+    destroy_ws(ctx, w);
+    return dd_fail(ctx, DD_ENOMEM, "pinned host buffers");
+  }
+  *out = w;
+  return DD_OK;
 }
 
 static dd_status ensure_ws(dd_mg* mg, int nrhs, bool outer) {
@@ -194,31 +228,13 @@ static dd_status ensure_ws(dd_mg* mg, int nrhs, bool outer) {
     outer = outer || w->outer;
     free_ws(mg);
   }
-  w = new Workspace();
-  w->nrhs = nrhs;
-  w->outer = outer;
-  w->arena.ctx = mg->ctx;
   const WsShape sh = ws_shape(mg);
-  const size_t bytes = ws_bytes(sh, nrhs, outer);
-  dd_status st = dd_alloc(mg->ctx, (void**)&w->arena.base, bytes);
-  if (st) {
-    delete w;
-    return st;
-  }
-  w->arena.cap = bytes;
-  w->arena.sizing = false;
-  // start from finite values everywhere (Krylov bases are read up to the longest cycle)
-  (void)hipMemset(w->arena.base, 0, bytes);
-  w->arena.used = 0;
-  carve_ws(*w, sh, nrhs, outer);
-  if (hipHostMalloc((void**)&w->hflags, sizeof(int) * 2 * nrhs) != hipSuccess ||
-      hipHostMalloc((void**)&w->hvals, sizeof(double) * 3 * nrhs) != hipSuccess) {
-    mg->ws = w;
-    free_ws(mg);
-    return dd_fail(mg->ctx, DD_ENOMEM, "pinned host buffers");
-  }
-  mg->ws = w;
-  return DD_OK;
+  return alloc_ws(mg->ctx, nrhs,
+                  [&](Workspace& x) {
+                    x.outer = outer;
+                    carve_ws(x, sh, nrhs, outer);
+                  },
+                  &mg->ws);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,11 +353,10 @@ static void issue_chunk(const CoarseOps& c, Workspace* w, Arnoldi& a, int passes
 
 // Run a chunk on `st`: directly, or by replaying its graph (captured on first use
 // on the workspace's own stream; capturing launches nothing).
-static dd_status run_chunk(dd_mg* mg, Workspace* w, bool graphs, const CoarseOps& c, int nrhs, long long ce,
-                           long long ld, long long vs, int j0, int len, bool ends, hipStream_t st) {
+static dd_status run_chunk(dd_ctx* ctx, int passes, Workspace* w, bool graphs, const CoarseOps& c, int nrhs,
+                           long long ce, long long ld, long long vs, int j0, int len, bool ends, hipStream_t st) {
   Arnoldi& a = w->ca;
   char* CV = (char*)w->CV;
-  const int passes = mg->p.coarse_cgs_passes;
   if (!graphs) {
     issue_chunk(c, w, a, passes, nrhs, ce, ld, vs, CV, j0, len, ends, st);
     return DD_OK;
@@ -349,8 +364,8 @@ static dd_status run_chunk(dd_mg* mg, Workspace* w, bool graphs, const CoarseOps
   const std::array<int, 9> key = {nrhs, (int)c.vt, (int)c.basis, (int)c.bt, c.spw, c.hm ? 1 : 0, j0, len, ends ? 1 : 0};
   auto it = w->graphs.find(key);
   if (it == w->graphs.end()) {
-    if (!w->cap) DD_HIP(mg->ctx, hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
-    DD_HIP(mg->ctx, hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
+    if (!w->cap) DD_HIP(ctx, hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking));
+    DD_HIP(ctx, hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal));
     double b0, f0, b1, f1;
     ktimer_model(&b0, &f0);
     ktimer_suspend(true);
@@ -359,14 +374,14 @@ static dd_status run_chunk(dd_mg* mg, Workspace* w, bool graphs, const CoarseOps
     ktimer_model(&b1, &f1);
     ktimer_model_set(b0, f0);   // capturing executes nothing; the replay below accounts for it
     hipGraph_t gr = nullptr;
-    DD_HIP(mg->ctx, hipStreamEndCapture(w->cap, &gr));
+    DD_HIP(ctx, hipStreamEndCapture(w->cap, &gr));
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
-    if (e != hipSuccess) return dd_hip_check(mg->ctx, e, "hipGraphInstantiate (coarse GMRES chunk)");
+    if (e != hipSuccess) return dd_hip_check(ctx, e, "hipGraphInstantiate (coarse GMRES chunk)");
     it = w->graphs.emplace(key, Workspace::Captured{ex, b1 - b0, f1 - f0}).first;
   }
-  DD_HIP(mg->ctx, hipGraphLaunch(it->second.exec, st));
+  DD_HIP(ctx, hipGraphLaunch(it->second.exec, st));
   ktimer_account(it->second.bytes, it->second.flops);
   return DD_OK;
 }
@@ -391,48 +406,59 @@ struct HostArr {
   T& operator[](int i) { return p[i]; }
 };
 
-// y ~= D_c^-1 b by GMRES on the even-site Schur complement, then the odd sites,
-// on workspace w (coarse part), chunks replayed from graphs when `graphs`.
-static dd_status coarse_solve(dd_mg* mg, Workspace* w, bool graphs, dd_dtype vt, int nrhs, const void* b, void* y,
-                              int* iters_out, hipStream_t st) {
-  CoarseOps c = coarse_ops(mg, vt);
+// iteration controls of one even-odd GMRES solve
+struct CoarseIter {
+  int fixed_iters, max_iters, passes;
+  double tol;
+};
+
+static CoarseIter coarse_iter(const dd_mg* mg) {
+  return {mg->p.coarse_fixed_iters, mg->p.coarse_max_iters, mg->p.coarse_cgs_passes, mg->p.coarse_tol};
+}
+
+// y ~= A^-1 b by GMRES on the even-site Schur complement, then the odd sites,
+// for the stencil operator A that c describes, on workspace w (coarse part),
+// chunks replayed from graphs when `graphs`.
+static dd_status coarse_solve_ops(dd_ctx* ctx, Workspace* w, bool graphs, const CoarseOps& c, const CoarseIter& ci,
+                                  int nrhs, const void* b, void* y, int* iters_out, hipStream_t st) {
+  const dd_dtype vt = c.vt;
   const GeomDev& g = *c.g;
   const int nc = c.nc;
   const long long ld = (long long)g.Vc * nc, ce = (long long)g.Vch * nc;
   const size_t vb = vector_pair_bytes(vt);
   Arnoldi& a = w->ca;
   const int m = a.m;
-  const bool fixed = mg->p.coarse_fixed_iters > 0;
-  const int cap = fixed ? mg->p.coarse_fixed_iters : mg->p.coarse_max_iters;
-  const double tol = fixed ? 0.0 : mg->p.coarse_tol;
+  const bool fixed = ci.fixed_iters > 0;
+  const int cap = fixed ? ci.fixed_iters : ci.max_iters;
+  const double tol = fixed ? 0.0 : ci.tol;
   // rhs' = b_e - D_eo D_oo^-1 b_o
   launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, b, 0.0, nullptr, 0.0, nullptr, w->ct1, st, c.spw, c.bt, c.hm);
   launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vch, 0.0, nullptr, -1.0, w->ct1, 1.0, b, w->cr, st, c.spw, c.bt, c.hm);
-  DD_HIP(mg->ctx, hipMemsetAsync(y, 0, (size_t)nrhs * ld * vb, st));
+  DD_HIP(ctx, hipMemsetAsync(y, 0, (size_t)nrhs * ld * vb, st));
   // tolerance: tol * |rhs'|
   norms2(w, vt, nrhs, ce, ld, w->cr, a.nrm2, st);
   {
     HostArr<double2> n2(nrhs);
     HostArr<double> tl(nrhs);
     HostArr<int> fin(nrhs, 0);
-    DD_HIP(mg->ctx, hipMemcpyAsync(n2.p, a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
-    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+    DD_HIP(ctx, hipMemcpyAsync(n2.p, a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(ctx, hipStreamSynchronize(st));
     for (int r = 0; r < nrhs; ++r) tl[r] = tol * std::sqrt(n2[r].x);
-    DD_HIP(mg->ctx, hipMemcpyAsync(a.tolabs, tl.p, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.p, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+    DD_HIP(ctx, hipMemcpyAsync(a.tolabs, tl.p, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(ctx, hipMemcpyAsync(a.finished, fin.p, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(ctx, hipStreamSynchronize(st));
   }
   const long long vs = (long long)nrhs * ld;   // basis stride
   char* CV = (char*)w->CV;
   if (w->cv_type != c.basis) {
-    DD_HIP(mg->ctx, hipMemsetAsync(CV, 0, w->cv_bytes, st));
+    DD_HIP(ctx, hipMemsetAsync(CV, 0, w->cv_bytes, st));
     w->cv_type = c.basis;
   }
   int iters = 0;
   while (iters < cap) {
     // r = rhs' - S y  (first cycle: y = 0)
     if (iters == 0) {
-      DD_HIP(mg->ctx, hipMemcpyAsync(w->cres, w->cr, (size_t)nrhs * ld * vb, hipMemcpyDeviceToDevice, st));
+      DD_HIP(ctx, hipMemcpyAsync(w->cres, w->cr, (size_t)nrhs * ld * vb, hipMemcpyDeviceToDevice, st));
     } else {
       schur_apply(c, nrhs, y, w->cw, w->ct1, w->ct2, st);
       launch_sub(vt, (long long)nrhs * ld, w->cr, w->cw, w->cres, st);
@@ -448,7 +474,7 @@ static dd_status coarse_solve(dd_mg* mg, Workspace* w, bool graphs, dd_dtype vt,
     for (int j = 0; j < mm;) {
       const int len = mm - j < 4 ? mm - j : 4;
       const bool ends = j + len == mm;
-      dd_status cs = run_chunk(mg, w, graphs, c, nrhs, ce, ld, vs, j, len, ends, st);
+      dd_status cs = run_chunk(ctx, ci.passes, w, graphs, c, nrhs, ce, ld, vs, j, len, ends, st);
       if (cs) return cs;
       iters += len;
       j += len;
@@ -457,23 +483,274 @@ static dd_status coarse_solve(dd_mg* mg, Workspace* w, bool graphs, dd_dtype vt,
     launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
     launch_multi_axpy(c.basis, vt, nrhs, ce, ld, CV, max_kcyc(w, a, nrhs, st), vs, a.y, m, 0, 1.0, y, st);
     // RHS whose estimate met the tolerance are finished
-    DD_HIP(mg->ctx, hipMemcpyAsync(w->hvals, a.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    DD_HIP(mg->ctx, hipMemcpyAsync(w->hvals + nrhs, a.tolabs, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    DD_HIP(mg->ctx, hipMemcpyAsync(w->hflags, a.finished, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
-    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+    DD_HIP(ctx, hipMemcpyAsync(w->hvals, a.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(ctx, hipMemcpyAsync(w->hvals + nrhs, a.tolabs, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(ctx, hipMemcpyAsync(w->hflags, a.finished, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(ctx, hipStreamSynchronize(st));
     int nfin = 0;
     for (int r = 0; r < nrhs; ++r) {
       if (w->hvals[r] <= w->hvals[nrhs + r]) w->hflags[r] = 1;
       nfin += w->hflags[r];
     }
-    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, w->hflags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(ctx, hipMemcpyAsync(a.finished, w->hflags, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
     if (nfin == nrhs) break;
   }
   // odd sites: y_o = D_oo^-1 (b_o - D_oe y_e)
   launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, g.Vch, g.Vch, 0.0, nullptr, -1.0, y, 1.0, b, w->ct1, st, c.spw, c.bt, c.hm);
   launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 1, nrhs, g.Vch, g.Vch, 1.0, w->ct1, 0.0, nullptr, 0.0, nullptr, y, st, c.spw, c.bt, c.hm);
-  DD_HIP(mg->ctx, hipGetLastError());
+  DD_HIP(ctx, hipGetLastError());
   if (iters_out) *iters_out = iters;
+  return DD_OK;
+}
+
+// the coarse level's own solve: even-odd GMRES on D_c
+static dd_status coarse_solve(dd_mg* mg, Workspace* w, bool graphs, dd_dtype vt, int nrhs, const void* b, void* y,
+                              int* iters_out, hipStream_t st) {
+  return coarse_solve_ops(mg->ctx, w, graphs, coarse_ops(mg, vt), coarse_iter(mg), nrhs, b, y, iters_out, st);
+}
+
+// ---------------------------------------------------------------------------
+// third level (kernels in level3.hip): P2, D3 = P2^dag D_c P2, and the coarse
+// correction as one flexible GMRES cycle on D_c right preconditioned by
+//   M2 v = MR_k(D_c; v, x0 = P2 D3^-1 R2 v),
+// D3^-1 being the even-odd GMRES above run on the level-3 lattice.
+// ---------------------------------------------------------------------------
+struct Level3 {
+  dd_level3_params p{};
+  int n2 = 0, nc3 = 0, Vc3 = 0;
+  int NB3[4] = {0, 0, 0, 0};
+  GeomDev g3{};                  // the level-3 lattice as the stencil kernels read it: Vc, Vch, blk_nbr
+  std::vector<int> h_lex3;       // lexicographic index of level-3 slot X
+  // one allocation: tables, test vectors, P2 and the level-3 blocks
+  char* base = nullptr;
+  size_t bytes = 0;
+  int *nbr3, *slot_of, *l3_of, *loc_of, *flag;
+  double2* tv2;                  // [n2][Vc][2n], coarse slot order
+  double2* P2_64;                // [Vc3][2][n2][16 n]
+  float2* P2_32;
+  double2 *D3_64, *Dinv3_64;     // [Vc3][9][col][row], odd sites [Vc3 / 2][col][row]
+  float2 *D3_32, *Dinv3_32;      // FP32 copies in the matrix-core order
+  Workspace* w3 = nullptr;       // level-3 even-odd GMRES
+  Workspace* wk = nullptr;       // level-2 FGMRES cycle and its smoother
+  int last_steps = 0, last_l3 = 0;
+};
+
+static void l3_carve(Level3* L, Arena& a, long long Vc, int n) {
+  const long long Vc3 = L->Vc3, nc3 = L->nc3, nvec = (long long)L->n2 * Vc * 2 * n;
+  L->nbr3 = a.take<int>(8 * Vc3);
+  L->slot_of = a.take<int>(Vc);
+  L->l3_of = a.take<int>(Vc);
+  L->loc_of = a.take<int>(Vc);
+  L->flag = a.take<int>(1);
+  L->tv2 = a.take<double2>(nvec);
+  L->P2_64 = a.take<double2>(nvec);
+  L->P2_32 = a.take<float2>(nvec);
+  L->D3_64 = a.take<double2>(Vc3 * 9 * nc3 * nc3);
+  L->Dinv3_64 = a.take<double2>(Vc3 / 2 * nc3 * nc3);
+  L->D3_32 = a.take<float2>(Vc3 * 9 * nc3 * nc3);
+  L->Dinv3_32 = a.take<float2>(Vc3 / 2 * nc3 * nc3);
+}
+
+static void l3_free_ws(dd_mg* mg) {
+  Level3* L = mg->l3;
+  if (!L) return;
+  destroy_ws(mg->ctx, L->w3);
+  destroy_ws(mg->ctx, L->wk);
+  L->w3 = L->wk = nullptr;
+}
+
+static void l3_free(dd_mg* mg) {
+  Level3* L = mg->l3;
+  if (!L) return;
+  l3_free_ws(mg);
+  dd_free(mg->ctx, L->base, L->bytes);
+  delete L;
+  mg->l3 = nullptr;
+}
+
+// level-2 FGMRES workspace: D_c z, the smoother's r and D_c r, R2 v and its
+// level-3 solve, the Arnoldi basis v_0 .. v_m and the directions z_0 .. z_{m-1}
+static void carve_k2(Workspace& w, long long ldc, long long ld3, int nrhs, int m, dd_dtype vt) {
+  Arena& a = w.arena;
+  const size_t vb = vector_pair_bytes(vt);
+  const long long coarse = ldc * nrhs;
+  w.cw = a.take<char>(coarse * vb);
+  w.cr = a.take<char>(coarse * vb);
+  w.ct1 = a.take<char>(coarse * vb);
+  w.cb = a.take<char>(ld3 * nrhs * vb);
+  w.cy = a.take<char>(ld3 * nrhs * vb);
+  w.cv_bytes = (size_t)(m + 1) * coarse * vb;
+  w.CV = a.take<char>(w.cv_bytes);
+  w.Z = a.take<char>((size_t)m * coarse * vb);
+  w.fa.carve(a, nrhs, m);
+  w.mr = a.take<double2>(3 * (size_t)nrhs);
+  size_t np = (size_t)nrhs * 16 * dots_blocks(ldc, nrhs) * 2;
+  const size_t np_gs = (size_t)nrhs * m * gs_blocks(ldc) * 2;
+  w.partial = a.take<double>(std::max(np, np_gs));
+}
+
+static dd_status l3_ensure_ws(dd_mg* mg, int nrhs) {
+  Level3* L = mg->l3;
+  if (L->w3 && L->w3->nrhs >= nrhs) return DD_OK;
+  if (L->w3 && L->w3->nrhs > nrhs) nrhs = L->w3->nrhs;
+  l3_free_ws(mg);
+  const dd_dtype vt = inner_vt(mg);
+  const WsShape s3{0, L->Vc3, L->Vc3 / 2, L->nc3, L->p.l3_restart, 1, vt};
+  dd_status s = alloc_ws(mg->ctx, nrhs, [&](Workspace& x) { carve_ws(x, s3, nrhs, false, false); }, &L->w3);
+  if (s) return s;
+  const long long ldc = (long long)mg->g->geo.Vc * mg->nc, ld3 = (long long)L->Vc3 * L->nc3;
+  s = alloc_ws(mg->ctx, nrhs, [&](Workspace& x) { carve_k2(x, ldc, ld3, nrhs, L->p.kcycle_max_iters, vt); }, &L->wk);
+  if (s) l3_free_ws(mg);
+  return s;
+}
+
+static CoarseOps l3_ops(const dd_mg* mg, dd_dtype vt) {
+  const Level3* L = mg->l3;
+  CoarseOps c;
+  c.g = &L->g3;
+  c.vt = vt;
+  c.nc = L->nc3;
+  c.Dc = vt == DD_F64 ? (const void*)L->D3_64 : (const void*)L->D3_32;
+  c.Dinv = vt == DD_F64 ? (const void*)L->Dinv3_64 : (const void*)L->Dinv3_32;
+  c.spw = mg->g->tune.coarse_spw;
+  c.bt = vt == DD_F64 ? DD_F64 : DD_F32;
+  c.hm = false;
+  c.basis = vt;
+  c.bb = vector_pair_bytes(vt);
+  return c;
+}
+
+// z = M2 v on the level-2 workspace; *it3 <- level-3 GMRES steps
+static dd_status precond2(dd_mg* mg, dd_dtype vt, int nrhs, const void* v, void* z, int* it3, hipStream_t st) {
+  Level3* L = mg->l3;
+  Workspace* w = L->wk;
+  const GeomDev& g = mg->g->geo;
+  const int nc = mg->nc, n = mg->n;
+  const long long ld = (long long)g.Vc * nc;
+  const void* P2 = vt == DD_F64 ? (const void*)L->P2_64 : (const void*)L->P2_32;
+  launch_restrict2(vt, g.Vc, L->Vc3, n, L->n2, L->slot_of, P2, nrhs, v, w->cb, st);
+  const CoarseIter ci{L->p.l3_fixed_iters, L->p.l3_max_iters, mg->p.coarse_cgs_passes, L->p.l3_tol};
+  dd_status s = coarse_solve_ops(mg->ctx, L->w3, mg->graphs >= 1, l3_ops(mg, vt), ci, nrhs, w->cb, w->cy, it3, st);
+  if (s) return s;
+  launch_prolong2(vt, g.Vc, L->Vc3, n, L->n2, L->l3_of, L->loc_of, P2, nrhs, w->cy, z, st);
+  if (L->p.mr_steps == 0) return DD_OK;
+  const CoarseOps c = coarse_ops(mg, vt);
+  // r = v - D_c z, then per step: alpha = <D_c r, r> / <D_c r, D_c r>, z += alpha r, r -= alpha D_c r
+  launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vc, -1.0, z, -1.0, z, 1.0, v, w->cr, st, c.spw, c.bt, c.hm);
+  double2 *num = w->mr, *den = w->mr + nrhs, *alpha = w->mr + 2 * nrhs;
+  const int nblk = dots_blocks(ld, nrhs);
+  for (int k = 0; k < L->p.mr_steps; ++k) {
+    launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vc, 1.0, w->cr, 1.0, w->cr, 0.0, nullptr, w->ct1, st,
+                     c.spw, c.bt, c.hm);
+    launch_dots(vt, vt, nrhs, ld, ld, w->ct1, 1, 0, w->cr, w->partial, nblk, num, 1, 0, st);
+    launch_dots(vt, vt, nrhs, ld, ld, w->ct1, 1, 0, w->ct1, w->partial, nblk, den, 1, 0, st);
+    launch_mr_alpha(nrhs, num, den, alpha, st);
+    launch_multi_axpy(vt, vt, nrhs, ld, ld, w->cr, 1, 0, alpha, 1, 0, 1.0, z, st);
+    if (k + 1 < L->p.mr_steps) launch_multi_axpy(vt, vt, nrhs, ld, ld, w->ct1, 1, 0, alpha, 1, 0, -1.0, w->cr, st);
+  }
+  return DD_OK;
+}
+
+// y ~= D_c^-1 b: one flexible GMRES cycle from y = 0, right preconditioned by M2
+static dd_status kcycle_solve(dd_mg* mg, dd_dtype vt, int nrhs, const void* b, void* y, int* iters_out,
+                              hipStream_t st) {
+  Level3* L = mg->l3;
+  dd_status s = l3_ensure_ws(mg, nrhs);
+  if (s) return s;
+  Workspace* w = L->wk;
+  const GeomDev& g = mg->g->geo;
+  const int nc = mg->nc;
+  const long long ld = (long long)g.Vc * nc, vs = (long long)nrhs * ld;
+  const size_t vb = vector_pair_bytes(vt);
+  const CoarseOps c = coarse_ops(mg, vt);
+  Arnoldi& a = w->fa;
+  const int m = a.m;
+  const double tol = L->p.kcycle_fixed ? 0.0 : L->p.kcycle_tol;
+  char *V = (char*)w->CV, *Z = (char*)w->Z;
+  norms2(w, vt, nrhs, ld, ld, b, a.nrm2, st);
+  {
+    HostArr<double2> n2(nrhs);
+    HostArr<double> tl(nrhs);
+    HostArr<int> fin(nrhs, 0);
+    DD_HIP(mg->ctx, hipMemcpyAsync(n2.p, a.nrm2, sizeof(double2) * nrhs, hipMemcpyDeviceToHost, st));
+    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; ++r) tl[r] = tol * std::sqrt(n2[r].x);
+    DD_HIP(mg->ctx, hipMemcpyAsync(a.tolabs, tl.p, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(mg->ctx, hipMemcpyAsync(a.finished, fin.p, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  }
+  launch_cycle_init(nrhs, m, a.nrm2, a.tolabs, a.finished, a.gv, a.beta, a.active, a.kcyc, st);
+  launch_zero(y, (size_t)nrhs * ld * vb, st);
+  int steps = 0, total3 = 0;
+  if (count_active(w, a.active, nrhs, st) > 0) {
+    launch_normalize(vt, nrhs, ld, ld, b, nullptr, a.beta, a.active, V, st, vt);
+    for (int j = 0; j < m; ++j) {
+      char* Vj = V + (size_t)j * vs * vb;
+      char* Zj = Z + (size_t)j * vs * vb;
+      int it3 = 0;
+      if ((s = precond2(mg, vt, nrhs, Vj, Zj, &it3, st))) return s;
+      total3 += it3;
+      launch_coarse_mv(g, vt, nc, c.Dc, c.Dinv, 0, nrhs, 0, g.Vc, 1.0, Zj, 1.0, Zj, 0.0, nullptr, w->cw, st, c.spw,
+                       c.bt, c.hm);
+      cgs(w, a, vt, nrhs, ld, ld, V, vs, j + 1, w->cw, 1, st, vt);
+      launch_arnoldi(nrhs, m, j, a.h1, nullptr, a.nrm2, a.H, a.cs, a.sn, a.gv, a.tolabs, a.active, a.kcyc, a.est,
+                     a.hnext, st);
+      steps = j + 1;
+      if (j + 1 == m) break;
+      launch_normalize(vt, nrhs, ld, ld, w->cw, nullptr, a.hnext, a.active, V + (size_t)(j + 1) * vs * vb, st, vt);
+      if (count_active(w, a.active, nrhs, st) == 0) break;
+    }
+    launch_lsq(nrhs, m, a.H, a.gv, a.kcyc, a.y, st);
+    launch_multi_axpy(vt, vt, nrhs, ld, ld, Z, max_kcyc(w, a, nrhs, st), vs, a.y, m, 0, 1.0, y, st);
+  }
+  DD_HIP(mg->ctx, hipGetLastError());
+  L->last_steps = steps;
+  L->last_l3 = total3;
+  if (iters_out) *iters_out = steps;
+  return DD_OK;
+}
+
+// the coarse correction's solve: two-level GMRES, or the level-2 cycle when a third level is attached
+static dd_status coarse_correction(dd_mg* mg, Workspace* w, bool graphs, dd_dtype vt, int nrhs, const void* b,
+                                   void* y, int* iters_out, hipStream_t st) {
+  if (mg->l3) return kcycle_solve(mg, vt, nrhs, b, y, iters_out, st);
+  return coarse_solve(mg, w, graphs, vt, nrhs, b, y, iters_out, st);
+}
+
+// P2 from the level-2 test vectors, then D3 and its odd-site inverses
+static dd_status l3_build(dd_mg* mg, hipStream_t st) {
+  Level3* L = mg->l3;
+  const GeomDev& G = mg->g->geo;
+  const int neg = -1;
+  int bad = -1;
+  DD_HIP(mg->ctx, hipMemcpyAsync(L->flag, &neg, sizeof(int), hipMemcpyHostToDevice, st));
+  launch_gs2(G.Vc, L->Vc3, mg->n, L->n2, L->slot_of, L->tv2, L->P2_64, L->flag, st);
+  DD_HIP(mg->ctx, hipMemcpyAsync(&bad, L->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  if (bad >= 0)
+    return dd_fail(mg->ctx, DD_EINVAL,
+                   "level-2 test vectors are rank deficient on level-3 site " + std::to_string(L->h_lex3[bad / 2]) +
+                       " chirality " + std::to_string(bad % 2));
+  const long long nvec = (long long)L->n2 * G.Vc * mg->nc;
+  launch_convert_pairs(DD_F32, L->P2_64, nullptr, L->P2_32, nvec, st);
+  return DD_OK;
+}
+
+static dd_status l3_galerkin(dd_mg* mg, hipStream_t st) {
+  Level3* L = mg->l3;
+  const GeomDev& G = mg->g->geo;
+  const int neg = -1, nc3 = L->nc3;
+  int bad = -1;
+  launch_galerkin3(G, L->Vc3, mg->n, L->n2, L->slot_of, L->l3_of, L->loc_of, mg->Dc64, L->P2_64, L->D3_64, st);
+  DD_HIP(mg->ctx, hipMemcpyAsync(L->flag, &neg, sizeof(int), hipMemcpyHostToDevice, st));
+  launch_coarse_invert(L->g3, nc3, L->D3_64, L->Dinv3_64, L->flag, st);
+  launch_coarse_tile(nc3, L->D3_64, 9LL * L->Vc3, L->D3_32, DD_F64, nullptr, st);
+  launch_coarse_tile(nc3, L->Dinv3_64, L->Vc3 / 2, L->Dinv3_32, DD_F64, nullptr, st);
+  DD_HIP(mg->ctx, hipMemcpyAsync(&bad, L->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(mg->ctx, hipStreamSynchronize(st));
+  DD_HIP(mg->ctx, hipGetLastError());
+  if (bad >= 0)
+    return dd_fail(mg->ctx, DD_EINVAL, "singular level-3 self block on level-3 site " + std::to_string(L->h_lex3[bad]));
   return DD_OK;
 }
 
@@ -485,7 +762,7 @@ static dd_status vcycle(dd_mg* mg, int nrhs, const void* v, void* out, int* cite
   dd_dtype vt = inner_vt(mg);
   const GeomDev& g = mg->g->geo;
   launch_restrict(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, v, w->cb, st);
-  dd_status s = coarse_solve(mg, w, mg->graphs == 1, vt, nrhs, w->cb, w->cy, citers, st);
+  dd_status s = coarse_correction(mg, w, mg->graphs == 1, vt, nrhs, w->cb, w->cy, citers, st);
   if (s) return s;
   launch_prolong(g, vt, P_inner_dt(mg), mg->n, P_inner(mg), nrhs, w->cy, out, st);
   dd_dtype od = op_dtype(mg);
@@ -609,9 +886,12 @@ static dd_status vcycle_graph(dd_mg* mg, int nrhs, const void* v, void* out, hip
   return DD_OK;
 }
 
+// M as one graph (mode 2; with a third level, whose GMRES checks convergence on the host, mode 2 runs as mode 1)
+static bool whole_graph(const dd_mg* mg) { return mg->graphs == 2 && !mg->l3; }
+
 // M v in the mode the setup is in
 static dd_status apply_M(dd_mg* mg, int nrhs, const void* v, void* out, int* citers, hipStream_t st) {
-  if (mg->graphs == 2) {
+  if (whole_graph(mg)) {
     if (citers) *citers = 0;   // counted on the device (Workspace::citers)
     return vcycle_graph(mg, nrhs, v, out, st);
   }
@@ -715,6 +995,7 @@ static size_t mg_bytes_Dc(const dd_mg* mg, size_t pb) { return pb * mg->g->geo.V
 static size_t mg_bytes_Dinv(const dd_mg* mg, size_t pb) { return pb * mg->g->geo.Vch * 1ULL * mg->nc * mg->nc; }
 
 static void mg_free(dd_mg* mg) {
+  l3_free(mg);
   free_ws(mg);
   dd_free(mg->ctx, mg->P64, mg_bytes_P64(mg));
   dd_free(mg->ctx, mg->tv, mg_bytes_tv(mg));
@@ -904,7 +1185,8 @@ dd_status dd_setup_update_mass(dd_mg* mg, double m0) {
   DD_HIP(mg->ctx, hipSetDevice(mg->ctx->device));
   dd_status s = gauge_set_mass(mg->g, m0);
   if (s) return s;
-  return build(mg, 0);
+  if ((s = build(mg, 0))) return s;
+  return mg->l3 ? l3_galerkin(mg, 0) : DD_OK;   // D3 from the new D_c and the kept P2
 }
 
 dd_status dd_gauge_set_tuning(dd_gauge* g, const dd_tuning* t) {
@@ -945,6 +1227,7 @@ dd_status dd_gauge_get_tuning(const dd_gauge* g, dd_tuning* t) {
 dd_status dd_autotune(dd_mg* mg, int nrhs, const char* cache_path, char* report, size_t report_cap) {
   if (!mg || nrhs < 1) return DD_EINVAL;
   if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
+  if (mg->l3) return dd_fail(mg->ctx, DD_ESTATE, "tune before adding a third level");
   dd_gauge* g = mg->g;
   const GeomDev& G = g->geo;
   std::string key;
@@ -1131,6 +1414,7 @@ dd_status dd_mg_release_workspace(dd_mg* mg) {
   if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
   DD_HIP(mg->ctx, hipDeviceSynchronize());
   free_ws(mg);
+  l3_free_ws(mg);
   return DD_OK;
 }
 
@@ -1208,7 +1492,7 @@ dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void
   if (dt == DD_F64 && inner_vt(mg) != DD_F64)
     return dd_fail(mg->ctx, DD_EINVAL, "an FP32 setup's workspace holds no FP64 coarse basis: use DD_F32");
   if ((s = ensure_ws(mg, nrhs, false))) return s;
-  return coarse_solve(mg, mg->ws, mg->graphs == 1, dt, nrhs, in, out, iters, (hipStream_t)stream);
+  return coarse_correction(mg, mg->ws, mg->graphs == 1, dt, nrhs, in, out, iters, (hipStream_t)stream);
 }
 
 dd_status dd_coarse_solve_noalloc(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out, int* iters,
@@ -1217,6 +1501,7 @@ dd_status dd_coarse_solve_noalloc(dd_mg* mg, dd_dtype dt, int nrhs, const void* 
   if (s) return s;
   if (dt == DD_F64 && inner_vt(mg) != DD_F64)
     return dd_fail(mg->ctx, DD_EINVAL, "an FP32 setup's coarse solve runs in DD_F32");
+  if (mg->l3) return dd_fail(mg->ctx, DD_ESTATE, "the allocation-free coarse solve is the two-level one: remove the third level");
   if (nrhs > kHostRhs)
     return dd_fail(mg->ctx, DD_EINVAL, "the allocation-free coarse solve takes at most " + std::to_string(kHostRhs) +
                                            " right-hand sides");
@@ -1306,6 +1591,215 @@ dd_status dd_export_vectors(const dd_mg* mg, double* tv_host) {
 // ---------------------------------------------------------------------------
 // outer flexible GMRES (FP64), right preconditioned by M
 // ---------------------------------------------------------------------------
+void dd_level3_params_default(dd_level3_params* p) {
+  if (!p) return;
+  p->n_vec2 = 8;
+  p->setup_iters = 2;
+  p->mr_steps = 4;
+  p->kcycle_max_iters = 20;
+  p->kcycle_fixed = 0;
+  p->l3_restart = 60;
+  p->l3_max_iters = 300;
+  p->l3_fixed_iters = 0;
+  p->kcycle_tol = 5e-2;
+  p->l3_tol = 5e-2;
+  p->seed = 0x13d3ULL;
+}
+
+dd_status dd_mg_add_level(dd_mg* mg, const dd_level3_params* p, const double* tv2_host) {
+  if (!mg || !p) return DD_EINVAL;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
+  if (mg->l3) return dd_fail(mg->ctx, DD_ESTATE, "a third level is already attached");
+  const int n2 = p->n_vec2;
+  if (n2 != 6 && n2 != 8 && n2 != 12 && n2 != 16 && n2 != 20 && n2 != 24)
+    return dd_fail(mg->ctx, DD_ESHAPE, "n_vec2 must be one of 6, 8, 12, 16, 20, 24");
+  if (p->setup_iters < 0 || p->mr_steps < 0 || p->l3_fixed_iters < 0 || p->kcycle_max_iters < 1 ||
+      p->kcycle_max_iters > 64 || p->l3_restart < 1 || p->l3_restart > 256 || p->l3_max_iters < 1 ||
+      (p->kcycle_fixed != 0 && p->kcycle_fixed != 1) || !(p->kcycle_tol >= 0.0) || !(p->l3_tol >= 0.0))
+    return dd_fail(mg->ctx, DD_EINVAL, "level-3 parameters out of range");
+  const GeomDev& G = mg->g->geo;
+  int NB[4];
+  for (int m = 0; m < 4; ++m) {
+    NB[m] = G.L[m] / G.b[m];
+    if (NB[m] % 4) return dd_fail(mg->ctx, DD_ESHAPE, "every coarse-lattice extent must be a multiple of 4");
+  }
+  DD_HIP(mg->ctx, hipSetDevice(mg->ctx->device));
+  Level3* L = new Level3();
+  L->p = *p;
+  L->n2 = n2;
+  L->nc3 = 2 * n2;
+  for (int m = 0; m < 4; ++m) L->NB3[m] = NB[m] / 2;
+  const int* N3 = L->NB3;
+  L->Vc3 = N3[0] * N3[1] * N3[2] * N3[3];
+  const int Vc3 = L->Vc3, Vch3 = Vc3 / 2;
+  auto lex3 = [&](const int* c) { return c[0] + N3[0] * (c[1] + N3[1] * (c[2] + N3[2] * c[3])); };
+  // level-3 slots as the block slots: even sites (coordinate sum even) first
+  std::vector<int> slot3_of_lex(Vc3), coord3(4 * (size_t)Vc3);
+  L->h_lex3.assign(Vc3, 0);
+  for (int s3 = 0; s3 < Vc3; ++s3) {
+    const int c = s3 / Vch3, k = s3 % Vch3, rest = (2 * k) / N3[0];
+    int* x = &coord3[4 * (size_t)s3];
+    x[1] = rest % N3[1];
+    x[2] = (rest / N3[1]) % N3[2];
+    x[3] = rest / (N3[1] * N3[2]);
+    x[0] = (2 * k) % N3[0] + ((c + x[1] + x[2] + x[3]) & 1);
+    L->h_lex3[s3] = lex3(x);
+    slot3_of_lex[L->h_lex3[s3]] = s3;
+  }
+  std::vector<int> nbr3(8 * (size_t)Vc3);
+  for (int s3 = 0; s3 < Vc3; ++s3)
+    for (int mu = 0; mu < 4; ++mu)
+      for (int sg = 0; sg < 2; ++sg) {
+        int d[4] = {coord3[4 * s3], coord3[4 * s3 + 1], coord3[4 * s3 + 2], coord3[4 * s3 + 3]};
+        d[mu] = (d[mu] + (sg == 0 ? 1 : -1) + N3[mu]) % N3[mu];
+        nbr3[(sg * 4 + mu) * (size_t)Vc3 + s3] = slot3_of_lex[lex3(d)];
+      }
+  std::vector<int> slot_of(G.Vc), l3_of(G.Vc), loc_of(G.Vc);
+  for (int x = 0; x < G.Vc; ++x) {
+    const int bc = mg->g->h_blk_coord[x];
+    const int c[4] = {bc & 255, (bc >> 8) & 255, (bc >> 16) & 255, (bc >> 24) & 255};
+    const int h[4] = {c[0] / 2, c[1] / 2, c[2] / 2, c[3] / 2};
+    const int l = (c[0] & 1) + 2 * ((c[1] & 1) + 2 * ((c[2] & 1) + 2 * (c[3] & 1)));
+    const int X3 = slot3_of_lex[lex3(h)];
+    slot_of[X3 * 16 + l] = x;
+    l3_of[x] = X3;
+    loc_of[x] = l;
+  }
+  Arena a;
+  a.sizing = true;
+  l3_carve(L, a, G.Vc, mg->n);
+  L->bytes = a.used + 256;
+  dd_status s = dd_alloc(mg->ctx, (void**)&L->base, L->bytes);
+  if (s) {
+    delete L;
+    return s;
+  }
+  a.base = L->base;
+  a.cap = L->bytes;
+  a.sizing = false;
+  a.used = 0;
+  l3_carve(L, a, G.Vc, mg->n);
+  mg->l3 = L;
+  auto fail = [&](dd_status e) {
+    (void)hipDeviceSynchronize();
+    l3_free(mg);
+    return e;
+  };
+  if (hipMemcpy(L->nbr3, nbr3.data(), sizeof(int) * nbr3.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(L->slot_of, slot_of.data(), sizeof(int) * G.Vc, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(L->l3_of, l3_of.data(), sizeof(int) * G.Vc, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(L->loc_of, loc_of.data(), sizeof(int) * G.Vc, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(dd_fail(mg->ctx, DD_EDEVICE, "level-3 table upload"));
+  L->g3.Vc = Vc3;
+  L->g3.Vch = Vch3;
+  L->g3.blk_nbr = L->nbr3;
+  // level-2 test vectors
+  const hipStream_t st = 0;
+  const long long ldc = (long long)G.Vc * mg->nc, nvec = ldc * n2;
+  if (tv2_host) {
+    double2* stage = nullptr;
+    if ((s = dd_alloc(mg->ctx, (void**)&stage, sizeof(double2) * nvec))) return fail(s);
+    hipError_t e = hipMemcpy(stage, tv2_host, sizeof(double2) * nvec, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      launch_coarse_perm(G, DD_F64, mg->nc, n2, 1, stage, L->tv2, st);
+      e = hipStreamSynchronize(st);
+    }
+    dd_free(mg->ctx, stage, sizeof(double2) * nvec);
+    if (e != hipSuccess) return fail(dd_hip_check(mg->ctx, e, "level-2 test vector upload"));
+  } else {
+    launch_gauss(p->seed, nvec, L->tv2, st);
+    if (p->setup_iters > 0) {
+      // inverse iteration with the two-level coarse solve, in the setup's inner dtype
+      const dd_dtype vt = inner_vt(mg);
+      const size_t vb = vector_pair_bytes(vt);
+      if ((s = ensure_ws(mg, n2, false))) return fail(s);
+      char* buf = nullptr;
+      if ((s = dd_alloc(mg->ctx, (void**)&buf, 2 * nvec * vb))) return fail(s);
+      char *u = buf, *y = buf + nvec * vb;
+      Workspace* w = mg->ws;
+      launch_vec_convert(DD_F64, vt, L->tv2, u, nvec, st);
+      for (int k = 0; k < p->setup_iters && !s; ++k) {
+        s = coarse_solve(mg, w, false, vt, n2, u, y, nullptr, st);
+        norms2(w, vt, n2, ldc, ldc, y, w->ca.nrm2, st);
+        launch_normalize(vt, n2, ldc, ldc, y, w->ca.nrm2, nullptr, nullptr, u, st, vt);
+      }
+      launch_vec_convert(vt, DD_F64, u, L->tv2, nvec, st);
+      const hipError_t e = hipStreamSynchronize(st);
+      dd_free(mg->ctx, buf, 2 * nvec * vb);
+      if (s) return fail(s);
+      if (e != hipSuccess) return fail(dd_hip_check(mg->ctx, e, "level-2 test vectors"));
+    }
+  }
+  if ((s = l3_build(mg, st)) || (s = l3_galerkin(mg, st))) return fail(s);
+  return DD_OK;
+}
+
+dd_status dd_mg_remove_level(dd_mg* mg) {
+  if (!mg) return DD_EINVAL;
+  if (mg->live) return dd_fail(mg->ctx, DD_ESTATE, "a stepwise solve holds this multigrid's workspace");
+  (void)hipDeviceSynchronize();
+  l3_free(mg);
+  return DD_OK;
+}
+
+dd_status dd_level3_shape(const dd_mg* mg, int32_t* vc3, int32_t* nc3) {
+  if (!mg || !vc3 || !nc3) return DD_EINVAL;
+  *vc3 = mg->l3 ? mg->l3->Vc3 : 0;
+  *nc3 = mg->l3 ? mg->l3->nc3 : 0;
+  return DD_OK;
+}
+
+dd_status dd_level3_last(const dd_mg* mg, int32_t* kcycle_steps, int32_t* l3_steps) {
+  if (!mg || !kcycle_steps || !l3_steps) return DD_EINVAL;
+  if (!mg->l3) return dd_fail(mg->ctx, DD_ESTATE, "no third level");
+  *kcycle_steps = mg->l3->last_steps;
+  *l3_steps = mg->l3->last_l3;
+  return DD_OK;
+}
+
+dd_status dd_export_level3(const dd_mg* mg, double* tv2_host, double* p2_host, double* d3_host) {
+  if (!mg) return DD_EINVAL;
+  const Level3* L = mg->l3;
+  if (!L) return dd_fail(mg->ctx, DD_ESTATE, "no third level");
+  const GeomDev& G = mg->g->geo;
+  const long long nvec = (long long)L->n2 * G.Vc * mg->nc, K = 16LL * mg->n, set = (long long)L->n2 * K;
+  const int nc3 = L->nc3;
+  if (tv2_host) {
+    double2* stage = nullptr;
+    dd_status s = dd_alloc(mg->ctx, (void**)&stage, sizeof(double2) * nvec);
+    if (s) return s;
+    launch_coarse_perm(G, DD_F64, mg->nc, L->n2, 0, L->tv2, stage, 0);
+    const hipError_t e = hipMemcpy(tv2_host, stage, sizeof(double2) * nvec, hipMemcpyDeviceToHost);
+    dd_free(mg->ctx, stage, sizeof(double2) * nvec);
+    if (e != hipSuccess) return dd_hip_check(mg->ctx, e, "export level-2 vectors");
+  }
+  if (p2_host) {
+    std::vector<double2> buf(nvec);
+    DD_HIP(mg->ctx, hipMemcpy(buf.data(), L->P2_64, sizeof(double2) * nvec, hipMemcpyDeviceToHost));
+    for (int X = 0; X < L->Vc3; ++X)
+      for (long long e = 0; e < 2 * set; ++e) {
+        const double2 v = buf[(size_t)X * 2 * set + e];
+        double* o = p2_host + 2 * ((size_t)L->h_lex3[X] * 2 * set + e);
+        o[0] = v.x;
+        o[1] = v.y;
+      }
+  }
+  if (d3_host) {
+    std::vector<double2> buf((size_t)L->Vc3 * 9 * nc3 * nc3);
+    DD_HIP(mg->ctx, hipMemcpy(buf.data(), L->D3_64, sizeof(double2) * buf.size(), hipMemcpyDeviceToHost));
+    for (int X = 0; X < L->Vc3; ++X)
+      for (int d = 0; d < 9; ++d)
+        for (int col = 0; col < nc3; ++col)
+          for (int row = 0; row < nc3; ++row) {
+            const double2 v = buf[(((size_t)X * 9 + d) * nc3 + col) * nc3 + row];
+            double* o = d3_host + 2 * ((((size_t)L->h_lex3[X] * 9 + d) * nc3 + row) * nc3 + col);
+            o[0] = v.x;
+            o[1] = v.y;
+          }
+  }
+  return DD_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1484,7 +1978,7 @@ dd_status dd_solve_begin(dd_mg* mg, int capacity, double tol, void* stream, dd_s
   S->relres.assign(capacity, 1.0);
   S->t0 = std::chrono::steady_clock::now();
   ktimer_model(&S->mb0, &S->mf0);
-  if (mg->graphs == 2) launch_zero(mg->ws->citers, sizeof(int), S->st);   // coarse steps counted on the device
+  if (whole_graph(mg)) launch_zero(mg->ws->citers, sizeof(int), S->st);   // coarse steps counted on the device
   mg->live = S;
   *out = S;
   return DD_OK;
@@ -1512,7 +2006,7 @@ dd_status dd_solve_take(dd_solve_state* S, int slot, double* x_canon_dev, dd_sol
   dd_mg* mg = S->mg;
   const long long cnt = 12LL * mg->g->geo.V;
   launch_unpack_fine(mg->g->geo, DD_F64, 1, mg->ws->x64 + (size_t)slot * cnt, (double2*)x_canon_dev, S->st);
-  if (mg->graphs == 2)
+  if (whole_graph(mg))
     DD_HIP(mg->ctx, hipMemcpyAsync(&S->total_coarse, mg->ws->citers, sizeof(int), hipMemcpyDeviceToHost, S->st));
   DD_HIP(mg->ctx, hipStreamSynchronize(S->st));
   solve_info(S, slot, info);

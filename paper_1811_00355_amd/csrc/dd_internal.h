@@ -361,6 +361,7 @@ struct dd_gauge {
 };
 
 struct Workspace;
+struct Level3;
 
 struct dd_mg {
   dd_ctx* ctx;
@@ -384,6 +385,7 @@ struct dd_mg {
   Workspace* ws = nullptr;
   int graphs = 0;   // 0: launches; 1: coarse GMRES chunks replayed from graphs; 2: all of M from one graph
   dd_solve_state* live = nullptr;   // the stepwise solve that holds the workspace, if any
+  Level3* l3 = nullptr;             // third level: coarse solves by a two-level cycle on D_c, when added
 };
 
 // ---------------------------------------------------------------------------
@@ -507,6 +509,17 @@ void launch_arnoldi(int nrhs, int m, int j, const double2* h1, const double2* h2
                     int* kcyc, double* est, double* hnext, hipStream_t st);
 void launch_lsq(int nrhs, int m, const double2* H, const double2* gv, const int* kcyc, double2* y,
                 hipStream_t st);
+
+// third level (blocks of 2^4 coarse sites, chirality-split aggregates)
+void launch_gs2(int Vc, int Vc3, int n, int n2, const int* slot_of, const double2* tv, double2* P2, int* bad,
+                hipStream_t st);
+void launch_restrict2(dd_dtype vt, int Vc, int Vc3, int n, int n2, const int* slot_of, const void* P2, int nrhs,
+                      const void* v, void* out, hipStream_t st);
+void launch_prolong2(dd_dtype vt, int Vc, int Vc3, int n, int n2, const int* l3_of, const int* loc_of,
+                     const void* P2, int nrhs, const void* y, void* out, hipStream_t st);
+void launch_galerkin3(const GeomDev& g2, int Vc3, int n, int n2, const int* slot_of, const int* l3_of,
+                      const int* loc_of, const double2* Dc64, const double2* P2, double2* D3, hipStream_t st);
+void launch_mr_alpha(int nrhs, const double2* num, const double2* den, double2* alpha, hipStream_t st);
 
 dd_status ensure_opset(dd_gauge* g, dd_dtype dt);
 dd_status gauge_set_mass(dd_gauge* g, double m0);
