@@ -366,6 +366,21 @@ def measure(B, g, cfg, args, store_name, b):
         tuning = dict(chosen=g.dd_gauge_get_tuning(), seconds=round(time.perf_counter() - t0, 2),
                       candidates=[l for l in rep.splitlines() if " ms" in l])
         log(f"[bench] autotune ({tuning['seconds']} s): " + "; ".join(rep.splitlines()[1:]))
+    level3 = None
+    if args.levels == 3:
+        # third level after the tuning (the autotuner refuses a setup with one); its setup time counts
+        p3 = B.level3_params(n_vec2=args.l3_nvec2, setup_iters=args.l3_setup_iters, mr_steps=args.l3_mr,
+                             kcycle_max_iters=args.l3_kmax)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mg.add_level(p3)
+        torch.cuda.synchronize()
+        t_l3 = time.perf_counter() - t0
+        t_setup += t_l3
+        vc3, nc3 = mg.level3_shape()
+        level3 = dict(setup_s=round(t_l3, 3), sites=vc3, components=nc3, n_vec2=args.l3_nvec2,
+                      setup_iters=args.l3_setup_iters, mr_steps=args.l3_mr, kcycle_max_iters=args.l3_kmax)
+        log(f"[bench] third level: {level3}")
 
     def step():
         info = []
@@ -377,7 +392,12 @@ def measure(B, g, cfg, args, store_name, b):
             if st or bad:
                 raise RuntimeError(f"solve did not converge (status {st}, rhs {bad}): {ik}")
             info += ik
+            if level3 is not None:
+                k2, k3 = mg.level3_last()
+                level3_steps.append((k2, k3))
         return info
+
+    level3_steps = []
 
     for w in range(args.warmup):
         info = step()
@@ -430,8 +450,10 @@ def measure(B, g, cfg, args, store_name, b):
                       info_flops_model=int(binfo[0]["flops_model"]), info_bytes_model=int(binfo[0]["bytes_model"]))
     log(f"[bench] store {store_name}: {value:.2f} solves/s; dominant kernel {dom}: {roofline}; kernels {kernels}")
     log(f"[bench] step model {step_model}")
+    if level3 is not None:
+        level3["last_cycle_steps"] = level3_steps[-1] if level3_steps else None
     whole_m = None
-    if args.graphs != 2 and not args.no_whole_m_graph:
+    if args.graphs != 2 and not args.no_whole_m_graph and level3 is None:
         # the same solves with all of M replayed from one graph per call (graph mode 2: no host
         # synchronisation inside M, the coarse GMRES stopped on the device): bits and iterations equal
         mg.dd_mg_set_graphs(2)
@@ -451,7 +473,7 @@ def measure(B, g, cfg, args, store_name, b):
         # the same setup with half-precision coarse blocks on half matrix cores and an FP16 coarse basis
         t = g.dd_gauge_get_tuning()
         g.dd_gauge_set_tuning(**dict(t, coarse_half=1, coarse_basis_half=1, coarse_mfma_half=1))
-        if args.autotune:
+        if args.autotune and level3 is None:
             mg.dd_autotune(kb, args.tune_cache)
         step()
         torch.cuda.synchronize()
@@ -469,7 +491,7 @@ def measure(B, g, cfg, args, store_name, b):
     return dict(value=round(value, 3), ms_per_step=round(1e3 * elapsed / args.steps, 2), elapsed=elapsed,
                 setup_s=round(t_setup, 3), outer=round(outer, 2), coarse_per_vcycle=coarse_per_vcycle,
                 tuning=tuning, roofline=roofline, kernels=kernels, half_coarse=half_coarse, step_model=step_model,
-                whole_m=whole_m)
+                whole_m=whole_m, level3=level3)
 
 
 def main():
@@ -515,6 +537,12 @@ def main():
                     help="also time the paper's comparison solver (SAP-preconditioned BiCGstab) on the same sources")
     ap.add_argument("--sigma-iters", type=int, default=8,
                     help="inverse-iteration steps of the sigma_min leg (0: skip it)")
+    ap.add_argument("--levels", type=int, default=2, choices=[2, 3],
+                    help="3: add the third multigrid level (level-2 FGMRES cycle as the coarse solve)")
+    ap.add_argument("--l3-nvec2", type=int, default=8, help="third level: level-2 test vectors")
+    ap.add_argument("--l3-setup-iters", type=int, default=2, help="third level: inverse iterations of its vectors")
+    ap.add_argument("--l3-mr", type=int, default=4, help="third level: MR smoothing steps on D_c")
+    ap.add_argument("--l3-kmax", type=int, default=20, help="third level: level-2 FGMRES steps at most")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -590,7 +618,7 @@ def main():
                                             else " (f32 coarse blocks and products on matrix cores)"),
         "data": "synthetic (seeded SU(3) links, point sources)",
         "config": {"workload": f"{args.config}: {L[0]}^3x{L[3]} Wilson-clover, 12 point-source RHS "
-                               f"(solve calls of {args.rhs_batch}), 2-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
+                               f"(solve calls of {args.rhs_batch}), {args.levels}-level DD-alpha-AMG n={n_vec}, 4^4 blocks",
                    "lattice": list(L), "rhs": nrhs, "rhs_batch": args.rhs_batch, "m0": cfg["m0"],
                    "c_sw": cfg["c_sw"], "eps": cfg["eps"], "store_dtype": stores[0], "graphs": args.graphs,
                    "coarse_restart": args.coarse_restart, "coarse_cgs_passes": args.coarse_cgs_passes,
@@ -605,6 +633,7 @@ def main():
                    "tuning": r0["tuning"],
                    "half_coarse_arithmetic": r0["half_coarse"],
                    "whole_m_graph": r0["whole_m"],
+                   "level3": r0["level3"],
                    "step_model": r0["step_model"],
                    "other_stores": {st_: {k: r[k] for k in ("value", "ms_per_step", "setup_s", "outer")}
                                     for st_, r in zip(stores[1:], runs[1:])},

@@ -1710,13 +1710,18 @@ dd_status dd_mg_add_level(dd_mg* mg, const dd_level3_params* p, const double* tv
     launch_gauss(p->seed, nvec, L->tv2, st);
     if (p->setup_iters > 0) {
       // inverse iteration with the two-level coarse solve, in the setup's inner dtype
+      // (on a coarse-only workspace of its own: the setup's workspace may hold an outer solver's vectors)
       const dd_dtype vt = inner_vt(mg);
       const size_t vb = vector_pair_bytes(vt);
-      if ((s = ensure_ws(mg, n2, false))) return fail(s);
+      Workspace* w = nullptr;
+      const WsShape sh = ws_shape(mg);
+      if ((s = alloc_ws(mg->ctx, n2, [&](Workspace& x) { carve_ws(x, sh, n2, false, false); }, &w))) return fail(s);
       char* buf = nullptr;
-      if ((s = dd_alloc(mg->ctx, (void**)&buf, 2 * nvec * vb))) return fail(s);
+      if ((s = dd_alloc(mg->ctx, (void**)&buf, 2 * nvec * vb))) {
+        destroy_ws(mg->ctx, w);
+        return fail(s);
+      }
       char *u = buf, *y = buf + nvec * vb;
-      Workspace* w = mg->ws;
       launch_vec_convert(DD_F64, vt, L->tv2, u, nvec, st);
       for (int k = 0; k < p->setup_iters && !s; ++k) {
         s = coarse_solve(mg, w, false, vt, n2, u, y, nullptr, st);
@@ -1726,6 +1731,7 @@ dd_status dd_mg_add_level(dd_mg* mg, const dd_level3_params* p, const double* tv
       launch_vec_convert(vt, DD_F64, u, L->tv2, nvec, st);
       const hipError_t e = hipStreamSynchronize(st);
       dd_free(mg->ctx, buf, 2 * nvec * vb);
+      destroy_ws(mg->ctx, w);
       if (s) return fail(s);
       if (e != hipSuccess) return fail(dd_hip_check(mg->ctx, e, "level-2 test vectors"));
     }
