@@ -333,6 +333,55 @@ def _roofline(kernel, ks, elapsed_ms_per_launch_set, args, store_name, layout):
     return r
 
 
+def _level3_params(B, args):
+    return B.level3_params(n_vec2=args.l3_nvec2, setup_iters=args.l3_setup_iters, mr_steps=args.l3_mr,
+                           kcycle_max_iters=args.l3_kmax, l3_tol=args.l3_tol)
+
+
+def level3_leg(B, mg, args, step, value2):
+    """The same solves with the third level added to the same setup (the coarse
+    correction then a level-2 FGMRES cycle preconditioned by the level-3 solve
+    and MR smoothing): its setup time, one untimed step with every kernel
+    timed, then args.steps timed steps; the level is removed afterwards."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mg.add_level(_level3_params(B, args))
+    torch.cuda.synchronize()
+    t_l3 = time.perf_counter() - t0
+    vc3, nc3 = mg.level3_shape()
+    step()
+    mg.dd_mg_set_graphs(0)
+    B.kernel_timer_enable("*")
+    binfo = step()
+    torch.cuda.synchronize()
+    kf = {k: B.kernel_timer_read(k) for k in B.kernel_timer_names()}
+    B.kernel_timer_enable(None)
+    mg.dd_mg_set_graphs(args.graphs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    mg.remove_level()
+    nrhs = len(infos[0])
+    value = nrhs * args.steps / el
+    outer = [i["outer_iters"] for inf in infos for i in inf]
+    tot = sum(v["ms"] for v in kf.values())
+    out = dict(value=round(value, 3), ms_per_step=round(1e3 * el / args.steps, 2),
+               speedup_vs_two_levels=round(value / value2, 3), setup_s=round(t_l3, 3),
+               level3_sites=vc3, level3_components=nc3, n_vec2=args.l3_nvec2, setup_iters=args.l3_setup_iters,
+               mr_steps=args.l3_mr, kcycle_max_iters=args.l3_kmax, l3_tol=args.l3_tol,
+               outer_iters_mean=round(float(np.mean(outer)), 2),
+               level2_steps_total=[i["coarse_iters_total"] for i in binfo[::max(1, min(args.rhs_batch, nrhs))]],
+               max_true_relres=float(max(i["true_relres"] for inf in infos for i in inf)),
+               kernels={k: dict(ms_per_step=round(v["ms"], 3), share=round(v["ms"] / max(tot, 1e-9), 3),
+                                launches_per_step=v["launches"])
+                        for k, v in sorted(kf.items(), key=lambda kv: -kv[1]["ms"])[:10]})
+    log(f"[bench] three levels: {out}")
+    return out
+
+
 def measure(B, g, cfg, args, store_name, b):
     """Setup with operands stored as `store_name`, autotune, warm up, one
     untimed step with every kernel timed (the breakdown, which names the
@@ -369,8 +418,7 @@ def measure(B, g, cfg, args, store_name, b):
     level3 = None
     if args.levels == 3:
         # third level after the tuning (the autotuner refuses a setup with one); its setup time counts
-        p3 = B.level3_params(n_vec2=args.l3_nvec2, setup_iters=args.l3_setup_iters, mr_steps=args.l3_mr,
-                             kcycle_max_iters=args.l3_kmax)
+        p3 = _level3_params(B, args)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         mg.add_level(p3)
@@ -487,11 +535,14 @@ def measure(B, g, cfg, args, store_name, b):
                            outer_iters_mean=round(float(np.mean([i["outer_iters"] for inf in infh for i in inf])), 2),
                            max_true_relres=float(max(i["true_relres"] for inf in infh for i in inf)))
         log(f"[bench] store {store_name}, half-precision coarse arithmetic: {half_coarse}")
+    three = None
+    if level3 is None and not args.no_level3_leg:
+        three = level3_leg(B, mg, args, step, value)
     mg.destroy()
     return dict(value=round(value, 3), ms_per_step=round(1e3 * elapsed / args.steps, 2), elapsed=elapsed,
                 setup_s=round(t_setup, 3), outer=round(outer, 2), coarse_per_vcycle=coarse_per_vcycle,
                 tuning=tuning, roofline=roofline, kernels=kernels, half_coarse=half_coarse, step_model=step_model,
-                whole_m=whole_m, level3=level3)
+                whole_m=whole_m, level3=level3, three_level=three)
 
 
 def main():
@@ -539,10 +590,13 @@ def main():
                     help="inverse-iteration steps of the sigma_min leg (0: skip it)")
     ap.add_argument("--levels", type=int, default=2, choices=[2, 3],
                     help="3: add the third multigrid level (level-2 FGMRES cycle as the coarse solve)")
-    ap.add_argument("--l3-nvec2", type=int, default=8, help="third level: level-2 test vectors")
-    ap.add_argument("--l3-setup-iters", type=int, default=2, help="third level: inverse iterations of its vectors")
-    ap.add_argument("--l3-mr", type=int, default=4, help="third level: MR smoothing steps on D_c")
-    ap.add_argument("--l3-kmax", type=int, default=20, help="third level: level-2 FGMRES steps at most")
+    ap.add_argument("--l3-nvec2", type=int, default=24, help="third level: level-2 test vectors")
+    ap.add_argument("--l3-setup-iters", type=int, default=6, help="third level: inverse iterations of its vectors")
+    ap.add_argument("--l3-mr", type=int, default=6, help="third level: MR smoothing steps on D_c")
+    ap.add_argument("--l3-kmax", type=int, default=40, help="third level: level-2 FGMRES steps at most")
+    ap.add_argument("--l3-tol", type=float, default=0.1, help="third level: level-3 GMRES relative residual")
+    ap.add_argument("--no-level3-leg", action="store_true",
+                    help="skip the side run with the third level added to the same setup")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -634,6 +688,7 @@ def main():
                    "half_coarse_arithmetic": r0["half_coarse"],
                    "whole_m_graph": r0["whole_m"],
                    "level3": r0["level3"],
+                   "three_level": r0["three_level"],
                    "step_model": r0["step_model"],
                    "other_stores": {st_: {k: r[k] for k in ("value", "ms_per_step", "setup_s", "outer")}
                                     for st_, r in zip(stores[1:], runs[1:])},
