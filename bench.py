@@ -338,7 +338,7 @@ def _level3_params(B, args):
                            kcycle_max_iters=args.l3_kmax, l3_tol=args.l3_tol)
 
 
-def level3_leg(B, mg, args, step, value2):
+def level3_leg(B, mg, args, step, value2, half_store):
     """The same solves with the third level added to the same setup (the coarse
     correction then a level-2 FGMRES cycle preconditioned by the level-3 solve
     and MR smoothing): its setup time, one untimed step with every kernel
@@ -363,6 +363,21 @@ def level3_leg(B, mg, args, step, value2):
     infos = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    half = None
+    if half_store and not args.no_half_coarse:
+        # the same with half-precision coarse blocks (D_c and D3) on half matrix cores, FP16 bases
+        t = mg.g.dd_gauge_get_tuning()
+        mg.g.dd_gauge_set_tuning(**dict(t, coarse_half=1, coarse_basis_half=1, coarse_mfma_half=1))
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infh = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        elh = time.perf_counter() - t0
+        mg.g.dd_gauge_set_tuning(**t)
+        half = dict(value=round(len(infh[0]) * args.steps / elh, 3), ms_per_step=round(1e3 * elh / args.steps, 2),
+                    outer_iters_mean=round(float(np.mean([i["outer_iters"] for inf in infh for i in inf])), 2),
+                    max_true_relres=float(max(i["true_relres"] for inf in infh for i in inf)))
     mg.remove_level()
     nrhs = len(infos[0])
     value = nrhs * args.steps / el
@@ -375,6 +390,7 @@ def level3_leg(B, mg, args, step, value2):
                outer_iters_mean=round(float(np.mean(outer)), 2),
                level2_steps_total=[i["coarse_iters_total"] for i in binfo[::max(1, min(args.rhs_batch, nrhs))]],
                max_true_relres=float(max(i["true_relres"] for inf in infos for i in inf)),
+               half_coarse_arithmetic=half,
                kernels={k: dict(ms_per_step=round(v["ms"], 3), share=round(v["ms"] / max(tot, 1e-9), 3),
                                 launches_per_step=v["launches"])
                         for k, v in sorted(kf.items(), key=lambda kv: -kv[1]["ms"])[:10]})
@@ -537,7 +553,7 @@ def measure(B, g, cfg, args, store_name, b):
         log(f"[bench] store {store_name}, half-precision coarse arithmetic: {half_coarse}")
     three = None
     if level3 is None and not args.no_level3_leg:
-        three = level3_leg(B, mg, args, step, value)
+        three = level3_leg(B, mg, args, step, value, half_store)
     mg.destroy()
     return dict(value=round(value, 3), ms_per_step=round(1e3 * elapsed / args.steps, 2), elapsed=elapsed,
                 setup_s=round(t_setup, 3), outer=round(outer, 2), coarse_per_vcycle=coarse_per_vcycle,
@@ -594,7 +610,7 @@ def main():
     ap.add_argument("--l3-setup-iters", type=int, default=6, help="third level: inverse iterations of its vectors")
     ap.add_argument("--l3-mr", type=int, default=6, help="third level: MR smoothing steps on D_c")
     ap.add_argument("--l3-kmax", type=int, default=40, help="third level: level-2 FGMRES steps at most")
-    ap.add_argument("--l3-tol", type=float, default=0.1, help="third level: level-3 GMRES relative residual")
+    ap.add_argument("--l3-tol", type=float, default=0.2, help="third level: level-3 GMRES relative residual")
     ap.add_argument("--no-level3-leg", action="store_true",
                     help="skip the side run with the third level added to the same setup")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

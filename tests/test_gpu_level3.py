@@ -193,16 +193,21 @@ def test_level3_after_mass_change_and_device_vectors(ctx):
     _close(d)
 
 
-@pytest.mark.parametrize("inner,store", [(0, 0), (1, 1), (1, 3)])
-def test_three_level_solve_true_residual(ctx, inner, store):
+@pytest.mark.parametrize("inner,store,half", [(0, 0, 0), (1, 1, 0), (1, 3, 0), (1, 2, 1), (1, 3, 1)])
+def test_three_level_solve_true_residual(ctx, inner, store, half):
     """Whole solves with three levels (device-generated level-2 vectors, the
-    default cycle) reach |b - D x| / |b| <= 1e-10 on the oracle's operator."""
+    default cycle) reach |b - D x| / |b| <= 1e-10 on the oracle's operator;
+    also with the half-precision coarse options (D_c and D3 blocks in the
+    storage type on half matrix cores, FP16 Krylov bases on both levels)."""
     import torch
     import _gpu
     from paper_1811_00355_amd import level3_params
     from workloads import gauss_spinor
     d = _build(ctx, "l8x16", inner_dtype=inner, store_dtype=store, init_sap_apps=2, setup_iters=2)
     lat, mg = d["lat"], d["mg"]
+    if half:
+        t = d["g"].dd_gauge_get_tuning()
+        d["g"].dd_gauge_set_tuning(**dict(t, coarse_half=1, coarse_basis_half=1, coarse_mfma_half=1))
     nrhs = 3
     b = gauss_spinor(lat.L, nrhs, 63)
     bd = _gpu.to_dev(b.reshape(nrhs, -1))
@@ -215,7 +220,7 @@ def test_three_level_solve_true_residual(ctx, inner, store):
     x = _gpu.to_host(xd).reshape(b.shape)
     for r in range(nrhs):
         res = np.linalg.norm(b[r] - d["W"].apply(x[r])) / np.linalg.norm(b[r])
-        print(f"inner={inner} store={store} rhs {r}: outer iterations {info[r]['outer_iters']} with three levels, "
+        print(f"inner={inner} store={store} half={half} rhs {r}: outer iterations {info[r]['outer_iters']} with three levels, "
               f"{info2[r]['outer_iters']} with two; relres(oracle D) {res:.2e}", flush=True)
         assert info[r]["converged"] and res <= 1e-10
     _close(d)
