@@ -225,12 +225,15 @@ __global__ void __launch_bounds__(256) k_axpy_dots(int nrhs, long long count, lo
 
 // Classical Gram-Schmidt against a whole basis (nv <= kGsMaxNv) in two passes:
 // k_gs_dots forms <V_i, w> for every i, k_gs_axpy_norm then w <- w - sum c_i V_i
-// and |w|^2.  A workgroup owns a fixed tile of kGsTile entries (so the
-// reduction tree depends on the vector length only); each thread keeps
-// kGsEpt entries of w in registers and streams kGsGroup basis vectors at a
-// time, and a wave folds the 2 kGsGroup sums of its lanes with a butterfly
-// that halves the set at every exchange.
-constexpr int kGsEpt = 8, kGsTile = 256 * kGsEpt, kGsGroup = 4, kGsMaxNv = 128;
+// and |w|^2.  A workgroup owns a fixed tile of 256 EPT entries (so the
+// reduction tree depends on the vector length only); each thread keeps EPT
+// entries of w in registers and streams kGsGroup basis vectors at a time, and
+// a wave folds the 2 kGsGroup sums of its lanes with a butterfly that halves
+// the set at every exchange.  Long vectors take EPT = 8; short ones (the
+// coarse lattices of small volumes, the level-3 lattice) EPT = 1, so that
+// they still spread over a few hundred workgroups.
+constexpr int kGsGroup = 4, kGsMaxNv = 128;
+constexpr long long kGsShort = 1LL << 17;   // entries per right-hand side up to which EPT = 1
 
 // a[0..7] of every lane -> value (lane >> 3) summed over the wave (10 exchanges)
 __device__ __forceinline__ double fold8(double* a, int lane) {
@@ -264,8 +267,8 @@ __device__ __forceinline__ double fold8(double* a, int lane) {
 
 // The loads of a group carry no conditions (indices are clamped into the
 // vectors and out-of-range terms are multiplied by zero), so a thread has all
-// kGsEpt * kGsGroup of them in flight at once.
-template <typename Tv, typename Tw>
+// EPT * kGsGroup of them in flight at once.
+template <typename Tv, typename Tw, int EPT>
 __global__ void __launch_bounds__(256) k_gs_dots(int nrhs, long long count, long long rs, const Tv* __restrict__ V,
                                                  int nv, long long vstride, const Tw* __restrict__ w,
                                                  double* __restrict__ partial, int nblk, Gate gt) {
@@ -273,32 +276,32 @@ __global__ void __launch_bounds__(256) k_gs_dots(int nrhs, long long count, long
   static_assert(kGsGroup == 4, "fold8 folds 2 x 4 values");
   __shared__ double red[4][2 * kGsMaxNv];
   const int r = blockIdx.y, blk = blockIdx.x, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long e0 = (long long)blk * kGsTile + threadIdx.x;
+  const long long e0 = (long long)blk * (256 * EPT) + threadIdx.x;
   const Tw* wr = w + (long long)r * rs;
   const Tv* vr = V + (long long)r * rs;
-  cx<double> x[kGsEpt];
-  long long ek[kGsEpt];
+  cx<double> x[EPT];
+  long long ek[EPT];
 #pragma unroll
-  for (int k = 0; k < kGsEpt; ++k) {
+  for (int k = 0; k < EPT; ++k) {
     const long long e = e0 + 256LL * k;
     ek[k] = e < count ? e : count - 1;
     const cx<double> v = ld<double, Tw>(wr + ek[k]);
     x[k] = e < count ? v : cx<double>{0.0, 0.0};   // entries past the end contribute zero
   }
   for (int i0 = 0; i0 < nv; i0 += kGsGroup) {
-    Tv raw[kGsGroup][kGsEpt];
+    Tv raw[kGsGroup][EPT];
 #pragma unroll
     for (int g = 0; g < kGsGroup; ++g) {
       const Tv* vi = vr + (long long)(i0 + g < nv ? i0 + g : nv - 1) * vstride;   // past nv: discarded below
 #pragma unroll
-      for (int k = 0; k < kGsEpt; ++k) raw[g][k] = vi[ek[k]];
+      for (int k = 0; k < EPT; ++k) raw[g][k] = vi[ek[k]];
     }
     double a[2 * kGsGroup];
 #pragma unroll
     for (int g = 0; g < kGsGroup; ++g) {
       cx<double> acc = {0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < kGsEpt; ++k) cfma_conj(acc, ld<double, Tv>(&raw[g][k]), x[k]);
+      for (int k = 0; k < EPT; ++k) cfma_conj(acc, ld<double, Tv>(&raw[g][k]), x[k]);
       a[2 * g] = acc.re;
       a[2 * g + 1] = acc.im;
     }
@@ -312,7 +315,7 @@ __global__ void __launch_bounds__(256) k_gs_dots(int nrhs, long long count, long
 }
 
 // w[r] <- w[r] - sum_{i < nv} coef[r * ldc + i] V_i[r], partial sums of |w|^2 over the same tiles
-template <typename Tv, typename Tw>
+template <typename Tv, typename Tw, int EPT>
 __global__ void __launch_bounds__(256) k_gs_axpy_norm(int nrhs, long long count, long long rs,
                                                       const Tv* __restrict__ V, int nv, long long vstride,
                                                       const double2* __restrict__ coef, int ldc, Tw* __restrict__ w,
@@ -327,35 +330,35 @@ __global__ void __launch_bounds__(256) k_gs_axpy_norm(int nrhs, long long count,
     c[i] = {v.x, v.y};
   }
   __syncthreads();
-  const long long e0 = (long long)blk * kGsTile + threadIdx.x;
+  const long long e0 = (long long)blk * (256 * EPT) + threadIdx.x;
   Tw* wr = w + (long long)r * rs;
   const Tv* vr = V + (long long)r * rs;
-  cx<double> x[kGsEpt];
-  long long ek[kGsEpt];
+  cx<double> x[EPT];
+  long long ek[EPT];
 #pragma unroll
-  for (int k = 0; k < kGsEpt; ++k) {
+  for (int k = 0; k < EPT; ++k) {
     const long long e = e0 + 256LL * k;
     ek[k] = e < count ? e : count - 1;
     x[k] = ld<double, Tw>(wr + ek[k]);
   }
   for (int i0 = 0; i0 < nv; i0 += kGsGroup) {
-    Tv raw[kGsGroup][kGsEpt];
+    Tv raw[kGsGroup][EPT];
 #pragma unroll
     for (int g = 0; g < kGsGroup; ++g) {
       const Tv* vi = vr + (long long)(i0 + g < nv ? i0 + g : nv - 1) * vstride;   // past nv: weight zero
 #pragma unroll
-      for (int k = 0; k < kGsEpt; ++k) raw[g][k] = vi[ek[k]];
+      for (int k = 0; k < EPT; ++k) raw[g][k] = vi[ek[k]];
     }
 #pragma unroll
     for (int g = 0; g < kGsGroup; ++g) {
       const cx<double> cg = c[i0 + g];
 #pragma unroll
-      for (int k = 0; k < kGsEpt; ++k) x[k] = x[k] - cg * ld<double, Tv>(&raw[g][k]);
+      for (int k = 0; k < EPT; ++k) x[k] = x[k] - cg * ld<double, Tv>(&raw[g][k]);
     }
   }
   double n2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < kGsEpt; ++k) {
+  for (int k = 0; k < EPT; ++k) {
     const long long e = e0 + 256LL * k;
     if (e < count) {
       st<Tw, double>(wr + e, x[k]);
@@ -810,19 +813,29 @@ void launch_axpy_norm(dd_dtype vt, int nrhs, long long count, long long rs, cons
 #undef DD_BASIS_DISPATCH
 
 int gs_max_nv() { return kGsMaxNv; }
-int gs_blocks(long long count) { return (int)((count + kGsTile - 1) / kGsTile); }
+static int gs_ept(long long count) { return count <= kGsShort ? 1 : 8; }
+int gs_blocks(long long count) {
+  const long long tile = 256LL * gs_ept(count);
+  return (int)((count + tile - 1) / tile);
+}
 
-// basis V of dtype bt (DD_F16 only with FP32 vectors), vector w of dtype vt
-#define DD_GS_DISPATCH(KERNEL, ...)                                                                  \
-  if (vt == DD_F64)                                                                                   \
-    KERNEL<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,   \
-                                                   __VA_ARGS__, (double2*)w, partial, nblk, current_gate());          \
-  else if (bt == DD_F16)                                                                              \
-    KERNEL<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride,    \
-                                                  __VA_ARGS__, (float2*)w, partial, nblk, current_gate());            \
-  else                                                                                                \
-    KERNEL<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,      \
-                                                 __VA_ARGS__, (float2*)w, partial, nblk, current_gate());
+// basis V of dtype bt (DD_F16 only with FP32 vectors), vector w of dtype vt, EPT entries per thread
+#define DD_GS_LAUNCH(KERNEL, EPT, ...)                                                                          \
+  if (vt == DD_F64)                                                                                             \
+    KERNEL<double2, double2, EPT><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,        \
+                                                        __VA_ARGS__, (double2*)w, partial, nblk, current_gate()); \
+  else if (bt == DD_F16)                                                                                        \
+    KERNEL<__half2, float2, EPT><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride,         \
+                                                       __VA_ARGS__, (float2*)w, partial, nblk, current_gate());  \
+  else                                                                                                          \
+    KERNEL<float2, float2, EPT><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,           \
+                                                      __VA_ARGS__, (float2*)w, partial, nblk, current_gate());
+#define DD_GS_DISPATCH(KERNEL, ...)            \
+  if (gs_ept(count) == 1) {                    \
+    DD_GS_LAUNCH(KERNEL, 1, __VA_ARGS__)       \
+  } else {                                     \
+    DD_GS_LAUNCH(KERNEL, 8, __VA_ARGS__)       \
+  }
 
 void launch_gs_dots(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long long rs, const void* V, int nv,
                     long long vstride, const void* w, double* partial, double2* out, int ldo, hipStream_t st) {
@@ -830,18 +843,21 @@ void launch_gs_dots(dd_dtype bt, dd_dtype vt, int nrhs, long long count, long lo
   dim3 grid(nblk, nrhs);
   const size_t es = vt == DD_F64 ? sizeof(double2) : sizeof(float2), eb = bt == DD_F16 ? 4 : es;
   const double bytes = (double)nrhs * count * (nv * eb + es), flops = 8.0 * nrhs * count * nv;
-  if (vt == DD_F64)
-    DD_TIMED("k_gs_dots", st, bytes, flops,
-             (k_gs_dots<double2, double2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,
-                                                                (const double2*)w, partial, nblk, current_gate())));
-  else if (bt == DD_F16)
-    DD_TIMED("k_gs_dots", st, bytes, flops,
-             (k_gs_dots<__half2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride,
-                                                               (const float2*)w, partial, nblk, current_gate())));
+#define DD_GS_DOTS(EPT)                                                                                          \
+  if (vt == DD_F64)                                                                                              \
+    k_gs_dots<double2, double2, EPT><<<grid, 256, 0, st>>>(nrhs, count, rs, (const double2*)V, nv, vstride,      \
+                                                           (const double2*)w, partial, nblk, current_gate());     \
+  else if (bt == DD_F16)                                                                                         \
+    k_gs_dots<__half2, float2, EPT><<<grid, 256, 0, st>>>(nrhs, count, rs, (const __half2*)V, nv, vstride,       \
+                                                          (const float2*)w, partial, nblk, current_gate());       \
+  else                                                                                                           \
+    k_gs_dots<float2, float2, EPT><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,         \
+                                                         (const float2*)w, partial, nblk, current_gate());
+  if (gs_ept(count) == 1)
+    DD_TIMED("k_gs_dots", st, bytes, flops, DD_GS_DOTS(1));
   else
-    DD_TIMED("k_gs_dots", st, bytes, flops,
-             (k_gs_dots<float2, float2><<<grid, 256, 0, st>>>(nrhs, count, rs, (const float2*)V, nv, vstride,
-                                                              (const float2*)w, partial, nblk, current_gate())));
+    DD_TIMED("k_gs_dots", st, bytes, flops, DD_GS_DOTS(8));
+#undef DD_GS_DOTS
   k_reduce<<<nrhs * nv, 256, 0, st>>>(nv, nblk, partial, out, ldo, 0, current_gate());
 }
 
@@ -856,6 +872,7 @@ void launch_gs_axpy_norm(dd_dtype bt, dd_dtype vt, int nrhs, long long count, lo
   k_reduce<<<nrhs, 256, 0, st>>>(1, nblk, partial, out, 1, 0, current_gate());
 }
 #undef DD_GS_DISPATCH
+#undef DD_GS_LAUNCH
 
 void launch_normalize(dd_dtype vt, int nrhs, long long count, long long rs, const void* src, const double2* nrm2,
                       const double* nrm, const int* mask, void* dst, hipStream_t st, dd_dtype dt, void* copy32) {
