@@ -105,6 +105,8 @@ typedef struct {
 } dd_mg_params;
 
 typedef struct {
+  /* coarse_iters_total: Arnoldi steps of the coarse even-odd GMRES summed over the call's V-cycles
+   * (with a third level: steps of the level-2 FGMRES cycles) */
   int32_t outer_iters, restarts, coarse_iters_total, converged;
   double true_relres;          /* |b - D x| / |b| with the FP64 operator */
   double t_setup_s, t_solve_s;
@@ -320,7 +322,8 @@ dd_status dd_prolong(dd_mg* mg, dd_dtype dt, int nrhs, const void* coarse_in, vo
                      void* stream);    /* Eq. 4 */
 dd_status dd_coarse_apply(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out,
                           void* stream);   /* Eq. 2 stencil */
-/* approximate D_c^-1: even-odd GMRES to coarse_tol (or coarse_fixed_iters).
+/* approximate D_c^-1: even-odd GMRES to coarse_tol (or coarse_fixed_iters), or, with a third level
+ * attached, the level-2 FGMRES cycle (dd_mg_add_level); *iters gets the GMRES (level-2) steps.
  * DD_F64 needs an all-FP64 setup (inner_dtype DD_F64); DD_F32 works on either. */
 dd_status dd_coarse_solve(dd_mg* mg, dd_dtype dt, int nrhs, const void* in, void* out,
                           int* iters, void* stream);
