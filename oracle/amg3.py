@@ -22,7 +22,7 @@ once more, to the coarse operator D_c of Eq. (2), written out plainly in FP64:
     (k steps of minimal residual started from the coarse correction), one
     classical Gram-Schmidt pass per step, stopped when its residual estimate
     reaches tol |b| or after max_iters steps.
-None of this is in the paper; the design doc lists these readings.
+None of this is printed in the paper: each point above is a reading of it.
 """
 from dataclasses import dataclass
 from types import SimpleNamespace
