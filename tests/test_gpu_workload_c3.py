@@ -161,24 +161,25 @@ def test_c3_restrict_prolong_sampled(c3):
     torch.cuda.empty_cache()
 
 
-def test_c3_solve_residual_sampled(c3):
-    """The benchmark's whole configuration: adaptive setup (BF16 test vectors,
-    4 setup iterations), FP16 coarse Krylov basis and BF16 coarse products,
-    one Gram-Schmidt pass in the outer solver, graphs, and one batched solve
-    of the 12 spin-colour point sources at the origin to 1e-10.  Every solve
-    converges, and the oracle's residual at the sampled sites (the source and
-    its neighbours included) is below the tolerance."""
-    import torch
-    import _gpu
-    from oracle import dirac
+def _bench_mg(c3):
+    """The benchmark's setup: adaptive (BF16 test vectors, 4 setup iterations), one outer Gram-Schmidt pass,
+    graph mode 1, the benchmark's launch choices."""
     from paper_1811_00355_amd import MG, default_params
-    lat, cfg, U = c3.lat, c3.cfg, c3.U
+    cfg = c3.cfg
     p = default_params(block=cfg["block"], n_vec=cfg["n_vec"], setup_iters=cfg["setup_iters"], inner_dtype=1,
                        store_dtype=3, seed=cfg["tv_seed"], coarse_restart=60, coarse_max_iters=300,
                        coarse_cgs_passes=1, outer_cgs_passes=1)
     mg = MG(c3.g, p)
     mg.dd_mg_set_graphs(1)
     _bench_tuning(c3.g)
+    return mg
+
+
+def _solve_point_sources(c3, mg):
+    """One batched solve of the 12 spin-colour point sources at the origin to 1e-10; returns x on the host."""
+    import torch
+    import _gpu
+    lat = c3.lat
     b = torch.zeros((NRHS, lat.V * 12), dtype=torch.complex128, device="cuda")
     for k in range(NRHS):
         b[k, k] = 1.0
@@ -190,8 +191,14 @@ def test_c3_solve_residual_sampled(c3):
     assert st == 0 and all(i["converged"] and i["true_relres"] <= TOL for i in info)
     xs = _gpu.to_host(x).reshape(NRHS, lat.V, 4, 3)
     del b, x
-    mg.destroy()
-    torch.cuda.empty_cache()
+    return xs
+
+
+def _check_point_source_residual(c3, xs):
+    """The oracle's residual of the point-source solves at the sampled sites (the source and its neighbours
+    included) is below the tolerance (|b| = 1)."""
+    from oracle import dirac
+    lat, cfg, U = c3.lat, c3.cfg, c3.U
     s = np.unique(np.concatenate([c3.sites] + [lat.nbr(np.array([0]), mu, sg)[0] for mu in range(4) for sg in (1, -1)]))
     A = dirac.clover_matrix(U, lat, cfg["m0"], cfg["c_sw"], sites=s)
     bs = np.zeros((NRHS, len(s), 12), dtype=np.complex128)   # source k: 1 in component k at site 0 (= s[0])
@@ -203,3 +210,56 @@ def test_c3_solve_residual_sampled(c3):
         worst = max(worst, float(np.sqrt(np.sum(np.abs(res) ** 2, axis=(1, 2))).max()))
     print(f"largest per-site residual at {len(s)} sites: {worst:.2e} (|b| = 1)", flush=True)
     assert worst <= TOL
+
+
+def test_c3_solve_residual_sampled(c3):
+    """The benchmark's whole configuration: adaptive setup (BF16 test vectors,
+    4 setup iterations), one Gram-Schmidt pass in the outer solver, graphs,
+    and one batched solve of the 12 spin-colour point sources at the origin to
+    1e-10.  Every solve converges, and the oracle's residual at the sampled
+    sites (the source and its neighbours included) is below the tolerance."""
+    import torch
+    mg = _bench_mg(c3)
+    xs = _solve_point_sources(c3, mg)
+    mg.destroy()
+    torch.cuda.empty_cache()
+    _check_point_source_residual(c3, xs)
+
+
+def test_c3_three_level_sampled(c3):
+    """The benchmark's three-level side run at full size (its default third
+    level on the benchmark's setup): properties that hold at any size -- every
+    (level-3 site, chirality) set of P2 orthonormal, D3 Gamma5-hermitian block
+    by block (Gamma5 D3(X, +mu) Gamma5 = D3(X + mu, -mu)^dag, the self block
+    hermitian after Gamma5) -- and the batched point-source solve meeting 1e-10
+    on the oracle's residual at the sampled sites."""
+    import torch
+    from oracle import amg, amg3
+    from paper_1811_00355_amd import level3_params
+    mg = _bench_mg(c3)
+    mg.add_level(level3_params())
+    tv2, P2, D3 = mg.export_level3()
+    del tv2
+    n2 = P2.shape[2]
+    worst_o = max(float(np.abs(np.einsum("sik,sjk->sij", np.conj(P2[X]), P2[X]) - np.eye(n2)).max())
+                  for X in range(P2.shape[0]))
+    lev = amg3.Level2Lattice(c3.lat)
+    nb = amg.coarse_neighbors(lev.lat3)
+    g5 = np.r_[np.ones(n2), -np.ones(n2)]
+    scale = float(np.abs(D3).max())
+    worst_h = 0.0
+    for X in range(lev.Vc3):
+        worst_h = max(worst_h, float(np.abs(g5[:, None] * D3[X, 0] * g5[None, :] - D3[X, 0].conj().T).max()))
+        for dd in range(1, 9):
+            back = dd + 4 if dd <= 4 else dd - 4
+            Y = nb[dd][X]
+            worst_h = max(worst_h, float(np.abs(g5[:, None] * D3[X, dd] * g5[None, :] - D3[Y, back].conj().T).max()))
+    print(f"full-size third level: {lev.Vc3} sites x {2 * n2}: orthonormality {worst_o:.1e}, "
+          f"gamma5-hermiticity {worst_h / scale:.1e} (relative to the largest entry)", flush=True)
+    assert worst_o < 1e-12 and worst_h < 1e-12 * scale
+    del P2, D3
+    xs = _solve_point_sources(c3, mg)
+    print(f"level-2 steps of the last cycle, level-3 steps: {mg.level3_last()}", flush=True)
+    mg.destroy()
+    torch.cuda.empty_cache()
+    _check_point_source_residual(c3, xs)
