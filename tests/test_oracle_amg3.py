@@ -95,3 +95,44 @@ def test_three_level_solve_converges():
     true = np.linalg.norm(b - W.apply(x)) / np.linalg.norm(b)
     print(f"three-level solve: {info['outer_iters']} outer iterations, true relative residual {true:.2e}")
     assert info["converged"] and true <= 1e-10
+
+
+def test_mr_step_is_the_least_squares_minimiser():
+    """One minimal-residual step x1 = x0 + alpha r picks the complex alpha that
+    minimises |b - A x1|: the same alpha as a library least-squares solve of
+    min |r - alpha A r|; further steps never raise the residual.  A conjugated
+    or swapped inner product in alpha fails the first check."""
+    rng = np.random.default_rng(21)
+    m = 60
+    A = 3.0 * np.eye(m) + 0.8 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))) / np.sqrt(m)
+    A[0, 1] += 2.0j                                   # clearly non-normal
+    b = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    x0 = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    apply = lambda v: A @ v
+    r = b - A @ x0
+    alpha_ls = np.linalg.lstsq((A @ r)[:, None], r, rcond=None)[0][0]
+    x1 = amg3.mr_smooth(apply, b, x0, 1)
+    assert np.allclose(x1, x0 + alpha_ls * r, rtol=0, atol=1e-12 * np.abs(x1).max())
+    res = [np.linalg.norm(b - A @ amg3.mr_smooth(apply, b, x0, k)) for k in range(6)]
+    assert all(res[k + 1] <= res[k] * (1 + 1e-12) for k in range(5))
+
+
+def test_level3_correction_is_galerkin_orthogonal():
+    """With the level-3 system solved accurately, the coarse-grid correction
+    x = P2 D3^-1 R2 v leaves a residual v - D_c x that R2 annihilates
+    (R2 D_c P2 = D3): a wrong restriction, prolongation or level-3 operator
+    breaks it."""
+    n, n2 = 4, 3
+    lat, W, two, p = _coarse((8, 8, 8, 8), n)
+    lev = amg3.Level2Lattice(lat)
+    rng = np.random.default_rng(12)
+    tv2 = rng.standard_normal((n2, lat.Vc, 2 * n)) + 1j * rng.standard_normal((n2, lat.Vc, 2 * n))
+    p3 = amg3.L3Params(n_vec2=n2, l3_tol=1e-13, l3_restart=200, l3_max_iters=2000)
+    three = amg3.ThreeLevelCoarse(lat, n, two.Dc, tv2, p3, p)
+    v = rng.standard_normal((lat.Vc, 2 * n)) + 1j * rng.standard_normal((lat.Vc, 2 * n))
+    e3 = three.ceo3.solve(amg3.restrict2(lev, n, three.P2, v), three.p_l3)
+    x = amg3.prolong2(lev, n, three.P2, e3)
+    r = v - three.apply_Dc(x)
+    ratio = np.linalg.norm(amg3.restrict2(lev, n, three.P2, r)) / np.linalg.norm(amg3.restrict2(lev, n, three.P2, v))
+    print(f"|R2 (v - D_c P2 D3^-1 R2 v)| / |R2 v| = {ratio:.2e}")
+    assert ratio < 1e-10
