@@ -31,12 +31,83 @@ __global__ void __launch_bounds__(256) k_dirac(GeomDev g, const S* __restrict__ 
   store_spinor<R, To>(out + (long long)r * 12 * g.V, g.V, I, acc);
 }
 
+// With one right-hand side the streams read or written once per launch (the
+// clover operand, the output spinor) take non-temporal accesses, so that L2
+// keeps what neighbouring sites read again: the links (a site's forward link
+// is its backward neighbour's backward link) and the face spinors of
+// neighbouring blocks.  With several right-hand sides each RHS's workgroup
+// re-reads the clover, and L2 should keep it.
+template <typename R, typename S>
+__device__ __forceinline__ cx<R> ld_stream(const S* p) {
+  return ld<R, S>(p);
+}
+template <>
+__device__ __forceinline__ cx<double> ld_stream<double, double2>(const double2* p) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ cx<float> ld_stream<float, float2>(const float2* p) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return {v.x, v.y};
+}
+template <typename To, typename R>
+__device__ __forceinline__ void st_stream(To* p, cx<R> v) {
+  st<To, R>(p, v);
+}
+template <>
+__device__ __forceinline__ void st_stream<double2, double>(double2* p, cx<double> v) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2{v.re, v.im}, reinterpret_cast<v2*>(p));
+}
+template <>
+__device__ __forceinline__ void st_stream<float2, float>(float2* p, cx<float> v) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2{v.re, v.im}, reinterpret_cast<v2*>(p));
+}
+
+// C psi for the packed clover (two Hermitian 6x6 blocks), operand read as a stream
+template <typename R, typename S>
+__device__ __forceinline__ void clover_mul_stream(const S* C, long long V, long long I, const cx<R>* in,
+                                                  cx<R>* out) {
+#pragma unroll 1
+  for (int c = 0; c < 2; ++c) {
+    const S* B = C + (long long)(18 * c) * V + I;
+    cx<R> v[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) v[r] = c ? in[6 + r] : in[r];
+    cx<R> o[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const cx<R> d = ld_stream<R, S>(B + k * V);
+      o[2 * k] = d.re * v[2 * k];
+      o[2 * k + 1] = d.im * v[2 * k + 1];
+    }
+    int k = 3;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int q = r + 1; q < 6; ++q) {
+        const cx<R> u = ld_stream<R, S>(B + (long long)(k++) * V);
+        cfma4(o[r], u, v[q]);
+        cfma4_conj(o[q], u, v[r]);
+      }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {   // constant indices (c is not unrolled): acc stays in registers
+      if (c) out[6 + r] = o[r];
+      else out[r] = o[r];
+    }
+  }
+}
+
 // Block form (4^4 blocks: one workgroup of Bv = 256 threads per block and
 // right-hand side).  The block's spinors are staged in LDS once; hops to sites
 // of the same block read them there, so memory sees one read of every spinor
 // plus the hops across the block faces (a quarter of the sites per direction),
 // instead of eight gathers per site that the L2 cannot hold between hops.
-template <typename R, typename S, typename Tv, typename To = Tv>
+template <typename R, typename S, typename Tv, typename To = Tv, bool NT = false>
 __global__ void __launch_bounds__(256) k_dirac_blk(GeomDev g, const S* __restrict__ links,
                                                    const S* __restrict__ clov, int nrhs, const Tv* __restrict__ in,
                                                    To* __restrict__ out) {
@@ -52,7 +123,8 @@ __global__ void __launch_bounds__(256) k_dirac_blk(GeomDev g, const S* __restric
 #pragma unroll
   for (int c = 0; c < 12; ++c) sp[c][threadIdx.x] = psi[c];
   __syncthreads();
-  clover_mul<R, S, false>(clov, g.V, I, psi, acc);
+  if constexpr (NT) clover_mul_stream<R, S>(clov, g.V, I, psi, acc);
+  else clover_mul<R, S, false>(clov, g.V, I, psi, acc);
   auto fetch = [&](long long J, bool inside, cx<R>* p) {
     if (inside) {
       const int j = (int)(J - base);
@@ -63,7 +135,13 @@ __global__ void __launch_bounds__(256) k_dirac_blk(GeomDev g, const S* __restric
     }
   };
   hop_all<R, S>(g, links, s, I, false, fetch, acc);
-  store_spinor<R, To>(out + (long long)r * 12 * g.V, g.V, I, acc);
+  To* o = out + (long long)r * 12 * g.V;
+  if constexpr (NT) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st_stream<To, R>(o + (long long)c * g.V + I, acc[c]);
+  } else {
+    store_spinor<R, To>(o, g.V, I, acc);
+  }
 }
 
 // Half-precision operands, several right-hand sides (4^4 blocks): one workgroup
@@ -178,6 +256,31 @@ constexpr double kDiracFlopsPerSite = 1320.0 + 504.0 + 24.0;
 
 }  // namespace
 
+// block form of every storage type; NT: streaming clover and output (one right-hand side)
+template <bool NT>
+static void blk_dispatch(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
+                         hipStream_t st) {
+  const unsigned nb = xcd_grid(g.Vc, nrhs);
+  switch (dt) {
+    case DD_F64:
+      k_dirac_blk<double, double2, double2, double2, NT><<<nb, 256, 0, st>>>(
+          g, (const double2*)ops.links, (const double2*)ops.clover, nrhs, (const double2*)in, (double2*)out);
+      break;
+    case DD_F32:
+      k_dirac_blk<float, float2, float2, float2, NT><<<nb, 256, 0, st>>>(
+          g, (const float2*)ops.links, (const float2*)ops.clover, nrhs, (const float2*)in, (float2*)out);
+      break;
+    case DD_F16:
+      k_dirac_blk<float, __half2, float2, float2, NT><<<nb, 256, 0, st>>>(
+          g, (const __half2*)ops.links, (const __half2*)ops.clover, nrhs, (const float2*)in, (float2*)out);
+      break;
+    case DD_BF16:
+      k_dirac_blk<float, bf16x2, float2, float2, NT><<<nb, 256, 0, st>>>(
+          g, (const bf16x2*)ops.links, (const bf16x2*)ops.clover, nrhs, (const float2*)in, (float2*)out);
+      break;
+  }
+}
+
 static void dirac_dispatch(const GeomDev& g, dd_dtype dt, const OpSet& ops, int nrhs, const void* in, void* out,
                            int threads, hipStream_t st) {
   if (g.Bv == 256 && g.Vc % 16 == 0 && nrhs >= 2 && (dt == DD_F16 || dt == DD_BF16)) {
@@ -192,27 +295,10 @@ static void dirac_dispatch(const GeomDev& g, dd_dtype dt, const OpSet& ops, int 
     return;
   }
   if (g.Bv == 256 && g.Vc % 16 == 0) {   // block form, slab order over the blocks
-    const unsigned nb = xcd_grid(g.Vc, nrhs);
-    switch (dt) {
-      case DD_F64:
-        k_dirac_blk<double, double2, double2><<<nb, 256, 0, st>>>(g, (const double2*)ops.links,
-                                                                   (const double2*)ops.clover, nrhs,
-                                                                   (const double2*)in, (double2*)out);
-        break;
-      case DD_F32:
-        k_dirac_blk<float, float2, float2><<<nb, 256, 0, st>>>(g, (const float2*)ops.links, (const float2*)ops.clover,
-                                                               nrhs, (const float2*)in, (float2*)out);
-        break;
-      case DD_F16:
-        k_dirac_blk<float, __half2, float2><<<nb, 256, 0, st>>>(g, (const __half2*)ops.links,
-                                                                (const __half2*)ops.clover, nrhs,
-                                                                (const float2*)in, (float2*)out);
-        break;
-      case DD_BF16:
-        k_dirac_blk<float, bf16x2, float2><<<nb, 256, 0, st>>>(g, (const bf16x2*)ops.links, (const bf16x2*)ops.clover,
-                                                               nrhs, (const float2*)in, (float2*)out);
-        break;
-    }
+    if (nrhs == 1)
+      blk_dispatch<true>(g, dt, ops, nrhs, in, out, st);
+    else
+      blk_dispatch<false>(g, dt, ops, nrhs, in, out, st);
     return;
   }
   if (threads != 64 && threads != 128) threads = 256;
@@ -253,9 +339,14 @@ void launch_dirac_f32_in(const GeomDev& g, const OpSet& ops64, int nrhs, const f
   const double2* L = (const double2*)ops64.links;
   const double2* C = (const double2*)ops64.clover;
   if (g.Bv == 256 && g.Vc % 16 == 0) {
-    DD_TIMED("k_dirac", st, bytes, flops,
-             (k_dirac_blk<double, double2, float2, double2><<<xcd_grid(g.Vc, nrhs), 256, 0, st>>>(g, L, C, nrhs, in,
-                                                                                               out)));
+    if (nrhs == 1)
+      DD_TIMED("k_dirac", st, bytes, flops,
+               (k_dirac_blk<double, double2, float2, double2, true><<<xcd_grid(g.Vc, nrhs), 256, 0, st>>>(
+                   g, L, C, nrhs, in, out)));
+    else
+      DD_TIMED("k_dirac", st, bytes, flops,
+               (k_dirac_blk<double, double2, float2, double2, false><<<xcd_grid(g.Vc, nrhs), 256, 0, st>>>(
+                   g, L, C, nrhs, in, out)));
     return;
   }
   if (threads != 64 && threads != 128) threads = 256;
