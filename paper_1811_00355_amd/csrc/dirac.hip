@@ -102,6 +102,41 @@ __device__ __forceinline__ void clover_mul_stream(const S* C, long long V, long 
   }
 }
 
+// The eight hops in the order of hop_all (forward then backward per direction),
+// with both links of a direction loaded together: the backward neighbour's
+// forward link U_mu(x - mu) lies, for most sites, in the lines the workgroup's
+// own forward loads have just fetched, which the L2 does not keep until a
+// later backward hop once many blocks stream through it.
+template <typename R, typename S, typename Fetch>
+__device__ __forceinline__ void hop_pairs(const GeomDev& g, const S* links, const SiteLoc& s, long long I,
+                                          Fetch fetch, cx<R>* acc) {
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    bool wf, inf, wb, inb;
+    const long long Jf = neighbor(g, s, mu, +1, wf, inf);
+    const long long Jb = neighbor(g, s, mu, -1, wb, inb);
+    cx<R> uf[9], ub[9], psi[12];
+    load_link<R, S>(links, g.V, mu, I, uf);
+    load_link<R, S>(links, g.V, mu, Jb, ub);
+    fetch(Jf, inf, psi);
+    const R cf = (R)1 * (R)(wf ? -0.5 * g.bc_t : -0.5);
+    switch (mu) {
+      case 0: hop_t<0, -1, false, R>(uf, psi, cf, acc); break;
+      case 1: hop_t<1, -1, false, R>(uf, psi, cf, acc); break;
+      case 2: hop_t<2, -1, false, R>(uf, psi, cf, acc); break;
+      default: hop_t<3, -1, false, R>(uf, psi, cf, acc); break;
+    }
+    fetch(Jb, inb, psi);
+    const R cb = (R)1 * (R)(wb ? -0.5 * g.bc_t : -0.5);
+    switch (mu) {
+      case 0: hop_t<0, +1, true, R>(ub, psi, cb, acc); break;
+      case 1: hop_t<1, +1, true, R>(ub, psi, cb, acc); break;
+      case 2: hop_t<2, +1, true, R>(ub, psi, cb, acc); break;
+      default: hop_t<3, +1, true, R>(ub, psi, cb, acc); break;
+    }
+  }
+}
+
 // Block form (4^4 blocks: one workgroup of Bv = 256 threads per block and
 // right-hand side).  The block's spinors are staged in LDS once; hops to sites
 // of the same block read them there, so memory sees one read of every spinor
@@ -134,7 +169,7 @@ __global__ void __launch_bounds__(256) k_dirac_blk(GeomDev g, const S* __restric
       load_spinor<R, Tv>(x, g.V, J, p);
     }
   };
-  hop_all<R, S>(g, links, s, I, false, fetch, acc);
+  hop_pairs<R, S>(g, links, s, I, fetch, acc);
   To* o = out + (long long)r * 12 * g.V;
   if constexpr (NT) {
 #pragma unroll
