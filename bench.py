@@ -393,7 +393,7 @@ def level3_leg(B, mg, args, step, value2, half_store):
                half_coarse_arithmetic=half,
                kernels={k: dict(ms_per_step=round(v["ms"], 3), share=round(v["ms"] / max(tot, 1e-9), 3),
                                 launches_per_step=v["launches"])
-                        for k, v in sorted(kf.items(), key=lambda kv: -kv[1]["ms"])[:10]})
+                        for k, v in sorted(kf.items(), key=lambda kv: -kv[1]["ms"])[:14]})
     log(f"[bench] three levels: {out}")
     return out
 

@@ -85,52 +85,39 @@ __global__ void __launch_bounds__(256) k_gs2(int Vc, int n, int n2, const int* _
 }
 
 // out[r][X3][s*n2 + i] = sum_{l, c} conj(P2[X3][s][i][l*n + c]) v[r][slot_of[X3][l]][s*n + c]
-// One workgroup per X3; 16 lanes per output keep their P2 entries in registers
-// (K / 16 <= 24 each) across the right-hand sides, so P2 is read once per launch.
-constexpr int kMaxPer = 24;   // K / 16 for n <= 24
+// one workgroup per (X3, r), 16 lanes per output (one workgroup looping over the right-hand
+// sides with P2 in registers was slower: too few workgroups for the level-3 lattice)
 template <typename Tp, typename Tv>
 __global__ void __launch_bounds__(256) k_restrict2(int Vc, int Vc3, int n, int n2, const int* __restrict__ slot_of,
-                                                   const Tp* __restrict__ P2, int nrhs, const Tv* __restrict__ v,
+                                                   const Tp* __restrict__ P2, const Tv* __restrict__ v,
                                                    Tv* __restrict__ out) {
-  const int X3 = blockIdx.x, K = kL * n;
+  const int X3 = blockIdx.x, r = blockIdx.y, K = kL * n;
   const int lane16 = threadIdx.x & 15;
   for (int o = threadIdx.x >> 4; o < 2 * n2; o += blockDim.x >> 4) {
     const int s = o / n2, i = o - s * n2;
     const Tp* p = P2 + ((long long)(X3 * 2 + s) * n2 + i) * K;
-    Tp pk[kMaxPer];
-    int off[kMaxPer];
-#pragma unroll
-    for (int j = 0; j < kMaxPer; ++j) {
-      const int k = lane16 + 16 * j;
-      const bool ok = k < K;
-      const int l = ok ? k / n : 0, c = ok ? k - l * n : 0;
-      pk[j] = ok ? p[k] : Tp{};
-      off[j] = ok ? slot_of[X3 * kL + l] * 2 * n + s * n + c : -1;
+    double re = 0.0, im = 0.0;
+    for (int k = lane16; k < K; k += 16) {
+      const int l = k / n, c = k - l * n;
+      const Tp a = p[k];
+      const Tv b = v[((long long)r * Vc + slot_of[X3 * kL + l]) * 2 * n + s * n + c];
+      re += (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+      im += (double)a.x * (double)b.y - (double)a.y * (double)b.x;
     }
-    for (int r = 0; r < nrhs; ++r) {
-      const Tv* vr = v + (long long)r * Vc * 2 * n;
-      double re = 0.0, im = 0.0;
-#pragma unroll
-      for (int j = 0; j < kMaxPer; ++j) {
-        if (off[j] < 0) continue;
-        const Tp a = pk[j];
-        const Tv b = vr[off[j]];
-        re += (double)a.x * (double)b.x + (double)a.y * (double)b.y;
-        im += (double)a.x * (double)b.y - (double)a.y * (double)b.x;
-      }
-      for (int sh = 8; sh > 0; sh >>= 1) {
-        re += __shfl_xor(re, sh, 16);
-        im += __shfl_xor(im, sh, 16);
-      }
-      if (lane16 == 0) {
-        Tv res;
-        res.x = (decltype(res.x))re;
-        res.y = (decltype(res.y))im;
-        out[((long long)r * Vc3 + X3) * 2 * n2 + o] = res;
-      }
+    for (int off = 8; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 16);
+      im += __shfl_xor(im, off, 16);
+    }
+    if (lane16 == 0) {
+      Tv res;
+      res.x = (decltype(res.x))re;
+      res.y = (decltype(res.y))im;
+      out[((long long)r * Vc3 + X3) * 2 * n2 + o] = res;
     }
   }
 }
+
+constexpr int kMaxPer = 24;   // n2 <= 24
 
 // out[r][x][s*n + c] = sum_i P2[X3(x)][s][i][l(x)*n + c] y[r][X3(x)][s*n2 + i]; one thread per (x, component),
 // its n2 entries of P2 in registers across the right-hand sides
@@ -248,16 +235,17 @@ void launch_gs2(int Vc, int Vc3, int n, int n2, const int* slot_of, const double
 
 void launch_restrict2(dd_dtype vt, int Vc, int Vc3, int n, int n2, const int* slot_of, const void* P2, int nrhs,
                       const void* v, void* out, hipStream_t st) {
+  const dim3 grid(Vc3, nrhs);
   const double bytes = (double)nrhs * Vc * 2 * n * vector_pair_bytes(vt) + (double)Vc * 2 * n * n2 * vector_pair_bytes(vt);
   const double flops = 8.0 * nrhs * Vc * 2 * n * n2;
   if (vt == DD_F64)
     DD_TIMED("k_restrict2", st, bytes, flops,
-             (k_restrict2<double2, double2><<<Vc3, 256, 0, st>>>(Vc, Vc3, n, n2, slot_of, (const double2*)P2, nrhs,
-                                                                 (const double2*)v, (double2*)out)));
+             (k_restrict2<double2, double2><<<grid, 256, 0, st>>>(Vc, Vc3, n, n2, slot_of, (const double2*)P2,
+                                                                  (const double2*)v, (double2*)out)));
   else
     DD_TIMED("k_restrict2", st, bytes, flops,
-             (k_restrict2<float2, float2><<<Vc3, 256, 0, st>>>(Vc, Vc3, n, n2, slot_of, (const float2*)P2, nrhs,
-                                                               (const float2*)v, (float2*)out)));
+             (k_restrict2<float2, float2><<<grid, 256, 0, st>>>(Vc, Vc3, n, n2, slot_of, (const float2*)P2,
+                                                                (const float2*)v, (float2*)out)));
 }
 
 void launch_prolong2(dd_dtype vt, int Vc, int Vc3, int n, int n2, const int* l3_of, const int* loc_of, const void* P2,
