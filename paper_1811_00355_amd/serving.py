@@ -49,6 +49,31 @@ def library_footprint(L, block, n_vec, store, nrhs):
     return B.footprint(L, block, p, nrhs)
 
 
+def level3_supported(L, block):
+    """A third level needs every coarse-lattice extent to be a multiple of 4."""
+    return all((L[m] // block[m]) % 4 == 0 for m in range(4))
+
+
+def level3_bytes(L, block, n_vec, store, nrhs, n2=24, kmax=40, l3_restart=60, coarse_restart=60):
+    """Device bytes of a default third level (dd_mg_add_level without host
+    vectors), from the library's layout: `static` (tables, level-2 vectors, P2
+    in FP64 and FP32, D3 and its odd-site inverses in FP64, FP32 and, for half
+    storage, the half type), `workspace` (the level-2 FGMRES cycle and the
+    level-3 GMRES for nrhs right-hand sides, FP32) and `transient` (the
+    inverse-iteration buffers and coarse workspace while the level is added).
+    A few percent of alignment and small per-RHS state are covered by a margin."""
+    Vc = int(np.prod([L[m] // block[m] for m in range(4)]))
+    Vc3, nc, nc3 = Vc // 16, 2 * n_vec, 2 * n2
+    nvec = n2 * Vc * nc
+    half = 4 if store in ("f16", "bf16") else 0
+    static = 4 * (8 * Vc3 + 3 * Vc + 1) + nvec * (16 + 16 + 8) + (9 * Vc3 + Vc3 // 2) * nc3 * nc3 * (16 + 8 + half)
+    coarse2, coarse3 = Vc * nc * nrhs, Vc3 * nc3 * nrhs
+    workspace = 8 * (coarse2 * (2 * kmax + 4) + 2 * coarse3) + 8 * coarse3 * (l3_restart + 9)
+    transient = 8 * 2 * nvec + 8 * Vc * nc * n2 * (coarse_restart + 9)
+    margin = lambda b: int(1.05 * b) + (1 << 20)   # noqa: E731
+    return dict(static=margin(static), workspace=margin(workspace), transient=margin(transient))
+
+
 # ----------------------------------------------------------------------------
 # requests
 # ----------------------------------------------------------------------------
@@ -499,7 +524,7 @@ class GpuExecutor:
     latency); sources are drawn on the device from a per-request seed."""
 
     def __init__(self, ctx, links, block=(4, 4, 4, 4), n_vec=20, store="f32", c_sw=1.0, setup_iters=4,
-                 tol=1e-10, graphs=False, tune_cache=None):
+                 tol=1e-10, graphs=False, tune_cache=None, levels=2):
         from . import binding as B
         import torch
         self.B = B
@@ -508,6 +533,8 @@ class GpuExecutor:
         self.block = tuple(block)
         self.n = n_vec
         self.store = B.DTYPES[store]
+        self.store_name = store
+        self.levels = levels          # 3: fields whose coarse extents allow it get the default third level
         self.c_sw = c_sw
         self.setup_iters = setup_iters
         self.tol = tol
@@ -527,15 +554,23 @@ class GpuExecutor:
     def _fp(self, f, nrhs=1):
         return library_footprint(f.L, self.block, self.n, self.store, nrhs)
 
+    def _three(self, f):
+        return self.levels == 3 and level3_supported(f.L, self.block)
+
+    def _l3(self, f, nrhs=1):
+        return level3_bytes(f.L, self.block, self.n, self.store_name, nrhs) if self._three(f) else None
+
     def footprint(self, f):
-        fp = self._fp(f)
-        return fp["gauge"] + fp["setup"]
+        fp, l3 = self._fp(f), self._l3(f)
+        return fp["gauge"] + fp["setup"] + (l3["static"] if l3 else 0)
 
     def transient(self, f):
-        return self._fp(f)["scratch"]
+        l3 = self._l3(f)
+        return max(self._fp(f)["scratch"], l3["transient"] if l3 else 0)
 
     def workspace(self, f, nrhs):
-        return self._fp(f, nrhs)["workspace"]
+        l3 = self._l3(f, nrhs)
+        return self._fp(f, nrhs)["workspace"] + (l3["workspace"] if l3 else 0)
 
     def load(self, f):
         B = self.B
@@ -547,6 +582,8 @@ class GpuExecutor:
             mg.dd_mg_set_graphs(self.graphs)
             if self.tune_cache:
                 mg.dd_autotune(12, self.tune_cache)
+            if self._three(f):
+                mg.add_level(B.level3_params())
         except Exception:
             if "mg" in locals():
                 mg.destroy()
@@ -663,6 +700,8 @@ def main(argv=None):
     ap.add_argument("--store", default="bf16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--max-lanes", type=int, default=6, help="fields solved at once (1: one batch at a time)")
     ap.add_argument("--shapes", default="all", help="'all' or a count of the smallest shapes to use")
+    ap.add_argument("--levels", type=int, default=2, choices=[2, 3],
+                    help="3: fields whose coarse extents are multiples of 4 get the default third level")
     args = ap.parse_args(argv)
     from . import binding as B
     from workloads import su3_field
@@ -678,7 +717,7 @@ def main(argv=None):
     log(f"[serve] {sum(len(v) for v in pool.values())} fields generated on the host in {time.perf_counter() - t0:.1f} s")
     budget = int(args.hbm_gib * (1 << 30))
     ctx = B.Context(0, hbm_budget_bytes=budget)
-    ex = GpuExecutor(ctx, links, store=args.store)
+    ex = GpuExecutor(ctx, links, store=args.store, levels=args.levels)
     cap, mu = None, None
     if not (args.skip_capacity and args.rate):
         # closed loop: everything queued at t = 0 gives the capacity
@@ -699,7 +738,7 @@ def main(argv=None):
         L = "x".join(map(str, next(f.L for v in pool.values() for f in v if f.key == d.field)))
         by_shape.setdefault(L, []).append(d.latency)
     res.update(capacity_requests_per_s=None if mu is None else round(mu, 4), arrival_rate_per_s=round(rate, 4),
-               store=args.store, max_lanes=args.max_lanes, closed_loop=cap,
+               store=args.store, max_lanes=args.max_lanes, levels=args.levels, closed_loop=cap,
                shapes=["x".join(map(str, L)) for L in shapes], fields_per_shape=args.per_shape,
                p50_by_shape={k: round(float(np.percentile(v, 50)), 3) for k, v in by_shape.items()},
                p99_by_shape={k: round(float(np.percentile(v, 99)), 3) for k, v in by_shape.items()})

@@ -92,3 +92,40 @@ def test_reported_footprint_is_what_the_library_allocates(store):
     g.destroy()
     assert ctx.bytes_in_use() == 0
     ctx.close()
+
+
+def test_level3_memory_model_bounds_the_allocation():
+    """The serving loop's third-level model (serving.level3_bytes) bounds what
+    dd_mg_add_level and a solve with the level actually allocate, within its
+    stated margin: static arrays within 1.3x of the model, and the level's
+    workspace for the solve's right-hand sides below the model."""
+    import torch
+    from paper_1811_00355_amd import Context, Gauge, MG, binding as B, level3_params
+    from paper_1811_00355_amd import serving as S
+    from workloads import su3_field, gauss_spinor
+    L, blk, n, nrhs = (16, 16, 16, 16), (4, 4, 4, 4), 20, 3
+    assert S.level3_supported(L, blk)
+    fp = S.library_footprint(L, blk, n, B.DD_BF16, nrhs)
+    model = S.level3_bytes(L, blk, n, "bf16", nrhs)
+    ctx = Context(0)
+    g = Gauge(ctx, L, blk, su3_field(L, 0.2, 6202), -0.15, 1.0)
+    p = B.default_params(block=blk, n_vec=n, setup_iters=1, inner_dtype=B.DD_F32, store_dtype=B.DD_BF16, seed=8)
+    mg = MG(g, p)
+    base = ctx.bytes_in_use()
+    assert base == fp["gauge"] + fp["setup"]
+    mg.add_level(level3_params())
+    static = ctx.bytes_in_use() - base
+    b = torch.from_numpy(gauss_spinor(L, nrhs, 6).reshape(nrhs, -1)).cuda()
+    x = torch.zeros_like(b)
+    info, _ = mg.dd_solve(nrhs, b, x, 1e-10)
+    torch.cuda.synchronize()
+    ws3 = ctx.bytes_in_use() - base - static - fp["workspace"]
+    print(f"third level: static {static} (model {model['static']}), workspace {ws3} (model {model['workspace']})",
+          flush=True)
+    assert all(i["converged"] for i in info)
+    assert static <= model["static"] <= 1.3 * static + (2 << 20)
+    assert 0 < ws3 <= model["workspace"]
+    mg.destroy()
+    g.destroy()
+    assert ctx.bytes_in_use() == 0
+    ctx.close()
